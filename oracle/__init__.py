@@ -1,0 +1,398 @@
+"""FP64 CPU oracle for the Chebyshev-filtered FE Hamiltonian of a biased slab.
+
+TEST INFRASTRUCTURE ONLY: the independent reference the GPU library is checked
+against.  Only the tests, the smoke check and the CPU-baseline leg of the
+benchmark import it.  It shares no code with the GPU library.
+
+The heavy parts (reference element, CSR assembly, sparse products, filter,
+adjoint) are plain C in ``oracle.c``; the dense steps (Lanczos bounds,
+Cholesky-QR, Rayleigh-Ritz) are numpy/LAPACK here.
+
+Parity unpinned: nothing here is unpinned; every function has at least one pin
+in ``tests/test_oracle_*.py``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "_oracle.so")
+_SRC = os.path.join(_HERE, "oracle.c")
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into _oracle.so (gcc, -O2, OpenMP)."""
+    if force or not os.path.exists(_SO):
+        tmp = _SO + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-D_DEFAULT_SOURCE", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+class _Mesh(C.Structure):
+    _fields_ = [("L", C.c_double * 3), ("ncell", C.c_int * 3), ("p", C.c_int),
+                ("bc", C.c_int * 3), ("rule", C.c_int)]
+
+
+class _CSR(C.Structure):
+    _fields_ = [("n", C.c_int64), ("rowptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p)]
+
+
+class _CSC(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nproj", C.c_int64), ("colptr", C.c_void_p),
+                ("row", C.c_void_p), ("val", C.c_void_p)]
+
+
+_lib = None
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = C.CDLL(_SO)
+        L.or_gll.argtypes = [C.c_int, _dp, _dp]
+        L.or_gauss.argtypes = [C.c_int, _dp, _dp]
+        L.or_lagrange_eval.argtypes = [C.c_int, C.c_double, _dp, _dp]
+        L.or_cell_stiffness.argtypes = [C.c_int, C.c_int, C.c_double, _dp]
+        L.or_n_free.argtypes = [C.POINTER(_Mesh)]
+        L.or_n_free.restype = C.c_int64
+        L.or_cell_dofs.argtypes = [C.POINTER(_Mesh), _i64p]
+        L.or_quad_points.argtypes = [C.POINTER(_Mesh), _dp]
+        L.or_mass.argtypes = [C.POINTER(_Mesh), _dp]
+        L.or_dof_coords.argtypes = [C.POINTER(_Mesh), _dp]
+        L.or_assemble.argtypes = [C.POINTER(_Mesh), C.c_int, C.c_void_p, C.c_double, C.c_double]
+        L.or_assemble.restype = C.POINTER(_CSR)
+        L.or_csr_free.argtypes = [C.POINTER(_CSR)]
+        L.or_csr_nnz.argtypes = [C.POINTER(_CSR)]
+        L.or_csr_nnz.restype = C.c_int64
+        L.or_csr_export.argtypes = [C.POINTER(_CSR), _i64p, _i32p, _dp]
+        L.or_projectors.argtypes = [C.POINTER(_Mesh), C.c_int, _dp, C.c_double, C.c_double]
+        L.or_projectors.restype = C.POINTER(_CSC)
+        L.or_csc_free.argtypes = [C.POINTER(_CSC)]
+        L.or_csc_nnz.argtypes = [C.POINTER(_CSC)]
+        L.or_csc_nnz.restype = C.c_int64
+        L.or_csc_export.argtypes = [C.POINTER(_CSC), _i64p, _i64p, _dp]
+        L.or_apply.argtypes = [C.POINTER(_CSR), C.c_void_p, C.c_void_p, _dp, _dp, C.c_int64]
+        L.or_cheb_coeffs.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, _dp, _dp,
+                                     C.POINTER(C.c_double)]
+        L.or_cheb_filter.argtypes = [C.POINTER(_CSR), C.c_void_p, C.c_void_p, _dp, _dp, C.c_int64,
+                                     C.c_int, C.c_double, C.c_double, C.c_double, C.c_void_p]
+        L.or_cheb_filter.restype = C.c_int
+        L.or_cheb_filter_vjp.argtypes = [C.POINTER(_CSR), C.c_void_p, C.c_void_p, _dp, _dp, C.c_int64,
+                                         C.c_int, C.c_double, C.c_double, C.c_double, _dp, _dp]
+        L.or_cheb_filter_vjp.restype = C.c_int
+        L.or_potential_vjp.argtypes = [C.POINTER(_Mesh), _dp, C.c_double, _dp, C.POINTER(C.c_double)]
+        L.or_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
+
+
+# ------------------------------------------------------------------ 1-D rules
+
+def gll(p: int):
+    """GLL nodes and weights of degree p on [-1, 1]."""
+    xi = np.zeros(p + 1); w = np.zeros(p + 1)
+    assert lib().or_gll(p, xi, w) == 0
+    return xi, w
+
+
+def gauss(q: int):
+    x = np.zeros(q); w = np.zeros(q)
+    assert lib().or_gauss(q, x, w) == 0
+    return x, w
+
+
+def lagrange(p: int, x: float):
+    """Values and derivatives of the p+1 GLL Lagrange polynomials at x."""
+    l = np.zeros(p + 1); dl = np.zeros(p + 1)
+    lib().or_lagrange_eval(p, float(x), l, dl)
+    return l, dl
+
+
+def cell_stiffness(p: int, rule: int = 0, h: float = 1.0) -> np.ndarray:
+    """Dense stiffness of one cubic cell, (p+1)^3 x (p+1)^3, local i fastest."""
+    nc = (p + 1) ** 3
+    K = np.zeros(nc * nc)
+    assert lib().or_cell_stiffness(p, rule, h, K) == 0
+    return K.reshape(nc, nc)
+
+
+# ------------------------------------------------------------------- the mesh
+
+class Mesh:
+    """Structured box of cubic cells with per-axis boundary conditions
+    (0 Dirichlet, 1 periodic, 2 zero-Neumann) and GLL degree p."""
+
+    def __init__(self, L, ncell, p, bc, rule=0):
+        self.L = tuple(float(x) for x in L)
+        self.ncell = tuple(int(x) for x in ncell)
+        self.p = int(p)
+        self.bc = tuple(int(x) for x in bc)
+        self.rule = int(rule)
+        self._m = _Mesh((C.c_double * 3)(*self.L), (C.c_int * 3)(*self.ncell), self.p,
+                        (C.c_int * 3)(*self.bc), self.rule)
+
+    @classmethod
+    def from_workload(cls, wl, rule=None):
+        return cls(wl.L, wl.ncell, wl.p, wl.bc, wl.rule if rule is None else rule)
+
+    @property
+    def nc(self) -> int:
+        return (self.p + 1) ** 3
+
+    @property
+    def n_cells(self) -> int:
+        return self.ncell[0] * self.ncell[1] * self.ncell[2]
+
+    @property
+    def n(self) -> int:
+        return int(lib().or_n_free(C.byref(self._m)))
+
+    def cell_dofs(self) -> np.ndarray:
+        out = np.zeros(self.n_cells * self.nc, dtype=np.int64)
+        lib().or_cell_dofs(C.byref(self._m), out)
+        return out.reshape(self.n_cells, self.nc)
+
+    def quad_points(self) -> np.ndarray:
+        out = np.zeros(self.n_cells * self.nc * 3)
+        lib().or_quad_points(C.byref(self._m), out)
+        return out.reshape(self.n_cells, self.nc, 3)
+
+    def mass(self) -> np.ndarray:
+        out = np.zeros(self.n)
+        lib().or_mass(C.byref(self._m), out)
+        return out
+
+    def dof_coords(self) -> np.ndarray:
+        out = np.zeros(self.n * 3)
+        lib().or_dof_coords(C.byref(self._m), out)
+        return out.reshape(self.n, 3)
+
+
+class CSR:
+    """Owning wrapper of an assembled CSR matrix."""
+
+    def __init__(self, ptr):
+        if not ptr:
+            raise MemoryError("oracle assembly failed")
+        self._p = ptr
+        self.n = ptr.contents.n
+
+    def __del__(self):
+        if getattr(self, "_p", None):
+            lib().or_csr_free(self._p)
+            self._p = None
+
+    @property
+    def nnz(self) -> int:
+        return int(lib().or_csr_nnz(self._p))
+
+    def to_scipy(self):
+        import scipy.sparse as sp
+        rp = np.zeros(self.n + 1, dtype=np.int64)
+        col = np.zeros(self.nnz, dtype=np.int32)
+        val = np.zeros(self.nnz)
+        lib().or_csr_export(self._p, rp, col, val)
+        return sp.csr_matrix((val, col, rp), shape=(self.n, self.n))
+
+
+class Projectors:
+    """Owning wrapper of the collocated projector matrix C~ (CSC, n x 9*n_site)."""
+
+    def __init__(self, mesh: Mesh, centres, r_cut: float, r_g: float):
+        centres = np.ascontiguousarray(centres, dtype=np.float64)
+        self.n_site = centres.shape[0]
+        self._p = lib().or_projectors(C.byref(mesh._m), self.n_site, centres.reshape(-1),
+                                      float(r_cut), float(r_g))
+        if not self._p:
+            raise MemoryError("projector construction failed")
+        self.n = mesh.n
+        self.nproj = 9 * self.n_site
+
+    def __del__(self):
+        if getattr(self, "_p", None):
+            lib().or_csc_free(self._p)
+            self._p = None
+
+    def to_scipy(self):
+        import scipy.sparse as sp
+        nnz = int(lib().or_csc_nnz(self._p))
+        cp = np.zeros(self.nproj + 1, dtype=np.int64)
+        row = np.zeros(nnz, dtype=np.int64)
+        val = np.zeros(nnz)
+        lib().or_csc_export(self._p, cp, row, val)
+        return sp.csc_matrix((val, row, cp), shape=(self.n, self.nproj))
+
+
+class Operator:
+    """H~ = M^-1/2 (1/2 K + V) M^-1/2 (+ C~ diag(D) C~^T), assembled on the CPU."""
+
+    def __init__(self, mesh: Mesh, Vq: Optional[np.ndarray], E: float, z0: float,
+                 projectors: Optional[Projectors] = None, Dnl: Optional[np.ndarray] = None):
+        self.mesh = mesh
+        self.E = float(E); self.z0 = float(z0)
+        vq = None
+        if Vq is not None:
+            self._Vq = np.ascontiguousarray(Vq, dtype=np.float64).reshape(-1)
+            assert self._Vq.size == mesh.n_cells * mesh.nc
+            vq = self._Vq.ctypes.data
+        self.A = CSR(lib().or_assemble(C.byref(mesh._m), 1, vq, self.E, self.z0))
+        self.n = self.A.n
+        self.proj = projectors
+        self.Dnl = None
+        if projectors is not None:
+            self.Dnl = np.ascontiguousarray(Dnl, dtype=np.float64).reshape(-1)
+            assert self.Dnl.size == projectors.nproj
+
+    def _nl(self):
+        if self.proj is None:
+            return None, None
+        return C.cast(self.proj._p, C.c_void_p), self.Dnl.ctypes.data
+
+    def apply(self, X: np.ndarray) -> np.ndarray:
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        one = X.ndim == 1
+        X2 = X.reshape(self.n, -1)
+        Y = np.zeros_like(X2)
+        c, d = self._nl()
+        lib().or_apply(self.A._p, c, d, X2, Y, X2.shape[1])
+        return Y.reshape(X.shape) if one else Y
+
+    def filter(self, X: np.ndarray, m: int, a: float, b: float, a0: float = float("nan"),
+               store: bool = False):
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        N = X.shape[1]
+        Y = np.zeros_like(X)
+        S = np.zeros((m + 1,) + X.shape) if store else None
+        c, d = self._nl()
+        rc = lib().or_cheb_filter(self.A._p, c, d, X, Y, N, m, a, b, a0,
+                                  None if S is None else S.ctypes.data)
+        if rc != 0:
+            raise ValueError(f"oracle filter failed ({rc})")
+        return (Y, S) if store else Y
+
+    def filter_vjp(self, X: np.ndarray, G: np.ndarray, m: int, a: float, b: float,
+                   a0: float = float("nan")):
+        """(Xbar, g) with g_I = dL/dv_I for the diagonal potential term."""
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        G = np.ascontiguousarray(G, dtype=np.float64)
+        Xb = np.zeros_like(X); g = np.zeros(self.n)
+        c, d = self._nl()
+        rc = lib().or_cheb_filter_vjp(self.A._p, c, d, X, G, X.shape[1], m, a, b, a0, Xb, g)
+        if rc != 0:
+            raise ValueError(f"oracle vjp failed ({rc})")
+        return Xb, g
+
+    def potential_vjp(self, g: np.ndarray):
+        """(Vbar at quadrature points (n_cells, nc), Ebar) from g = dL/dv."""
+        Vb = np.zeros(self.mesh.n_cells * self.mesh.nc)
+        Eb = C.c_double(0.0)
+        lib().or_potential_vjp(C.byref(self.mesh._m), np.ascontiguousarray(g), self.z0, Vb, C.byref(Eb))
+        return Vb.reshape(self.mesh.n_cells, self.mesh.nc), Eb.value
+
+
+def stiffness(mesh: Mesh):
+    """Global stiffness K (no 1/2, unscaled) as scipy CSR."""
+    return CSR(lib().or_assemble(C.byref(mesh._m), 0, None, 0.0, 0.0)).to_scipy()
+
+
+def cheb_coeffs(m: int, a: float, b: float, a0: float = float("nan")):
+    al = np.zeros(m); be = np.zeros(m); c = C.c_double(0.0)
+    lib().or_cheb_coeffs(m, a, b, a0, al, be, C.byref(c))
+    return al, be, c.value
+
+
+# -------------------------------------------------------- dense steps (numpy)
+
+def lanczos_bounds(op, v0: np.ndarray, k: int = 10):
+    """k-step Lanczos with full reorthogonalisation from start vector v0.
+
+    Returns (a0, b, theta): a0 = smallest Ritz value, b = largest Ritz value
+    + |beta_k| (an upper bound of the spectrum, Zhou & Li 2011), theta all
+    Ritz values.  `op(v)` applies the operator to a vector.
+    """
+    n = v0.size
+    Q = np.zeros((n, k + 1))
+    alpha = np.zeros(k); beta = np.zeros(k)
+    Q[:, 0] = v0 / np.linalg.norm(v0)
+    for j in range(k):
+        w = op(Q[:, j])
+        alpha[j] = Q[:, j] @ w
+        w = w - Q[:, : j + 1] @ (Q[:, : j + 1].T @ w)
+        w = w - Q[:, : j + 1] @ (Q[:, : j + 1].T @ w)
+        beta[j] = np.linalg.norm(w)
+        if beta[j] == 0.0:
+            k = j + 1
+            break
+        Q[:, j + 1] = w / beta[j]
+    T = np.diag(alpha[:k]) + np.diag(beta[: k - 1], 1) + np.diag(beta[: k - 1], -1)
+    theta = np.linalg.eigvalsh(T)
+    return float(theta[0]), float(theta[-1] + abs(beta[k - 1])), theta
+
+
+def weyl_cut(a0: float, b: float, N: int, n: int) -> float:
+    """First cut a = a0 + (b - a0) (N/n)^(2/3): a Weyl-law guess of lambda_N."""
+    return a0 + (b - a0) * (N / n) ** (2.0 / 3.0)
+
+
+def cholqr2(Y: np.ndarray):
+    """Two passes of Cholesky-QR: Q = Y R^-1 with Q^T Q = I."""
+    Q = Y
+    R = np.eye(Y.shape[1])
+    for _ in range(2):
+        S = Q.T @ Q
+        Rk = np.linalg.cholesky(S).T          # S = Rk^T Rk
+        Q = np.linalg.solve(Rk.T, Q.T).T      # Q Rk^-1
+        R = Rk @ R
+    return Q, R
+
+
+def rayleigh_ritz(apply, Q: np.ndarray):
+    """Ritz values/vectors of the operator on span(Q) (Q orthonormal)."""
+    P = apply(Q)
+    Hs = Q.T @ P
+    Hs = 0.5 * (Hs + Hs.T)
+    theta, W = np.linalg.eigh(Hs)
+    return theta, Q @ W
+
+
+def subspace_iteration(op: Operator, X0: np.ndarray, m: int, iters: int, a: float, b: float, a0: float):
+    """Chebyshev-filtered subspace iteration: filter, CholQR2, Rayleigh-Ritz;
+    the cut a and the scaling point a0 follow the current Ritz values."""
+    X = X0
+    hist = []
+    for _ in range(iters):
+        Y = op.filter(X, m, a, b, a0)
+        Q, _ = cholqr2(Y)
+        theta, X = rayleigh_ritz(op.apply, Q)
+        hist.append(theta)
+        a, a0 = float(theta[-1]), float(theta[0])
+    return hist, X
+
+
+def chebyshev_T(m: int, t: np.ndarray) -> np.ndarray:
+    """T_m(t) from the closed forms cos(m acos t) (|t|<=1) and
+    sign(t)^m cosh(m acosh |t|) (|t|>1)."""
+    t = np.asarray(t, dtype=np.float64)
+    out = np.empty_like(t)
+    inside = np.abs(t) <= 1.0
+    out[inside] = np.cos(m * np.arccos(t[inside]))
+    ti = t[~inside]
+    out[~inside] = np.sign(ti) ** m * np.cosh(m * np.arccosh(np.abs(ti)))
+    return out
