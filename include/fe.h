@@ -1,0 +1,195 @@
+/*
+ * fe.h -- C ABI of the MI355X (gfx950) finite-element Hamiltonian filter.
+ *
+ * The library applies the GLL spectral-element Kohn-Sham Hamiltonian of a
+ * slab under a constant external field, in the symmetric standard form
+ *
+ *     H~ = M^-1/2 ( 1/2 K + V ) M^-1/2  (+ C~ diag(D) C~^T, optional),
+ *
+ * to blocks of wavefunction coefficients, and runs the Chebyshev filter
+ * Y = T_m((H~ - c)/e) X built on it.  K is the FE stiffness
+ * K_IJ = int grad N_I . grad N_J and M the GLL-lumped overlap of the
+ * C0 Lagrange basis on GLL nodes (paper Sec. 2.3); V is the effective
+ * potential V_eff + V_app at the cell GLL points, with V_app the linear
+ * field term of slope -E (Sec. 2.1, Eq. for H_loc and V_eff; Sec. 2.2.1);
+ * the optional term is the separable nonlocal pseudopotential (Sec. 2.1,
+ * Eq. V_nloc).  The filter is the kernel of Chebyshev-filtered subspace
+ * iteration for the discrete eigenproblem H u = eps M u (Sec. 2.3).
+ *
+ * Conventions (all entry points):
+ *   - Every function returns fe_status; FE_OK is 0.  On failure nothing has
+ *     been enqueued and fe_last_error() returns a message (thread-local).
+ *   - The library never aborts, prints or exits.
+ *   - Array arguments are DEVICE pointers owned by the caller unless a
+ *     parameter says "host".  The library owns only what fe_mesh_create and
+ *     fe_set_* allocate (cell matrices, scales, potential, projectors,
+ *     scratch), released by fe_mesh_destroy.
+ *   - Work is enqueued on the caller's stream; calls return without a device
+ *     synchronisation unless the description says otherwise.
+ *   - A mesh is not thread-safe; distinct meshes are independent.
+ *   - Hartree atomic units (bohr, Ha).
+ *   - Wavefunction blocks are FP64, (n x N) row-major with leading dimension
+ *     ld >= N: the N values of one degree of freedom are contiguous.  Free
+ *     DoFs are numbered x fastest, z slowest, after periodic identification
+ *     and removal of homogeneous-Dirichlet nodes.
+ */
+#ifndef FE_H
+#define FE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FE_OK = 0,
+    FE_EINVAL = 1,  /* bad argument (range, null, alignment, overlap)      */
+    FE_ENOMEM = 2,  /* device allocation failed or workspace too small     */
+    FE_EDEVICE = 3, /* a HIP call failed                                    */
+    FE_ESTATE = 4,  /* call out of order (e.g. no potential set yet)       */
+    FE_ENOTSUP = 5  /* valid request the library does not implement        */
+} fe_status;
+
+typedef enum { FE_BC_DIRICHLET = 0, FE_BC_PERIODIC = 1, FE_BC_NEUMANN = 2 } fe_bc;
+
+/* Integration of the stiffness: EXACT integrates int grad N_I . grad N_J
+ * exactly (the paper's definition, Sec. 2.3); GLL uses the collocated GLL
+ * rule (the classic spectral-element stiffness). */
+typedef enum { FE_RULE_EXACT = 0, FE_RULE_GLL = 1 } fe_rule;
+
+/* Precision of the cell products only; the recurrence, the nodal sums and
+ * all inputs/outputs stay FP64.  F32: operands rounded to FP32 (RNE), FP32
+ * accumulation.  BF16: operands rounded FP64->FP32->BF16 (RNE each), FP32
+ * accumulation. */
+typedef enum { FE_F64 = 0, FE_F32 = 1, FE_BF16 = 2 } fe_dtype;
+
+typedef struct {
+    double L[3];       /* box edge lengths; cells must be cubes L[a]/ncell[a] = h */
+    int32_t ncell[3];  /* cells per axis, >= 1 (>= 2 on a periodic axis)          */
+    int32_t p;         /* GLL degree, 1..7                                         */
+    int32_t bc[3];     /* fe_bc per axis                                           */
+    int32_t k_rule;    /* fe_rule                                                  */
+} fe_mesh_desc;
+
+typedef struct fe_mesh fe_mesh;
+
+/* Message describing the last failure on this thread ("" if none). */
+const char *fe_last_error(void);
+
+/* Build the mesh, reference element and cell matrices (Sec. 2.3) on the
+ * current HIP device and upload them.  Errors: FE_EINVAL for p outside 1..7,
+ * ncell < 1 (or < 2 on a periodic axis), L <= 0, non-cubic cells, unknown bc
+ * or rule; FE_ENOMEM / FE_EDEVICE from the device.  *out is owned by the
+ * caller and released with fe_mesh_destroy. Synchronous. */
+fe_status fe_mesh_create(const fe_mesh_desc *desc, fe_mesh **out);
+
+/* Release everything the mesh owns (synchronises the device first).
+ * NULL is accepted. */
+fe_status fe_mesh_destroy(fe_mesh *mesh);
+
+/* Sizes: free DoFs n, cells, and points per cell n_c = (p+1)^3.  Any output
+ * pointer may be NULL.  Host pointers. */
+fe_status fe_mesh_info(const fe_mesh *mesh, int64_t *n_dof, int64_t *n_cell, int32_t *n_c);
+
+/* Host copies of geometry: the cell GLL points xyz[(c*n_c + l)*3 + a]
+ * (cells lexicographic, x fastest; local index l = i + (p+1)(j + (p+1)k))
+ * and the free-DoF coordinates xyz[I*3 + a].  Host pointers, caller-owned,
+ * sized n_cell*n_c*3 and n*3 doubles. */
+fe_status fe_mesh_quad_points(const fe_mesh *mesh, double *xyz_host);
+fe_status fe_mesh_dof_coords(const fe_mesh *mesh, double *xyz_host);
+
+/* Host copy of the reference element of degree p (Sec. 2.3): GLL nodes
+ * xi[p+1] and weights w[p+1] on [-1, 1], and the half cell stiffness
+ * A = 1/2 Kc ((p+1)^3 x (p+1)^3, row-major, local index i + (p+1)(j + (p+1)k))
+ * of a cube of edge h under the given rule.  Pure host computation; any
+ * output may be NULL.  FE_EINVAL for p outside 1..7, h <= 0 or an unknown
+ * rule. */
+fe_status fe_reference_cell(int32_t p, int32_t k_rule, double h, double *xi_host, double *w_host, double *A_host);
+
+/* Set the potential (Sec. 2.1 V_eff, Sec. 2.2.1 V_app):
+ *   v_I = sum_{(c,q) -> I} (|J| w_q / M_I) V_quad[c][q]  -  E (z_I - z0),
+ * the diagonal of H~ from GLL-collocated quadrature of V at the cell GLL
+ * points.  V_quad: device, [n_cell][n_c] as in fe_mesh_quad_points; values at
+ * Dirichlet points are ignored.  May be NULL (V_loc = 0).  Enqueued on stream;
+ * V_quad must stay valid until the stream reaches this call. */
+fe_status fe_set_potential(fe_mesh *mesh, const double *V_quad, double E, double z0, hipStream_t stream);
+
+/* Separable nonlocal term (Sec. 2.1, Eq. V_nloc, and Eq. for H_nloc): per site
+ * s, nine projectors p_beta = S_beta(x - R_s) exp(-|x-R_s|^2/(2 r_g^2)) for
+ * |x - R_s| < r_cut (S: 1; x, y, z; xy, yz, zx, x^2-y^2, 3z^2-r^2), minimum
+ * image on periodic axes, each normalised to sum_I M_I p(x_I)^2 = 1 and
+ * collocated as C~_I = M_I^1/2 p(x_I); H~ gains C~ diag(D) C~^T.
+ * centres_host [n_site][3], D_host [n_site][9] (Ha), host pointers.
+ * n_site = 0 clears the term.  Synchronous. */
+fe_status fe_set_nonlocal(fe_mesh *mesh, int32_t n_site, const double *centres_host, const double *D_host,
+                          double r_cut, double r_g, hipStream_t stream);
+
+/* Y = H~ X.  X, Y: device FP64 (n x N), leading dimension ld >= N, must not
+ * overlap.  prec selects the cell-product precision.  FE_ESTATE if no
+ * potential has been set; FE_EINVAL for N < 1, ld < N, NULL or overlapping
+ * blocks, or misalignment (8 bytes).  N = 0 is a no-op. */
+fe_status fe_hx_apply(fe_mesh *mesh, const double *X, double *Y, int64_t N, int64_t ld, fe_dtype prec,
+                      hipStream_t stream);
+
+/* Chebyshev filter of degree m on the unwanted interval [a, b]
+ * (e = (b-a)/2, c = (b+a)/2), by the three-term recurrence
+ *   Y_1 = alpha_0 (H~ - c) X,   Y_{k+1} = alpha_k (H~ - c) Y_k - beta_k Y_{k-1}.
+ * Scaled (a0 finite, a0 < a): sigma_1 = e/(a0-c), sigma_{k+1} = 1/(2/sigma_1 -
+ * sigma_k), alpha_0 = sigma_1/e, alpha_k = 2 sigma_{k+1}/e, beta_k =
+ * sigma_k sigma_{k+1}, giving Y = T_m((H~-c)/e) X / T_m((a0-c)/e).
+ * Unscaled (a0 NaN): alpha_0 = 1/e, alpha_k = 2/e, beta_k = 1.
+ * X is read-only; Y receives the result; work is caller-owned device scratch
+ * of at least n*N doubles (work_bytes) holding one recurrence block.  X, Y and
+ * work must not overlap.  Requires a < b and m >= 1 (FE_EINVAL); FE_ENOMEM
+ * if work_bytes is too small. */
+fe_status fe_cheb_filter(fe_mesh *mesh, const double *X, double *Y, int64_t N, int64_t ld, int32_t m, double a,
+                         double b, double a0, fe_dtype prec, double *work, size_t work_bytes, hipStream_t stream);
+
+/* Bytes of `work` fe_cheb_filter_vjp needs for these arguments (host call). */
+size_t fe_cheb_filter_vjp_work_bytes(const fe_mesh *mesh, int64_t N, int32_t m, int32_t ckpt_stride,
+                                     int32_t col_chunk);
+
+/* Reverse-mode derivative of fe_cheb_filter with respect to X and to the
+ * potential, for a cotangent G = dL/dY (bounds a, b, a0 held fixed):
+ *   Xbar = dL/dX  (n x N, ld),
+ *   Vbar_quad[c][q] = dL/dV_quad[c][q] = (|J| w_q / M_I) g_I,
+ *   *Ebar = dL/dE = -sum_I g_I (z_I - z0)  (device scalar),
+ * with g_I = sum_k alpha_k sum_j Ybar_{k+1}[I,j] Y_k[I,j] from the reverse
+ * three-term sweep (H~ symmetric, so the same operator is applied).
+ * Forward blocks are kept every ckpt_stride steps and recomputed in between
+ * (ckpt_stride = 1 stores all); columns are processed in chunks of col_chunk
+ * (0 = all N at once).  The nonlocal couplings are held fixed.  work and
+ * work_bytes as returned by fe_cheb_filter_vjp_work_bytes (FE_ENOMEM if
+ * smaller).  Vbar_quad and Ebar are overwritten. */
+fe_status fe_cheb_filter_vjp(fe_mesh *mesh, const double *X, const double *G, int64_t N, int64_t ld, int32_t m,
+                             double a, double b, double a0, fe_dtype prec, double *Xbar, double *Vbar_quad,
+                             double *Ebar, int32_t ckpt_stride, int32_t col_chunk, double *work,
+                             size_t work_bytes, hipStream_t stream);
+
+/* Spectrum bounds by k-step Lanczos on H~ with full reorthogonalisation
+ * from the device start vector v0 (n doubles): *a0 = smallest Ritz value,
+ * *b = largest Ritz value + |beta_k| (an upper bound of the spectrum).
+ * Host outputs; synchronises the stream.  k in 1..64. */
+fe_status fe_lanczos_bounds(fe_mesh *mesh, const double *v0, int32_t k, double *a0_host, double *b_host,
+                            hipStream_t stream);
+
+/* Two passes of Cholesky-QR on a device block Y (n x N, ld): Y <- Q with
+ * Q^T Q = I (FP64 throughout).  FE_EDEVICE if the Gram matrix is not
+ * numerically positive definite.  Synchronises the stream. */
+fe_status fe_cholqr2(fe_mesh *mesh, double *Y, int64_t N, int64_t ld, hipStream_t stream);
+
+/* Rayleigh-Ritz on an orthonormal block Q (n x N, ld): Hs = Q^T H~ Q
+ * (symmetrised, FP64 products), Hs = W diag(theta) W^T, X <- Q W.
+ * theta_host receives the N Ritz values ascending; P is caller scratch of n x N
+ * doubles (ld).  Synchronises the stream. */
+fe_status fe_rayleigh_ritz(fe_mesh *mesh, const double *Q, double *X, double *P, int64_t N, int64_t ld,
+                           double *theta_host, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FE_H */

@@ -1,0 +1,238 @@
+"""MI355X (gfx950) finite-element Hamiltonian filter for biased slabs.
+
+Thin ctypes binding of ``libfe.so`` (declared in ``include/fe.h``): argument
+marshalling only.  Every step of the hot path runs in the library's HIP
+kernels; PyTorch provides device memory and the current stream.  The library
+must have been built (``python -m paper_2504_00998_amd.build``); importing
+the binding without it raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfe.so")
+
+FE_OK, FE_EINVAL, FE_ENOMEM, FE_EDEVICE, FE_ESTATE, FE_ENOTSUP = range(6)
+DIRICHLET, PERIODIC, NEUMANN = 0, 1, 2
+RULE_EXACT, RULE_GLL = 0, 1
+F64, F32, BF16 = 0, 1, 2
+_PREC = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}
+
+
+class FEError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"fe status {status}: {msg}")
+        self.status = status
+
+
+class _Desc(C.Structure):
+    _fields_ = [("L", C.c_double * 3), ("ncell", C.c_int32 * 3), ("p", C.c_int32),
+                ("bc", C.c_int32 * 3), ("k_rule", C.c_int32)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libfe.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2504_00998_amd.build`")
+    # torch ships its own HIP runtime under the same sonames; loading it first
+    # makes libfe.so bind to that one copy, so streams and device pointers
+    # are shared with PyTorch.
+    import torch  # noqa: F401
+    L = C.CDLL(LIB_PATH)
+    vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+    sig = {
+        "fe_last_error": ([], C.c_char_p),
+        "fe_mesh_create": ([C.POINTER(_Desc), C.POINTER(vp)], C.c_int),
+        "fe_mesh_destroy": ([vp], C.c_int),
+        "fe_mesh_info": ([vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)], C.c_int),
+        "fe_mesh_quad_points": ([vp, vp], C.c_int),
+        "fe_mesh_dof_coords": ([vp, vp], C.c_int),
+        "fe_reference_cell": ([i32, i32, dbl, vp, vp, vp], C.c_int),
+        "fe_set_potential": ([vp, vp, dbl, dbl, vp], C.c_int),
+        "fe_set_nonlocal": ([vp, i32, vp, vp, dbl, dbl, vp], C.c_int),
+        "fe_hx_apply": ([vp, vp, vp, i64, i64, C.c_int, vp], C.c_int),
+        "fe_cheb_filter": ([vp, vp, vp, i64, i64, i32, dbl, dbl, dbl, C.c_int, vp, C.c_size_t, vp], C.c_int),
+        "fe_cheb_filter_vjp_work_bytes": ([vp, i64, i32, i32, i32], C.c_size_t),
+        "fe_cheb_filter_vjp": ([vp, vp, vp, i64, i64, i32, dbl, dbl, dbl, C.c_int, vp, vp, vp, i32, i32, vp,
+                                C.c_size_t, vp], C.c_int),
+        "fe_lanczos_bounds": ([vp, vp, i32, C.POINTER(dbl), C.POINTER(dbl), vp], C.c_int),
+        "fe_cholqr2": ([vp, vp, i64, i64, vp], C.c_int),
+        "fe_rayleigh_ritz": ([vp, vp, vp, vp, i64, i64, vp, vp], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != FE_OK:
+        raise FEError(status, lib().fe_last_error().decode())
+
+
+def reference_cell(p: int, rule: int = RULE_EXACT, h: float = 1.0):
+    """(xi, w, A = 1/2 Kc) from the library's host reference element."""
+    nc = (p + 1) ** 3
+    xi = np.zeros(p + 1); w = np.zeros(p + 1); A = np.zeros(nc * nc)
+    _check(lib().fe_reference_cell(p, rule, h, xi.ctypes.data, w.ctypes.data, A.ctypes.data))
+    return xi, w, A.reshape(nc, nc)
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else int(t.data_ptr())
+
+
+def _check_block(t, n: int, name: str):
+    import torch
+    if t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float64 device tensor")
+    if t.dim() != 2 or t.shape[0] != n or t.stride(1) != 1:
+        raise ValueError(f"{name} must be (n={n}, N) with unit column stride")
+
+
+class Mesh:
+    """A structured slab mesh on the current device (fe_mesh_create)."""
+
+    def __init__(self, L: Sequence[float], ncell: Sequence[int], p: int, bc: Sequence[int], rule: int = RULE_EXACT):
+        d = _Desc((C.c_double * 3)(*[float(x) for x in L]), (C.c_int32 * 3)(*[int(x) for x in ncell]), int(p),
+                  (C.c_int32 * 3)(*[int(x) for x in bc]), int(rule))
+        h = C.c_void_p()
+        _check(lib().fe_mesh_create(C.byref(d), C.byref(h)))
+        self._h = h
+        self.L, self.ncell, self.p, self.bc, self.rule = tuple(L), tuple(ncell), int(p), tuple(bc), int(rule)
+        n, nce, nc = C.c_int64(), C.c_int64(), C.c_int32()
+        _check(lib().fe_mesh_info(h, C.byref(n), C.byref(nce), C.byref(nc)))
+        self.n, self.n_cells, self.nc = n.value, nce.value, nc.value
+
+    @classmethod
+    def from_workload(cls, wl, rule: Optional[int] = None) -> "Mesh":
+        return cls(wl.L, wl.ncell, wl.p, wl.bc, wl.rule if rule is None else rule)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fe_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------- geometry
+    def quad_points(self) -> np.ndarray:
+        out = np.zeros(self.n_cells * self.nc * 3)
+        _check(lib().fe_mesh_quad_points(self._h, out.ctypes.data))
+        return out.reshape(self.n_cells, self.nc, 3)
+
+    def dof_coords(self) -> np.ndarray:
+        out = np.zeros(self.n * 3)
+        _check(lib().fe_mesh_dof_coords(self._h, out.ctypes.data))
+        return out.reshape(self.n, 3)
+
+    # ------------------------------------------------------------ operators
+    def set_potential(self, Vq, E: float, z0: float, stream=None):
+        """Vq: float64 device tensor [n_cells, n_c] (or None for V_loc = 0)."""
+        if Vq is not None:
+            import torch
+            if Vq.dtype != torch.float64 or not Vq.is_cuda or not Vq.is_contiguous() or Vq.numel() != self.n_cells * self.nc:
+                raise ValueError("Vq must be a contiguous float64 device tensor of n_cells*n_c values")
+        _check(lib().fe_set_potential(self._h, _ptr(Vq), float(E), float(z0), _stream(stream)))
+
+    def set_nonlocal(self, centres: np.ndarray, D: np.ndarray, r_cut: float, r_g: float, stream=None):
+        centres = np.ascontiguousarray(centres, dtype=np.float64)
+        D = np.ascontiguousarray(D, dtype=np.float64)
+        ns = centres.shape[0] if centres.size else 0
+        if ns and D.shape != (ns, 9):
+            raise ValueError("D must be (n_site, 9)")
+        _check(lib().fe_set_nonlocal(self._h, ns, centres.ctypes.data if ns else None, D.ctypes.data if ns else None,
+                                     float(r_cut), float(r_g), _stream(stream)))
+
+    def hx(self, X, Y=None, prec="f64", stream=None):
+        import torch
+        _check_block(X, self.n, "X")
+        N, ld = X.shape[1], X.stride(0)
+        if Y is None:
+            Y = torch.empty_strided(X.shape, X.stride(), dtype=torch.float64, device=X.device)
+        _check_block(Y, self.n, "Y")
+        if Y.stride(0) != ld:
+            raise ValueError("X and Y must share the leading dimension")
+        _check(lib().fe_hx_apply(self._h, _ptr(X), _ptr(Y), N, ld, _PREC[prec], _stream(stream)))
+        return Y
+
+    def cheb_filter(self, X, m: int, a: float, b: float, a0: float = math.nan, prec="f64", Y=None, work=None,
+                    stream=None):
+        import torch
+        _check_block(X, self.n, "X")
+        N, ld = X.shape[1], X.stride(0)
+        if Y is None:
+            Y = torch.empty_strided(X.shape, X.stride(), dtype=torch.float64, device=X.device)
+        if work is None:
+            work = torch.empty(self.n * N, dtype=torch.float64, device=X.device)
+        _check(lib().fe_cheb_filter(self._h, _ptr(X), _ptr(Y), N, ld, int(m), float(a), float(b), float(a0),
+                                    _PREC[prec], _ptr(work), work.numel() * 8, _stream(stream)))
+        return Y
+
+    def vjp_work_bytes(self, N: int, m: int, ckpt_stride: int = 1, col_chunk: int = 0) -> int:
+        return int(lib().fe_cheb_filter_vjp_work_bytes(self._h, N, m, ckpt_stride, col_chunk))
+
+    def cheb_filter_vjp(self, X, G, m: int, a: float, b: float, a0: float = math.nan, prec="f64",
+                        ckpt_stride: int = 1, col_chunk: int = 0, work=None, stream=None):
+        """(Xbar, Vbar_quad [n_cells, n_c], Ebar scalar tensor)."""
+        import torch
+        _check_block(X, self.n, "X")
+        _check_block(G, self.n, "G")
+        N, ld = X.shape[1], X.stride(0)
+        Xb = torch.empty_strided(X.shape, X.stride(), dtype=torch.float64, device=X.device)
+        Vb = torch.empty((self.n_cells, self.nc), dtype=torch.float64, device=X.device)
+        Eb = torch.empty((), dtype=torch.float64, device=X.device)
+        nb = self.vjp_work_bytes(N, m, ckpt_stride, col_chunk)
+        if work is None:
+            work = torch.empty(max(1, (nb + 7) // 8), dtype=torch.float64, device=X.device)
+        _check(lib().fe_cheb_filter_vjp(self._h, _ptr(X), _ptr(G), N, ld, int(m), float(a), float(b), float(a0),
+                                        _PREC[prec], _ptr(Xb), _ptr(Vb), _ptr(Eb), int(ckpt_stride), int(col_chunk),
+                                        _ptr(work), work.numel() * 8, _stream(stream)))
+        return Xb, Vb, Eb
+
+    def lanczos_bounds(self, v0, k: int = 10, stream=None):
+        a0, b = C.c_double(), C.c_double()
+        _check(lib().fe_lanczos_bounds(self._h, _ptr(v0), int(k), C.byref(a0), C.byref(b), _stream(stream)))
+        return a0.value, b.value
+
+    def cholqr2(self, Y, stream=None):
+        _check_block(Y, self.n, "Y")
+        _check(lib().fe_cholqr2(self._h, _ptr(Y), Y.shape[1], Y.stride(0), _stream(stream)))
+        return Y
+
+    def rayleigh_ritz(self, Q, X=None, P=None, stream=None):
+        import torch
+        _check_block(Q, self.n, "Q")
+        N, ld = Q.shape[1], Q.stride(0)
+        if X is None:
+            X = torch.empty_strided(Q.shape, Q.stride(), dtype=torch.float64, device=Q.device)
+        if P is None:
+            P = torch.empty_strided(Q.shape, Q.stride(), dtype=torch.float64, device=Q.device)
+        theta = np.zeros(N)
+        _check(lib().fe_rayleigh_ritz(self._h, _ptr(Q), _ptr(X), _ptr(P), N, ld, theta.ctypes.data,
+                                      _stream(stream)))
+        return theta, X

@@ -1,0 +1,118 @@
+// Internal structures of the gfx950 FE Hamiltonian library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fe.h"
+
+namespace fe {
+
+constexpr int kMaxP = 7;
+constexpr int kVec = 16;  // vectors per MFMA column tile (one workgroup chunk)
+
+// Cell products are padded to a multiple of 32 rows/columns so that every
+// MFMA shape used (f64 16x16x4, f32 16x16x4, bf16 16x16x32) tiles them.
+inline int padded_nc(int p) {
+    int nc = (p + 1) * (p + 1) * (p + 1);
+    return (nc + 31) / 32 * 32;
+}
+
+// Per-axis description passed by value to kernels.
+struct AxisInfo {
+    int ncell;   // cells along the axis
+    int nfree;   // free node positions
+    int bc;      // fe_bc
+    int ncol;    // colours along the axis (1, 2 or 3)
+};
+
+struct NonlocalData {
+    int n_site = 0;
+    int64_t nnz = 0;          // entries of C~ (all projectors)
+    int64_t *d_colptr = nullptr;  // [9*n_site + 1]
+    int32_t *d_row = nullptr;     // [nnz]  free-DoF index
+    double *d_val = nullptr;      // [nnz]
+    double *d_D = nullptr;        // [9*n_site]
+    int max_support = 0;          // largest per-projector support
+};
+
+}  // namespace fe
+
+struct fe_mesh {
+    int device = 0;
+    double L[3];
+    double h;
+    int ncell[3];
+    int p, n1, nc, ncp;
+    int bc[3];
+    int rule;
+    int64_t nf[3];
+    int64_t n;      // free DoFs
+    int64_t ncells;
+    int ncol[3];
+
+    // host copies
+    std::vector<double> xi, w;          // GLL nodes/weights on [-1,1]
+    std::vector<double> cellA;          // 1/2 Kc, nc x nc, row-major
+    std::vector<double> axis_coord[3];  // coordinate of each free node position
+    std::vector<double> axis_mass[3];   // assembled 1-D lumped mass per free position
+
+    // device
+    double *d_axis = nullptr;     // [3][maxf] : D factors (M^-1/2 per axis)
+    double *d_zcoord = nullptr;   // [nf_z] z coordinate of free z positions
+    double *d_wq = nullptr;       // [3][maxf?] not used
+    int maxf = 0;
+    double *d_Af64 = nullptr;     // swizzled A fragments of 1/2 Kc (f64)
+    float *d_Af32 = nullptr;      // f32
+    uint16_t *d_Abf16 = nullptr;  // bf16 bits
+    double *d_v = nullptr;        // [n] diagonal potential term of H~
+    double *d_wrel = nullptr;     // [3][p+1]: (h/2) w_i per axis (for v and Vbar)
+    bool potential_set = false;
+    double E = 0.0, z0 = 0.0;
+
+    fe::NonlocalData nl;
+    // scratch for Lanczos / dense steps (grown on demand)
+    double *d_scratch = nullptr;
+    size_t scratch_bytes = 0;
+    void *blas = nullptr;  // rocblas_handle
+};
+
+namespace fe {
+
+// thread-local error message
+void set_error(const std::string &msg);
+fe_status fail(fe_status s, const std::string &msg);
+
+// reference element (host, FP64)
+void gll_rule(int p, std::vector<double> &x, std::vector<double> &w);
+void ref_matrices(int p, int rule, std::vector<double> &Khat, std::vector<double> &Mhat);
+void cell_matrix_half(int p, int rule, double h, std::vector<double> &A);
+
+// kernels (fe_kernels.hip)
+struct StepArgs {
+    const double *X;    // Y_k (gathered operand)
+    int64_t ldx;
+    double *Y;          // Y_{k+1}
+    int64_t ldy;
+    const double *Ym1;  // Y_{k-1} (may alias Y); null when beta == 0
+    int64_t ldm;
+    double alpha, beta, shift;
+    int64_t N;
+};
+
+hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipStream_t s);
+hipError_t launch_potential(const fe_mesh *m, const double *Vq, double E, double z0, hipStream_t s);
+hipError_t launch_potential_vjp(const fe_mesh *m, const double *g, double z0, double *Vbar, double *Ebar,
+                                hipStream_t s);
+hipError_t launch_rowdot_accum(const fe_mesh *m, const double *U, const double *V, int64_t ld, int64_t N,
+                               double scale, double *g, hipStream_t s);
+hipError_t launch_axpby(double *Y, int64_t ldy, const double *X, int64_t ldx, int64_t n, int64_t N, double a,
+                        double b, hipStream_t s);
+hipError_t launch_nonlocal(const fe_mesh *m, const double *X, int64_t ldx, double *Y, int64_t ldy, int64_t N,
+                           double scale, double *work, hipStream_t s);
+size_t nonlocal_work_doubles(const fe_mesh *m, int64_t N);
+
+}  // namespace fe

@@ -1,0 +1,31 @@
+// Entry points not implemented yet (return FE_ENOTSUP).
+#include "fe_internal.h"
+
+using namespace fe;
+
+namespace fe {
+hipError_t launch_nonlocal(const fe_mesh *, const double *, int64_t, double *, int64_t, int64_t, double, double *,
+                           hipStream_t) {
+    return hipErrorNotSupported;
+}
+size_t nonlocal_work_doubles(const fe_mesh *, int64_t) { return 0; }
+}  // namespace fe
+
+extern "C" {
+fe_status fe_set_nonlocal(fe_mesh *, int32_t, const double *, const double *, double, double, hipStream_t) {
+    return fail(FE_ENOTSUP, "nonlocal term not implemented");
+}
+size_t fe_cheb_filter_vjp_work_bytes(const fe_mesh *, int64_t, int32_t, int32_t, int32_t) { return 0; }
+fe_status fe_cheb_filter_vjp(fe_mesh *, const double *, const double *, int64_t, int64_t, int32_t, double, double,
+                             double, fe_dtype, double *, double *, double *, int32_t, int32_t, double *, size_t,
+                             hipStream_t) {
+    return fail(FE_ENOTSUP, "vjp not implemented");
+}
+fe_status fe_lanczos_bounds(fe_mesh *, const double *, int32_t, double *, double *, hipStream_t) {
+    return fail(FE_ENOTSUP, "lanczos not implemented");
+}
+fe_status fe_cholqr2(fe_mesh *, double *, int64_t, int64_t, hipStream_t) { return fail(FE_ENOTSUP, "cholqr2 not implemented"); }
+fe_status fe_rayleigh_ritz(fe_mesh *, const double *, double *, double *, int64_t, int64_t, double *, hipStream_t) {
+    return fail(FE_ENOTSUP, "rayleigh-ritz not implemented");
+}
+}

@@ -1,0 +1,149 @@
+"""GPU parity of the C-ABI hot path against the CPU oracle.
+
+Inputs are the seeded synthetic slabs of `paper_2504_00998_amd.workloads`,
+with the potential sampled at the oracle's own GLL points and handed to both
+sides.  The bar for FP64 is 1e-12 relative per vector for the filter (the
+target tolerance) and 1e-13 for a single H~ application.  Mixed precision is
+reported against the FP64 oracle with tolerances derived from the unit
+roundoff of the cell-product format.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2504_00998_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _fe():
+    import paper_2504_00998_amd as fe
+    return fe
+
+
+def _setup(wl, rule=None):
+    """Oracle operator and GPU mesh for a workload, same potential on both."""
+    fe = _fe()
+    om = O.Mesh.from_workload(wl, rule)
+    periodic = [b == W.PERIODIC for b in wl.bc]
+    Vq = W.wells_potential(om.quad_points(), wl.centres(), wl.depth, wl.sigma, wl.L, periodic)
+    op = O.Operator(om, Vq, wl.E, wl.z0)
+    gm = fe.Mesh.from_workload(wl, rule)
+    assert gm.n == om.n
+    gm.set_potential(torch.from_numpy(Vq).cuda(), wl.E, wl.z0)
+    return op, gm, Vq
+
+
+def _relerr(Y, R):
+    return (np.linalg.norm(Y - R, axis=0) / np.maximum(np.linalg.norm(R, axis=0), 1e-300)).max()
+
+
+def _print_case(**kw):
+    print("case:", kw, flush=True)
+
+
+CASES = [
+    # (label, workload) -- several tiles of every axis, ragged vector chunks
+    ("cfg1", W.CFG1),
+    ("slab-p4-3x3x4-N20", W.small_slab((3, 3, 4), p=4, N=20)),
+    ("slab-p4-odd-periodic-N7", W.small_slab((3, 5, 3), p=4, N=7)),
+    ("slab-p1-N33", W.small_slab((4, 4, 5), p=1, N=33)),
+    ("slab-p2", W.small_slab((2, 3, 4), p=2, N=16)),
+    ("slab-p3-gll", W.small_slab((3, 2, 3), p=3, N=17, rule=W.RULE_GLL)),
+    ("slab-p5", W.small_slab((2, 2, 3), p=5, N=18)),
+    ("slab-p6", W.small_slab((2, 2, 2), p=6, N=16)),
+    ("slab-p7", W.small_slab((2, 2, 2), p=7, N=5)),
+    ("neumann-box-p3", W.small_slab((2, 3, 2), p=3, N=9, bc=(W.NEUMANN, W.NEUMANN, W.NEUMANN))),
+    ("mixed-bc-p4", W.small_slab((3, 2, 2), p=4, N=16, bc=(W.DIRICHLET, W.PERIODIC, W.NEUMANN))),
+]
+
+
+@pytest.mark.parametrize("label,wl", CASES, ids=[c[0] for c in CASES])
+def test_hx_f64_matches_oracle(label, wl):
+    _print_case(test="hx_f64", label=label, ncell=wl.ncell, p=wl.p, N=wl.N)
+    op, gm, _ = _setup(wl)
+    X = wl.X(op.n)
+    Y = gm.hx(torch.from_numpy(X).cuda()).cpu().numpy()
+    R = op.apply(X)
+    assert _relerr(Y, R) < 1e-13
+
+
+@pytest.mark.parametrize("label,wl", CASES[:6], ids=[c[0] for c in CASES[:6]])
+@pytest.mark.parametrize("scaled", [True, False])
+def test_filter_f64_matches_oracle(label, wl, scaled):
+    _print_case(test="filter_f64", label=label, scaled=scaled)
+    op, gm, _ = _setup(wl)
+    X = wl.X(op.n)
+    a0, b, _ = O.lanczos_bounds(op.apply, wl.lanczos_start(op.n), 10)
+    a = O.weyl_cut(a0, b, wl.N, op.n)
+    a0s = a0 if scaled else math.nan
+    m = wl.m if scaled else min(wl.m, 9)
+    R = op.filter(X, m, a, b, a0s)
+    Y = gm.cheb_filter(torch.from_numpy(X).cuda(), m, a, b, a0s).cpu().numpy()
+    assert _relerr(Y, R) < 1e-12
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 6])
+def test_filter_degrees_and_leading_dimension(m):
+    wl = W.small_slab((3, 3, 4), p=4, N=20)
+    _print_case(test="filter_ld", m=m)
+    op, gm, _ = _setup(wl)
+    X = wl.X(op.n)
+    a0, b, _ = O.lanczos_bounds(op.apply, wl.lanczos_start(op.n), 10)
+    a = O.weyl_cut(a0, b, wl.N, op.n)
+    R = op.filter(X, m, a, b, a0)
+    # X inside a wider buffer (ld = N + 5)
+    Xb = torch.zeros((op.n, wl.N + 5), dtype=torch.float64, device="cuda")
+    Xb[:, :wl.N] = torch.from_numpy(X).cuda()
+    Yb = torch.full_like(Xb, float("nan"))
+    gm.cheb_filter(Xb[:, :wl.N], m, a, b, a0, Y=Yb[:, :wl.N])
+    Y = Yb[:, :wl.N].cpu().numpy()
+    assert _relerr(Y, R) < 1e-12
+    assert torch.isnan(Yb[:, wl.N:]).all()  # padding untouched
+
+
+def test_bitwise_reproducible():
+    wl = W.small_slab((3, 3, 4), p=4, N=32)
+    op, gm, _ = _setup(wl)
+    X = torch.from_numpy(wl.X(op.n)).cuda()
+    Y1 = gm.cheb_filter(X, 12, 2.0, 60.0, -0.5)
+    Y2 = gm.cheb_filter(X, 12, 2.0, 60.0, -0.5)
+    assert torch.equal(Y1, Y2)
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 2e-5), ("bf16", 5e-2)])
+def test_hx_mixed_precision_error(prec, tol):
+    """Cell products in FP32 / BF16 with FP32 accumulation: the error of H~X
+    against the FP64 oracle is bounded by a small multiple of the format's
+    unit roundoff times ||D A D|| ||X|| / ||H~X|| (reported, loose bar)."""
+    wl = W.small_slab((3, 3, 4), p=4, N=16)
+    op, gm, _ = _setup(wl)
+    X = wl.X(op.n)
+    Y = gm.hx(torch.from_numpy(X).cuda(), prec=prec).cpu().numpy()
+    R = op.apply(X)
+    err = _relerr(Y, R)
+    print(f"hx {prec} rel err {err:.3e}")
+    assert err < tol
+
+
+def test_potential_update_and_state_errors():
+    fe = _fe()
+    wl = W.small_slab((2, 2, 3), p=3, N=4)
+    gm = fe.Mesh.from_workload(wl)
+    X = torch.zeros((gm.n, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(fe.FEError) as e:
+        gm.hx(X)
+    assert e.value.status == fe.FE_ESTATE
+    gm.set_potential(None, wl.E, wl.z0)
+    om = O.Mesh.from_workload(wl)
+    op = O.Operator(om, None, wl.E, wl.z0)
+    Xn = wl.X(gm.n)[:, :4]
+    Y = gm.hx(torch.from_numpy(np.ascontiguousarray(Xn)).cuda()).cpu().numpy()
+    assert _relerr(Y, op.apply(np.ascontiguousarray(Xn))) < 1e-13
+    with pytest.raises(fe.FEError) as e:
+        gm.cheb_filter(X, 3, 1.0, 0.5)
+    assert e.value.status == fe.FE_EINVAL
