@@ -1,0 +1,180 @@
+"""Benchmark of the Chebyshev-filtered FE Hamiltonian hot path on one MI355X.
+
+Workload (default): the 24x24x48-bohr slab, 24x24x48 cubic cells of GLL
+degree 4 (1,760,256 free DoFs, periodic x/y, Dirichlet z), Gaussian-well
+potential on a 6-layer 4x4 lattice plus the field -E z (E = 0.005), N = 256
+random vectors, filter degree m = 30, FP64 cell products.  One step is one
+pass of the path over the block: the potential update (fe_set_potential)
+and the degree-m filter (fe_cheb_filter), with spectrum bounds from a
+10-step Lanczos run on the device beforehand.
+
+Metric: GDoF.vec/s = m * n * N / t_step / 1e9.
+
+Prints one JSON line.  Also reports the roofline of the dominant kernel (the
+fused step kernel, timed live with HIP events on the stream it runs on) and
+the CPU oracle timed on this host on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "H·X GDoF·vec/s in Chebyshev filter, FP64 vs FP32/BF16 at ≤1e-7 Ha Ritz err"
+UNIT = "GDoF·vec/s"
+PEAK = {"f64": (78.6, "mfma"), "f32": (157.3, "mfma"), "bf16": (2500.0, "mfma")}  # TFLOP/s, dense MFMA
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, a, b, a0, ncols: int = 4):
+    """The oracle (CSR SpMM recurrence) on `ncols` columns of the same workload."""
+    import numpy as np
+    import oracle as O
+    from paper_2504_00998_amd import workloads as W
+
+    t0 = time.time()
+    om = O.Mesh.from_workload(wl)
+    Vq = W.workload_potential(wl, om.quad_points())
+    op = O.Operator(om, Vq, wl.E, wl.z0)
+    X = wl.X(om.n, cols=range(ncols))
+    log(f"[cpu_baseline] assembled H~ (nnz {op.A.nnz}) in {time.time() - t0:.1f} s")
+    t = time.perf_counter()
+    op.filter(X, wl.m, a, b, a0)
+    dt = time.perf_counter() - t
+    return {
+        "value": wl.m * om.n * ncols / dt / 1e9,
+        "unit": UNIT,
+        "cores": O.num_threads(),
+        "kind": "oracle",
+        "sample": f"degree-{wl.m} filter on {ncols} of {wl.N} columns of the full mesh "
+                  f"(CSR SpMM, nnz {op.A.nnz}); assembly excluded; {dt:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--cfg", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-cols", type=int, default=4)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU split is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2504_00998_amd as fe
+    from paper_2504_00998_amd import workloads as W
+
+    wl = W.CONFIGS[args.cfg]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    gm = fe.Mesh.from_workload(wl)
+    n, N, m = gm.n, wl.N, wl.m
+    Vq = torch.from_numpy(W.workload_potential(wl, gm.quad_points())).to(dev)
+    gm.set_potential(Vq, wl.E, wl.z0)
+    X = torch.from_numpy(wl.X(n)).to(dev)
+    Y = torch.empty_like(X)
+    work = torch.empty(n * N, dtype=torch.float64, device=dev)
+    v0 = torch.from_numpy(wl.lanczos_start(n)).to(dev)
+    a0, b = gm.lanczos_bounds(v0, 10)
+    a = a0 + (b - a0) * (N / n) ** (2.0 / 3.0)
+    log(f"[bench] {wl.name}: n={n} N={N} m={m} prec={args.prec} bounds a0={a0:.4f} a={a:.4f} b={b:.4f} "
+        f"(setup {time.time() - t0:.1f} s)")
+
+    stream = torch.cuda.current_stream()
+
+    def one_step():
+        gm.set_potential(Vq, wl.E, wl.z0)
+        gm.cheb_filter(X, m, a, b, a0, prec=args.prec, Y=Y, work=work)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    # potential update alone (to separate it from the step-kernel time)
+    pe0, pe1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    pe0.record(stream)
+    for _ in range(10):
+        gm.set_potential(Vq, wl.E, wl.z0)
+    pe1.record(stream)
+    torch.cuda.synchronize()
+    t_pot = pe0.elapsed_time(pe1) / 10.0
+
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        one_step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    value = m * n * N / (ms * 1e-3) / 1e9
+    if not torch.isfinite(Y).all():
+        raise RuntimeError("non-finite filter output")
+
+    # dominant kernel: one colour pass of the fused step kernel (8 colours per step)
+    ncol = 1
+    for a_ in range(3):
+        nce, bc = wl.ncell[a_], wl.bc[a_]
+        ncol *= 3 if (bc == W.PERIODIC and nce % 2) else (2 if nce >= 2 else 1)
+    launches = ncol * m
+    nc = (wl.p + 1) ** 3
+    cells = wl.n_cells
+    flops_per_launch = 2.0 * nc * nc * (cells / ncol) * N
+    launch_ms = (ms - t_pot) / launches
+    achieved = flops_per_launch / (launch_ms * 1e-3) / 1e12
+    peak, bound = PEAK[args.prec]
+    rec = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name} (box {wl.L[0]:g}x{wl.L[1]:g}x{wl.L[2]:g} bohr, cells "
+                               f"{wl.ncell[0]}x{wl.ncell[1]}x{wl.ncell[2]}, GLL p={wl.p}, n={n} free DoFs, "
+                               f"N={N}, filter degree m={m}, cell products {args.prec})",
+                   "n_dof": n, "N": N, "m": m, "p": wl.p, "cells": list(wl.ncell), "prec": args.prec},
+        "roofline": {
+            "bound": bound,
+            "achieved": round(achieved, 3),
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4),
+            "traffic": None,
+            "kernel": f"step_kernel<{wl.p},{ {'f64': 0, 'f32': 1, 'bf16': 2}[args.prec]}> (one colour pass)",
+            "flops_per_launch": flops_per_launch,
+            "avg_launch_ms": round(launch_ms, 5),
+            "launches_per_step": launches,
+        },
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(wl, a, b, a0, args.cpu_cols)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,229 @@
+// Dense steps of Chebyshev-filtered subspace iteration on the device, FP64:
+// spectrum bounds by Lanczos (Zhou & Li 2011 upper bound), Cholesky-QR in two
+// passes, and Rayleigh-Ritz.  Tall-skinny products go through rocBLAS, the
+// N x N factorisations through rocSOLVER; the Hamiltonian applications are
+// the library's own kernels.
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "fe_internal.h"
+
+namespace fe {
+
+static fe_status blas_fail(rocblas_status s, const char *what) {
+    return fail(FE_EDEVICE, std::string(what) + ": " + rocblas_status_to_string(s));
+}
+
+#define FE_BLAS(call, what)                                   \
+    do {                                                      \
+        rocblas_status _s = (call);                           \
+        if (_s != rocblas_status_success) return blas_fail(_s, what); \
+    } while (0)
+
+#define FE_HIPD(call, what)                                                                        \
+    do {                                                                                           \
+        hipError_t _e = (call);                                                                    \
+        if (_e != hipSuccess) return fail(FE_EDEVICE, std::string(what) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+static fe_status handle(fe_mesh *m, hipStream_t s, rocblas_handle &h) {
+    if (!m->blas) {
+        rocblas_handle hh;
+        FE_BLAS(rocblas_create_handle(&hh), "rocblas_create_handle");
+        m->blas = hh;
+    }
+    h = static_cast<rocblas_handle>(m->blas);
+    FE_BLAS(rocblas_set_stream(h, s), "rocblas_set_stream");
+    FE_BLAS(rocblas_set_pointer_mode(h, rocblas_pointer_mode_host), "rocblas_set_pointer_mode");
+    return FE_OK;
+}
+
+// Eigenvalues of a small symmetric matrix (row-major, n x n) by cyclic Jacobi.
+static void jacobi_eigvals(std::vector<double> A, int n, std::vector<double> &ev) {
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j) off += A[i * n + j] * A[i * n + j];
+        if (off < 1e-300) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                double apq = A[p * n + q];
+                if (apq == 0.0) continue;
+                double th = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+                double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+                double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < n; ++k) {
+                    double akp = A[k * n + p], akq = A[k * n + q];
+                    A[k * n + p] = c * akp - s * akq;
+                    A[k * n + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    double apk = A[p * n + k], aqk = A[q * n + k];
+                    A[p * n + k] = c * apk - s * aqk;
+                    A[q * n + k] = s * apk + c * aqk;
+                }
+            }
+    }
+    ev.resize(n);
+    for (int i = 0; i < n; ++i) ev[i] = A[i * n + i];
+    std::sort(ev.begin(), ev.end());
+}
+
+fe_status ensure_scratch_dense(fe_mesh *m, size_t bytes) {
+    if (m->scratch_bytes >= bytes) return FE_OK;
+    if (m->d_scratch) {
+        FE_HIPD(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        FE_HIPD(hipFree(m->d_scratch), "hipFree");
+        m->d_scratch = nullptr;
+        m->scratch_bytes = 0;
+    }
+    if (hipMalloc(&m->d_scratch, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FE_ENOMEM, "scratch allocation failed");
+    }
+    m->scratch_bytes = bytes;
+    return FE_OK;
+}
+
+}  // namespace fe
+
+using namespace fe;
+
+extern "C" {
+
+fe_status fe_lanczos_bounds(fe_mesh *m, const double *v0, int32_t k, double *a0, double *b, hipStream_t s) {
+    if (!m || !v0 || !a0 || !b) return fail(FE_EINVAL, "NULL argument");
+    if (k < 1 || k > 64) return fail(FE_EINVAL, "k must be in 1..64");
+    if (!m->potential_set) return fail(FE_ESTATE, "fe_set_potential has not been called");
+    int64_t n = m->n;
+    // scratch: V [n x (k+1)] column-major, w [n], h [k+1]
+    size_t need = ((size_t)n * (k + 2) + (k + 1) + 1024) * sizeof(double);
+    fe_status st = ensure_scratch_dense(m, need);
+    if (st != FE_OK) return st;
+    double *V = m->d_scratch + 1024, *w = V + (size_t)n * (k + 1), *hv = w + n;
+    rocblas_handle h;
+    if ((st = handle(m, s, h)) != FE_OK) return st;
+    int ni = (int)n;
+    double nrm;
+    FE_BLAS(rocblas_dnrm2(h, ni, v0, 1, &nrm), "dnrm2");
+    if (!(nrm > 0.0)) return fail(FE_EINVAL, "start vector is zero");
+    FE_HIPD(hipMemcpyAsync(V, v0, n * sizeof(double), hipMemcpyDeviceToDevice, s), "copy v0");
+    double inv = 1.0 / nrm;
+    FE_BLAS(rocblas_dscal(h, ni, &inv, V, 1), "dscal");
+    std::vector<double> alpha(k), beta(k);
+    int kk = k;
+    for (int j = 0; j < k; ++j) {
+        double *vj = V + (size_t)j * n;
+        StepArgs a{vj, 1, w, 1, nullptr, 0, 1.0, 0.0, 0.0, 1};
+        FE_HIPD(launch_step(m, a, FE_F64, s), "step kernel launch");
+        if (m->nl.n_site > 0) {
+            if ((st = ensure_scratch_dense(m, std::max(need, (size_t)(1024 + nonlocal_work_doubles(m, 1)) * 8))) != FE_OK)
+                return st;
+            V = m->d_scratch + 1024; w = V + (size_t)n * (k + 1); hv = w + n; vj = V + (size_t)j * n;
+            FE_HIPD(launch_nonlocal(m, vj, 1, w, 1, 1, 1.0, m->d_scratch + need / 8, s), "nonlocal");
+        }
+        FE_BLAS(rocblas_ddot(h, ni, vj, 1, w, 1, &alpha[j]), "ddot");
+        // full reorthogonalisation, twice: w -= V (V^T w)
+        for (int pass = 0; pass < 2; ++pass) {
+            double one = 1.0, zero = 0.0, mone = -1.0;
+            FE_BLAS(rocblas_dgemv(h, rocblas_operation_transpose, ni, j + 1, &one, V, ni, w, 1, &zero, hv, 1), "dgemv T");
+            FE_BLAS(rocblas_dgemv(h, rocblas_operation_none, ni, j + 1, &mone, V, ni, hv, 1, &one, w, 1), "dgemv N");
+        }
+        FE_BLAS(rocblas_dnrm2(h, ni, w, 1, &beta[j]), "dnrm2");
+        if (beta[j] == 0.0) { kk = j + 1; break; }
+        if (j + 1 < k) {
+            double ib = 1.0 / beta[j];
+            FE_HIPD(hipMemcpyAsync(V + (size_t)(j + 1) * n, w, n * sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
+            FE_BLAS(rocblas_dscal(h, ni, &ib, V + (size_t)(j + 1) * n, 1), "dscal");
+        }
+    }
+    std::vector<double> T((size_t)kk * kk, 0.0), ev;
+    for (int i = 0; i < kk; ++i) {
+        T[i * kk + i] = alpha[i];
+        if (i + 1 < kk) T[i * kk + i + 1] = T[(i + 1) * kk + i] = beta[i];
+    }
+    jacobi_eigvals(T, kk, ev);
+    *a0 = ev.front();
+    *b = ev.back() + std::fabs(beta[kk - 1]);
+    return FE_OK;
+}
+
+fe_status fe_cholqr2(fe_mesh *m, double *Y, int64_t N, int64_t ld, hipStream_t s) {
+    if (!m || !Y) return fail(FE_EINVAL, "NULL argument");
+    if (N < 1 || ld < N) return fail(FE_EINVAL, "need N >= 1 and ld >= N");
+    if (N > m->n) return fail(FE_EINVAL, "N exceeds the number of DoFs");
+    int64_t n = m->n;
+    size_t need = (1024 + (size_t)N * N + 64) * sizeof(double);
+    fe_status st = ensure_scratch_dense(m, need);
+    if (st != FE_OK) return st;
+    double *S = m->d_scratch + 1024;
+    rocblas_int *info = reinterpret_cast<rocblas_int *>(S + (size_t)N * N);
+    rocblas_handle h;
+    if ((st = handle(m, s, h)) != FE_OK) return st;
+    int Ni = (int)N, ni = (int)n, ldi = (int)ld;
+    for (int pass = 0; pass < 2; ++pass) {
+        // Y is row-major (n x N) = column-major (N x n) with leading dim ld: S = Y^T Y = Ycm Ycm^T
+        double one = 1.0, zero = 0.0;
+        FE_BLAS(rocblas_dsyrk(h, rocblas_fill_upper, rocblas_operation_none, Ni, ni, &one, Y, ldi, &zero, S, Ni),
+                "dsyrk");
+        FE_BLAS(rocsolver_dpotrf(h, rocblas_fill_upper, Ni, S, Ni, info), "dpotrf");
+        rocblas_int hinfo = 0;
+        FE_HIPD(hipMemcpyAsync(&hinfo, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, s), "copy info");
+        FE_HIPD(hipStreamSynchronize(s), "sync");
+        if (hinfo != 0) return fail(FE_EDEVICE, "Gram matrix not positive definite (potrf info " + std::to_string(hinfo) + ")");
+        // S = U^T U;  Q = Y U^-1  <=>  Qcm = U^-T Ycm
+        FE_BLAS(rocblas_dtrsm(h, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
+                              rocblas_diagonal_non_unit, Ni, ni, &one, S, Ni, Y, ldi),
+                "dtrsm");
+    }
+    return FE_OK;
+}
+
+fe_status fe_rayleigh_ritz(fe_mesh *m, const double *Q, double *X, double *P, int64_t N, int64_t ld, double *theta,
+                           hipStream_t s) {
+    if (!m || !Q || !X || !P || !theta) return fail(FE_EINVAL, "NULL argument");
+    if (N < 1 || ld < N) return fail(FE_EINVAL, "need N >= 1 and ld >= N");
+    if (!m->potential_set) return fail(FE_ESTATE, "fe_set_potential has not been called");
+    int64_t n = m->n;
+    // P = H~ Q (FP64 cell products)
+    StepArgs a{Q, ld, P, ld, nullptr, 0, 1.0, 0.0, 0.0, N};
+    FE_HIPD(launch_step(m, a, FE_F64, s), "step kernel launch");
+    size_t need = (1024 + 2 * (size_t)N * N + 2 * (size_t)N + 64) * sizeof(double);
+    if (m->nl.n_site > 0) need += nonlocal_work_doubles(m, N) * sizeof(double);
+    fe_status st = ensure_scratch_dense(m, need);
+    if (st != FE_OK) return st;
+    double *Hs = m->d_scratch + 1024, *Ht = Hs + (size_t)N * N, *d = Ht + (size_t)N * N, *e = d + N;
+    rocblas_int *info = reinterpret_cast<rocblas_int *>(e + N);
+    if (m->nl.n_site > 0)
+        FE_HIPD(launch_nonlocal(m, Q, ld, P, ld, N, 1.0, reinterpret_cast<double *>(info + 64), s), "nonlocal");
+    rocblas_handle h;
+    if ((st = handle(m, s, h)) != FE_OK) return st;
+    int Ni = (int)N, ni = (int)n, ldi = (int)ld;
+    double one = 1.0, zero = 0.0, half = 0.5;
+    // Hs = Q^T P  (column-major: Qcm Pcm^T), then symmetrise Hs = (Hs + Hs^T)/2
+    FE_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, Ni, Ni, ni, &one, Q, ldi, P, ldi,
+                          &zero, Hs, Ni),
+            "dgemm QtP");
+    FE_BLAS(rocblas_dgeam(h, rocblas_operation_none, rocblas_operation_transpose, Ni, Ni, &half, Hs, Ni, &half, Hs, Ni,
+                          Ht, Ni),
+            "dgeam");
+    FE_BLAS(rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, Ni, Ht, Ni, d, e, info), "dsyevd");
+    rocblas_int hinfo = 0;
+    FE_HIPD(hipMemcpyAsync(&hinfo, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, s), "copy info");
+    FE_HIPD(hipMemcpyAsync(theta, d, N * sizeof(double), hipMemcpyDeviceToHost, s), "copy theta");
+    FE_HIPD(hipStreamSynchronize(s), "sync");
+    if (hinfo != 0) return fail(FE_EDEVICE, "syevd failed (info " + std::to_string(hinfo) + ")");
+    // X = Q W  (column-major: Xcm = W^T Qcm)
+    FE_BLAS(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, Ni, ni, Ni, &one, Ht, Ni, Q, ldi,
+                          &zero, X, ldi),
+            "dgemm QW");
+    return FE_OK;
+}
+
+}  // extern "C"

@@ -21,11 +21,4 @@ fe_status fe_cheb_filter_vjp(fe_mesh *, const double *, const double *, int64_t,
                              hipStream_t) {
     return fail(FE_ENOTSUP, "vjp not implemented");
 }
-fe_status fe_lanczos_bounds(fe_mesh *, const double *, int32_t, double *, double *, hipStream_t) {
-    return fail(FE_ENOTSUP, "lanczos not implemented");
-}
-fe_status fe_cholqr2(fe_mesh *, double *, int64_t, int64_t, hipStream_t) { return fail(FE_ENOTSUP, "cholqr2 not implemented"); }
-fe_status fe_rayleigh_ritz(fe_mesh *, const double *, double *, double *, int64_t, int64_t, double *, hipStream_t) {
-    return fail(FE_ENOTSUP, "rayleigh-ritz not implemented");
-}
 }

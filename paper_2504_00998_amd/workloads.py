@@ -140,6 +140,49 @@ def wells_potential(points: np.ndarray, centres: np.ndarray, depth: float, sigma
     return out.reshape(pts.shape[:-1])
 
 
+def axis_points(quad_points: np.ndarray, ncell) -> list:
+    """Per-axis coordinates (ncell_a, p+1) of a tensor-product set of cell
+    GLL points given as (n_cells, (p+1)^3, 3), cells x fastest."""
+    n1 = round(quad_points.shape[1] ** (1.0 / 3.0))
+    nx, ny, _ = ncell
+    q = quad_points.reshape(ncell[2], ny, nx, n1, n1, n1, 3)  # [cz, cy, cx, k, j, i, a]
+    return [q[0, 0, :, 0, 0, :, 0], q[0, :, 0, 0, :, 0, 1], q[:, 0, 0, :, 0, 0, 2]]
+
+
+def wells_potential_cells(axis_pts, centres: np.ndarray, depth: float, sigma: float, L, periodic) -> np.ndarray:
+    """The Gaussian-well sum of `wells_potential` on a tensor-product set of
+    cell points, using exp(-|d|^2/2s^2) = prod_a exp(-d_a^2/2s^2).
+
+    axis_pts: three arrays (ncell_a, p+1) of coordinates.  Returns
+    (n_cells, (p+1)^3) with cells x fastest and local index i + n1 (j + n1 k).
+    """
+    inv = 1.0 / (2.0 * sigma * sigma)
+    G = []
+    for a in range(3):
+        x = np.asarray(axis_pts[a], dtype=np.float64).reshape(-1)          # (ncell_a * n1)
+        d = x[None, :] - np.asarray(centres, dtype=np.float64)[:, a][:, None]  # (n_site, .)
+        if periodic[a]:
+            d -= L[a] * np.round(d / L[a])
+        G.append(np.exp(-(d * d) * inv))
+    gx, gy, gz = G
+    ns = gx.shape[0]
+    pxy = (gx[:, None, :] * gy[:, :, None]).reshape(ns, -1)    # (s, [cy j][cx i])
+    V = depth * (gz.T @ pxy)                                   # ([cz k], [cy j][cx i])
+    ncz, n1 = np.asarray(axis_pts[2]).shape
+    ncy = np.asarray(axis_pts[1]).shape[0]
+    ncx = np.asarray(axis_pts[0]).shape[0]
+    V = V.reshape(ncz, n1, ncy, n1, ncx, n1)                   # cz k cy j cx i
+    V = V.transpose(0, 2, 4, 1, 3, 5)                          # cz cy cx k j i
+    return np.ascontiguousarray(V.reshape(ncz * ncy * ncx, n1 ** 3))
+
+
+def workload_potential(wl: "Workload", quad_points: np.ndarray) -> np.ndarray:
+    """V_loc of the workload at the given cell GLL points, (n_cells, (p+1)^3)."""
+    periodic = [b == PERIODIC for b in wl.bc]
+    return wells_potential_cells(axis_points(quad_points, wl.ncell), wl.centres(), wl.depth, wl.sigma,
+                                 wl.L, periodic)
+
+
 def _lat(lo, n, s=3.0):
     return tuple(lo + s * i for i in range(n))
 

@@ -29,8 +29,7 @@ def _setup(wl, rule=None):
     """Oracle operator and GPU mesh for a workload, same potential on both."""
     fe = _fe()
     om = O.Mesh.from_workload(wl, rule)
-    periodic = [b == W.PERIODIC for b in wl.bc]
-    Vq = W.wells_potential(om.quad_points(), wl.centres(), wl.depth, wl.sigma, wl.L, periodic)
+    Vq = W.workload_potential(wl, om.quad_points())
     op = O.Operator(om, Vq, wl.E, wl.z0)
     gm = fe.Mesh.from_workload(wl, rule)
     assert gm.n == om.n
@@ -147,3 +146,26 @@ def test_potential_update_and_state_errors():
     with pytest.raises(fe.FEError) as e:
         gm.cheb_filter(X, 3, 1.0, 0.5)
     assert e.value.status == fe.FE_EINVAL
+
+
+def test_lanczos_cholqr_rayleigh_ritz_on_device():
+    """Device Lanczos bound b >= lambda_max (dense eigh), CholQR2
+    orthonormality and Rayleigh-Ritz values against the oracle's."""
+    wl = W.CFG1
+    op, gm, _ = _setup(wl)
+    H = op.A.to_scipy().toarray()
+    lam = np.linalg.eigvalsh(H)
+    v0 = wl.lanczos_start(op.n)
+    a0g, bg = gm.lanczos_bounds(torch.from_numpy(v0).cuda(), 10)
+    a0o, bo, _ = O.lanczos_bounds(op.apply, v0, 10)
+    assert bg >= lam[-1] and abs(bg - bo) < 1e-10 * abs(bo) and abs(a0g - a0o) < 1e-10 * abs(bo)
+    Y = torch.from_numpy(wl.X(op.n)).cuda()
+    Q = gm.cholqr2(Y.clone())
+    Qh = Q.cpu().numpy()
+    assert np.abs(Qh.T @ Qh - np.eye(wl.N)).max() < 1e-13
+    Qo, _ = O.cholqr2(wl.X(op.n))
+    # same span: projectors agree
+    assert np.abs(Qh @ Qh.T - Qo @ Qo.T).max() < 1e-12
+    theta, Xr = gm.rayleigh_ritz(Q)
+    th_o, _ = O.rayleigh_ritz(op.apply, Qh)
+    np.testing.assert_allclose(theta, th_o, atol=1e-12 * np.abs(lam).max())
