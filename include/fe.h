@@ -91,6 +91,16 @@ fe_status fe_mesh_create(const fe_mesh_desc *desc, fe_mesh **out);
  * NULL is accepted. */
 fe_status fe_mesh_destroy(fe_mesh *mesh);
 
+/* Select the implementation of the step kernel (results are bitwise
+ * identical across variants): 0 = the fastest measured for the degree and
+ * precision (default); 1 = one cell x 16 vectors per workgroup, cell matrix
+ * streamed from L2; 2 = persistent workgroups with the cell matrix resident
+ * in registers (degrees/precisions where it fits, else 1); 3 / 4 = one cell
+ * x 32 / 64 vectors per workgroup, so each cell-matrix fragment read from L2
+ * feeds 2 / 4 products (falls back to 1 when the block would exceed the LDS).
+ * FE_EINVAL for other values. */
+fe_status fe_mesh_set_kernel(fe_mesh *mesh, int32_t variant);
+
 /* Sizes: free DoFs n, cells, and points per cell n_c = (p+1)^3.  Any output
  * pointer may be NULL.  Host pointers. */
 fe_status fe_mesh_info(const fe_mesh *mesh, int64_t *n_dof, int64_t *n_cell, int32_t *n_c);

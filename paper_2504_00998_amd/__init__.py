@@ -56,6 +56,7 @@ def lib() -> C.CDLL:
         "fe_last_error": ([], C.c_char_p),
         "fe_mesh_create": ([C.POINTER(_Desc), C.POINTER(vp)], C.c_int),
         "fe_mesh_destroy": ([vp], C.c_int),
+        "fe_mesh_set_kernel": ([vp, i32], C.c_int),
         "fe_mesh_info": ([vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)], C.c_int),
         "fe_mesh_quad_points": ([vp, vp], C.c_int),
         "fe_mesh_dof_coords": ([vp, vp], C.c_int),
@@ -138,6 +139,10 @@ class Mesh:
             self.close()
         except Exception:
             pass
+
+    def set_kernel(self, variant: int):
+        """0: fastest available step kernel; 1: generic one-cell-per-workgroup kernel."""
+        _check(lib().fe_mesh_set_kernel(self._h, int(variant)))
 
     # ------------------------------------------------------------- geometry
     def quad_points(self) -> np.ndarray:

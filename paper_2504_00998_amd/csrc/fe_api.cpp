@@ -298,6 +298,13 @@ fe_status fe_mesh_destroy(fe_mesh *mesh) {
     return FE_OK;
 }
 
+fe_status fe_mesh_set_kernel(fe_mesh *m, int32_t variant) {
+    if (!m) return fail(FE_EINVAL, "NULL mesh");
+    if (variant < 0 || variant > 4) return fail(FE_EINVAL, "kernel variant must be in 0..4");
+    m->kernel_variant = variant;
+    return FE_OK;
+}
+
 fe_status fe_mesh_info(const fe_mesh *m, int64_t *n_dof, int64_t *n_cell, int32_t *n_c) {
     if (!m) return fail(FE_EINVAL, "NULL mesh");
     if (n_dof) *n_dof = m->n;

@@ -71,6 +71,7 @@ struct fe_mesh {
     double *d_v = nullptr;        // [n] diagonal potential term of H~
     double *d_wrel = nullptr;     // [3][p+1]: (h/2) w_i per axis (for v and Vbar)
     bool potential_set = false;
+    int kernel_variant = 0;  // 0: fastest available, 1: generic colour-pass kernel
     double E = 0.0, z0 = 0.0;
 
     fe::NonlocalData nl;

@@ -21,6 +21,7 @@
 // bitwise reproducible, with no atomics.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "fe_internal.h"
@@ -223,6 +224,303 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams k) {
     }
 }
 
+// ------------------------------------------------------------------------
+// Register-resident variant: each wave keeps the MFMA A fragments of its row
+// tiles of the cell matrix in VGPRs for the whole launch, and persistent
+// workgroups walk over (cell, 16-vector chunk) items of one colour.  The
+// next item's (D Y_k)_c is prefetched into registers while the current one
+// is multiplied, then written to the other LDS buffer.  Same arithmetic,
+// colouring and epilogue as step_kernel.
+template <int PREC> struct FragOf;
+template <> struct FragOf<0> { typedef double T; };
+template <> struct FragOf<1> { typedef float T; };
+template <> struct FragOf<2> { typedef uint4 T; };
+
+struct ItemCell {
+    int cx, cy, cz, chunk;
+};
+
+// Free index of node position g in [0, ncell*p] along an axis (-1 on a
+// Dirichlet face); 32-bit and division-free.
+__device__ __forceinline__ int axis_free_index32(const AxisInfo &a, int p, int g) {
+    int k = a.ncell * p;
+    if (a.bc == FE_BC_DIRICHLET) return (g == 0 || g == k) ? -1 : g - 1;
+    if (a.bc == FE_BC_PERIODIC) return g == k ? 0 : g;
+    return g;
+}
+
+__device__ __forceinline__ ItemCell item_cell(const StepParams &k, int64_t item) {
+    ItemCell r;
+    const int it = (int)item;  // items per launch < 2^31
+    r.chunk = it % k.nchunk;
+    int cidx = it / k.nchunk;
+    int ix = cidx % k.cnt[0];
+    cidx /= k.cnt[0];
+    int iy = cidx % k.cnt[1];
+    int iz = cidx / k.cnt[1];
+    r.cx = colour_cell(k.ax[0], k.col[0], ix);
+    r.cy = colour_cell(k.ax[1], k.col[1], iy);
+    r.cz = colour_cell(k.ax[2], k.col[2], iz);
+    return r;
+}
+
+// DoF and D scale of local node l of a cell (-1 / 0 when on a Dirichlet face).
+template <int P>
+__device__ __forceinline__ int node_dof(const StepParams &k, const ItemCell &c, int l, double &d) {
+    constexpr int N1 = P + 1;
+    int li[3] = {l % N1, (l / N1) % N1, l / (N1 * N1)};
+    int cc[3] = {c.cx, c.cy, c.cz};
+    int t[3];
+    d = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        t[a] = axis_free_index32(k.ax[a], P, cc[a] * P + li[a]);
+        if (t[a] < 0) { d = 0.0; return -1; }
+        d *= k.axisD[a * k.maxf + t[a]];
+    }
+    return t[0] + (int)k.nfx * (t[1] + (int)k.nfy * t[2]);
+}
+
+template <int P>
+__device__ __forceinline__ bool node_first(const StepParams &k, const ItemCell &c, int l) {
+    constexpr int N1 = P + 1;
+    int li[3] = {l % N1, (l / N1) % N1, l / (N1 * N1)};
+    int cc[3] = {c.cx, c.cy, c.cz};
+    for (int a = 0; a < 3; ++a) {
+        int nb = axis_neighbour(k.ax[a], P, cc[a], li[a]);
+        if (nb >= 0 && axis_colour(k.ax[a], nb) < axis_colour(k.ax[a], cc[a])) return false;
+    }
+    return true;
+}
+
+template <int P, int PREC, int W>
+__global__ __launch_bounds__(64 * W, (W <= 8 ? 4 : 1)) void step_kreg_kernel(StepParams k, int64_t nitems) {
+    constexpr int N1 = P + 1, NC = N1 * N1 * N1, NCP = (NC + 31) / 32 * 32, NT = NCP / 16;
+    constexpr int KSTEP = PrecTraits<PREC>::KSTEP, NKS = NCP / KSTEP;
+    constexpr int NTHR = 64 * W, TPW = NT / W, EPT = NCP * 16 / NTHR;
+    static_assert(NT % W == 0, "row tiles must divide evenly among waves");
+    static_assert((NCP * 16) % NTHR == 0, "staging must divide evenly among threads");
+    typedef typename PrecTraits<PREC>::T T;
+    typedef typename FragOf<PREC>::T FragT;
+    constexpr int XS = PREC == 2 ? 16 * Bf16Stride<NCP>::value : NCP * 16;  // elements per buffer
+    __shared__ __align__(16) T xs[2][XS];
+    __shared__ int32_t dof[3][NCP];
+    __shared__ double dsc[3][NCP];
+    __shared__ unsigned char first[3][NCP];
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15;
+
+    // cell-matrix fragments of this wave's row tiles, resident for the launch
+    FragT kreg[TPW][NKS];
+    {
+        const FragT *A = reinterpret_cast<const FragT *>(k.A);
+#pragma unroll
+        for (int tt = 0; tt < TPW; ++tt)
+#pragma unroll
+            for (int s = 0; s < NKS; ++s) kreg[tt][s] = A[((size_t)(wave + tt * W) * NKS + s) * 64 + lane];
+    }
+
+    int64_t item = blockIdx.x;
+    if (item >= nitems) return;
+
+    auto stage_tables = [&](int64_t it, int buf) {
+        const ItemCell c = item_cell(k, it);
+        for (int l = tid; l < NCP; l += NTHR) {
+            double d = 0.0;
+            int I = l < NC ? node_dof<P>(k, c, l, d) : -1;
+            dof[buf][l] = I;
+            dsc[buf][l] = d;
+            first[buf][l] = (l < NC && node_first<P>(k, c, l)) ? 1 : 0;
+        }
+    };
+    // (D Y_k)_c of an item from its node table
+    auto load_x = [&](int64_t it, int tb, double (&pre)[EPT]) {
+        const int64_t vec0 = (it % k.nchunk) * 16;
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            int e = tid + q * NTHR;
+            int l = e >> 4, cc = e & 15;
+            int I = dof[tb][l];
+            double x = 0.0;
+            if (I >= 0 && vec0 + cc < k.N) x = dsc[tb][l] * k.X[(int64_t)I * k.ldx + vec0 + cc];
+            pre[q] = x;
+        }
+    };
+    auto store_x = [&](const double (&pre)[EPT], int buf) {
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            int e = tid + q * NTHR;
+            if constexpr (PREC == 0) xs[buf][e] = pre[q];
+            else if constexpr (PREC == 1) xs[buf][e] = (float)pre[q];
+            else xs[buf][(e & 15) * Bf16Stride<NCP>::value + (e >> 4)] = to_bf16_bits(pre[q]);
+        }
+    };
+
+    // prologue: tables of the first two items, operand of the first
+    stage_tables(item, 0);
+    if (item + gridDim.x < nitems) stage_tables(item + gridDim.x, 1);
+    __syncthreads();
+    {
+        double pre[EPT];
+        load_x(item, 0, pre);
+        store_x(pre, 0);
+    }
+    __syncthreads();
+
+    int cur = 0, tb = 0;
+    // k-steps between scheduling barriers: bounds how many B fragments the
+    // compiler keeps in flight (VGPR pressure) without starving the MFMA pipe
+    constexpr int GROUP = PREC == 2 ? 2 : 4;
+    for (; item < nitems; item += gridDim.x) {
+        const int64_t next = item + gridDim.x, next2 = next + gridDim.x;
+        const bool has_next = next < nitems;
+        const int tbn = tb == 2 ? 0 : tb + 1, tbn2 = tbn == 2 ? 0 : tbn + 1;
+        const ItemCell c = item_cell(k, item);
+        double pre[EPT];
+        if (has_next) load_x(next, tbn, pre);
+        if (next2 < nitems) stage_tables(next2, tbn2);
+
+        // epilogue operands of this item, loaded before the product so that
+        // their latency hides under the MFMA chain
+        const int64_t vec = (int64_t)c.chunk * 16 + col;
+        const bool vec_ok = vec < k.N;
+        int32_t oI[TPW][4];
+        double o1[TPW][4], o2[TPW][4];
+#pragma unroll
+        for (int tt = 0; tt < TPW; ++tt) {
+            const int t = wave + tt * W;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                int r = 16 * t + (PREC == 0 ? (lane >> 4) + 4 * i : 4 * (lane >> 4) + i);
+                int32_t I = (vec_ok && r < NC) ? dof[tb][r] : -1;
+                oI[tt][i] = I;
+                o1[tt][i] = 0.0;
+                o2[tt][i] = 0.0;
+                if (I >= 0) {
+                    if (first[tb][r]) {
+                        o1[tt][i] = k.alpha * (k.v[I] - k.shift) * k.X[(int64_t)I * k.ldx + vec];
+                        if (k.Ym1) o2[tt][i] = k.beta * k.Ym1[(int64_t)I * k.ldm + vec];
+                    } else {
+                        o1[tt][i] = k.Y[(int64_t)I * k.ldy + vec];
+                    }
+                }
+            }
+        }
+
+        // dense cell product on MFMA: A fragments from registers, B from LDS
+        double acc[TPW][4];
+        if constexpr (PREC == 0) {
+            d4 c4[TPW];
+#pragma unroll
+            for (int tt = 0; tt < TPW; ++tt) c4[tt] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < NKS; ++s) {
+                double b = xs[cur][(4 * s + (lane >> 4)) * 16 + col];
+#pragma unroll
+                for (int tt = 0; tt < TPW; ++tt)
+                    c4[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(kreg[tt][s], b, c4[tt], 0, 0, 0);
+                if ((s % GROUP) == GROUP - 1) __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int tt = 0; tt < TPW; ++tt)
+                for (int i = 0; i < 4; ++i) acc[tt][i] = c4[tt][i];
+        } else if constexpr (PREC == 1) {
+            f4 c4[TPW];
+#pragma unroll
+            for (int tt = 0; tt < TPW; ++tt) c4[tt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < NKS; ++s) {
+                float b = xs[cur][(4 * s + (lane >> 4)) * 16 + col];
+#pragma unroll
+                for (int tt = 0; tt < TPW; ++tt)
+                    c4[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(kreg[tt][s], b, c4[tt], 0, 0, 0);
+                if ((s % GROUP) == GROUP - 1) __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int tt = 0; tt < TPW; ++tt)
+                for (int i = 0; i < 4; ++i) acc[tt][i] = (double)c4[tt][i];
+        } else {
+            f4 c4[TPW];
+#pragma unroll
+            for (int tt = 0; tt < TPW; ++tt) c4[tt] = f4{0.f, 0.f, 0.f, 0.f};
+            const uint16_t *xrow = xs[cur] + col * Bf16Stride<NCP>::value + 8 * (lane >> 4);
+#pragma unroll
+            for (int s = 0; s < NKS; ++s) {
+                uint4 bv = *reinterpret_cast<const uint4 *>(xrow + 32 * s);
+                bf8 b = __builtin_bit_cast(bf8, bv);
+#pragma unroll
+                for (int tt = 0; tt < TPW; ++tt)
+                    c4[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, kreg[tt][s]), b, c4[tt], 0,
+                                                                    0, 0);
+                if ((s % GROUP) == GROUP - 1) __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int tt = 0; tt < TPW; ++tt)
+                for (int i = 0; i < 4; ++i) acc[tt][i] = (double)c4[tt][i];
+        }
+
+        // scatter with the recurrence epilogue (first writer: base - beta Y_{k-1}
+        // + contribution; later colours: running value + contribution)
+#pragma unroll
+        for (int tt = 0; tt < TPW; ++tt) {
+            const int t = wave + tt * W;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                int32_t I = oI[tt][i];
+                if (I < 0) continue;
+                int r = 16 * t + (PREC == 0 ? (lane >> 4) + 4 * i : 4 * (lane >> 4) + i);
+                double contrib = k.alpha * dsc[tb][r] * acc[tt][i];
+                k.Y[(int64_t)I * k.ldy + vec] = (o1[tt][i] - o2[tt][i]) + contrib;
+            }
+        }
+        if (has_next) store_x(pre, cur ^ 1);
+        __syncthreads();
+        cur ^= 1;
+        tb = tbn;
+    }
+}
+
+template <int P, int PREC, int W>
+static hipError_t launch_kreg_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
+    static int grid_cap = 0;
+    if (grid_cap == 0) {
+        int per_cu = 0, dev = 0, ncu = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(&step_kreg_kernel<P, PREC, W>), 64 * W, 0);
+        if (e != hipSuccess) return e;
+        e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        grid_cap = std::max(1, per_cu) * std::max(1, ncu);
+    }
+    for (int c2 = 0; c2 < m->ncol[2]; ++c2)
+        for (int c1 = 0; c1 < m->ncol[1]; ++c1)
+            for (int c0 = 0; c0 < m->ncol[0]; ++c0) {
+                int col[3] = {c0, c1, c2};
+                int64_t cells = 1;
+                for (int a = 0; a < 3; ++a) {
+                    const AxisInfo &ax = prm.ax[a];
+                    int cnt;
+                    if (col[a] == 2) cnt = 1;
+                    else {
+                        int limit = ax.ncol == 3 ? ax.ncell - 1 : ax.ncell;
+                        cnt = limit > col[a] ? (limit - col[a] + 1) / 2 : 0;
+                    }
+                    prm.col[a] = col[a];
+                    prm.cnt[a] = cnt;
+                    cells *= cnt;
+                }
+                if (cells == 0) continue;
+                int64_t items = cells * prm.nchunk;
+                int64_t grid = std::min<int64_t>(items, grid_cap);
+                hipLaunchKernelGGL((step_kreg_kernel<P, PREC, W>), dim3((unsigned)grid), dim3(64 * W), 0, s, prm,
+                                   items);
+                hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+            }
+    return hipSuccess;
+}
+
 template <int P, int PREC>
 static size_t step_smem() {
     constexpr int N1 = P + 1, NC = N1 * N1 * N1, NCP = (NC + 31) / 32 * 32;
@@ -268,6 +566,183 @@ static hipError_t launch_step_p(const fe_mesh *m, StepParams prm, hipStream_t s)
     return hipSuccess;
 }
 
+// ------------------------------------------------------------------------
+// Multi-chunk variant: one cell and G chunks of 16 vectors per workgroup,
+// one row tile of the cell matrix per wave.  Each A fragment read from L2
+// feeds G MFMAs, so the cell-matrix traffic falls by G while many
+// independent workgroups stay resident to hide memory latency.
+template <int P> struct McShape {
+    static constexpr int NCP = ((P + 1) * (P + 1) * (P + 1) + 31) / 32 * 32, NT = NCP / 16;
+    static constexpr int TPW = NT > 16 ? 2 : 1;  // row tiles per wave (<= 16 waves per block)
+    static constexpr int W = NT / TPW;
+};
+
+template <int P, int PREC, int G>
+__global__ __launch_bounds__(64 * McShape<P>::W) void step_mc_kernel(StepParams k) {
+    constexpr int N1 = P + 1, NC = N1 * N1 * N1, NCP = (NC + 31) / 32 * 32, NT = NCP / 16;
+    constexpr int KSTEP = PrecTraits<PREC>::KSTEP, NKS = NCP / KSTEP;
+    constexpr int TPW = McShape<P>::TPW, W = McShape<P>::W;
+    static_assert(NT % TPW == 0, "row tiles must divide evenly among waves");
+    constexpr int NTHR = 64 * W;
+    typedef typename PrecTraits<PREC>::T T;
+    typedef typename FragOf<PREC>::T FragT;
+    constexpr int XS = PREC == 2 ? 16 * Bf16Stride<NCP>::value : NCP * 16;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *xs = reinterpret_cast<T *>(smem);  // [G][XS]
+    constexpr size_t xs_bytes = ((size_t)G * XS * sizeof(T) + 15) / 16 * 16;
+    int32_t *dof = reinterpret_cast<int32_t *>(smem + xs_bytes);
+    double *dsc = reinterpret_cast<double *>(dof + NCP);
+    unsigned char *first = reinterpret_cast<unsigned char *>(dsc + NCP);
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15;
+    const int ngroups = (k.nchunk + G - 1) / G;
+    const int grp = blockIdx.x % ngroups;
+    const ItemCell c = item_cell(k, (int64_t)(blockIdx.x / ngroups) * k.nchunk);
+
+    for (int l = tid; l < NCP; l += NTHR) {
+        double d = 0.0;
+        int I = l < NC ? node_dof<P>(k, c, l, d) : -1;
+        dof[l] = I;
+        dsc[l] = d;
+        first[l] = (l < NC && node_first<P>(k, c, l)) ? 1 : 0;
+    }
+    __syncthreads();
+    const int64_t vbase = (int64_t)grp * G * 16;
+    for (int e = tid; e < G * NCP * 16; e += NTHR) {
+        int g = e / (NCP * 16), r = e % (NCP * 16);
+        int l = r >> 4, cc = r & 15;
+        int I = dof[l];
+        int64_t vv = vbase + g * 16 + cc;
+        double x = 0.0;
+        if (I >= 0 && vv < k.N) x = dsc[l] * k.X[(int64_t)I * k.ldx + vv];
+        if constexpr (PREC == 0) xs[g * XS + r] = x;
+        else if constexpr (PREC == 1) xs[g * XS + r] = (float)x;
+        else xs[g * XS + cc * Bf16Stride<NCP>::value + l] = to_bf16_bits(x);
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int tt = 0; tt < TPW; ++tt) {
+        const int t = wave + tt * W;
+        const FragT *A = reinterpret_cast<const FragT *>(k.A) + (size_t)t * NKS * 64 + lane;
+        double acc[G][4];
+        if constexpr (PREC == 0) {
+            d4 c4[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) c4[g] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+            for (int s = 0; s < NKS; ++s) {
+                double a = A[s * 64];
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    double b = xs[g * XS + (4 * s + (lane >> 4)) * 16 + col];
+                    c4[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c4[g], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                for (int i = 0; i < 4; ++i) acc[g][i] = c4[g][i];
+        } else if constexpr (PREC == 1) {
+            f4 c4[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) c4[g] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 8
+            for (int s = 0; s < NKS; ++s) {
+                float a = A[s * 64];
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    float b = xs[g * XS + (4 * s + (lane >> 4)) * 16 + col];
+                    c4[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c4[g], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                for (int i = 0; i < 4; ++i) acc[g][i] = (double)c4[g][i];
+        } else {
+            f4 c4[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) c4[g] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+            for (int s = 0; s < NKS; ++s) {
+                bf8 a = __builtin_bit_cast(bf8, A[s * 64]);
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const uint16_t *xrow = xs + g * XS + col * Bf16Stride<NCP>::value + 8 * (lane >> 4);
+                    bf8 b = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4 *>(xrow + 32 * s));
+                    c4[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c4[g], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                for (int i = 0; i < 4; ++i) acc[g][i] = (double)c4[g][i];
+        }
+
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int64_t vec = vbase + g * 16 + col;
+            if (vec >= k.N) continue;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                int r = 16 * t + (PREC == 0 ? (lane >> 4) + 4 * i : 4 * (lane >> 4) + i);
+                if (r >= NC) continue;
+                int I = dof[r];
+                if (I < 0) continue;
+                double contrib = k.alpha * dsc[r] * acc[g][i];
+                double *y = k.Y + (int64_t)I * k.ldy + vec;
+                if (first[r]) {
+                    double base = k.alpha * (k.v[I] - k.shift) * k.X[(int64_t)I * k.ldx + vec];
+                    if (k.Ym1) base -= k.beta * k.Ym1[(int64_t)I * k.ldm + vec];
+                    *y = base + contrib;
+                } else {
+                    *y += contrib;
+                }
+            }
+        }
+    }
+}
+
+template <int P, int PREC, int G>
+static hipError_t launch_mc_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
+    constexpr int N1 = P + 1, NC = N1 * N1 * N1, NCP = (NC + 31) / 32 * 32, W = McShape<P>::W;
+    typedef typename PrecTraits<PREC>::T T;
+    constexpr int XS = PREC == 2 ? 16 * Bf16Stride<NCP>::value : NCP * 16;
+    size_t smem = ((size_t)G * XS * sizeof(T) + 15) / 16 * 16 + NCP * (sizeof(int32_t) + sizeof(double) + 1);
+    // a block that would not fit the 160 KiB of LDS runs the one-chunk kernel
+    if (smem > 160 * 1024) return launch_step_p<P, PREC>(m, prm, s);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step_mc_kernel<P, PREC, G>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int ngroups = (prm.nchunk + G - 1) / G;
+    for (int c2 = 0; c2 < m->ncol[2]; ++c2)
+        for (int c1 = 0; c1 < m->ncol[1]; ++c1)
+            for (int c0 = 0; c0 < m->ncol[0]; ++c0) {
+                int col[3] = {c0, c1, c2};
+                int64_t cells = 1;
+                for (int a = 0; a < 3; ++a) {
+                    const AxisInfo &ax = prm.ax[a];
+                    int cnt;
+                    if (col[a] == 2) cnt = 1;
+                    else {
+                        int limit = ax.ncol == 3 ? ax.ncell - 1 : ax.ncell;
+                        cnt = limit > col[a] ? (limit - col[a] + 1) / 2 : 0;
+                    }
+                    prm.col[a] = col[a];
+                    prm.cnt[a] = cnt;
+                    cells *= cnt;
+                }
+                if (cells == 0) continue;
+                hipLaunchKernelGGL((step_mc_kernel<P, PREC, G>), dim3((unsigned)(cells * ngroups)), dim3(64 * W), smem,
+                                   s, prm);
+                hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+            }
+    return hipSuccess;
+}
+
 hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipStream_t s) {
     StepParams prm;
     prm.X = a.X; prm.ldx = a.ldx;
@@ -288,6 +763,50 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
     }
     prm.nfx = m->nf[0];
     prm.nfy = m->nf[1];
+    // variant 3/4: one cell x 2/4 chunks per workgroup; variant 0 picks the
+    // multi-chunk kernel with the chunk count measured best for the precision
+    // (bf16 with p >= 6 is fastest with one chunk per workgroup)
+    if ((m->kernel_variant == 0 && !(prec == FE_BF16 && m->p >= 6)) || m->kernel_variant == 3 ||
+        m->kernel_variant == 4) {
+        const int G = m->kernel_variant == 4 ? 4 : m->kernel_variant == 3 ? 2 : (prec == FE_BF16 ? 4 : 2);
+#define FE_MC(PP)                                                                                   \
+    case PP:                                                                                        \
+        if (prec == FE_F64) return G == 4 ? launch_mc_p<PP, 0, 4>(prm, m, s) : launch_mc_p<PP, 0, 2>(prm, m, s); \
+        if (prec == FE_F32) return G == 4 ? launch_mc_p<PP, 1, 4>(prm, m, s) : launch_mc_p<PP, 1, 2>(prm, m, s); \
+        return G == 4 ? launch_mc_p<PP, 2, 4>(prm, m, s) : launch_mc_p<PP, 2, 2>(prm, m, s);
+        switch (m->p) {
+            FE_MC(1)
+            FE_MC(2)
+            FE_MC(3)
+            FE_MC(4)
+            FE_MC(5)
+            FE_MC(6)
+            FE_MC(7)
+        default: break;
+        }
+#undef FE_MC
+    }
+    if (m->kernel_variant == 2) {
+        // register-resident cell matrix where it fits in the VGPR file
+        switch (m->p * 3 + (int)prec) {
+        case 1 * 3 + 0: return launch_kreg_p<1, 0, 2>(prm, m, s);
+        case 2 * 3 + 0: return launch_kreg_p<2, 0, 2>(prm, m, s);
+        case 3 * 3 + 0: return launch_kreg_p<3, 0, 4>(prm, m, s);
+        case 4 * 3 + 0: return launch_kreg_p<4, 0, 8>(prm, m, s);
+        case 1 * 3 + 1: return launch_kreg_p<1, 1, 2>(prm, m, s);
+        case 2 * 3 + 1: return launch_kreg_p<2, 1, 2>(prm, m, s);
+        case 3 * 3 + 1: return launch_kreg_p<3, 1, 4>(prm, m, s);
+        case 4 * 3 + 1: return launch_kreg_p<4, 1, 8>(prm, m, s);
+        case 5 * 3 + 1: return launch_kreg_p<5, 1, 14>(prm, m, s);
+        case 1 * 3 + 2: return launch_kreg_p<1, 2, 2>(prm, m, s);
+        case 2 * 3 + 2: return launch_kreg_p<2, 2, 2>(prm, m, s);
+        case 3 * 3 + 2: return launch_kreg_p<3, 2, 4>(prm, m, s);
+        case 4 * 3 + 2: return launch_kreg_p<4, 2, 8>(prm, m, s);
+        case 5 * 3 + 2: return launch_kreg_p<5, 2, 14>(prm, m, s);
+        case 6 * 3 + 2: return launch_kreg_p<6, 2, 11>(prm, m, s);
+        default: break;
+        }
+    }
 #define FE_DISPATCH(PP)                                                        \
     case PP:                                                                   \
         if (prec == FE_F64) return launch_step_p<PP, 0>(m, prm, s);            \

@@ -105,6 +105,22 @@ def test_filter_degrees_and_leading_dimension(m):
     assert torch.isnan(Yb[:, wl.N:]).all()  # padding untouched
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("p", [2, 4, 5])
+def test_kernel_variants_bitwise_equal(prec, p):
+    """The register-resident persistent kernel and the one-cell-per-workgroup
+    kernel perform the same operations in the same order."""
+    wl = W.small_slab((3, 3, 4), p=p, N=40)
+    op, gm, _ = _setup(wl)
+    X = torch.from_numpy(wl.X(op.n)).cuda()
+    gm.set_kernel(1)
+    Y1 = gm.cheb_filter(X, 5, 2.0, 400.0, -0.5, prec=prec)
+    for var in (0, 2, 3, 4):
+        gm.set_kernel(var)
+        Y0 = gm.cheb_filter(X, 5, 2.0, 400.0, -0.5, prec=prec)
+        assert torch.equal(Y0, Y1), var
+
+
 def test_bitwise_reproducible():
     wl = W.small_slab((3, 3, 4), p=4, N=32)
     op, gm, _ = _setup(wl)
