@@ -241,3 +241,48 @@ class Mesh:
         _check(lib().fe_rayleigh_ritz(self._h, _ptr(Q), _ptr(X), _ptr(P), N, ld, theta.ctypes.data,
                                       _stream(stream)))
         return theta, X
+
+
+def _autograd_function():
+    import torch
+
+    class ChebFilter(torch.autograd.Function):
+        """Y = T_m((H~ - c)/e) X / T_m((a0 - c)/e) with H~ built from (V_quad, E).
+
+        Differentiable in X, V_quad ([n_cells, n_c] at the cell GLL points) and
+        E (0-dim tensor); the bounds a, b, a0 are held fixed.  forward calls
+        fe_set_potential + fe_cheb_filter, backward fe_cheb_filter_vjp.
+        """
+
+        @staticmethod
+        def forward(ctx, X, Vq, E, mesh, m, a, b, a0, z0, prec, ckpt_stride, col_chunk):
+            Ev = float(E.item()) if torch.is_tensor(E) else float(E)
+            mesh.set_potential(Vq.detach().contiguous(), Ev, z0)
+            Y = mesh.cheb_filter(X.detach().contiguous(), m, a, b, a0, prec=prec)
+            ctx.save_for_backward(X.detach(), Vq.detach())
+            ctx.cfg = (mesh, m, a, b, a0, z0, prec, ckpt_stride, col_chunk, Ev)
+            return Y
+
+        @staticmethod
+        def backward(ctx, G):
+            X, Vq = ctx.saved_tensors
+            mesh, m, a, b, a0, z0, prec, ckpt_stride, col_chunk, Ev = ctx.cfg
+            mesh.set_potential(Vq.contiguous(), Ev, z0)
+            Xb, Vb, Eb = mesh.cheb_filter_vjp(X.contiguous(), G.contiguous(), m, a, b, a0, prec=prec,
+                                              ckpt_stride=ckpt_stride, col_chunk=col_chunk)
+            return Xb, Vb, Eb, None, None, None, None, None, None, None, None, None
+
+    return ChebFilter
+
+
+_CHEB = None
+
+
+def cheb_filter(X, Vq, E, mesh: "Mesh", m: int, a: float, b: float, a0: float = math.nan, z0: float = 0.0,
+                prec="f64", ckpt_stride: int = 1, col_chunk: int = 0):
+    """Differentiable Chebyshev filter (see ChebFilter)."""
+    global _CHEB
+    if _CHEB is None:
+        _CHEB = _autograd_function()
+    return _CHEB.apply(X, Vq, E, mesh, int(m), float(a), float(b), float(a0), float(z0), prec, int(ckpt_stride),
+                       int(col_chunk))

@@ -63,6 +63,16 @@ static fe_status check_prec(fe_dtype prec) {
     return FE_OK;
 }
 
+fe_status validate_filter_args(fe_mesh *m, int64_t N, int32_t mdeg, double a, double b, double a0, fe_dtype prec) {
+    if (!m) return fail(FE_EINVAL, "NULL mesh");
+    if (N < 0) return fail(FE_EINVAL, "N must be >= 0");
+    if (mdeg < 1) return fail(FE_EINVAL, "m must be >= 1");
+    if (!(a < b) || !std::isfinite(a) || !std::isfinite(b)) return fail(FE_EINVAL, "need finite a < b");
+    if (!std::isnan(a0) && !(std::isfinite(a0) && a0 < a))
+        return fail(FE_EINVAL, "a0 must be NaN or finite and below a");
+    return check_prec(prec);
+}
+
 static fe_status ensure_scratch(fe_mesh *m, size_t bytes) {
     if (m->scratch_bytes >= bytes) return FE_OK;
     if (m->d_scratch) {
@@ -80,7 +90,7 @@ static fe_status ensure_scratch(fe_mesh *m, size_t bytes) {
 }
 
 // Filter coefficients (scaled when a0 is finite).
-static void cheb_coeffs(int mdeg, double a, double b, double a0, std::vector<double> &al, std::vector<double> &be,
+void cheb_coefficients(int mdeg, double a, double b, double a0, std::vector<double> &al, std::vector<double> &be,
                         double &c) {
     double e = 0.5 * (b - a);
     c = 0.5 * (b + a);
@@ -102,7 +112,7 @@ static void cheb_coeffs(int mdeg, double a, double b, double a0, std::vector<dou
 }
 
 // One recurrence step Y = alpha (H~ - c) X - beta Ym1, nonlocal term included.
-static fe_status step(fe_mesh *m, const double *X, int64_t ldx, double *Y, int64_t ldy, const double *Ym1,
+fe_status filter_step(fe_mesh *m, const double *X, int64_t ldx, double *Y, int64_t ldy, const double *Ym1,
                       int64_t ldm, double alpha, double beta, double shift, int64_t N, fe_dtype prec,
                       hipStream_t s) {
     StepArgs a{X, ldx, Y, ldy, Ym1, ldm, alpha, beta, shift, N};
@@ -364,20 +374,14 @@ fe_status fe_hx_apply(fe_mesh *m, const double *X, double *Y, int64_t N, int64_t
     if ((st = check_block(m, Y, N, ld, "Y")) != FE_OK) return st;
     if (overlap(X, m->n, N, ld, Y, m->n, N, ld)) return fail(FE_EINVAL, "X and Y overlap");
     if (!m->potential_set) return fail(FE_ESTATE, "fe_set_potential has not been called");
-    return step(m, X, ld, Y, ld, nullptr, 0, 1.0, 0.0, 0.0, N, prec, s);
+    return filter_step(m, X, ld, Y, ld, nullptr, 0, 1.0, 0.0, 0.0, N, prec, s);
 }
 
 fe_status fe_cheb_filter(fe_mesh *m, const double *X, double *Y, int64_t N, int64_t ld, int32_t mdeg, double a,
                          double b, double a0, fe_dtype prec, double *work, size_t work_bytes, hipStream_t s) {
-    if (!m) return fail(FE_EINVAL, "NULL mesh");
-    if (N < 0) return fail(FE_EINVAL, "N must be >= 0");
-    if (mdeg < 1) return fail(FE_EINVAL, "m must be >= 1");
-    if (!(a < b) || !std::isfinite(a) || !std::isfinite(b)) return fail(FE_EINVAL, "need finite a < b");
-    if (!std::isnan(a0) && !(std::isfinite(a0) && a0 < a))
-        return fail(FE_EINVAL, "a0 must be NaN or finite and below a");
+    fe_status st = validate_filter_args(m, N, mdeg, a, b, a0, prec);
+    if (st != FE_OK) return st;
     if (N == 0) return FE_OK;
-    fe_status st;
-    if ((st = check_prec(prec)) != FE_OK) return st;
     if ((st = check_block(m, X, N, ld, "X")) != FE_OK) return st;
     if ((st = check_block(m, Y, N, ld, "Y")) != FE_OK) return st;
     if (mdeg >= 2) {
@@ -390,7 +394,7 @@ fe_status fe_cheb_filter(fe_mesh *m, const double *X, double *Y, int64_t N, int6
     if (!m->potential_set) return fail(FE_ESTATE, "fe_set_potential has not been called");
     std::vector<double> al, be;
     double c;
-    cheb_coeffs(mdeg, a, b, a0, al, be, c);
+    cheb_coefficients(mdeg, a, b, a0, al, be, c);
     // Y_k for odd k lives in one buffer and even k >= 2 in the other, so that
     // Y_{k+1} overwrites Y_{k-1} in place and Y_m lands in Y.
     double *odd = (mdeg & 1) ? Y : work;
@@ -398,10 +402,11 @@ fe_status fe_cheb_filter(fe_mesh *m, const double *X, double *Y, int64_t N, int6
     int64_t ldo = (mdeg & 1) ? ld : N, lde = (mdeg & 1) ? N : ld;
     auto buf = [&](int k) -> double * { return k == 0 ? const_cast<double *>(X) : (k & 1) ? odd : even; };
     auto ldb = [&](int k) -> int64_t { return k == 0 ? ld : (k & 1) ? ldo : lde; };
-    st = step(m, X, ld, buf(1), ldb(1), nullptr, 0, al[0], 0.0, c, N, prec, s);
+    st = filter_step(m, X, ld, buf(1), ldb(1), nullptr, 0, al[0], 0.0, c, N, prec, s);
     if (st != FE_OK) return st;
     for (int k = 1; k < mdeg; ++k) {
-        st = step(m, buf(k), ldb(k), buf(k + 1), ldb(k + 1), buf(k - 1), ldb(k - 1), al[k], be[k], c, N, prec, s);
+        st = filter_step(m, buf(k), ldb(k), buf(k + 1), ldb(k + 1), buf(k - 1), ldb(k - 1), al[k], be[k], c, N, prec,
+                         s);
         if (st != FE_OK) return st;
     }
     return FE_OK;

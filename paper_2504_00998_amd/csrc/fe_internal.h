@@ -108,8 +108,14 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
 hipError_t launch_potential(const fe_mesh *m, const double *Vq, double E, double z0, hipStream_t s);
 hipError_t launch_potential_vjp(const fe_mesh *m, const double *g, double z0, double *Vbar, double *Ebar,
                                 hipStream_t s);
-hipError_t launch_rowdot_accum(const fe_mesh *m, const double *U, const double *V, int64_t ld, int64_t N,
-                               double scale, double *g, hipStream_t s);
+hipError_t launch_rowdot_accum(const fe_mesh *m, const double *U, int64_t ldu, const double *V, int64_t ldv,
+                               int64_t N, double scale, double *g, hipStream_t s);
+fe_status filter_step(fe_mesh *m, const double *X, int64_t ldx, double *Y, int64_t ldy, const double *Ym1,
+                      int64_t ldm, double alpha, double beta, double shift, int64_t N, fe_dtype prec, hipStream_t s);
+void cheb_coefficients(int mdeg, double a, double b, double a0, std::vector<double> &al, std::vector<double> &be,
+                       double &c);
+fe_status validate_filter_args(fe_mesh *m, int64_t N, int32_t mdeg, double a, double b, double a0, fe_dtype prec);
+hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_axpby(double *Y, int64_t ldy, const double *X, int64_t ldx, int64_t n, int64_t N, double a,
                         double b, hipStream_t s);
 hipError_t launch_nonlocal(const fe_mesh *m, const double *X, int64_t ldx, double *Y, int64_t ldy, int64_t N,

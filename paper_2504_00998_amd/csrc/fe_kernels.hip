@@ -983,23 +983,35 @@ hipError_t launch_potential_vjp(const fe_mesh *m, const double *g, double z0, do
     return hipGetLastError();
 }
 
-// g_I += scale * sum_j U[I,j] V[I,j]; one wave per row, fixed reduction order.
-__global__ void rowdot_kernel(const double *U, const double *V, int64_t ld, int64_t N, int64_t n, double scale,
-                              double *g) {
-    int64_t I = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    int lane = threadIdx.x & 63;
+// g_I += scale * sum_j U[I,j] V[I,j]; 16 lanes per row, fixed reduction order.
+__global__ void rowdot_kernel(const double *U, int64_t ldu, const double *V, int64_t ldv, int64_t N, int64_t n,
+                              double scale, double *g) {
+    int64_t I = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4;
+    int lane = threadIdx.x & 15;
     if (I >= n) return;
     double s = 0.0;
-    for (int64_t j = lane; j < N; j += 64) s += U[I * ld + j] * V[I * ld + j];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    for (int64_t j = lane; j < N; j += 16) s += U[I * ldu + j] * V[I * ldv + j];
+    for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
     if (lane == 0) g[I] += scale * s;
 }
 
-hipError_t launch_rowdot_accum(const fe_mesh *m, const double *U, const double *V, int64_t ld, int64_t N,
-                               double scale, double *g, hipStream_t s) {
-    int64_t threads = m->n * 64;
-    hipLaunchKernelGGL(rowdot_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, U, V, ld, N, m->n,
-                       scale, g);
+hipError_t launch_rowdot_accum(const fe_mesh *m, const double *U, int64_t ldu, const double *V, int64_t ldv,
+                               int64_t N, double scale, double *g, hipStream_t s) {
+    int64_t threads = m->n * 16;
+    hipLaunchKernelGGL(rowdot_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, U, ldu, V, ldv, N,
+                       m->n, scale, g);
+    return hipGetLastError();
+}
+
+// p[0..n) = v (a kernel rather than a memset, so the call is safe inside a
+// captured graph).
+__global__ void fill_kernel(double *p, int64_t n, double v) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s) {
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 

@@ -15,10 +15,4 @@ extern "C" {
 fe_status fe_set_nonlocal(fe_mesh *, int32_t, const double *, const double *, double, double, hipStream_t) {
     return fail(FE_ENOTSUP, "nonlocal term not implemented");
 }
-size_t fe_cheb_filter_vjp_work_bytes(const fe_mesh *, int64_t, int32_t, int32_t, int32_t) { return 0; }
-fe_status fe_cheb_filter_vjp(fe_mesh *, const double *, const double *, int64_t, int64_t, int32_t, double, double,
-                             double, fe_dtype, double *, double *, double *, int32_t, int32_t, double *, size_t,
-                             hipStream_t) {
-    return fail(FE_ENOTSUP, "vjp not implemented");
-}
 }
