@@ -61,6 +61,38 @@ def cpu_baseline(wl, a, b, a0, ncols: int = 4):
     }
 
 
+def mixed_precision_report(gm, wl, X, Y, work, a, b, a0, steps, ms_f64):
+    """FP32 / BF16 cell products on the same workload: filter throughput,
+    speedup over FP64, and the Ritz values after 5 subspace iterations
+    (filter in the given precision; CholQR2 and Rayleigh-Ritz in FP64)
+    against the same iteration with FP64 cell products."""
+    import numpy as np
+    import torch
+    from paper_2504_00998_amd import solver
+
+    stream = torch.cuda.current_stream()
+    n, N, m = gm.n, wl.N, wl.m
+    hist64, _ = solver.subspace_iteration(gm, X, m, 5, a, b, a0, prec="f64", work=work)
+    out = {"ritz_iterations": 5, "ritz_reference": "same subspace iteration with FP64 cell products"}
+    for prec in ("f32", "bf16"):
+        gm.cheb_filter(X, m, a, b, a0, prec=prec, Y=Y, work=work)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            gm.cheb_filter(X, m, a, b, a0, prec=prec, Y=Y, work=work)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        hist, _ = solver.subspace_iteration(gm, X, m, 5, a, b, a0, prec=prec, work=work)
+        d = np.abs(hist[-1] - hist64[-1])
+        out[prec] = {"value": round(m * n * N / (ms * 1e-3) / 1e9, 4), "ms_per_filter": round(ms, 4),
+                     "speedup_vs_f64": round(ms_f64 / ms, 3),
+                     "ritz_err_max_Ha": float(d.max()), "ritz_err_lowest_half_Ha": float(d[: N // 2].max()),
+                     "ritz_ok_1e-7": bool(d[: N // 2].max() <= 1e-7)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,7 +101,8 @@ def main():
     ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
     ap.add_argument("--cfg", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-cols", type=int, default=4)
+    ap.add_argument("--cpu-cols", type=int, default=24)
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32/BF16 report")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
@@ -171,6 +204,9 @@ def main():
             "launches_per_step": launches,
         },
     }
+    if not args.no_mixed and args.prec == "f64":
+        t_pot_ms = t_pot
+        rec["mixed_precision"] = mixed_precision_report(gm, wl, X, Y, work, a, b, a0, args.steps, ms - t_pot_ms)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(wl, a, b, a0, args.cpu_cols)
     print(json.dumps(rec), flush=True)

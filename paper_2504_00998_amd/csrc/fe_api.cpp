@@ -117,12 +117,8 @@ fe_status filter_step(fe_mesh *m, const double *X, int64_t ldx, double *Y, int64
                       hipStream_t s) {
     StepArgs a{X, ldx, Y, ldy, Ym1, ldm, alpha, beta, shift, N};
     FE_HIP(launch_step(m, a, prec, s), "step kernel launch");
-    if (m->nl.n_site > 0) {
-        fe_status st = ensure_scratch(m, std::max<size_t>(1024 * sizeof(double),
-                                                           nonlocal_work_doubles(m, N) * sizeof(double)));
-        if (st != FE_OK) return st;
-        FE_HIP(launch_nonlocal(m, X, ldx, Y, ldy, N, alpha, m->d_scratch, s), "nonlocal kernel launch");
-    }
+    // the nonlocal term after all colour passes: they write the base values
+    if (m->nl.n_site > 0) FE_HIP(launch_nonlocal(m, X, ldx, Y, ldy, N, alpha, s), "nonlocal kernel launch");
     return FE_OK;
 }
 
@@ -171,10 +167,7 @@ static void free_mesh(fe_mesh *m) {
     (void)hipFree(m->d_v);
     (void)hipFree(m->d_wrel);
     (void)hipFree(m->d_scratch);
-    (void)hipFree(m->nl.d_colptr);
-    (void)hipFree(m->nl.d_row);
-    (void)hipFree(m->nl.d_val);
-    (void)hipFree(m->nl.d_D);
+    nonlocal_release(m);
     if (m->blas) rocblas_destroy_handle(static_cast<rocblas_handle>(m->blas));
     delete m;
 }

@@ -122,12 +122,7 @@ fe_status fe_lanczos_bounds(fe_mesh *m, const double *v0, int32_t k, double *a0,
         double *vj = V + (size_t)j * n;
         StepArgs a{vj, 1, w, 1, nullptr, 0, 1.0, 0.0, 0.0, 1};
         FE_HIPD(launch_step(m, a, FE_F64, s), "step kernel launch");
-        if (m->nl.n_site > 0) {
-            if ((st = ensure_scratch_dense(m, std::max(need, (size_t)(1024 + nonlocal_work_doubles(m, 1)) * 8))) != FE_OK)
-                return st;
-            V = m->d_scratch + 1024; w = V + (size_t)n * (k + 1); hv = w + n; vj = V + (size_t)j * n;
-            FE_HIPD(launch_nonlocal(m, vj, 1, w, 1, 1, 1.0, m->d_scratch + need / 8, s), "nonlocal");
-        }
+        if (m->nl.n_site > 0) FE_HIPD(launch_nonlocal(m, vj, 1, w, 1, 1, 1.0, s), "nonlocal");
         FE_BLAS(rocblas_ddot(h, ni, vj, 1, w, 1, &alpha[j]), "ddot");
         // full reorthogonalisation, twice: w -= V (V^T w)
         for (int pass = 0; pass < 2; ++pass) {
@@ -195,13 +190,11 @@ fe_status fe_rayleigh_ritz(fe_mesh *m, const double *Q, double *X, double *P, in
     StepArgs a{Q, ld, P, ld, nullptr, 0, 1.0, 0.0, 0.0, N};
     FE_HIPD(launch_step(m, a, FE_F64, s), "step kernel launch");
     size_t need = (1024 + 2 * (size_t)N * N + 2 * (size_t)N + 64) * sizeof(double);
-    if (m->nl.n_site > 0) need += nonlocal_work_doubles(m, N) * sizeof(double);
     fe_status st = ensure_scratch_dense(m, need);
     if (st != FE_OK) return st;
     double *Hs = m->d_scratch + 1024, *Ht = Hs + (size_t)N * N, *d = Ht + (size_t)N * N, *e = d + N;
     rocblas_int *info = reinterpret_cast<rocblas_int *>(e + N);
-    if (m->nl.n_site > 0)
-        FE_HIPD(launch_nonlocal(m, Q, ld, P, ld, N, 1.0, reinterpret_cast<double *>(info + 64), s), "nonlocal");
+    if (m->nl.n_site > 0) FE_HIPD(launch_nonlocal(m, Q, ld, P, ld, N, 1.0, s), "nonlocal");
     rocblas_handle h;
     if ((st = handle(m, s, h)) != FE_OK) return st;
     int Ni = (int)N, ni = (int)n, ldi = (int)ld;

@@ -31,12 +31,18 @@ struct AxisInfo {
 
 struct NonlocalData {
     int n_site = 0;
-    int64_t nnz = 0;          // entries of C~ (all projectors)
-    int64_t *d_colptr = nullptr;  // [9*n_site + 1]
-    int32_t *d_row = nullptr;     // [nnz]  free-DoF index
-    double *d_val = nullptr;      // [nnz]
-    double *d_D = nullptr;        // [9*n_site]
-    int max_support = 0;          // largest per-projector support
+    int64_t nnz = 0;                 // support entries over all sites
+    int64_t n_node = 0;              // DoFs inside at least one support
+    int64_t *d_supp_ptr = nullptr;   // [n_site + 1]
+    int32_t *d_supp_dof = nullptr;   // [nnz] DoF of each support entry
+    double *d_vals = nullptr;        // [nnz][9] C~ values per projector
+    double *d_D = nullptr;           // [n_site][9] couplings
+    int32_t *d_node = nullptr;       // [n_node] DoFs with incident entries (ascending)
+    int64_t *d_inc_ptr = nullptr;    // [n_node + 1]
+    int64_t *d_inc_entry = nullptr;  // [nnz] incident entries, per node
+    int32_t *d_entry_site = nullptr; // [nnz] site of each entry
+    double *d_W = nullptr;           // projections C~^T X, grown on demand
+    size_t W_cap = 0;                // doubles
 };
 
 }  // namespace fe
@@ -118,8 +124,9 @@ fe_status validate_filter_args(fe_mesh *m, int64_t N, int32_t mdeg, double a, do
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_axpby(double *Y, int64_t ldy, const double *X, int64_t ldx, int64_t n, int64_t N, double a,
                         double b, hipStream_t s);
-hipError_t launch_nonlocal(const fe_mesh *m, const double *X, int64_t ldx, double *Y, int64_t ldy, int64_t N,
-                           double scale, double *work, hipStream_t s);
+hipError_t launch_nonlocal(fe_mesh *m, const double *X, int64_t ldx, double *Y, int64_t ldy, int64_t N,
+                           double alpha, hipStream_t s);
 size_t nonlocal_work_doubles(const fe_mesh *m, int64_t N);
+void nonlocal_release(fe_mesh *m);
 
 }  // namespace fe

@@ -1,0 +1,243 @@
+// Separable nonlocal pseudopotential term (paper Sec. 2.1, Eq. V_nloc and the
+// action of H_nloc):
+//
+//   H~ += C~ diag(D) C~^T,   C~_{I,(s,beta)} = M_I^{1/2} p_{s,beta}(x_I),
+//
+// with p_{s,beta}(x) = S_beta(x - R_s) exp(-|x - R_s|^2 / (2 r_g^2)) inside the
+// cutoff ball |x - R_s| < r_cut (minimum image on periodic axes), normalised
+// to sum_I M_I p(x_I)^2 = 1, and S_beta the real solid harmonics 1; x, y, z;
+// xy, yz, zx, x^2 - y^2, 3z^2 - r^2 (s, p, d channels).  The host builds the
+// per-site supports and a node -> (site, entry) incidence list so that the
+// application  Y += alpha C~ D C~^T X  is a deterministic gather on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "fe_internal.h"
+
+namespace fe {
+
+namespace {
+
+double solid_harmonic(int beta, double x, double y, double z) {
+    switch (beta) {
+    case 0: return 1.0;
+    case 1: return x;
+    case 2: return y;
+    case 3: return z;
+    case 4: return x * y;
+    case 5: return y * z;
+    case 6: return z * x;
+    case 7: return x * x - y * y;
+    default: return 2.0 * z * z - x * x - y * y;  // 3 z^2 - r^2
+    }
+}
+
+void free_nl(NonlocalData &nl) {
+    (void)hipFree(nl.d_supp_ptr);
+    (void)hipFree(nl.d_supp_dof);
+    (void)hipFree(nl.d_vals);
+    (void)hipFree(nl.d_D);
+    (void)hipFree(nl.d_node);
+    (void)hipFree(nl.d_inc_ptr);
+    (void)hipFree(nl.d_inc_entry);
+    (void)hipFree(nl.d_entry_site);
+    (void)hipFree(nl.d_W);
+    nl = NonlocalData();
+}
+
+}  // namespace
+
+void nonlocal_release(fe_mesh *m) { free_nl(m->nl); }
+
+// W[(s*9+beta)][j] = D_{s,beta} sum_{e in supp(s)} C~[e][beta] X[dof(e)][j]
+__global__ void nl_project_kernel(const double *X, int64_t ldx, int64_t N, const int64_t *supp_ptr,
+                                  const int32_t *supp_dof, const double *vals, const double *D, double *W) {
+    const int s = blockIdx.x;
+    const int64_t j = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    double acc[9];
+#pragma unroll
+    for (int b = 0; b < 9; ++b) acc[b] = 0.0;
+    for (int64_t e = supp_ptr[s]; e < supp_ptr[s + 1]; ++e) {
+        double x = X[(int64_t)supp_dof[e] * ldx + j];
+        const double *v = vals + e * 9;
+#pragma unroll
+        for (int b = 0; b < 9; ++b) acc[b] += v[b] * x;
+    }
+#pragma unroll
+    for (int b = 0; b < 9; ++b) W[((int64_t)s * 9 + b) * N + j] = D[s * 9 + b] * acc[b];
+}
+
+// Y[node][j] += alpha sum_{e incident to node} sum_beta C~[e][beta] W[(site(e)*9+beta)][j]
+__global__ void nl_expand_kernel(double *Y, int64_t ldy, int64_t N, double alpha, const int32_t *node,
+                                 const int64_t *inc_ptr, const int64_t *inc_entry, const int32_t *entry_site,
+                                 const double *vals, const double *W) {
+    const int64_t u = blockIdx.x;
+    const int64_t j = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    double acc = 0.0;
+    for (int64_t q = inc_ptr[u]; q < inc_ptr[u + 1]; ++q) {
+        int64_t e = inc_entry[q];
+        int s = entry_site[e];
+        const double *v = vals + e * 9;
+        const double *w = W + (int64_t)s * 9 * N + j;
+#pragma unroll
+        for (int b = 0; b < 9; ++b) acc += v[b] * w[(int64_t)b * N];
+    }
+    Y[(int64_t)node[u] * ldy + j] += alpha * acc;
+}
+
+size_t nonlocal_work_doubles(const fe_mesh *m, int64_t N) { return (size_t)m->nl.n_site * 9 * (size_t)N; }
+
+static hipError_t ensure_nl_work(fe_mesh *m, int64_t N) {
+    size_t need = nonlocal_work_doubles(m, N);
+    if (need <= m->nl.W_cap) return hipSuccess;
+    if (m->nl.d_W) {
+        hipError_t e = hipFree(m->nl.d_W);  // synchronises the device
+        if (e != hipSuccess) return e;
+        m->nl.d_W = nullptr;
+        m->nl.W_cap = 0;
+    }
+    hipError_t e = hipMalloc(&m->nl.d_W, need * sizeof(double));
+    if (e != hipSuccess) return e;
+    m->nl.W_cap = need;
+    return hipSuccess;
+}
+
+hipError_t launch_nonlocal(fe_mesh *m, const double *X, int64_t ldx, double *Y, int64_t ldy, int64_t N,
+                           double alpha, hipStream_t s) {
+    if (m->nl.n_site == 0) return hipSuccess;
+    hipError_t e = ensure_nl_work(m, N);
+    if (e != hipSuccess) return e;
+    const int TB = 128;
+    dim3 g1((unsigned)m->nl.n_site, (unsigned)((N + TB - 1) / TB));
+    hipLaunchKernelGGL(nl_project_kernel, g1, dim3(TB), 0, s, X, ldx, N, (const int64_t *)m->nl.d_supp_ptr,
+                       (const int32_t *)m->nl.d_supp_dof, (const double *)m->nl.d_vals, (const double *)m->nl.d_D,
+                       m->nl.d_W);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (m->nl.n_node == 0) return hipSuccess;
+    dim3 g2((unsigned)m->nl.n_node, (unsigned)((N + TB - 1) / TB));
+    hipLaunchKernelGGL(nl_expand_kernel, g2, dim3(TB), 0, s, Y, ldy, N, alpha, (const int32_t *)m->nl.d_node,
+                       (const int64_t *)m->nl.d_inc_ptr, (const int64_t *)m->nl.d_inc_entry,
+                       (const int32_t *)m->nl.d_entry_site, (const double *)m->nl.d_vals,
+                       (const double *)m->nl.d_W);
+    return hipGetLastError();
+}
+
+}  // namespace fe
+
+using namespace fe;
+
+extern "C" {
+
+fe_status fe_set_nonlocal(fe_mesh *m, int32_t n_site, const double *centres, const double *D, double r_cut,
+                          double r_g, hipStream_t st) {
+    if (!m) return fail(FE_EINVAL, "NULL mesh");
+    if (n_site < 0) return fail(FE_EINVAL, "n_site must be >= 0");
+    if (n_site > 0) {
+        if (!centres || !D) return fail(FE_EINVAL, "NULL centres or D");
+        if (!(r_cut > 0.0) || !(r_g > 0.0) || !std::isfinite(r_cut) || !std::isfinite(r_g))
+            return fail(FE_EINVAL, "r_cut and r_g must be positive");
+        for (int a = 0; a < 3; ++a)
+            if (m->bc[a] == FE_BC_PERIODIC && 2.0 * r_cut >= m->L[a])
+                return fail(FE_EINVAL, "cutoff ball wraps onto itself on a periodic axis");
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) return fail(FE_EDEVICE, "stream synchronisation failed");
+    free_nl(m->nl);
+    if (n_site == 0) return FE_OK;
+
+    // per-axis free positions within r_cut of each centre coordinate
+    std::vector<int64_t> supp_ptr(1, 0);
+    std::vector<int32_t> supp_dof;
+    std::vector<double> vals;
+    for (int s = 0; s < n_site; ++s) {
+        std::vector<std::pair<int64_t, double>> cand[3];  // (free index, signed offset)
+        for (int a = 0; a < 3; ++a) {
+            for (int64_t t = 0; t < m->nf[a]; ++t) {
+                double d = m->axis_coord[a][t] - centres[3 * s + a];
+                if (m->bc[a] == FE_BC_PERIODIC) d -= m->L[a] * std::nearbyint(d / m->L[a]);
+                if (std::fabs(d) < r_cut) cand[a].push_back({t, d});
+            }
+        }
+        std::vector<std::pair<int32_t, double>> pts;  // (dof, offsets encoded below)
+        std::vector<double> pv;
+        double nrm[9] = {0};
+        for (auto &z : cand[2])
+            for (auto &y : cand[1])
+                for (auto &x : cand[0]) {
+                    double r2 = x.second * x.second + y.second * y.second + z.second * z.second;
+                    if (!(r2 < r_cut * r_cut)) continue;
+                    int64_t I = x.first + m->nf[0] * (y.first + m->nf[1] * z.first);
+                    double M = m->axis_mass[0][x.first] * m->axis_mass[1][y.first] * m->axis_mass[2][z.first];
+                    double rad = std::exp(-r2 / (2.0 * r_g * r_g));
+                    pts.push_back({(int32_t)I, M});
+                    for (int b = 0; b < 9; ++b) {
+                        double p = solid_harmonic(b, x.second, y.second, z.second) * rad;
+                        pv.push_back(p);
+                        nrm[b] += M * p * p;
+                    }
+                }
+        // increasing DoF order within the support
+        std::vector<size_t> order(pts.size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+        std::sort(order.begin(), order.end(), [&](size_t u, size_t v) { return pts[u].first < pts[v].first; });
+        for (size_t oi : order) {
+            supp_dof.push_back(pts[oi].first);
+            double sq = std::sqrt(pts[oi].second);
+            for (int b = 0; b < 9; ++b) {
+                double sc = nrm[b] > 0.0 ? 1.0 / std::sqrt(nrm[b]) : 0.0;
+                vals.push_back(pv[oi * 9 + b] * sc * sq);
+            }
+        }
+        supp_ptr.push_back((int64_t)supp_dof.size());
+    }
+    // node -> incident support entries, nodes ascending, entries by site then position
+    std::vector<std::pair<int32_t, int64_t>> inc;  // (dof, entry)
+    inc.reserve(supp_dof.size());
+    for (int64_t e = 0; e < (int64_t)supp_dof.size(); ++e) inc.push_back({supp_dof[e], e});
+    std::stable_sort(inc.begin(), inc.end(), [](const auto &u, const auto &v) { return u.first < v.first; });
+    std::vector<int32_t> node;
+    std::vector<int64_t> inc_ptr(1, 0), inc_entry;
+    std::vector<int32_t> entry_site(supp_dof.size());
+    for (int s = 0; s < n_site; ++s)
+        for (int64_t e = supp_ptr[s]; e < supp_ptr[s + 1]; ++e) entry_site[e] = s;
+    for (size_t i = 0; i < inc.size(); ++i) {
+        if (node.empty() || node.back() != inc[i].first) {
+            if (!node.empty()) inc_ptr.push_back((int64_t)inc_entry.size());
+            node.push_back(inc[i].first);
+        }
+        inc_entry.push_back(inc[i].second);
+    }
+    inc_ptr.push_back((int64_t)inc_entry.size());
+
+    NonlocalData &nl = m->nl;
+    auto up = [&](void **dst, const void *src, size_t bytes) -> bool {
+        if (bytes == 0) bytes = 8;
+        if (hipMalloc(dst, bytes) != hipSuccess) return false;
+        return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    bool ok = up((void **)&nl.d_supp_ptr, supp_ptr.data(), supp_ptr.size() * sizeof(int64_t)) &&
+              up((void **)&nl.d_supp_dof, supp_dof.data(), supp_dof.size() * sizeof(int32_t)) &&
+              up((void **)&nl.d_vals, vals.data(), vals.size() * sizeof(double)) &&
+              up((void **)&nl.d_D, D, (size_t)n_site * 9 * sizeof(double)) &&
+              up((void **)&nl.d_node, node.data(), node.size() * sizeof(int32_t)) &&
+              up((void **)&nl.d_inc_ptr, inc_ptr.data(), inc_ptr.size() * sizeof(int64_t)) &&
+              up((void **)&nl.d_inc_entry, inc_entry.data(), inc_entry.size() * sizeof(int64_t)) &&
+              up((void **)&nl.d_entry_site, entry_site.data(), entry_site.size() * sizeof(int32_t));
+    if (!ok) {
+        (void)hipGetLastError();
+        free_nl(nl);
+        return fail(FE_ENOMEM, "device allocation failed in fe_set_nonlocal");
+    }
+    nl.n_site = n_site;
+    nl.nnz = (int64_t)supp_dof.size();
+    nl.n_node = (int64_t)node.size();
+    return FE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,82 @@
+"""GPU parity of the separable nonlocal term (Eq. V_nloc: nine Gaussian-radial
+s, p, d projectors per site, couplings U(-1,1) Ha) against the oracle's
+collocated projector matrix, for H~X, the filter and the adjoint."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2504_00998_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def nl_case():
+    import paper_2504_00998_amd as fe
+    wl = W.small_slab((5, 5, 6), p=3, N=20, m=8, cfg=5)
+    om = O.Mesh.from_workload(wl)
+    Vq = W.workload_potential(wl, om.quad_points())
+    cen = wl.centres()
+    D = wl.nonlocal_coupling()
+    P = O.Projectors(om, cen, wl.r_cut, wl.r_g)
+    op = O.Operator(om, Vq, wl.E, wl.z0, P, D.reshape(-1))
+    gm = fe.Mesh.from_workload(wl)
+    gm.set_potential(torch.from_numpy(Vq).cuda(), wl.E, wl.z0)
+    gm.set_nonlocal(cen, D, wl.r_cut, wl.r_g)
+    return wl, op, gm
+
+
+def _err(Y, R):
+    return (np.linalg.norm(Y - R, axis=0) / np.linalg.norm(R, axis=0)).max()
+
+
+def test_hx_with_nonlocal(nl_case):
+    wl, op, gm = nl_case
+    X = wl.X(op.n)
+    Y = gm.hx(torch.from_numpy(X).cuda()).cpu().numpy()
+    assert _err(Y, op.apply(X)) < 1e-13
+
+
+def test_filter_with_nonlocal(nl_case):
+    wl, op, gm = nl_case
+    X = wl.X(op.n)
+    a0, b, _ = O.lanczos_bounds(op.apply, wl.lanczos_start(op.n), 10)
+    a0g, bg = gm.lanczos_bounds(torch.from_numpy(wl.lanczos_start(op.n)).cuda(), 10)
+    assert abs(bg - b) < 1e-9 * abs(b) and abs(a0g - a0) < 1e-9 * abs(b)
+    a = O.weyl_cut(a0, b, wl.N, op.n)
+    for prec, tol in (("f64", 1e-12), ("f32", 1e-4)):
+        Y = gm.cheb_filter(torch.from_numpy(X).cuda(), wl.m, a, b, a0, prec=prec).cpu().numpy()
+        assert _err(Y, op.filter(X, wl.m, a, b, a0)) < tol, prec
+
+
+def test_vjp_with_nonlocal(nl_case):
+    wl, op, gm = nl_case
+    X = wl.X(op.n)
+    G = np.random.default_rng(9).standard_normal(X.shape)
+    a0, b, _ = O.lanczos_bounds(op.apply, wl.lanczos_start(op.n), 10)
+    a = O.weyl_cut(a0, b, wl.N, op.n)
+    Xb_o, g_o = op.filter_vjp(X, G, wl.m, a, b, a0)
+    Vb_o, Eb_o = op.potential_vjp(g_o)
+    Xb, Vb, Eb = gm.cheb_filter_vjp(torch.from_numpy(X).cuda(), torch.from_numpy(G).cuda(), wl.m, a, b, a0,
+                                    ckpt_stride=3, col_chunk=8)
+    assert _err(Xb.cpu().numpy(), Xb_o) < 1e-12
+    assert np.abs(Vb.cpu().numpy() - Vb_o).max() < 1e-11 * np.abs(Vb_o).max()
+    assert abs(Eb.item() - Eb_o) < 1e-11 * max(1.0, abs(Eb_o))
+
+
+def test_nonlocal_clear_and_errors(nl_case):
+    import paper_2504_00998_amd as fe
+    wl, op, gm = nl_case
+    om = O.Mesh.from_workload(wl)
+    Vq = W.workload_potential(wl, om.quad_points())
+    op_local = O.Operator(om, Vq, wl.E, wl.z0)
+    gm2 = fe.Mesh.from_workload(wl)
+    gm2.set_potential(torch.from_numpy(Vq).cuda(), wl.E, wl.z0)
+    gm2.set_nonlocal(wl.centres(), wl.nonlocal_coupling(), wl.r_cut, wl.r_g)
+    gm2.set_nonlocal(np.zeros((0, 3)), np.zeros((0, 9)), wl.r_cut, wl.r_g)  # clears the term
+    X = wl.X(op.n)
+    Y = gm2.hx(torch.from_numpy(X).cuda()).cpu().numpy()
+    assert _err(Y, op_local.apply(X)) < 1e-13
+    with pytest.raises(fe.FEError):
+        gm2.set_nonlocal(wl.centres(), wl.nonlocal_coupling(), 3.0, wl.r_g)  # ball wraps on a 5-bohr period
