@@ -106,7 +106,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU split is described in DESIGN.md, not built)", file=sys.stderr)
+              "(the domain split across GPUs is a design, not built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
