@@ -630,7 +630,8 @@ __global__ __launch_bounds__(64 * McShape<P>::W) void step_mc_kernel(StepParams 
             d4 c4[G];
 #pragma unroll
             for (int g = 0; g < G; ++g) c4[g] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 8
+            // all A fragments of the row tile issued at once (one L2 round trip)
+#pragma unroll
             for (int s = 0; s < NKS; ++s) {
                 double a = A[s * 64];
 #pragma unroll
@@ -743,6 +744,274 @@ static hipError_t launch_mc_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
     return hipSuccess;
 }
 
+// ------------------------------------------------------------------------
+// Tile variant: a workgroup owns a column of TXY x TXY cells in x-y and TZ
+// layers in z for one chunk of 16 vectors, with the cell matrix resident in
+// VGPRs.  It marches up the column, accumulating each cell's product rows in
+// an LDS ring of p+1 node planes (FP64), and emits a plane with the
+// recurrence epilogue once every cell touching it inside the tile is done.
+// Only nodes on tile boundaries are shared with other workgroups; tiles are
+// coloured per axis (as cells are in the other variants) and the first
+// colour to reach such a node writes the base term.  Inside a tile the
+// partial sums follow a fixed cell order, so results are reproducible run to
+// run (the association differs from the one-cell variants by rounding).
+struct TileParams {
+    StepParams k;
+    int tz;        // layers per tile (z)
+    int ntile[3];  // tiles per axis
+    int tcol[3];   // tile colour of this launch
+    int tcnt[3];   // tiles of this colour per axis
+    int tncol[3];  // tile colours per axis
+};
+
+__device__ __forceinline__ int tile_colour(int t, int nt, int ncol) { return (ncol == 3 && t == nt - 1) ? 2 : (t & 1); }
+
+// Neighbouring tile sharing a node at the tile's low (side = 0) or high
+// (side = 1) boundary, or -1.
+__device__ __forceinline__ int tile_neighbour(int t, int nt, int bc, int side) {
+    if (side == 0) return t > 0 ? t - 1 : (bc == FE_BC_PERIODIC ? nt - 1 : -1);
+    return t < nt - 1 ? t + 1 : (bc == FE_BC_PERIODIC ? 0 : -1);
+}
+
+template <int P, int PREC, int W, int TXY>
+__global__ __launch_bounds__(64 * W, (W <= 8 ? 4 : 1)) void step_tile_kernel(TileParams tp) {
+    const StepParams &k = tp.k;
+    constexpr int N1 = P + 1, NC = N1 * N1 * N1, NCP = (NC + 31) / 32 * 32, NT = NCP / 16;
+    constexpr int KSTEP = PrecTraits<PREC>::KSTEP, NKS = NCP / KSTEP;
+    constexpr int NTHR = 64 * W, TPW = NT / W, EPT = NCP * 16 / NTHR;
+    constexpr int CW = TXY * P + 1;  // closure width (nodes) in x and y
+    static_assert(NT % W == 0, "row tiles must divide evenly among waves");
+    static_assert((NCP * 16) % NTHR == 0, "staging must divide evenly among threads");
+    typedef typename PrecTraits<PREC>::T T;
+    typedef typename FragOf<PREC>::T FragT;
+    constexpr int XS = PREC == 2 ? 16 * Bf16Stride<NCP>::value : NCP * 16;
+    __shared__ __align__(16) T xs[XS];
+    __shared__ double ring[N1 * CW * CW * 16];
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15;
+
+    FragT kreg[TPW][NKS];
+    {
+        const FragT *A = reinterpret_cast<const FragT *>(k.A);
+#pragma unroll
+        for (int tt = 0; tt < TPW; ++tt)
+#pragma unroll
+            for (int s = 0; s < NKS; ++s) kreg[tt][s] = A[((size_t)(wave + tt * W) * NKS + s) * 64 + lane];
+    }
+
+    // which tile and chunk
+    const int chunk = blockIdx.x % k.nchunk;
+    int tix = blockIdx.x / k.nchunk;
+    int tc[3];
+    for (int a = 0; a < 3; ++a) {
+        int i = tix % tp.tcnt[a];
+        tix /= tp.tcnt[a];
+        tc[a] = tp.tcol[a] == 2 ? tp.ntile[a] - 1 : tp.tcol[a] + 2 * i;
+    }
+    const int c0x = tc[0] * TXY, c0y = tc[1] * TXY, c0z = tc[2] * tp.tz;
+    const int ncx = min(TXY, k.ax[0].ncell - c0x), ncy = min(TXY, k.ax[1].ncell - c0y);
+    const int ncz = min(tp.tz, k.ax[2].ncell - c0z);
+    const int64_t vec0 = (int64_t)chunk * 16;
+    const int64_t vec = vec0 + col;
+
+    for (int e = tid; e < N1 * CW * CW * 16; e += NTHR) ring[e] = 0.0;
+
+    auto load_x = [&](int cell, double (&pre)[EPT]) {
+        ItemCell c;
+        c.cx = c0x + cell % ncx;
+        c.cy = c0y + (cell / ncx) % ncy;
+        c.cz = c0z + cell / (ncx * ncy);
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            int e = tid + q * NTHR;
+            int l = e >> 4, cc = e & 15;
+            double x = 0.0;
+            if (l < NC && vec0 + cc < k.N) {
+                double d;
+                int I = node_dof<P>(k, c, l, d);
+                if (I >= 0) x = d * k.X[(int64_t)I * k.ldx + vec0 + cc];
+            }
+            pre[q] = x;
+        }
+    };
+    auto store_x = [&](const double (&pre)[EPT]) {
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            int e = tid + q * NTHR;
+            if constexpr (PREC == 0) xs[e] = pre[q];
+            else if constexpr (PREC == 1) xs[e] = (float)pre[q];
+            else xs[(e & 15) * Bf16Stride<NCP>::value + (e >> 4)] = to_bf16_bits(pre[q]);
+        }
+    };
+    // emit one completed plane (local z index gzl) of the tile closure
+    auto emit_plane = [&](int gzl) {
+        const int slot = gzl % N1;
+        const int gz = c0z * P + gzl;
+        const int tzv = axis_free_index32(k.ax[2], P, gz);
+        const int zside = gzl == 0 ? 0 : (gzl == ncz * P ? 1 : -1);
+        for (int e = tid; e < CW * CW * 16; e += NTHR) {
+            const int cc = e & 15, node = e >> 4;
+            const int a = node % CW, b = node / CW;
+            double *rp = &ring[(slot * CW * CW + node) * 16 + cc];
+            if (a > ncx * P || b > ncy * P) continue;
+            const double acc = *rp;
+            *rp = 0.0;
+            const int64_t v = vec0 + cc;
+            if (tzv < 0 || v >= k.N) continue;
+            const int tx = axis_free_index32(k.ax[0], P, c0x * P + a);
+            const int ty = axis_free_index32(k.ax[1], P, c0y * P + b);
+            if (tx < 0 || ty < 0) continue;
+            // first writer among the tiles sharing this node?
+            bool first = true;
+            const int side[3] = {a == 0 ? 0 : (a == ncx * P ? 1 : -1), b == 0 ? 0 : (b == ncy * P ? 1 : -1), zside};
+            for (int ax = 0; ax < 3; ++ax) {
+                if (side[ax] < 0) continue;
+                int nb = tile_neighbour(tc[ax], tp.ntile[ax], k.ax[ax].bc, side[ax]);
+                if (nb >= 0 && tile_colour(nb, tp.ntile[ax], tp.tncol[ax]) <
+                                   tile_colour(tc[ax], tp.ntile[ax], tp.tncol[ax]))
+                    first = false;
+            }
+            const int I = tx + (int)k.nfx * (ty + (int)k.nfy * tzv);
+            const double d = k.axisD[tx] * k.axisD[k.maxf + ty] * k.axisD[2 * k.maxf + tzv];
+            double *y = k.Y + (int64_t)I * k.ldy + v;
+            const double contrib = k.alpha * d * acc;
+            if (first) {
+                double base = k.alpha * (k.v[I] - k.shift) * k.X[(int64_t)I * k.ldx + v];
+                if (k.Ym1) base -= k.beta * k.Ym1[(int64_t)I * k.ldm + v];
+                *y = base + contrib;
+            } else {
+                *y += contrib;
+            }
+        }
+    };
+
+    const int ncell_t = ncx * ncy * ncz;
+    {
+        double pre[EPT];
+        load_x(0, pre);
+        store_x(pre);
+    }
+    __syncthreads();
+    constexpr int GROUP = PREC == 2 ? 2 : 4;
+    for (int cell = 0; cell < ncell_t; ++cell) {
+        const bool has_next = cell + 1 < ncell_t;
+        double pre[EPT];
+        if (has_next) load_x(cell + 1, pre);
+
+        double acc[TPW][4];
+        if constexpr (PREC == 0) {
+            d4 c4[TPW];
+#pragma unroll
+            for (int tt = 0; tt < TPW; ++tt) c4[tt] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < NKS; ++s) {
+                double b = xs[(4 * s + (lane >> 4)) * 16 + col];
+#pragma unroll
+                for (int tt = 0; tt < TPW; ++tt)
+                    c4[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(kreg[tt][s], b, c4[tt], 0, 0, 0);
+                if ((s % GROUP) == GROUP - 1) __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int tt = 0; tt < TPW; ++tt)
+                for (int i = 0; i < 4; ++i) acc[tt][i] = c4[tt][i];
+        } else if constexpr (PREC == 1) {
+            f4 c4[TPW];
+#pragma unroll
+            for (int tt = 0; tt < TPW; ++tt) c4[tt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < NKS; ++s) {
+                float b = xs[(4 * s + (lane >> 4)) * 16 + col];
+#pragma unroll
+                for (int tt = 0; tt < TPW; ++tt)
+                    c4[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(kreg[tt][s], b, c4[tt], 0, 0, 0);
+                if ((s % GROUP) == GROUP - 1) __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int tt = 0; tt < TPW; ++tt)
+                for (int i = 0; i < 4; ++i) acc[tt][i] = (double)c4[tt][i];
+        } else {
+            f4 c4[TPW];
+#pragma unroll
+            for (int tt = 0; tt < TPW; ++tt) c4[tt] = f4{0.f, 0.f, 0.f, 0.f};
+            const uint16_t *xrow = xs + col * Bf16Stride<NCP>::value + 8 * (lane >> 4);
+#pragma unroll
+            for (int s = 0; s < NKS; ++s) {
+                bf8 b = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4 *>(xrow + 32 * s));
+#pragma unroll
+                for (int tt = 0; tt < TPW; ++tt)
+                    c4[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, kreg[tt][s]), b, c4[tt], 0,
+                                                                    0, 0);
+                if ((s % GROUP) == GROUP - 1) __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int tt = 0; tt < TPW; ++tt)
+                for (int i = 0; i < 4; ++i) acc[tt][i] = (double)c4[tt][i];
+        }
+
+        // accumulate the rows into the ring (cells in a fixed order)
+        const int cxl = cell % ncx, cyl = (cell / ncx) % ncy, lz = cell / (ncx * ncy);
+#pragma unroll
+        for (int tt = 0; tt < TPW; ++tt) {
+            const int t = wave + tt * W;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                int r = 16 * t + (PREC == 0 ? (lane >> 4) + 4 * i : 4 * (lane >> 4) + i);
+                if (r >= NC) continue;
+                int li = r % N1, lj = (r / N1) % N1, lk = r / (N1 * N1);
+                int slot = (lz * P + lk) % N1;
+                int node = (cyl * P + lj) * CW + cxl * P + li;
+                ring[(slot * CW * CW + node) * 16 + col] += acc[tt][i];
+            }
+        }
+        __syncthreads();  // products of this cell are in the ring; xs is free
+        if (has_next) store_x(pre);
+        const bool layer_done = (cell + 1) % (ncx * ncy) == 0;
+        if (layer_done) {
+            // planes lz*P .. lz*P + P-1 are complete (and the top plane after the last layer)
+            for (int kz = 0; kz < P; ++kz) emit_plane(lz * P + kz);
+            if (lz == ncz - 1) emit_plane(ncz * P);
+        }
+        __syncthreads();
+    }
+}
+
+template <int P, int PREC, int W, int TXY>
+static hipError_t launch_tile_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
+    TileParams tp;
+    tp.k = prm;
+    tp.tz = 8;
+    const int tl[3] = {TXY, TXY, tp.tz};
+    for (int a = 0; a < 3; ++a) {
+        tp.ntile[a] = (m->ncell[a] + tl[a] - 1) / tl[a];
+        // a periodic axis needs two tiles (a tile may not wrap onto itself)
+        if (m->bc[a] == FE_BC_PERIODIC && tp.ntile[a] < 2) return hipErrorNotSupported;
+        tp.tncol[a] = (m->bc[a] == FE_BC_PERIODIC && (tp.ntile[a] & 1)) ? 3 : (tp.ntile[a] >= 2 ? 2 : 1);
+    }
+    for (int c2 = 0; c2 < tp.tncol[2]; ++c2)
+        for (int c1 = 0; c1 < tp.tncol[1]; ++c1)
+            for (int c0 = 0; c0 < tp.tncol[0]; ++c0) {
+                int col[3] = {c0, c1, c2};
+                int64_t tiles = 1;
+                for (int a = 0; a < 3; ++a) {
+                    int cnt;
+                    if (col[a] == 2) cnt = 1;
+                    else {
+                        int limit = tp.tncol[a] == 3 ? tp.ntile[a] - 1 : tp.ntile[a];
+                        cnt = limit > col[a] ? (limit - col[a] + 1) / 2 : 0;
+                    }
+                    tp.tcol[a] = col[a];
+                    tp.tcnt[a] = cnt;
+                    tiles *= cnt;
+                }
+                if (tiles == 0) continue;
+                hipLaunchKernelGGL((step_tile_kernel<P, PREC, W, TXY>), dim3((unsigned)(tiles * prm.nchunk)),
+                                   dim3(64 * W), 0, s, tp);
+                hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+            }
+    return hipSuccess;
+}
+
 hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipStream_t s) {
     StepParams prm;
     prm.X = a.X; prm.ldx = a.ldx;
@@ -763,11 +1032,27 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
     }
     prm.nfx = m->nf[0];
     prm.nfy = m->nf[1];
+    if (m->kernel_variant == 5) {
+        hipError_t e = hipErrorNotSupported;
+        switch (m->p * 3 + (int)prec) {
+        case 3 * 3 + 0: e = launch_tile_p<3, 0, 4, 2>(prm, m, s); break;
+        case 4 * 3 + 0: e = launch_tile_p<4, 0, 8, 2>(prm, m, s); break;
+        case 3 * 3 + 1: e = launch_tile_p<3, 1, 4, 2>(prm, m, s); break;
+        case 4 * 3 + 1: e = launch_tile_p<4, 1, 8, 2>(prm, m, s); break;
+        case 5 * 3 + 1: e = launch_tile_p<5, 1, 14, 1>(prm, m, s); break;
+        case 3 * 3 + 2: e = launch_tile_p<3, 2, 4, 2>(prm, m, s); break;
+        case 4 * 3 + 2: e = launch_tile_p<4, 2, 8, 2>(prm, m, s); break;
+        case 5 * 3 + 2: e = launch_tile_p<5, 2, 14, 1>(prm, m, s); break;
+        default: break;
+        }
+        if (e != hipErrorNotSupported) return e;
+        // otherwise: the multi-chunk kernel below
+    }
     // variant 3/4: one cell x 2/4 chunks per workgroup; variant 0 picks the
     // multi-chunk kernel with the chunk count measured best for the precision
     // (bf16 with p >= 6 is fastest with one chunk per workgroup)
     if ((m->kernel_variant == 0 && !(prec == FE_BF16 && m->p >= 6)) || m->kernel_variant == 3 ||
-        m->kernel_variant == 4) {
+        m->kernel_variant == 4 || m->kernel_variant == 5) {
         const int G = m->kernel_variant == 4 ? 4 : m->kernel_variant == 3 ? 2 : (prec == FE_BF16 ? 4 : 2);
 #define FE_MC(PP)                                                                                   \
     case PP:                                                                                        \

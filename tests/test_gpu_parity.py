@@ -121,6 +121,39 @@ def test_kernel_variants_bitwise_equal(prec, p):
         assert torch.equal(Y0, Y1), var
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("shape,p", [((5, 4, 19), 4), ((4, 6, 9), 3), ((6, 4, 10), 5), ((3, 3, 4), 4)])
+def test_tile_kernel_matches_oracle_and_is_reproducible(prec, shape, p):
+    """Tile-accumulation variant: same operator, partial sums in a different
+    (fixed) order -- equal to the one-cell variant to rounding, bitwise
+    reproducible run to run; ragged and odd tile counts included."""
+    wl = W.small_slab(shape, p=p, N=20)
+    print("case:", dict(prec=prec, shape=shape, p=p), flush=True)
+    op, gm, _ = _setup(wl)
+    X = torch.from_numpy(wl.X(op.n)).cuda()
+    gm.set_kernel(1)
+    Y1 = gm.cheb_filter(X, 5, 2.0, 600.0, -0.5, prec=prec)
+    gm.set_kernel(5)
+    Y5 = gm.cheb_filter(X, 5, 2.0, 600.0, -0.5, prec=prec)
+    Y5b = gm.cheb_filter(X, 5, 2.0, 600.0, -0.5, prec=prec)
+    assert torch.equal(Y5, Y5b)
+    tile_applies = p in (3, 4) or (p == 5 and prec != "f64")
+    if tile_applies and prec == "f64":
+        # the tile path sums each node's contributions in another order; equal
+        # bits would mean the one-cell path ran instead
+        assert not torch.equal(Y5, Y1)
+    rel = ((Y5 - Y1).norm(dim=0) / Y1.norm(dim=0)).max().item()
+    assert rel < (1e-13 if prec == "f64" else 1e-6 if prec == "f32" else 1e-2), rel
+    if prec == "f64":
+        a0, b, _ = O.lanczos_bounds(op.apply, wl.lanczos_start(op.n), 10)
+        a = O.weyl_cut(a0, b, wl.N, op.n)
+        R = op.filter(wl.X(op.n), wl.m, a, b, a0)
+        Y = gm.cheb_filter(X, wl.m, a, b, a0).cpu().numpy()
+        assert _relerr(Y, R) < 1e-12
+        Yh = gm.hx(X).cpu().numpy()
+        assert _relerr(Yh, op.apply(wl.X(op.n))) < 1e-13
+
+
 def test_bitwise_reproducible():
     wl = W.small_slab((3, 3, 4), p=4, N=32)
     op, gm, _ = _setup(wl)
