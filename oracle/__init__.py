@@ -93,6 +93,9 @@ def lib():
         L.or_cheb_filter_vjp.argtypes = [C.POINTER(_CSR), C.c_void_p, C.c_void_p, _dp, _dp, C.c_int64,
                                          C.c_int, C.c_double, C.c_double, C.c_double, _dp, _dp]
         L.or_cheb_filter_vjp.restype = C.c_int
+        L.or_apply_rows.argtypes = [C.POINTER(_Mesh), C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_void_p,
+                                    _i64p, C.c_int64, _dp, C.c_int64, _dp]
+        L.or_apply_rows.restype = C.c_int
         L.or_potential_vjp.argtypes = [C.POINTER(_Mesh), _dp, C.c_double, _dp, C.POINTER(C.c_double)]
         L.or_num_threads.restype = C.c_int
         _lib = L
@@ -305,6 +308,28 @@ class Operator:
         Eb = C.c_double(0.0)
         lib().or_potential_vjp(C.byref(self.mesh._m), np.ascontiguousarray(g), self.z0, Vb, C.byref(Eb))
         return Vb.reshape(self.mesh.n_cells, self.mesh.nc), Eb.value
+
+
+def apply_rows(mesh: Mesh, Vq: Optional[np.ndarray], E: float, z0: float, rows, X: np.ndarray,
+               projectors: Optional[Projectors] = None, Dnl: Optional[np.ndarray] = None) -> np.ndarray:
+    """Rows `rows` of H~ X (nonlocal term included when given), summed row by
+    row from the cell contributions; X is the full (n x N) block."""
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    N = X.shape[1]
+    Yr = np.zeros((rows.size, N))
+    vq = None
+    if Vq is not None:
+        Vq = np.ascontiguousarray(Vq, dtype=np.float64).reshape(-1)
+        vq = Vq.ctypes.data
+    cp, dp = None, None
+    if projectors is not None:
+        Dnl = np.ascontiguousarray(Dnl, dtype=np.float64).reshape(-1)
+        cp, dp = C.cast(projectors._p, C.c_void_p), Dnl.ctypes.data
+    rc = lib().or_apply_rows(C.byref(mesh._m), vq, float(E), float(z0), cp, dp, rows, rows.size, X, N, Yr)
+    if rc != 0:
+        raise MemoryError("or_apply_rows failed")
+    return Yr
 
 
 def stiffness(mesh: Mesh):

@@ -338,12 +338,48 @@ static int axis_cells(const or_mesh *m, int a, int64_t g, int *cell, int *loc) {
 }
 
 /*
- * Assemble a global matrix from identical cell matrices, row by row:
- *   A_IJ = s_I s_J sum_{cells c containing I and J} (alpha Kc + diag(mass_c V_c))[l_c(I), l_c(J)]
+ * Entries of one row I of the global matrix assembled from identical cell
+ * matrices:
+ *   A_IJ = sum_{cells c containing I and J} (alpha Kc + diag(mass_c V_c))[l_c(I), l_c(J)]
+ * (before the M^-1/2 scaling), with V_total(x_q) = Vq[c][q] - E (z_q - z0)
+ * at the GLL points (Vq may be NULL).  Writes the column/value pairs of
+ * every contribution into buf (unsorted, duplicates kept) and returns their
+ * number.
+ */
+static int row_contributions(const or_mesh *m, int64_t I, const double *Kc, double alpha, int with_potential,
+                             const double *Vq, double E, double z0, const double *xi, const double *w, entry *buf) {
+    int p = m->p, n1 = p + 1, nc = n1 * n1 * n1;
+    int64_t nf0 = axis_free(m, 0), nf1 = axis_free(m, 1);
+    int64_t t[3] = {I % nf0, (I / nf0) % nf1, I / (nf0 * nf1)};
+    int cs[3][2], ls[3][2], nk[3];
+    for (int a = 0; a < 3; ++a) nk[a] = axis_cells(m, a, axis_node(m, a, t[a]), cs[a], ls[a]);
+    int ne = 0;
+    for (int az = 0; az < nk[2]; ++az)
+    for (int ay = 0; ay < nk[1]; ++ay)
+    for (int ax = 0; ax < nk[0]; ++ax) {
+        int cx = cs[0][ax], cy = cs[1][ay], cz = cs[2][az];
+        int l = ls[0][ax] + n1 * (ls[1][ay] + n1 * ls[2][az]);
+        int64_t cidx = cx + (int64_t)m->ncell[0] * (cy + (int64_t)m->ncell[1] * cz);
+        for (int lp = 0; lp < nc; ++lp) {
+            int64_t J = dof_of(m, cx, cy, cz, lp % n1, (lp / n1) % n1, lp / (n1 * n1));
+            if (J < 0) continue;
+            double v = alpha * Kc[(size_t)l * nc + lp];
+            if (with_potential && lp == l) {
+                double zq = node_coord(m, 2, cz, lp / (n1 * n1), xi);
+                double V = (Vq ? Vq[cidx * nc + l] : 0.0) - E * (zq - z0);
+                v += cell_mass(m, w, l) * V;
+            }
+            buf[ne].j = J; buf[ne].v = v; ++ne;
+        }
+    }
+    return ne;
+}
+
+/*
+ * Assemble a global matrix from identical cell matrices, row by row.
  * kind 0: A = K (stiffness, alpha = 1, no potential, s = 1);
  * kind 1: A = H~ = M^-1/2 (1/2 K + V) M^-1/2 with V the GLL-collocated
- *         potential matrix of V_total(x_q) = Vq[c][q] - E (z_q - z0)
- *         (Vq may be NULL for V_loc = 0), s_I = M_I^-1/2.
+ *         potential matrix of V_total, s_I = M_I^-1/2.
  * Dirichlet rows/columns are dropped.  Returns NULL on allocation failure.
  */
 or_csr *or_assemble(const or_mesh *m, int kind, const double *Vq, double E, double z0) {
@@ -358,7 +394,6 @@ or_csr *or_assemble(const or_mesh *m, int kind, const double *Vq, double E, doub
     or_cell_stiffness(p, m->rule, h, Kc);
     double alpha = (kind == 0) ? 1.0 : 0.5;
     int64_t n = or_n_free(m);
-    int64_t nf0 = axis_free(m, 0), nf1 = axis_free(m, 1);
     double *M = NULL;
     if (kind == 1) { M = malloc(sizeof(double) * n); or_mass(m, M); }
 
@@ -381,28 +416,7 @@ or_csr *or_assemble(const or_mesh *m, int kind, const double *Vq, double E, doub
             entry *buf = malloc(sizeof(entry) * maxent);
             #pragma omp for schedule(dynamic, 256)
             for (int64_t I = 0; I < n; ++I) {
-                int64_t t[3] = {I % nf0, (I / nf0) % nf1, I / (nf0 * nf1)};
-                int cs[3][2], ls[3][2], nk[3];
-                for (int a = 0; a < 3; ++a) nk[a] = axis_cells(m, a, axis_node(m, a, t[a]), cs[a], ls[a]);
-                int ne = 0;
-                for (int az = 0; az < nk[2]; ++az)
-                for (int ay = 0; ay < nk[1]; ++ay)
-                for (int ax = 0; ax < nk[0]; ++ax) {
-                    int cx = cs[0][ax], cy = cs[1][ay], cz = cs[2][az];
-                    int l = ls[0][ax] + n1 * (ls[1][ay] + n1 * ls[2][az]);
-                    int64_t cidx = cx + (int64_t)m->ncell[0] * (cy + (int64_t)m->ncell[1] * cz);
-                    for (int lp = 0; lp < nc; ++lp) {
-                        int64_t J = dof_of(m, cx, cy, cz, lp % n1, (lp / n1) % n1, lp / (n1 * n1));
-                        if (J < 0) continue;
-                        double v = alpha * Kc[(size_t)l * nc + lp];
-                        if (kind == 1 && lp == l) {
-                            double zq = node_coord(m, 2, cz, lp / (n1 * n1), xi);
-                            double V = (Vq ? Vq[cidx * nc + l] : 0.0) - E * (zq - z0);
-                            v += cell_mass(m, w, l) * V;
-                        }
-                        buf[ne].j = J; buf[ne].v = v; ++ne;
-                    }
-                }
+                int ne = row_contributions(m, I, Kc, alpha, kind == 1, Vq, E, z0, xi, w, buf);
                 qsort(buf, ne, sizeof(entry), entry_cmp);
                 int64_t len = 0;
                 int64_t base = pass ? A->rowptr[I] : 0;
@@ -581,6 +595,71 @@ static void op_apply(const or_op *op, const double *X, double *Y, int64_t N) {
 void or_apply(const or_csr *A, const or_csc *C, const double *Dnl, const double *X, double *Y, int64_t N) {
     or_op op = {A, C, Dnl};
     op_apply(&op, X, Y, N);
+}
+
+/*
+ * Selected rows of Y = H~ X (plus the nonlocal term when C != NULL), without
+ * assembling the whole matrix: each row is summed from its own cell
+ * contributions by the same definition as or_assemble (kind 1).  X is the
+ * full (n x N) block; Yr receives (nrows x N).  Used where the whole
+ * operator is too large to assemble in test time.
+ */
+int or_apply_rows(const or_mesh *m, const double *Vq, double E, double z0, const or_csc *C, const double *Dnl,
+                  const int64_t *rows, int64_t nrows, const double *X, int64_t N, double *Yr) {
+    int p = m->p, n1 = p + 1, nc = n1 * n1 * n1;
+    double xi[16], w[16];
+    or_gll(p, xi, w);
+    double h = m->L[0] / m->ncell[0];
+    double *Kc = malloc(sizeof(double) * nc * nc);
+    if (!Kc) return -2;
+    or_cell_stiffness(p, m->rule, h, Kc);
+    int64_t n = or_n_free(m);
+    double *M = malloc(sizeof(double) * n);
+    or_mass(m, M);
+    #pragma omp parallel
+    {
+        entry *buf = malloc(sizeof(entry) * 8 * nc);
+        #pragma omp for schedule(dynamic, 1)
+        for (int64_t r = 0; r < nrows; ++r) {
+            int64_t I = rows[r];
+            int ne = row_contributions(m, I, Kc, 0.5, 1, Vq, E, z0, xi, w, buf);
+            double *y = Yr + r * N;
+            for (int64_t j = 0; j < N; ++j) y[j] = 0.0;
+            for (int e = 0; e < ne; ++e) {
+                double a = buf[e].v / sqrt(M[I] * M[buf[e].j]);
+                const double *x = X + buf[e].j * N;
+                for (int64_t j = 0; j < N; ++j) y[j] += a * x[j];
+            }
+        }
+        free(buf);
+    }
+    if (C && C->nproj > 0) {
+        /* W = diag(D) C^T X over all projectors, then the selected rows of C W */
+        double *W = calloc(C->nproj * N, sizeof(double));
+        #pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t b = 0; b < C->nproj; ++b) {
+            for (int64_t e = C->colptr[b]; e < C->colptr[b + 1]; ++e)
+                for (int64_t j = 0; j < N; ++j) W[b * N + j] += C->val[e] * X[C->row[e] * N + j];
+            for (int64_t j = 0; j < N; ++j) W[b * N + j] *= Dnl[b];
+        }
+        #pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t r = 0; r < nrows; ++r) {
+            int64_t I = rows[r];
+            for (int64_t b = 0; b < C->nproj; ++b) {
+                /* the support of a projector is sorted: binary search for I */
+                int64_t lo = C->colptr[b], hi = C->colptr[b + 1];
+                while (lo < hi) {
+                    int64_t mid = (lo + hi) / 2;
+                    if (C->row[mid] < I) lo = mid + 1; else hi = mid;
+                }
+                if (lo < C->colptr[b + 1] && C->row[lo] == I)
+                    for (int64_t j = 0; j < N; ++j) Yr[r * N + j] += C->val[lo] * W[b * N + j];
+            }
+        }
+        free(W);
+    }
+    free(Kc); free(M);
+    return 0;
 }
 
 /*

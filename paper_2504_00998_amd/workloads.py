@@ -97,6 +97,18 @@ class Workload:
             out[:, t] = np.random.default_rng([self.seed(2), int(j)]).standard_normal(n)
         return out
 
+    def X_device(self, n: Optional[int] = None, N: Optional[int] = None, device="cuda"):
+        """Random block (n, N), i.i.d. N(0,1), drawn on the device by torch's
+        seeded generator (seed(2)).  Used where the host recipe `X` would be
+        too slow (tens of GB); every consumer of a given test receives this
+        same array."""
+        import torch
+        n = self.n_free() if n is None else n
+        N = self.N if N is None else N
+        g = torch.Generator(device=device)
+        g.manual_seed(self.seed(2))
+        return torch.randn((n, N), generator=g, dtype=torch.float64, device=device)
+
     def lanczos_start(self, n: Optional[int] = None) -> np.ndarray:
         n = self.n_free() if n is None else n
         return np.random.default_rng(self.seed(3)).standard_normal(n)

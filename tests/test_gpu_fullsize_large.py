@@ -1,0 +1,166 @@
+"""Full-size checks of the large configurations.
+
+* p=5 slab, 40x40x80 cells (15,960,000 DoFs), 512 well sites with nine
+  nonlocal projectors each, N = 384: H~X against the oracle on sampled rows
+  and columns (each row summed from its own cell contributions -- the
+  assembled operator is too large for test time), FP64 and FP32 cell
+  products; the FP32 degree-40 filter against FP64; the adjoint with
+  checkpoint recomputation and column chunks, checked by the closed form
+  dL/dX = 2 Y W, the chain-rule identity and central differences in E.
+* p=6 slab, 16x16x32 cells (1,760,256 DoFs), N = 128, degree 20: the
+  autograd loss at full size, checked the same way.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2504_00998_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def cfg5():
+    import paper_2504_00998_amd as fe
+    wl = W.CFG5
+    om = O.Mesh.from_workload(wl)
+    Vq = W.workload_potential(wl, om.quad_points())
+    cen, D = wl.centres(), wl.nonlocal_coupling()
+    gm = fe.Mesh.from_workload(wl)
+    gm.set_potential(torch.from_numpy(Vq).cuda(), wl.E, wl.z0)
+    gm.set_nonlocal(cen, D, wl.r_cut, wl.r_g)
+    print(f"cfg5: n={gm.n} sites={cen.shape[0]}", flush=True)
+    return wl, om, gm, Vq, cen, D
+
+
+def test_cfg5_hx_sampled_rows(cfg5):
+    wl, om, gm, Vq, cen, D = cfg5
+    X = wl.X_device(gm.n, wl.N)
+    rng = np.random.default_rng(51)
+    rows = np.unique(np.concatenate([rng.choice(gm.n, 48, replace=False),
+                                     np.arange(0, 5), np.arange(gm.n - 5, gm.n)]))
+    # rows inside nonlocal supports: DoFs nearest to a few site centres
+    xyz = gm.dof_coords()
+    for s in (0, 137, 511):
+        rows = np.append(rows, np.argmin(((xyz - cen[s]) ** 2).sum(1)))
+    rows = np.unique(rows)
+    cols = [0, 191, 383]
+    Xh = X[:, cols].cpu().numpy()
+    P = O.Projectors(om, cen, wl.r_cut, wl.r_g)
+    R = O.apply_rows(om, Vq, wl.E, wl.z0, rows, Xh, P, D.reshape(-1))
+    rt = torch.from_numpy(rows).cuda()
+    for prec, tol in (("f64", 1e-13), ("f32", 1e-5)):
+        Y = gm.hx(X, prec=prec)
+        Ys = Y[rt][:, cols].cpu().numpy()
+        del Y
+        err = (np.linalg.norm(Ys - R, axis=0) / np.linalg.norm(R, axis=0)).max()
+        print(f"cfg5 hx {prec}: rel err on {rows.size} rows x {len(cols)} cols = {err:.3e}", flush=True)
+        assert err < tol
+    del X
+    torch.cuda.empty_cache()
+
+
+def test_cfg5_filter_fp32_against_fp64(cfg5):
+    wl, om, gm, Vq, cen, D = cfg5
+    v0 = torch.from_numpy(wl.lanczos_start(gm.n)).cuda()
+    a0, b = gm.lanczos_bounds(v0, 10)
+    a = a0 + (b - a0) * (wl.N / gm.n) ** (2.0 / 3.0)
+    X = wl.X_device(gm.n, wl.N)
+    Y32 = gm.cheb_filter(X, wl.m, a, b, a0, prec="f32")
+    assert torch.isfinite(Y32).all()
+    sub = X[:, :32].contiguous()
+    del X
+    torch.cuda.empty_cache()
+    Y64 = gm.cheb_filter(sub, wl.m, a, b, a0, prec="f64")
+    rel = ((Y32[:, :32] - Y64).norm(dim=0) / Y64.norm(dim=0)).max().item()
+    print(f"cfg5 filter m={wl.m}: FP32 vs FP64 cell products, max per-vector rel diff {rel:.3e}", flush=True)
+    assert rel < 1e-4
+    del Y32, Y64, sub
+    torch.cuda.empty_cache()
+
+
+def test_cfg5_adjoint_with_recomputation(cfg5):
+    """96 columns of the cfg5 block (storing every recurrence block would take
+    41 x 12 GB), checkpoints every 7 steps, 32-column chunks."""
+    import paper_2504_00998_amd as fe
+    wl, om, gm, Vq, cen, D = cfg5
+    Nsub, stride, chunk = 96, 7, 32
+    v0 = torch.from_numpy(wl.lanczos_start(gm.n)).cuda()
+    a0, b = gm.lanczos_bounds(v0, 10)
+    a = a0 + (b - a0) * (wl.N / gm.n) ** (2.0 / 3.0)
+    X = wl.X_device(gm.n, wl.N)[:, :Nsub].contiguous()
+    torch.cuda.empty_cache()
+    w = torch.from_numpy(wl.weights()[:Nsub]).cuda()
+    G = X * w
+    need = gm.vjp_work_bytes(Nsub, wl.m, stride, chunk)
+    print(f"cfg5 vjp work {need / 2**30:.1f} GiB (store-all would need "
+          f"{gm.vjp_work_bytes(Nsub, wl.m, 1, 0) / 2**30:.0f} GiB)", flush=True)
+    Xb, Vb, Eb = gm.cheb_filter_vjp(X, G, wl.m, a, b, a0, prec="f64", ckpt_stride=stride, col_chunk=chunk)
+    del G
+    torch.cuda.empty_cache()
+    Y = gm.cheb_filter(X, wl.m, a, b, a0, prec="f64")
+    # dL/dX of L = sum_i w_i <x_i, T(H) x_i> is Xbar + Y W = 2 Y W
+    rel = ((Xb + Y * w - 2 * Y * w).norm(dim=0) / (2 * Y * w).norm(dim=0)).max().item()
+    print(f"cfg5 vjp closed form rel err {rel:.3e}", flush=True)
+    assert rel < 1e-10
+    del Y, Xb
+    torch.cuda.empty_cache()
+    zq = om.quad_points()[..., 2]
+    Vbh = Vb.cpu().numpy()
+    chain = -(Vbh * (zq - wl.z0)).sum()
+    assert abs(Eb.item() - chain) < 1e-9 * max(1.0, abs(chain))
+    # central difference of L in E
+    hs = 1e-6
+
+    def L(E):
+        gm.set_potential(torch.from_numpy(Vq).cuda(), E, wl.z0)
+        Yp = gm.cheb_filter(X, wl.m, a, b, a0, prec="f64")
+        val = (w * (X * Yp).sum(0)).sum().item()
+        del Yp
+        return val
+    fd = (L(wl.E + hs) - L(wl.E - hs)) / (2 * hs)
+    gm.set_potential(torch.from_numpy(Vq).cuda(), wl.E, wl.z0)
+    print(f"cfg5 dL/dE adjoint {Eb.item():.10e} central diff {fd:.10e}", flush=True)
+    assert abs(fd - Eb.item()) < 1e-6 * max(1.0, abs(Eb.item()))
+    del X
+    torch.cuda.empty_cache()
+
+
+def test_cfg4_autograd_fullsize():
+    import paper_2504_00998_amd as fe
+    wl = W.CFG4
+    gm = fe.Mesh.from_workload(wl)
+    Vq = W.workload_potential(wl, gm.quad_points())
+    gm.set_potential(torch.from_numpy(Vq).cuda(), wl.E, wl.z0)
+    v0 = torch.from_numpy(wl.lanczos_start(gm.n)).cuda()
+    a0, b = gm.lanczos_bounds(v0, 10)
+    a = a0 + (b - a0) * (wl.N / gm.n) ** (2.0 / 3.0)
+    X = torch.from_numpy(wl.X(gm.n)).cuda().requires_grad_(True)
+    V = torch.from_numpy(Vq).cuda().requires_grad_(True)
+    E = torch.tensor(wl.E, dtype=torch.float64, device="cuda", requires_grad=True)
+    w = torch.from_numpy(wl.weights()).cuda()
+
+    def loss(X, V, E):
+        Y = fe.cheb_filter(X, V, E, gm, wl.m, a, b, a0, z0=wl.z0)
+        return (w * (X * Y).sum(0)).sum(), Y
+
+    L, Y = loss(X, V, E)
+    L.backward()
+    rel = ((X.grad - 2 * Y.detach() * w).norm(dim=0) / (2 * Y.detach() * w).norm(dim=0)).max().item()
+    print(f"cfg4 dL/dX closed form rel err {rel:.3e}", flush=True)
+    assert rel < 1e-10
+    zq = O.Mesh.from_workload(wl).quad_points()[..., 2]
+    chain = -(V.grad.cpu().numpy() * (zq - wl.z0)).sum()
+    assert abs(E.grad.item() - chain) < 1e-9 * max(1.0, abs(chain))
+    hs = 1e-6
+    with torch.no_grad():
+        for t, (dX, dV, dE) in enumerate(wl.fd_directions(2, X.numel(), V.numel())):
+            dXt = torch.from_numpy(dX.reshape(X.shape)).cuda()
+            dVt = torch.from_numpy(dV.reshape(V.shape)).cuda()
+            Lp = loss(X + hs * dXt, V + hs * dVt, E + hs * dE)[0].item()
+            Lm = loss(X - hs * dXt, V - hs * dVt, E - hs * dE)[0].item()
+            fd = (Lp - Lm) / (2 * hs)
+            an = (X.grad * dXt).sum().item() + (V.grad * dVt).sum().item() + E.grad.item() * dE
+            print(f"cfg4 FD direction {t}: fd {fd:.12e} adjoint {an:.12e}", flush=True)
+            assert abs(fd - an) < 1e-6 * max(1.0, abs(an))

@@ -528,3 +528,20 @@ def test_separable_wells_equal_pointwise_sum():
         V1 = W.wells_potential(qp, wl.centres(), wl.depth, wl.sigma, wl.L, [b == 1 for b in wl.bc])
         V2 = W.workload_potential(wl, qp)
         assert np.abs(V1 - V2).max() < 1e-13
+
+
+def test_apply_rows_equals_assembled_operator():
+    """Rows summed one by one from their cell contributions equal the same
+    rows of the assembled CSR product (with and without the nonlocal term)."""
+    wl = W.small_slab((5, 5, 6), p=3, N=6, cfg=5)
+    m = O.Mesh.from_workload(wl)
+    Vq = W.workload_potential(wl, m.quad_points())
+    P = O.Projectors(m, wl.centres(), wl.r_cut, wl.r_g)
+    D = wl.nonlocal_coupling().reshape(-1)
+    X = wl.X(m.n)
+    rows = np.random.default_rng(2).choice(m.n, size=40, replace=False)
+    for proj in (None, P):
+        op = O.Operator(m, Vq, wl.E, wl.z0, proj, D if proj is not None else None)
+        full = op.apply(X)[rows]
+        part = O.apply_rows(m, Vq, wl.E, wl.z0, rows, X, proj, D if proj is not None else None)
+        np.testing.assert_allclose(part, full, rtol=1e-13, atol=1e-13 * np.abs(full).max())
