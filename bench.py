@@ -30,6 +30,14 @@ if ROOT not in sys.path:
 METRIC = "H·X GDoF·vec/s in Chebyshev filter, FP64 vs FP32/BF16 at ≤1e-7 Ha Ritz err"
 UNIT = "GDoF·vec/s"
 PEAK = {"f64": (78.6, "mfma"), "f32": (157.3, "mfma"), "bf16": (2500.0, "mfma")}  # TFLOP/s, dense MFMA
+# sustained MFMA rate measured on the box with a register-only loop
+MEASURED_PEAK = {"f64": 41.9, "f32": 136.2}
+# HBM bytes per colour launch of the default step kernel on the p=4 slab
+# (N=256), from FETCH_SIZE/WRITE_SIZE counters scaled by a plain copy of known
+# size; valid for this kernel build only
+COUNTED_TRAFFIC = {("slab-p4-24x24x48", 256, "f64"): (2.625e9, "step_mc_kernel<4,0,2>"),
+                   ("slab-p4-24x24x48", 256, "f32"): (2.631e9, "step_mc_kernel<4,1,2>"),
+                   ("slab-p4-24x24x48", 256, "bf16"): (2.670e9, "step_mc_kernel<4,2,4>")}
 
 
 def log(*a):
@@ -174,6 +182,7 @@ def main():
     launch_ms = (ms - t_pot) / launches
     achieved = flops_per_launch / (launch_ms * 1e-3) / 1e12
     peak, bound = PEAK[args.prec]
+    traffic = COUNTED_TRAFFIC.get((wl.name, N, args.prec))
     rec = {
         "metric": METRIC,
         "value": round(value, 4),
@@ -197,8 +206,12 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4),
-            "traffic": None,
-            "kernel": f"step_kernel<{wl.p},{ {'f64': 0, 'f32': 1, 'bf16': 2}[args.prec]}> (one colour pass)",
+            "traffic": traffic[0] if traffic else None,
+            "traffic_unit": "B per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "algorithmic_bytes_per_launch": 24.0 * n * N / ncol,
+            "kernel": (traffic[1] if traffic else f"step kernel p={wl.p} {args.prec}") + " (one colour pass)",
+            "measured_peak": MEASURED_PEAK.get(args.prec),
+            "frac_of_measured_peak": round(achieved / MEASURED_PEAK[args.prec], 4) if args.prec in MEASURED_PEAK else None,
             "flops_per_launch": flops_per_launch,
             "avg_launch_ms": round(launch_ms, 5),
             "launches_per_step": launches,
