@@ -91,6 +91,37 @@ fe_status ensure_scratch_dense(fe_mesh *m, size_t bytes) {
     return FE_OK;
 }
 
+// Rows per split-K slice of the tall-skinny products, and rows per block of
+// the in-place right multiplication.
+constexpr int64_t kSliceRows = 8192;
+constexpr int64_t kBlockRows = 65536;
+
+// out (N x N, column-major) = A^T B for row-major (n x N) blocks A, B with
+// leading dimension ld, i.e. Acm Bcm^T.  The long dimension n is split into
+// slices (strided-batched GEMM) whose partial products are summed in slice
+// order, so the result is deterministic.  part: scratch of
+// (n / kSliceRows + 1) * N * N doubles.
+static fe_status tsgram(rocblas_handle h, const double *A, const double *B, int64_t n, int64_t N, int64_t ld,
+                        double *part, double *out, hipStream_t s) {
+    int64_t nfull = n / kSliceRows, rem = n - nfull * kSliceRows;
+    double one = 1.0, zero = 0.0;
+    int Ni = (int)N, ldi = (int)ld, kb = (int)kSliceRows;
+    if (nfull > 0)
+        FE_BLAS(rocblas_dgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_transpose, Ni, Ni, kb, &one,
+                                              A, ldi, kSliceRows * ld, B, ldi, kSliceRows * ld, &zero, part, Ni, N * N,
+                                              (int)nfull),
+                "dgemm_strided_batched (gram)");
+    if (rem > 0)
+        FE_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, Ni, Ni, (int)rem, &one,
+                              A + nfull * kSliceRows * ld, ldi, B + nfull * kSliceRows * ld, ldi, &zero,
+                              part + nfull * N * N, Ni),
+                "dgemm (gram tail)");
+    FE_HIPD(launch_sum_partials(part, nfull + (rem > 0 ? 1 : 0), N * N, out, s), "sum partials");
+    return FE_OK;
+}
+
+static size_t tsgram_doubles(int64_t n, int64_t N) { return (size_t)(n / kSliceRows + 1) * N * N; }
+
 }  // namespace fe
 
 using namespace fe;
@@ -154,28 +185,38 @@ fe_status fe_cholqr2(fe_mesh *m, double *Y, int64_t N, int64_t ld, hipStream_t s
     if (N < 1 || ld < N) return fail(FE_EINVAL, "need N >= 1 and ld >= N");
     if (N > m->n) return fail(FE_EINVAL, "N exceeds the number of DoFs");
     int64_t n = m->n;
-    size_t need = (1024 + (size_t)N * N + 64) * sizeof(double);
+    int64_t nb = std::min(kBlockRows, n);
+    // scratch: [1024 reserved][S: N*N][partials][T: nb*N][info]
+    size_t need = (1024 + (size_t)N * N + tsgram_doubles(n, N) + (size_t)nb * N + 64) * sizeof(double);
     fe_status st = ensure_scratch_dense(m, need);
     if (st != FE_OK) return st;
-    double *S = m->d_scratch + 1024;
-    rocblas_int *info = reinterpret_cast<rocblas_int *>(S + (size_t)N * N);
+    double *S = m->d_scratch + 1024, *part = S + (size_t)N * N, *T = part + tsgram_doubles(n, N);
+    rocblas_int *info = reinterpret_cast<rocblas_int *>(T + (size_t)nb * N);
     rocblas_handle h;
     if ((st = handle(m, s, h)) != FE_OK) return st;
-    int Ni = (int)N, ni = (int)n, ldi = (int)ld;
+    int Ni = (int)N, ldi = (int)ld;
     for (int pass = 0; pass < 2; ++pass) {
-        // Y is row-major (n x N) = column-major (N x n) with leading dim ld: S = Y^T Y = Ycm Ycm^T
-        double one = 1.0, zero = 0.0;
-        FE_BLAS(rocblas_dsyrk(h, rocblas_fill_upper, rocblas_operation_none, Ni, ni, &one, Y, ldi, &zero, S, Ni),
-                "dsyrk");
+        // S = Y^T Y, S = U^T U (Cholesky), Y <- Y U^-1
+        if ((st = tsgram(h, Y, Y, n, N, ld, part, S, s)) != FE_OK) return st;
         FE_BLAS(rocsolver_dpotrf(h, rocblas_fill_upper, Ni, S, Ni, info), "dpotrf");
         rocblas_int hinfo = 0;
         FE_HIPD(hipMemcpyAsync(&hinfo, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, s), "copy info");
         FE_HIPD(hipStreamSynchronize(s), "sync");
         if (hinfo != 0) return fail(FE_EDEVICE, "Gram matrix not positive definite (potrf info " + std::to_string(hinfo) + ")");
-        // S = U^T U;  Q = Y U^-1  <=>  Qcm = U^-T Ycm
-        FE_BLAS(rocblas_dtrsm(h, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
-                              rocblas_diagonal_non_unit, Ni, ni, &one, S, Ni, Y, ldi),
-                "dtrsm");
+        FE_BLAS(rocsolver_dtrtri(h, rocblas_fill_upper, rocblas_diagonal_non_unit, Ni, S, Ni, info), "dtrtri");
+        FE_HIPD(launch_zero_lower(S, Ni, s), "zero lower");
+        double one = 1.0, zero = 0.0;
+        for (int64_t r0 = 0; r0 < n; r0 += nb) {
+            int64_t rows = std::min(nb, n - r0);
+            double *Yb = Y + r0 * ld;
+            FE_HIPD(hipMemcpy2DAsync(T, N * sizeof(double), Yb, ld * sizeof(double), N * sizeof(double), rows,
+                                     hipMemcpyDeviceToDevice, s),
+                    "stage block");
+            // (Y_b U^-1) in column-major form: Ycm_b = U^-T Tcm
+            FE_BLAS(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, Ni, (int)rows, Ni, &one, S,
+                                  Ni, T, Ni, &zero, Yb, ldi),
+                    "dgemm (Y U^-1)");
+        }
     }
     return FE_OK;
 }
@@ -189,20 +230,19 @@ fe_status fe_rayleigh_ritz(fe_mesh *m, const double *Q, double *X, double *P, in
     // P = H~ Q (FP64 cell products)
     StepArgs a{Q, ld, P, ld, nullptr, 0, 1.0, 0.0, 0.0, N};
     FE_HIPD(launch_step(m, a, FE_F64, s), "step kernel launch");
-    size_t need = (1024 + 2 * (size_t)N * N + 2 * (size_t)N + 64) * sizeof(double);
+    size_t need = (1024 + 2 * (size_t)N * N + 2 * (size_t)N + 64 + tsgram_doubles(n, N)) * sizeof(double);
     fe_status st = ensure_scratch_dense(m, need);
     if (st != FE_OK) return st;
     double *Hs = m->d_scratch + 1024, *Ht = Hs + (size_t)N * N, *d = Ht + (size_t)N * N, *e = d + N;
     rocblas_int *info = reinterpret_cast<rocblas_int *>(e + N);
+    double *part = reinterpret_cast<double *>(info + 128);
     if (m->nl.n_site > 0) FE_HIPD(launch_nonlocal(m, Q, ld, P, ld, N, 1.0, s), "nonlocal");
     rocblas_handle h;
     if ((st = handle(m, s, h)) != FE_OK) return st;
     int Ni = (int)N, ni = (int)n, ldi = (int)ld;
     double one = 1.0, zero = 0.0, half = 0.5;
-    // Hs = Q^T P  (column-major: Qcm Pcm^T), then symmetrise Hs = (Hs + Hs^T)/2
-    FE_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, Ni, Ni, ni, &one, Q, ldi, P, ldi,
-                          &zero, Hs, Ni),
-            "dgemm QtP");
+    // Hs = Q^T P (split-K over the DoFs), then symmetrise Hs = (Hs + Hs^T)/2
+    if ((st = tsgram(h, Q, P, n, N, ld, part, Hs, s)) != FE_OK) return st;
     FE_BLAS(rocblas_dgeam(h, rocblas_operation_none, rocblas_operation_transpose, Ni, Ni, &half, Hs, Ni, &half, Hs, Ni,
                           Ht, Ni),
             "dgeam");

@@ -122,6 +122,8 @@ void cheb_coefficients(int mdeg, double a, double b, double a0, std::vector<doub
                        double &c);
 fe_status validate_filter_args(fe_mesh *m, int64_t N, int32_t mdeg, double a, double b, double a0, fe_dtype prec);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
+hipError_t launch_sum_partials(const double *P, int64_t nb, int64_t len, double *S, hipStream_t s);
+hipError_t launch_zero_lower(double *A, int N, hipStream_t s);
 hipError_t launch_axpby(double *Y, int64_t ldy, const double *X, int64_t ldx, int64_t n, int64_t N, double a,
                         double b, hipStream_t s);
 hipError_t launch_nonlocal(fe_mesh *m, const double *X, int64_t ldx, double *Y, int64_t ldy, int64_t N,

@@ -812,7 +812,6 @@ __global__ __launch_bounds__(64 * W, (W <= 8 ? 4 : 1)) void step_tile_kernel(Til
     const int ncx = min(TXY, k.ax[0].ncell - c0x), ncy = min(TXY, k.ax[1].ncell - c0y);
     const int ncz = min(tp.tz, k.ax[2].ncell - c0z);
     const int64_t vec0 = (int64_t)chunk * 16;
-    const int64_t vec = vec0 + col;
 
     for (int e = tid; e < N1 * CW * CW * 16; e += NTHR) ring[e] = 0.0;
 
@@ -1297,6 +1296,35 @@ __global__ void fill_kernel(double *p, int64_t n, double v) {
 
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s) {
     hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+// S[i] = sum_b P[b * len + i] for i < len, b in order (deterministic reduction
+// of split-K partial products).
+__global__ void sum_partials_kernel(const double *P, int64_t nb, int64_t len, double *S) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= len) return;
+    double s = 0.0;
+    for (int64_t b = 0; b < nb; ++b) s += P[b * len + i];
+    S[i] = s;
+}
+
+hipError_t launch_sum_partials(const double *P, int64_t nb, int64_t len, double *S, hipStream_t s) {
+    hipLaunchKernelGGL(sum_partials_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, P, nb, len, S);
+    return hipGetLastError();
+}
+
+// Zero the strictly lower triangle of a column-major N x N matrix.
+__global__ void zero_lower_kernel(double *A, int N) {
+    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= (int64_t)N * N) return;
+    int col = (int)(e / N), row = (int)(e % N);
+    if (row > col) A[e] = 0.0;
+}
+
+hipError_t launch_zero_lower(double *A, int N, hipStream_t s) {
+    int64_t tot = (int64_t)N * N;
+    hipLaunchKernelGGL(zero_lower_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, A, N);
     return hipGetLastError();
 }
 
