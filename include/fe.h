@@ -91,14 +91,21 @@ fe_status fe_mesh_create(const fe_mesh_desc *desc, fe_mesh **out);
  * NULL is accepted. */
 fe_status fe_mesh_destroy(fe_mesh *mesh);
 
-/* Select the implementation of the step kernel (results are bitwise
- * identical across variants): 0 = the fastest measured for the degree and
- * precision (default); 1 = one cell x 16 vectors per workgroup, cell matrix
- * streamed from L2; 2 = persistent workgroups with the cell matrix resident
- * in registers (degrees/precisions where it fits, else 1); 3 / 4 = one cell
- * x 32 / 64 vectors per workgroup, so each cell-matrix fragment read from L2
- * feeds 2 / 4 products (falls back to 1 when the block would exceed the LDS).
- * FE_EINVAL for other values. */
+/* Select the implementation of the step kernel: 0 = the fastest measured
+ * for the degree and precision (default); 1 = one cell x 16 vectors per
+ * workgroup, cell matrix streamed from L2; 2 = persistent workgroups with the
+ * cell matrix resident in registers (degrees/precisions where it fits, else
+ * 1); 3 / 4 = one cell x 32 / 64 vectors per workgroup, so each cell-matrix
+ * fragment read from L2 feeds 2 / 4 products (falls back to 1 when the block
+ * would exceed the LDS); 5 = tiles of cells accumulated in LDS (p = 3, 4 and,
+ * below FP64, 5; else 3); 6 = FP64 row-owner kernel (each thread loads
+ * everything its outputs need in one round trip before the cell product;
+ * else 3); 7 = FP64 persistent pipelined row-owner kernel with the cell
+ * matrix in registers (p <= 4; else 6).  Variants 0-4, 6 and 7 give
+ * bitwise-identical results, except that in FP64 variant 2 multiplies with
+ * 16x16x4 MFMA blocks where the others use 4x4x4 blocks (equal to rounding);
+ * variant 5 sums each node's contributions in another fixed order (equal to
+ * rounding, reproducible).  FE_EINVAL for other values. */
 fe_status fe_mesh_set_kernel(fe_mesh *mesh, int32_t variant);
 
 /* Sizes: free DoFs n, cells, and points per cell n_c = (p+1)^3.  Any output

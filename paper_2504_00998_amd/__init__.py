@@ -141,7 +141,9 @@ class Mesh:
             pass
 
     def set_kernel(self, variant: int):
-        """0: fastest available step kernel; 1: generic one-cell-per-workgroup kernel."""
+        """Step-kernel implementation (``fe_mesh_set_kernel``): 0 = fastest
+        measured (default), 1 = one cell x 16 vectors per workgroup, 2-7 =
+        the alternatives declared in ``include/fe.h``."""
         _check(lib().fe_mesh_set_kernel(self._h, int(variant)))
 
     # ------------------------------------------------------------- geometry

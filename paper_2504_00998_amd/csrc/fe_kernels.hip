@@ -100,6 +100,37 @@ template <> struct PrecTraits<2> { typedef uint16_t T; static constexpr int KSTE
 // spread the 16 column reads of a fragment over the banks.
 template <int NCP> struct Bf16Stride { static constexpr int value = NCP + 8; };
 
+// FP64 cell product on v_mfma_f64_4x4x4f64 (four 4x4x4 blocks per wave).
+// Lane l of a block instruction carries A[4b + l%4][l/16] and B[l/16][l%4]
+// of block b = (l/4)%4 and returns D[l/16][l%4] of that block.  The blocks
+// are taken as the four 4-row groups of a 16-row tile of (1/2)K_c, so the A
+// operand is exactly the 16x16x4 fragment A[l%16][l/16].  The four blocks
+// share one 4-column slice of B; instruction q = 0..3 gives lane l the slice
+// of vectors {4j + q}, j = l%4, so lane l accumulates row 4((l/4)%4) + l/16
+// of the tile for the four consecutive vectors 4(l%4) .. 4(l%4)+3, read from
+// a row of 16 vectors in LDS as 32 contiguous bytes.
+__device__ __forceinline__ void f64_quad_b(const double *xs, int s, int lane, double b[4]) {
+    const double2 *p = reinterpret_cast<const double2 *>(xs + (4 * s + (lane >> 4)) * 16 + 4 * (lane & 3));
+    double2 u = p[0], v = p[1];
+    b[0] = u.x;
+    b[1] = u.y;
+    b[2] = v.x;
+    b[3] = v.y;
+}
+
+// Row (within the 16-row tile) and vector (within the 16-vector chunk) of
+// accumulator i of a lane: FP64 4x4x4 blocks as above; the FP32 and BF16
+// 16x16 shapes put row 4(l/16) + i, vector l%16.
+template <int PREC> __device__ __forceinline__ void acc_position(int lane, int i, int &r, int &cv) {
+    if constexpr (PREC == 0) {
+        r = 4 * ((lane >> 2) & 3) + (lane >> 4);
+        cv = 4 * (lane & 3) + i;
+    } else {
+        r = 4 * (lane >> 4) + i;
+        cv = lane & 15;
+    }
+}
+
 template <int P, int PREC>
 __global__ __launch_bounds__(256) void step_kernel(StepParams k) {
     constexpr int N1 = P + 1, NC = N1 * N1 * N1, NCP = (NC + 31) / 32 * 32, NT = NCP / 16;
@@ -166,19 +197,20 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams k) {
 
     const int wave = tid >> 6, lane = tid & 63;
     const int col = lane & 15;
-    const int64_t vec = vec0 + col;
     for (int t = wave; t < NT; t += 4) {
         double acc[4];
         if constexpr (PREC == 0) {
             const double *A = reinterpret_cast<const double *>(k.A) + (size_t)t * NKS * 64 + lane;
-            d4 c4 = {0.0, 0.0, 0.0, 0.0};
+            double c[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
             for (int s = 0; s < NKS; ++s) {
                 double a = A[s * 64];
-                double b = xs[(4 * s + (lane >> 4)) * 16 + col];
-                c4 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c4, 0, 0, 0);
+                double b[4];
+                f64_quad_b(xs, s, lane, b);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) c[q] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b[q], c[q], 0, 0, 0);
             }
-            for (int i = 0; i < 4; ++i) acc[i] = c4[i];
+            for (int i = 0; i < 4; ++i) acc[i] = c[i];
         } else if constexpr (PREC == 1) {
             const float *A = reinterpret_cast<const float *>(k.A) + (size_t)t * NKS * 64 + lane;
             f4 c4 = {0.f, 0.f, 0.f, 0.f};
@@ -203,12 +235,12 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams k) {
             }
             for (int i = 0; i < 4; ++i) acc[i] = (double)c4[i];
         }
-        if (vec >= k.N) continue;
         for (int i = 0; i < 4; ++i) {
-            // output row of accumulator i: f64 16x16x4 puts row (lane/16) + 4i
-            // in lane's slot i; the f32 and bf16 shapes put row 4(lane/16) + i.
-            int r = 16 * t + (PREC == 0 ? (lane >> 4) + 4 * i : 4 * (lane >> 4) + i);
-            if (r >= NC) continue;
+            int r, cv;
+            acc_position<PREC>(lane, i, r, cv);
+            r += 16 * t;
+            const int64_t vec = vec0 + cv;
+            if (r >= NC || vec >= k.N) continue;
             int64_t I = dof[r];
             if (I < 0) continue;
             double contrib = k.alpha * dsc[r] * acc[i];
@@ -265,19 +297,50 @@ __device__ __forceinline__ ItemCell item_cell(const StepParams &k, int64_t item)
 }
 
 // DoF and D scale of local node l of a cell (-1 / 0 when on a Dirichlet face).
+// The three per-axis factors are fetched unconditionally (clamped index), so
+// their loads are independent and in flight together.
 template <int P>
 __device__ __forceinline__ int node_dof(const StepParams &k, const ItemCell &c, int l, double &d) {
     constexpr int N1 = P + 1;
-    int li[3] = {l % N1, (l / N1) % N1, l / (N1 * N1)};
-    int cc[3] = {c.cx, c.cy, c.cz};
-    int t[3];
-    d = 1.0;
-    for (int a = 0; a < 3; ++a) {
-        t[a] = axis_free_index32(k.ax[a], P, cc[a] * P + li[a]);
-        if (t[a] < 0) { d = 0.0; return -1; }
-        d *= k.axisD[a * k.maxf + t[a]];
-    }
-    return t[0] + (int)k.nfx * (t[1] + (int)k.nfy * t[2]);
+    const int t0 = axis_free_index32(k.ax[0], P, c.cx * P + l % N1);
+    const int t1 = axis_free_index32(k.ax[1], P, c.cy * P + (l / N1) % N1);
+    const int t2 = axis_free_index32(k.ax[2], P, c.cz * P + l / (N1 * N1));
+    const bool ok = t0 >= 0 && t1 >= 0 && t2 >= 0;
+    const double d0 = k.axisD[max(t0, 0)];
+    const double d1 = k.axisD[k.maxf + max(t1, 0)];
+    const double d2 = k.axisD[2 * k.maxf + max(t2, 0)];
+    d = ok ? (d0 * d1) * d2 : 0.0;
+    return ok ? t0 + (int)k.nfx * (t1 + (int)k.nfy * t2) : -1;
+}
+
+// Branch-free form for any padded row r < NCP: DoF (-1 off the cell or on a
+// Dirichlet face) and the three per-axis D factors, loaded here but combined
+// only by node_scale, so that nothing waits on them before the caller's
+// other loads are in flight.
+struct NodeRef {
+    int I;
+    double f[3];
+};
+
+template <int P>
+__device__ __forceinline__ NodeRef node_ref(const StepParams &k, const ItemCell &c, int r) {
+    constexpr int N1 = P + 1, NC = N1 * N1 * N1;
+    const int l = min(r, NC - 1);
+    const int t0 = axis_free_index32(k.ax[0], P, c.cx * P + l % N1);
+    const int t1 = axis_free_index32(k.ax[1], P, c.cy * P + (l / N1) % N1);
+    const int t2 = axis_free_index32(k.ax[2], P, c.cz * P + l / (N1 * N1));
+    const bool ok = r < NC && t0 >= 0 && t1 >= 0 && t2 >= 0;
+    NodeRef n;
+    n.I = ok ? t0 + (int)k.nfx * (t1 + (int)k.nfy * t2) : -1;
+    n.f[0] = k.axisD[max(t0, 0)];
+    n.f[1] = k.axisD[k.maxf + max(t1, 0)];
+    n.f[2] = k.axisD[2 * k.maxf + max(t2, 0)];
+    return n;
+}
+
+// D factor of the node (same rounding as node_dof: (d0 d1) d2).
+__device__ __forceinline__ double node_scale(const NodeRef &n) {
+    return n.I >= 0 ? (n.f[0] * n.f[1]) * n.f[2] : 0.0;
 }
 
 template <int P>
@@ -627,22 +690,27 @@ __global__ __launch_bounds__(64 * McShape<P>::W) void step_mc_kernel(StepParams 
         const FragT *A = reinterpret_cast<const FragT *>(k.A) + (size_t)t * NKS * 64 + lane;
         double acc[G][4];
         if constexpr (PREC == 0) {
-            d4 c4[G];
+            double c[G][4];
 #pragma unroll
-            for (int g = 0; g < G; ++g) c4[g] = d4{0.0, 0.0, 0.0, 0.0};
+            for (int g = 0; g < G; ++g)
+                for (int q = 0; q < 4; ++q) c[g][q] = 0.0;
             // all A fragments of the row tile issued at once (one L2 round trip)
-#pragma unroll
+            // up to p = 5; in batches of 8 above that (register budget)
+            constexpr int UNR = NKS <= 40 ? NKS : 8;
+#pragma unroll UNR
             for (int s = 0; s < NKS; ++s) {
                 double a = A[s * 64];
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
-                    double b = xs[g * XS + (4 * s + (lane >> 4)) * 16 + col];
-                    c4[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c4[g], 0, 0, 0);
+                    double b[4];
+                    f64_quad_b(xs + g * XS, s, lane, b);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) c[g][q] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b[q], c[g][q], 0, 0, 0);
                 }
             }
 #pragma unroll
             for (int g = 0; g < G; ++g)
-                for (int i = 0; i < 4; ++i) acc[g][i] = c4[g][i];
+                for (int i = 0; i < 4; ++i) acc[g][i] = c[g][i];
         } else if constexpr (PREC == 1) {
             f4 c4[G];
 #pragma unroll
@@ -680,12 +748,13 @@ __global__ __launch_bounds__(64 * McShape<P>::W) void step_mc_kernel(StepParams 
 
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            const int64_t vec = vbase + g * 16 + col;
-            if (vec >= k.N) continue;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                int r = 16 * t + (PREC == 0 ? (lane >> 4) + 4 * i : 4 * (lane >> 4) + i);
-                if (r >= NC) continue;
+                int r, cv;
+                acc_position<PREC>(lane, i, r, cv);
+                r += 16 * t;
+                const int64_t vec = vbase + g * 16 + cv;
+                if (r >= NC || vec >= k.N) continue;
                 int I = dof[r];
                 if (I < 0) continue;
                 double contrib = k.alpha * dsc[r] * acc[g][i];
@@ -738,6 +807,399 @@ static hipError_t launch_mc_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
                 if (cells == 0) continue;
                 hipLaunchKernelGGL((step_mc_kernel<P, PREC, G>), dim3((unsigned)(cells * ngroups)), dim3(64 * W), smem,
                                    s, prm);
+                hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+            }
+    return hipSuccess;
+}
+
+// ------------------------------------------------------------------------
+// Row-owner variant (FP64): one cell x G chunks of 16 vectors per workgroup,
+// and each thread owns the outputs its 4x4x4 accumulators hold -- one row of
+// the cell (per row tile it covers) for four consecutive vectors per chunk.
+// Everything those outputs need from HBM (X for D X and the base term, the
+// previous iterate or the old Y, v) is loaded in one round trip at the start,
+// before the barrier; after the cell product each thread writes its outputs
+// without reading memory again.  Same arithmetic, in the same order, as the
+// other FP64 variants.
+template <int P, int TPW> struct RowShape {
+    static constexpr int NCP = ((P + 1) * (P + 1) * (P + 1) + 31) / 32 * 32, NT = NCP / 16, W = NT / TPW;
+    static_assert(NT % TPW == 0, "row tiles must divide evenly among waves");
+};
+// G chunks of 16 vectors per workgroup, TPW row tiles per wave, OCC waves
+// per SIMD the register allocation aims at, A fragments fetched in batches
+// of BK k-steps (0: one k-step at a time)
+template <int P, int G, int TPW, int OCC, int BK>
+__global__ __launch_bounds__((64 * RowShape<P, TPW>::W)) __attribute__((amdgpu_waves_per_eu(OCC)))
+void step_row_kernel(StepParams k) {
+    constexpr int N1 = P + 1, NC = N1 * N1 * N1, NCP = (NC + 31) / 32 * 32, NKS = NCP / 4;
+    constexpr int W = RowShape<P, TPW>::W, XS = NCP * 16;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *xs = reinterpret_cast<double *>(smem);  // [G][NCP][16], D X
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int ngroups = (k.nchunk + G - 1) / G;
+    const int grp = blockIdx.x % ngroups;
+    const ItemCell c = item_cell(k, (int64_t)(blockIdx.x / ngroups) * k.nchunk);
+    const int rl = 4 * ((lane >> 2) & 3) + (lane >> 4);            // row within a tile
+    const int64_t v0 = (int64_t)grp * G * 16 + 4 * (lane & 3);     // first vector of chunk 0
+
+    int I[TPW];
+    double d[TPW];
+    // per output: the first writer's base term alpha (v - c) X - beta Y_{k-1},
+    // or the Y already there.  All addresses first, then every load of the
+    // thread's rows as one straight run (unconditional, from clamped valid
+    // addresses, masked afterwards), then the consumers.
+    double bo[TPW][G][4];
+    NodeRef nr[TPW];
+    bool fst[TPW];
+#pragma unroll
+    for (int tt = 0; tt < TPW; ++tt) {
+        const int r = 16 * (wave + tt * W) + rl;
+        nr[tt] = node_ref<P>(k, c, r);
+        fst[tt] = r < NC && node_first<P>(k, c, r);
+    }
+    double xv[TPW][G][4], ov[TPW][G][4], vraw[TPW];
+#pragma unroll
+    for (int tt = 0; tt < TPW; ++tt) {
+        const int64_t Ic = max(nr[tt].I, 0);
+        const double *orow =
+            !fst[tt] ? k.Y + Ic * k.ldy : (k.Ym1 ? k.Ym1 + Ic * k.ldm : k.X + Ic * k.ldx);
+        const double *xrow = k.X + Ic * k.ldx;
+        vraw[tt] = k.v[Ic];
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t vc = min(v0 + 16 * g + q, k.N - 1);
+                xv[tt][g][q] = xrow[vc];
+                ov[tt][g][q] = orow[vc];
+            }
+    }
+#pragma unroll
+    for (int tt = 0; tt < TPW; ++tt) {
+        const int r = 16 * (wave + tt * W) + rl;
+        I[tt] = nr[tt].I;
+        const bool useo = !fst[tt] || k.Ym1 != nullptr;
+        const double vI = (nr[tt].I >= 0 && fst[tt]) ? vraw[tt] : 0.0;
+        const double sc = k.alpha * (vI - k.shift);
+        d[tt] = node_scale(nr[tt]);
+        double xm[G][4];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool ok = nr[tt].I >= 0 && v0 + 16 * g + q < k.N;
+                xm[g][q] = ok ? xv[tt][g][q] : 0.0;
+                const double o = (ok && useo) ? ov[tt][g][q] : 0.0;
+                double base = sc * xm[g][q];
+                if (k.Ym1) base -= k.beta * o;
+                bo[tt][g][q] = fst[tt] ? base : o;
+            }
+            double2 *dst = reinterpret_cast<double2 *>(xs + g * XS + r * 16 + 4 * (lane & 3));
+            dst[0] = double2{d[tt] * xm[g][0], d[tt] * xm[g][1]};
+            dst[1] = double2{d[tt] * xm[g][2], d[tt] * xm[g][3]};
+        }
+    }
+    __syncthreads();
+
+    // the wave's TPW row tiles share each B read from LDS
+    double acc[TPW][G][4];
+#pragma unroll
+    for (int tt = 0; tt < TPW; ++tt)
+        for (int g = 0; g < G; ++g)
+            for (int q = 0; q < 4; ++q) acc[tt][g][q] = 0.0;
+    {
+        const double *A = reinterpret_cast<const double *>(k.A) + (size_t)wave * NKS * 64 + lane;
+        constexpr size_t TS = (size_t)W * NKS * 64;  // fragment stride between the wave's tiles
+        // A fragments in batches of BK k-steps, batch j + 1 in flight while
+        // batch j is multiplied (loads complete in issue order, so a wait for
+        // batch j leaves the later batch outstanding)
+        constexpr int BKE = BK > 0 ? BK : 1, NB = NKS / BKE;
+        static_assert(NKS % BKE == 0, "k-steps must split into batches");
+        auto mul_step = [&](const double (&a)[TPW], int s) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                double b[4];
+                f64_quad_b(xs + g * XS, s, lane, b);
+#pragma unroll
+                for (int tt = 0; tt < TPW; ++tt)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        acc[tt][g][q] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[tt], b[q], acc[tt][g][q], 0, 0, 0);
+            }
+        };
+        if constexpr (BK == 0) {
+            constexpr int UNR = NKS <= 40 ? NKS : 8;
+#pragma unroll UNR
+            for (int s = 0; s < NKS; ++s) {
+                double a[TPW];
+#pragma unroll
+                for (int tt = 0; tt < TPW; ++tt) a[tt] = A[tt * TS + (size_t)s * 64];
+                mul_step(a, s);
+            }
+        } else {
+            auto load_batch = [&](double (&ab)[BKE][TPW], int sb) {
+#pragma unroll
+                for (int j = 0; j < BKE; ++j)
+#pragma unroll
+                    for (int tt = 0; tt < TPW; ++tt) ab[j][tt] = A[tt * TS + (size_t)(sb * BKE + j) * 64];
+            };
+            auto mul_batch = [&](const double (&ab)[BKE][TPW], int sb) {
+#pragma unroll
+                for (int j = 0; j < BKE; ++j) mul_step(ab[j], sb * BKE + j);
+            };
+            double ab0[BKE][TPW], ab1[BKE][TPW];
+            load_batch(ab0, 0);
+#pragma unroll(NB <= 8 ? NB : 1)
+            for (int sb = 0; sb < NB; sb += 2) {
+                if (sb + 1 < NB) load_batch(ab1, sb + 1);
+                mul_batch(ab0, sb);
+                if (sb + 1 < NB) {
+                    if (sb + 2 < NB) load_batch(ab0, sb + 2);
+                    mul_batch(ab1, sb + 1);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int tt = 0; tt < TPW; ++tt) {
+        if (I[tt] < 0) continue;
+        double *yrow = k.Y + (int64_t)I[tt] * k.ldy;
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t vec = v0 + 16 * g + q;
+                if (vec >= k.N) continue;
+                yrow[vec] = bo[tt][g][q] + k.alpha * d[tt] * acc[tt][g][q];
+            }
+    }
+}
+
+template <int P, int G, int TPW, int OCC, int BK>
+static hipError_t launch_row_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
+    constexpr int N1 = P + 1, NC = N1 * N1 * N1, NCP = (NC + 31) / 32 * 32, W = RowShape<P, TPW>::W;
+    const size_t smem = (size_t)G * NCP * 16 * sizeof(double);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step_row_kernel<P, G, TPW, OCC, BK>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int ngroups = (prm.nchunk + G - 1) / G;
+    for (int c2 = 0; c2 < m->ncol[2]; ++c2)
+        for (int c1 = 0; c1 < m->ncol[1]; ++c1)
+            for (int c0 = 0; c0 < m->ncol[0]; ++c0) {
+                int col[3] = {c0, c1, c2};
+                int64_t cells = 1;
+                for (int a = 0; a < 3; ++a) {
+                    const AxisInfo &ax = prm.ax[a];
+                    int cnt;
+                    if (col[a] == 2) cnt = 1;
+                    else {
+                        int limit = ax.ncol == 3 ? ax.ncell - 1 : ax.ncell;
+                        cnt = limit > col[a] ? (limit - col[a] + 1) / 2 : 0;
+                    }
+                    prm.col[a] = col[a];
+                    prm.cnt[a] = cnt;
+                    cells *= cnt;
+                }
+                if (cells == 0) continue;
+                hipLaunchKernelGGL((step_row_kernel<P, G, TPW, OCC, BK>), dim3((unsigned)(cells * ngroups)), dim3(64 * W), smem, s,
+                                   prm);
+                hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+            }
+    return hipSuccess;
+}
+
+// ------------------------------------------------------------------------
+// Pipelined row-owner variant (FP64, p <= 4): persistent workgroups walk the
+// items (cell, chunk of 16 vectors) of a colour with stride gridDim.x.  Each
+// wave owns two row tiles of (1/2)K_c, held in registers for the whole
+// launch, so one LDS read of B feeds eight 4x4x4 products; each thread owns
+// one row of each tile for four consecutive vectors.  While the cell product
+// of item i runs from one LDS buffer, the HBM loads of item i + gridDim.x
+// (X, the previous iterate or the old Y, v) are in flight into registers --
+// the product loop issues no vector-memory instruction, so nothing waits on
+// them -- and they are staged into the other buffer after item i's outputs
+// are written.  Same arithmetic, in the same order, as the other FP64
+// variants.
+template <int P> struct PipeShape {
+    static constexpr int NCP = ((P + 1) * (P + 1) * (P + 1) + 31) / 32 * 32, NT = NCP / 16;
+    static constexpr int TPW = 2, W = NT / TPW;
+};
+
+struct RowItem {
+    NodeRef n;
+    bool fst;
+    double vI;
+    double x[4], o[4];
+};
+
+template <int P>
+__device__ __forceinline__ void pipe_load(const StepParams &k, int64_t item, int wave, int lane, RowItem (&L)[2]) {
+    constexpr int N1 = P + 1, NC = N1 * N1 * N1, W = PipeShape<P>::W;
+    const ItemCell c = item_cell(k, item);
+    const int rl = 4 * ((lane >> 2) & 3) + (lane >> 4);
+    const int64_t v0 = (int64_t)c.chunk * 16 + 4 * (lane & 3);
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) {
+        const int r = 16 * (wave + tt * W) + rl;
+        L[tt].n = node_ref<P>(k, c, r);
+        const int I = L[tt].n.I;
+        L[tt].fst = r < NC && node_first<P>(k, c, r);
+        L[tt].vI = (I >= 0 && L[tt].fst) ? k.v[I] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t vec = v0 + q;
+            double x = 0.0, o = 0.0;
+            if (I >= 0 && vec < k.N) {
+                x = k.X[(int64_t)I * k.ldx + vec];
+                if (!L[tt].fst) o = k.Y[(int64_t)I * k.ldy + vec];
+                else if (k.Ym1) o = k.Ym1[(int64_t)I * k.ldm + vec];
+            }
+            L[tt].x[q] = x;
+            L[tt].o[q] = o;
+        }
+    }
+}
+
+// D X of the item into an LDS buffer; the first writer's base term (or the
+// old Y) into bo; the row's DoF and D factor kept for the epilogue.
+template <int P>
+__device__ __forceinline__ void pipe_stage(const StepParams &k, const RowItem (&L)[2], double *xs, int wave, int lane,
+                                           double (&bo)[2][4], int (&I)[2], double (&d)[2]) {
+    constexpr int W = PipeShape<P>::W;
+    const int rl = 4 * ((lane >> 2) & 3) + (lane >> 4);
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) {
+        const int r = 16 * (wave + tt * W) + rl;
+        const double sc = k.alpha * (L[tt].vI - k.shift);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            double base = sc * L[tt].x[q];
+            if (k.Ym1) base -= k.beta * L[tt].o[q];
+            bo[tt][q] = L[tt].fst ? base : L[tt].o[q];
+        }
+        const double dn = node_scale(L[tt].n);
+        double2 *dst = reinterpret_cast<double2 *>(xs + r * 16 + 4 * (lane & 3));
+        dst[0] = double2{dn * L[tt].x[0], dn * L[tt].x[1]};
+        dst[1] = double2{dn * L[tt].x[2], dn * L[tt].x[3]};
+        I[tt] = L[tt].n.I;
+        d[tt] = dn;
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(64 * PipeShape<P>::W) void step_pipe_kernel(StepParams k, int64_t nitems) {
+    constexpr int NCP = PipeShape<P>::NCP, NKS = NCP / 4, W = PipeShape<P>::W;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *xbuf = reinterpret_cast<double *>(smem);  // [2][NCP][16]
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    int64_t item = blockIdx.x;
+    if (item >= nitems) return;  // whole workgroup
+    RowItem L[2];
+    double bo[2][4], d[2];
+    int I[2];
+    pipe_load<P>(k, item, wave, lane, L);
+    pipe_stage<P>(k, L, xbuf, wave, lane, bo, I, d);
+    __syncthreads();
+    int cur = 0;
+    double ar[2][NKS];  // fragments of row tiles wave and wave + W
+    {
+        const double *A0 = reinterpret_cast<const double *>(k.A) + (size_t)wave * NKS * 64 + lane;
+        const double *A1 = A0 + (size_t)W * NKS * 64;
+#pragma unroll
+        for (int s = 0; s < NKS; ++s) {
+            ar[0][s] = A0[s * 64];
+            ar[1][s] = A1[s * 64];
+        }
+    }
+    for (;;) {
+        const int64_t next = item + gridDim.x;
+        const bool more = next < nitems;  // uniform over the workgroup
+        if (more) pipe_load<P>(k, next, wave, lane, L);
+
+        const double *xs = xbuf + cur * NCP * 16;
+        double acc[2][4];
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt)
+            for (int q = 0; q < 4; ++q) acc[tt][q] = 0.0;
+#pragma unroll
+        for (int s = 0; s < NKS; ++s) {
+            double b[4];
+            f64_quad_b(xs, s, lane, b);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                acc[0][q] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[0][s], b[q], acc[0][q], 0, 0, 0);
+                acc[1][q] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[1][s], b[q], acc[1][q], 0, 0, 0);
+            }
+        }
+        const int64_t v0 = (int64_t)(item % k.nchunk) * 16 + 4 * (lane & 3);
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+            if (I[tt] < 0) continue;
+            double *yrow = k.Y + (int64_t)I[tt] * k.ldy;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t vec = v0 + q;
+                if (vec < k.N) yrow[vec] = bo[tt][q] + k.alpha * d[tt] * acc[tt][q];
+            }
+        }
+        if (!more) break;
+        cur ^= 1;
+        pipe_stage<P>(k, L, xbuf + cur * NCP * 16, wave, lane, bo, I, d);
+        __syncthreads();
+        item = next;
+    }
+}
+
+template <int P>
+static hipError_t launch_pipe_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
+    constexpr int NCP = PipeShape<P>::NCP, W = PipeShape<P>::W;
+    const size_t smem = (size_t)2 * NCP * 16 * sizeof(double);
+    static bool attr = false;
+    static int resident = 0;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step_pipe_kernel<P>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        if (e != hipSuccess) return e;
+        int per_cu = 0, dev = 0, cus = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&step_pipe_kernel<P>),
+                                                         64 * W, smem);
+        if (e != hipSuccess) return e;
+        e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        resident = std::max(1, per_cu) * std::max(1, cus);
+        attr = true;
+    }
+    for (int c2 = 0; c2 < m->ncol[2]; ++c2)
+        for (int c1 = 0; c1 < m->ncol[1]; ++c1)
+            for (int c0 = 0; c0 < m->ncol[0]; ++c0) {
+                int col[3] = {c0, c1, c2};
+                int64_t cells = 1;
+                for (int a = 0; a < 3; ++a) {
+                    const AxisInfo &ax = prm.ax[a];
+                    int cnt;
+                    if (col[a] == 2) cnt = 1;
+                    else {
+                        int limit = ax.ncol == 3 ? ax.ncell - 1 : ax.ncell;
+                        cnt = limit > col[a] ? (limit - col[a] + 1) / 2 : 0;
+                    }
+                    prm.col[a] = col[a];
+                    prm.cnt[a] = cnt;
+                    cells *= cnt;
+                }
+                if (cells == 0) continue;
+                const int64_t nitems = cells * prm.nchunk;
+                const int64_t grid = std::min<int64_t>(nitems, resident);
+                hipLaunchKernelGGL((step_pipe_kernel<P>), dim3((unsigned)grid), dim3(64 * W), smem, s, prm, nitems);
                 hipError_t e = hipGetLastError();
                 if (e != hipSuccess) return e;
             }
@@ -1047,11 +1509,35 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
         if (e != hipErrorNotSupported) return e;
         // otherwise: the multi-chunk kernel below
     }
+    if (m->kernel_variant == 7 && prec == FE_F64) {
+        switch (m->p) {
+        case 1: return launch_pipe_p<1>(prm, m, s);
+        case 2: return launch_pipe_p<2>(prm, m, s);
+        case 3: return launch_pipe_p<3>(prm, m, s);
+        case 4: return launch_pipe_p<4>(prm, m, s);
+        default: break;
+        }
+    }
+    if ((m->kernel_variant == 0 || m->kernel_variant == 6 || m->kernel_variant == 7) && prec == FE_F64) {
+        switch (m->p) {
+        // 32 vectors per workgroup and one row tile per wave measured best
+        // where the tiles fit one workgroup (p <= 5); above that two tiles
+        // per wave keep the workgroup within 1024 threads
+        case 1: return launch_row_p<1, 2, 1, 5, 4>(prm, m, s);
+        case 2: return launch_row_p<2, 2, 1, 5, 4>(prm, m, s);
+        case 3: return launch_row_p<3, 2, 1, 5, 4>(prm, m, s);
+        case 4: return launch_row_p<4, 2, 1, 5, 4>(prm, m, s);
+        case 5: return launch_row_p<5, 2, 1, 5, 4>(prm, m, s);
+        case 6: return launch_row_p<6, 1, 2, 5, 2>(prm, m, s);
+        case 7: return launch_row_p<7, 1, 2, 5, 2>(prm, m, s);
+        default: break;
+        }
+    }
     // variant 3/4: one cell x 2/4 chunks per workgroup; variant 0 picks the
     // multi-chunk kernel with the chunk count measured best for the precision
     // (bf16 with p >= 6 is fastest with one chunk per workgroup)
     if ((m->kernel_variant == 0 && !(prec == FE_BF16 && m->p >= 6)) || m->kernel_variant == 3 ||
-        m->kernel_variant == 4 || m->kernel_variant == 5) {
+        m->kernel_variant == 4 || m->kernel_variant >= 5) {
         const int G = m->kernel_variant == 4 ? 4 : m->kernel_variant == 3 ? 2 : (prec == FE_BF16 ? 4 : 2);
 #define FE_MC(PP)                                                                                   \
     case PP:                                                                                        \

@@ -108,17 +108,23 @@ def test_filter_degrees_and_leading_dimension(m):
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("p", [2, 4, 5])
 def test_kernel_variants_bitwise_equal(prec, p):
-    """The register-resident persistent kernel and the one-cell-per-workgroup
-    kernel perform the same operations in the same order."""
+    """The multi-vector kernels and the one-cell-per-workgroup kernel perform
+    the same operations in the same order.  In FP64 the register-resident
+    persistent kernel (variant 2) issues 16x16x4 MFMA blocks where the others
+    issue 4x4x4 blocks; it agrees with them to rounding."""
     wl = W.small_slab((3, 3, 4), p=p, N=40)
     op, gm, _ = _setup(wl)
     X = torch.from_numpy(wl.X(op.n)).cuda()
     gm.set_kernel(1)
     Y1 = gm.cheb_filter(X, 5, 2.0, 400.0, -0.5, prec=prec)
-    for var in (0, 2, 3, 4):
+    for var in (0, 2, 3, 4, 6, 7):
         gm.set_kernel(var)
         Y0 = gm.cheb_filter(X, 5, 2.0, 400.0, -0.5, prec=prec)
-        assert torch.equal(Y0, Y1), var
+        if var == 2 and prec == "f64":
+            rel = ((Y0 - Y1).norm(dim=0) / Y1.norm(dim=0)).max().item()
+            assert rel < 1e-13, rel
+        else:
+            assert torch.equal(Y0, Y1), var
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
