@@ -30,12 +30,14 @@ if ROOT not in sys.path:
 METRIC = "H·X GDoF·vec/s in Chebyshev filter, FP64 vs FP32/BF16 at ≤1e-7 Ha Ritz err"
 UNIT = "GDoF·vec/s"
 PEAK = {"f64": (78.6, "mfma"), "f32": (157.3, "mfma"), "bf16": (2500.0, "mfma")}  # TFLOP/s, dense MFMA
-# sustained MFMA rate measured on the box with a register-only loop
-MEASURED_PEAK = {"f64": 41.9, "f32": 136.2}
+# sustained rate of the instruction each default step kernel multiplies with,
+# measured on the box with a register-only loop (FP64: 4x4x4 blocks, FP32:
+# 16x16x4); see paper_2504_00998_amd/microbench/mfma_rate.hip
+MEASURED_PEAK = {"f64": 74.2, "f32": 155.0}
 # HBM bytes per colour launch of the default step kernel on the p=4 slab
 # (N=256), from FETCH_SIZE/WRITE_SIZE counters scaled by a plain copy of known
 # size; valid for this kernel build only
-COUNTED_TRAFFIC = {("slab-p4-24x24x48", 256, "f64"): (2.625e9, "step_mc_kernel<4,0,2>"),
+COUNTED_TRAFFIC = {("slab-p4-24x24x48", 256, "f64"): (2.228e9, "step_row_kernel<4,2,1,5,4>"),
                    ("slab-p4-24x24x48", 256, "f32"): (2.631e9, "step_mc_kernel<4,1,2>"),
                    ("slab-p4-24x24x48", 256, "bf16"): (2.670e9, "step_mc_kernel<4,2,4>")}
 

@@ -98,10 +98,10 @@ fe_status fe_mesh_destroy(fe_mesh *mesh);
  * 1); 3 / 4 = one cell x 32 / 64 vectors per workgroup, so each cell-matrix
  * fragment read from L2 feeds 2 / 4 products (falls back to 1 when the block
  * would exceed the LDS); 5 = tiles of cells accumulated in LDS (p = 3, 4 and,
- * below FP64, 5; else 3); 6 = FP64 row-owner kernel (each thread loads
+ * below FP64, 5; else 3); 6 = row-owner kernel (each thread loads
  * everything its outputs need in one round trip before the cell product;
- * else 3); 7 = FP64 persistent pipelined row-owner kernel with the cell
- * matrix in registers (p <= 4; else 6).  Variants 0-4, 6 and 7 give
+ * the FP64 default); 7 = FP64 persistent pipelined row-owner kernel with the
+ * cell matrix in registers (p <= 4; else 6; below FP64, 3).  Variants 0-4, 6 and 7 give
  * bitwise-identical results, except that in FP64 variant 2 multiplies with
  * 16x16x4 MFMA blocks where the others use 4x4x4 blocks (equal to rounding);
  * variant 5 sums each node's contributions in another fixed order (equal to

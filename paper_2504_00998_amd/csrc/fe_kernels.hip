@@ -1016,6 +1016,171 @@ static hipError_t launch_row_p(StepParams prm, const fe_mesh *m, hipStream_t s) 
 }
 
 // ------------------------------------------------------------------------
+// Row-owner variant for the FP32 / BF16 cell products (16x16 MFMA shapes):
+// each lane's accumulator i holds row 4(l/16) + i of its tile for vector l%16
+// of a chunk, so each thread owns four consecutive cell rows for one vector
+// per chunk.  As in the FP64 row-owner kernel, every HBM load those outputs
+// need is issued in one round trip before the barrier, D X is staged in LDS
+// rounded to the product precision, and Y is written without re-reading it.
+// Same arithmetic, in the same order, as the other variants of the precision.
+template <int P, int PREC, int G, int OCC>
+__global__ __launch_bounds__(64 * McShape<P>::W) __attribute__((amdgpu_waves_per_eu(OCC)))
+void step_row16_kernel(StepParams k) {
+    constexpr int N1 = P + 1, NC = N1 * N1 * N1, NCP = (NC + 31) / 32 * 32;
+    constexpr int KSTEP = PrecTraits<PREC>::KSTEP, NKS = NCP / KSTEP;
+    constexpr int TPW = McShape<P>::TPW, W = McShape<P>::W;
+    typedef typename PrecTraits<PREC>::T T;
+    typedef typename FragOf<PREC>::T FragT;
+    constexpr int XS = PREC == 2 ? 16 * Bf16Stride<NCP>::value : NCP * 16;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *xs = reinterpret_cast<T *>(smem);  // [G][XS]
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15;
+    const int ngroups = (k.nchunk + G - 1) / G;
+    const int grp = blockIdx.x % ngroups;
+    const ItemCell c = item_cell(k, (int64_t)(blockIdx.x / ngroups) * k.nchunk);
+    const int64_t v0 = (int64_t)grp * G * 16 + col;
+
+    constexpr int R = TPW * 4;  // rows owned by the thread
+    NodeRef nr[R];
+    bool fst[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int r = 16 * (wave + (j / 4) * W) + 4 * (lane >> 4) + (j % 4);
+        nr[j] = node_ref<P>(k, c, r);
+        fst[j] = r < NC && node_first<P>(k, c, r);
+    }
+    double xv[R][G], ov[R][G], vraw[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int64_t Ic = max(nr[j].I, 0);
+        const double *orow = !fst[j] ? k.Y + Ic * k.ldy : (k.Ym1 ? k.Ym1 + Ic * k.ldm : k.X + Ic * k.ldx);
+        const double *xrow = k.X + Ic * k.ldx;
+        vraw[j] = k.v[Ic];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int64_t vc = min(v0 + 16 * g, k.N - 1);
+            xv[j][g] = xrow[vc];
+            ov[j][g] = orow[vc];
+        }
+    }
+    double bo[R][G], d[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int r = 16 * (wave + (j / 4) * W) + 4 * (lane >> 4) + (j % 4);
+        const bool useo = !fst[j] || k.Ym1 != nullptr;
+        const double vI = (nr[j].I >= 0 && fst[j]) ? vraw[j] : 0.0;
+        const double sc = k.alpha * (vI - k.shift);
+        d[j] = node_scale(nr[j]);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const bool ok = nr[j].I >= 0 && v0 + 16 * g < k.N;
+            const double x = ok ? xv[j][g] : 0.0;
+            const double o = (ok && useo) ? ov[j][g] : 0.0;
+            double base = sc * x;
+            if (k.Ym1) base -= k.beta * o;
+            bo[j][g] = fst[j] ? base : o;
+            const double dx = d[j] * x;
+            if constexpr (PREC == 1) xs[g * XS + r * 16 + col] = (float)dx;
+            else xs[g * XS + col * Bf16Stride<NCP>::value + r] = to_bf16_bits(dx);
+        }
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int tt = 0; tt < TPW; ++tt) {
+        const int t = wave + tt * W;
+        const FragT *A = reinterpret_cast<const FragT *>(k.A) + (size_t)t * NKS * 64 + lane;
+        double acc[G][4];
+        if constexpr (PREC == 1) {
+            f4 c4[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) c4[g] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 8
+            for (int s = 0; s < NKS; ++s) {
+                float a = A[s * 64];
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    float b = xs[g * XS + (4 * s + (lane >> 4)) * 16 + col];
+                    c4[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c4[g], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                for (int i = 0; i < 4; ++i) acc[g][i] = (double)c4[g][i];
+        } else {
+            f4 c4[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) c4[g] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+            for (int s = 0; s < NKS; ++s) {
+                bf8 a = __builtin_bit_cast(bf8, A[s * 64]);
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const uint16_t *xrow = xs + g * XS + col * Bf16Stride<NCP>::value + 8 * (lane >> 4);
+                    bf8 b = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4 *>(xrow + 32 * s));
+                    c4[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c4[g], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                for (int i = 0; i < 4; ++i) acc[g][i] = (double)c4[g][i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int j = tt * 4 + i;
+            if (nr[j].I < 0) continue;
+            double *yrow = k.Y + (int64_t)nr[j].I * k.ldy;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int64_t vec = v0 + 16 * g;
+                if (vec < k.N) yrow[vec] = bo[j][g] + k.alpha * d[j] * acc[g][i];
+            }
+        }
+    }
+}
+
+template <int P, int PREC, int G, int OCC>
+static hipError_t launch_row16_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
+    constexpr int N1 = P + 1, NC = N1 * N1 * N1, NCP = (NC + 31) / 32 * 32, W = McShape<P>::W;
+    typedef typename PrecTraits<PREC>::T T;
+    constexpr int XS = PREC == 2 ? 16 * Bf16Stride<NCP>::value : NCP * 16;
+    const size_t smem = ((size_t)G * XS * sizeof(T) + 15) / 16 * 16;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step_row16_kernel<P, PREC, G, OCC>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int ngroups = (prm.nchunk + G - 1) / G;
+    for (int c2 = 0; c2 < m->ncol[2]; ++c2)
+        for (int c1 = 0; c1 < m->ncol[1]; ++c1)
+            for (int c0 = 0; c0 < m->ncol[0]; ++c0) {
+                int col[3] = {c0, c1, c2};
+                int64_t cells = 1;
+                for (int a = 0; a < 3; ++a) {
+                    const AxisInfo &ax = prm.ax[a];
+                    int cnt;
+                    if (col[a] == 2) cnt = 1;
+                    else {
+                        int limit = ax.ncol == 3 ? ax.ncell - 1 : ax.ncell;
+                        cnt = limit > col[a] ? (limit - col[a] + 1) / 2 : 0;
+                    }
+                    prm.col[a] = col[a];
+                    prm.cnt[a] = cnt;
+                    cells *= cnt;
+                }
+                if (cells == 0) continue;
+                hipLaunchKernelGGL((step_row16_kernel<P, PREC, G, OCC>), dim3((unsigned)(cells * ngroups)),
+                                   dim3(64 * W), smem, s, prm);
+                hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+            }
+    return hipSuccess;
+}
+
+// ------------------------------------------------------------------------
 // Pipelined row-owner variant (FP64, p <= 4): persistent workgroups walk the
 // items (cell, chunk of 16 vectors) of a colour with stride gridDim.x.  Each
 // wave owns two row tiles of (1/2)K_c, held in registers for the whole
@@ -1515,6 +1680,19 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
         case 2: return launch_pipe_p<2>(prm, m, s);
         case 3: return launch_pipe_p<3>(prm, m, s);
         case 4: return launch_pipe_p<4>(prm, m, s);
+        default: break;
+        }
+    }
+    if (m->kernel_variant == 6 && prec != FE_F64) {
+        const bool f32 = prec == FE_F32;
+        switch (m->p) {
+        case 1: return f32 ? launch_row16_p<1, 1, 2, 6>(prm, m, s) : launch_row16_p<1, 2, 2, 6>(prm, m, s);
+        case 2: return f32 ? launch_row16_p<2, 1, 2, 6>(prm, m, s) : launch_row16_p<2, 2, 2, 6>(prm, m, s);
+        case 3: return f32 ? launch_row16_p<3, 1, 2, 6>(prm, m, s) : launch_row16_p<3, 2, 2, 6>(prm, m, s);
+        case 4: return f32 ? launch_row16_p<4, 1, 2, 6>(prm, m, s) : launch_row16_p<4, 2, 2, 6>(prm, m, s);
+        case 5: return f32 ? launch_row16_p<5, 1, 2, 6>(prm, m, s) : launch_row16_p<5, 2, 2, 6>(prm, m, s);
+        case 6: return f32 ? launch_row16_p<6, 1, 1, 5>(prm, m, s) : launch_row16_p<6, 2, 1, 5>(prm, m, s);
+        case 7: return f32 ? launch_row16_p<7, 1, 1, 5>(prm, m, s) : launch_row16_p<7, 2, 1, 5>(prm, m, s);
         default: break;
         }
     }
