@@ -101,8 +101,10 @@ fe_status fe_mesh_destroy(fe_mesh *mesh);
  * below FP64, 5; else 3); 6 = row-owner kernel (each thread loads
  * everything its outputs need in one round trip before the cell product;
  * the FP64 default); 7 = FP64 persistent pipelined row-owner kernel with the
- * cell matrix in registers (p <= 4; else 6; below FP64, 3).  Variants 0-4, 6 and 7 give
- * bitwise-identical results, except that in FP64 variant 2 multiplies with
+ * cell matrix in registers (p <= 4; else 6; below FP64, 3); 8 = persistent
+ * warp-specialised row-owner kernel, compute waves and memory waves
+ * exchanging double-buffered LDS tiles (p <= 4; else 6).  Variants 0-4 and
+ * 6-8 give bitwise-identical results, except that in FP64 variant 2 multiplies with
  * 16x16x4 MFMA blocks where the others use 4x4x4 blocks (equal to rounding);
  * variant 5 sums each node's contributions in another fixed order (equal to
  * rounding, reproducible).  FE_EINVAL for other values. */

@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cstdint>
 
 #include "fe_internal.h"
@@ -814,35 +815,75 @@ static hipError_t launch_mc_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------------
-// Row-owner variant (FP64): one cell x G chunks of 16 vectors per workgroup,
-// and each thread owns the outputs its 4x4x4 accumulators hold -- one row of
-// the cell (per row tile it covers) for four consecutive vectors per chunk.
+// Row-owner variant: one cell x G chunks of 16 vectors per workgroup, one
+// 16-row tile of (1/2)K_c per wave (TPW tiles where the tiles outnumber 16
+// waves), and each thread owns the outputs its accumulators hold: one row of
+// the cell per tile, four consecutive vectors per chunk.
+//   FP64: 4x4x4 blocks (see f64_quad_b): lane l owns row 4((l/4)%4) + l/16,
+//         vectors 4(l%4) .. 4(l%4)+3.
+//   FP32 / BF16: the 16x16 products are taken transposed, Y_c^T = X_c^T A^T,
+//         i.e. with the X slice as the first operand and the cell-matrix
+//         fragment as the second (both operands keep their 16x16 fragment
+//         layouts); lane l then owns row l%16, vectors 4(l/16) .. 4(l/16)+3.
 // Everything those outputs need from HBM (X for D X and the base term, the
 // previous iterate or the old Y, v) is loaded in one round trip at the start,
-// before the barrier; after the cell product each thread writes its outputs
-// without reading memory again.  Same arithmetic, in the same order, as the
-// other FP64 variants.
+// before the barrier; the cell-matrix fragments stream from L2 in batches of
+// BK k-steps; each thread then writes its outputs without reading memory
+// again.
 template <int P, int TPW> struct RowShape {
     static constexpr int NCP = ((P + 1) * (P + 1) * (P + 1) + 31) / 32 * 32, NT = NCP / 16, W = NT / TPW;
     static_assert(NT % TPW == 0, "row tiles must divide evenly among waves");
 };
+
+// largest divisor of nks not above bk
+constexpr int batch_size(int nks, int bk) {
+    for (int b = bk < nks ? bk : nks; b > 1; --b)
+        if (nks % b == 0) return b;
+    return 1;
+}
+
+template <int PREC, int G, int NCP> struct RowLds {
+    typedef typename PrecTraits<PREC>::T T;
+    static constexpr int XS = PREC == 2 ? 16 * Bf16Stride<NCP>::value : NCP * 16;  // per chunk
+    static constexpr size_t bytes = ((size_t)G * XS * sizeof(T) + 15) / 16 * 16;
+};
+
 // G chunks of 16 vectors per workgroup, TPW row tiles per wave, OCC waves
-// per SIMD the register allocation aims at, A fragments fetched in batches
-// of BK k-steps (0: one k-step at a time)
-template <int P, int G, int TPW, int OCC, int BK>
+// per SIMD the register allocation aims at, cell-matrix fragments fetched in
+// batches of BK k-steps (0: one k-step at a time)
+template <int P, int PREC, int G, int TPW, int OCC, int BK>
 __global__ __launch_bounds__((64 * RowShape<P, TPW>::W)) __attribute__((amdgpu_waves_per_eu(OCC)))
 void step_row_kernel(StepParams k) {
-    constexpr int N1 = P + 1, NC = N1 * N1 * N1, NCP = (NC + 31) / 32 * 32, NKS = NCP / 4;
-    constexpr int W = RowShape<P, TPW>::W, XS = NCP * 16;
+    constexpr int N1 = P + 1, NC = N1 * N1 * N1, NCP = (NC + 31) / 32 * 32;
+    constexpr int KSTEP = PrecTraits<PREC>::KSTEP, NKS = NCP / KSTEP;
+    constexpr int W = RowShape<P, TPW>::W, XS = RowLds<PREC, G, NCP>::XS;
+    typedef typename PrecTraits<PREC>::T T;
+    typedef typename FragOf<PREC>::T FragT;
     extern __shared__ __align__(16) unsigned char smem[];
-    double *xs = reinterpret_cast<double *>(smem);  // [G][NCP][16], D X
+    T *xs = reinterpret_cast<T *>(smem);  // [G][XS], D X rounded to the product precision
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int ngroups = (k.nchunk + G - 1) / G;
     const int grp = blockIdx.x % ngroups;
     const ItemCell c = item_cell(k, (int64_t)(blockIdx.x / ngroups) * k.nchunk);
-    const int rl = 4 * ((lane >> 2) & 3) + (lane >> 4);            // row within a tile
-    const int64_t v0 = (int64_t)grp * G * 16 + 4 * (lane & 3);     // first vector of chunk 0
+    const int rl = PREC == 0 ? 4 * ((lane >> 2) & 3) + (lane >> 4) : (lane & 15);  // row within a tile
+    const int vq = PREC == 0 ? 4 * (lane & 3) : 4 * (lane >> 4);                   // first vector in a chunk
+    const int64_t v0 = (int64_t)grp * G * 16 + vq;
+
+    // cell-matrix fragments: the first batch is requested before the HBM
+    // loads so that it has arrived when the product starts
+    const FragT *A = reinterpret_cast<const FragT *>(k.A) + (size_t)wave * NKS * 64 + lane;
+    constexpr size_t TS = (size_t)W * NKS * 64;  // fragment stride between the wave's tiles
+    constexpr int BKE = batch_size(NKS, BK > 0 ? BK : 1), NB = NKS / BKE;
+    static_assert(NKS % BKE == 0, "k-steps must split into batches");
+    auto load_batch = [&](FragT (&ab)[BKE][TPW], int sb) {
+#pragma unroll
+        for (int j = 0; j < BKE; ++j)
+#pragma unroll
+            for (int tt = 0; tt < TPW; ++tt) ab[j][tt] = A[tt * TS + (size_t)(sb * BKE + j) * 64];
+    };
+    FragT ab0[BKE][TPW], ab1[BKE][TPW];
+    if constexpr (BK > 0) load_batch(ab0, 0);
 
     int I[TPW];
     double d[TPW];
@@ -884,73 +925,91 @@ void step_row_kernel(StepParams k) {
         const double vI = (nr[tt].I >= 0 && fst[tt]) ? vraw[tt] : 0.0;
         const double sc = k.alpha * (vI - k.shift);
         d[tt] = node_scale(nr[tt]);
-        double xm[G][4];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
+            double dx[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const bool ok = nr[tt].I >= 0 && v0 + 16 * g + q < k.N;
-                xm[g][q] = ok ? xv[tt][g][q] : 0.0;
+                const double x = ok ? xv[tt][g][q] : 0.0;
                 const double o = (ok && useo) ? ov[tt][g][q] : 0.0;
-                double base = sc * xm[g][q];
+                double base = sc * x;
                 if (k.Ym1) base -= k.beta * o;
                 bo[tt][g][q] = fst[tt] ? base : o;
+                dx[q] = d[tt] * x;
             }
-            double2 *dst = reinterpret_cast<double2 *>(xs + g * XS + r * 16 + 4 * (lane & 3));
-            dst[0] = double2{d[tt] * xm[g][0], d[tt] * xm[g][1]};
-            dst[1] = double2{d[tt] * xm[g][2], d[tt] * xm[g][3]};
+            if constexpr (PREC == 0) {
+                double2 *dst = reinterpret_cast<double2 *>(xs + g * XS + r * 16 + vq);
+                dst[0] = double2{dx[0], dx[1]};
+                dst[1] = double2{dx[2], dx[3]};
+            } else if constexpr (PREC == 1) {
+                *reinterpret_cast<f4 *>(xs + g * XS + r * 16 + vq) =
+                    f4{(float)dx[0], (float)dx[1], (float)dx[2], (float)dx[3]};
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) xs[g * XS + (vq + q) * Bf16Stride<NCP>::value + r] = to_bf16_bits(dx[q]);
+            }
         }
     }
     __syncthreads();
 
     // the wave's TPW row tiles share each B read from LDS
     double acc[TPW][G][4];
-#pragma unroll
-    for (int tt = 0; tt < TPW; ++tt)
-        for (int g = 0; g < G; ++g)
-            for (int q = 0; q < 4; ++q) acc[tt][g][q] = 0.0;
     {
-        const double *A = reinterpret_cast<const double *>(k.A) + (size_t)wave * NKS * 64 + lane;
-        constexpr size_t TS = (size_t)W * NKS * 64;  // fragment stride between the wave's tiles
-        // A fragments in batches of BK k-steps, batch j + 1 in flight while
-        // batch j is multiplied (loads complete in issue order, so a wait for
-        // batch j leaves the later batch outstanding)
-        constexpr int BKE = BK > 0 ? BK : 1, NB = NKS / BKE;
-        static_assert(NKS % BKE == 0, "k-steps must split into batches");
-        auto mul_step = [&](const double (&a)[TPW], int s) {
+        typedef typename std::conditional<PREC == 0, double, f4>::type AccT;
+        AccT cacc[TPW][G][PREC == 0 ? 4 : 1];
+#pragma unroll
+        for (int tt = 0; tt < TPW; ++tt)
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int q = 0; q < (PREC == 0 ? 4 : 1); ++q) {
+                    if constexpr (PREC == 0) cacc[tt][g][q] = 0.0;
+                    else cacc[tt][g][q] = f4{0.f, 0.f, 0.f, 0.f};
+                }
+        auto mul_step = [&](const FragT (&a)[TPW], int s) {
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                double b[4];
-                f64_quad_b(xs + g * XS, s, lane, b);
+                if constexpr (PREC == 0) {
+                    double b[4];
+                    f64_quad_b(xs + g * XS, s, lane, b);
 #pragma unroll
-                for (int tt = 0; tt < TPW; ++tt)
+                    for (int tt = 0; tt < TPW; ++tt)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        acc[tt][g][q] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[tt], b[q], acc[tt][g][q], 0, 0, 0);
+                        for (int q = 0; q < 4; ++q)
+                            cacc[tt][g][q] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[tt], b[q], cacc[tt][g][q], 0, 0, 0);
+                } else if constexpr (PREC == 1) {
+                    const float b = xs[g * XS + (4 * s + (lane >> 4)) * 16 + (lane & 15)];
+#pragma unroll
+                    for (int tt = 0; tt < TPW; ++tt)
+                        cacc[tt][g][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(b, a[tt], cacc[tt][g][0], 0, 0, 0);
+                } else {
+                    const uint16_t *xcol = xs + g * XS + (lane & 15) * Bf16Stride<NCP>::value + 8 * (lane >> 4);
+                    const bf8 b = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4 *>(xcol + 32 * s));
+#pragma unroll
+                    for (int tt = 0; tt < TPW; ++tt)
+                        cacc[tt][g][0] =
+                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(b, __builtin_bit_cast(bf8, a[tt]), cacc[tt][g][0], 0, 0, 0);
+                }
             }
         };
         if constexpr (BK == 0) {
             constexpr int UNR = NKS <= 40 ? NKS : 8;
 #pragma unroll UNR
             for (int s = 0; s < NKS; ++s) {
-                double a[TPW];
+                FragT a[TPW];
 #pragma unroll
                 for (int tt = 0; tt < TPW; ++tt) a[tt] = A[tt * TS + (size_t)s * 64];
                 mul_step(a, s);
             }
         } else {
-            auto load_batch = [&](double (&ab)[BKE][TPW], int sb) {
-#pragma unroll
-                for (int j = 0; j < BKE; ++j)
-#pragma unroll
-                    for (int tt = 0; tt < TPW; ++tt) ab[j][tt] = A[tt * TS + (size_t)(sb * BKE + j) * 64];
-            };
-            auto mul_batch = [&](const double (&ab)[BKE][TPW], int sb) {
+            // batch j + 1 in flight while batch j is multiplied (loads complete
+            // in issue order, so a wait for batch j leaves the later batch
+            // outstanding); batch 0 was requested at the start
+            auto mul_batch = [&](const FragT (&ab)[BKE][TPW], int sb) {
 #pragma unroll
                 for (int j = 0; j < BKE; ++j) mul_step(ab[j], sb * BKE + j);
             };
-            double ab0[BKE][TPW], ab1[BKE][TPW];
-            load_batch(ab0, 0);
 #pragma unroll(NB <= 8 ? NB : 1)
             for (int sb = 0; sb < NB; sb += 2) {
                 if (sb + 1 < NB) load_batch(ab1, sb + 1);
@@ -961,6 +1020,15 @@ void step_row_kernel(StepParams k) {
                 }
             }
         }
+#pragma unroll
+        for (int tt = 0; tt < TPW; ++tt)
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if constexpr (PREC == 0) acc[tt][g][q] = cacc[tt][g][q];
+                    else acc[tt][g][q] = (double)cacc[tt][g][0][q];
+                }
     }
 #pragma unroll
     for (int tt = 0; tt < TPW; ++tt) {
@@ -977,13 +1045,13 @@ void step_row_kernel(StepParams k) {
     }
 }
 
-template <int P, int G, int TPW, int OCC, int BK>
+template <int P, int PREC, int G, int TPW, int OCC, int BK>
 static hipError_t launch_row_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
     constexpr int N1 = P + 1, NC = N1 * N1 * N1, NCP = (NC + 31) / 32 * 32, W = RowShape<P, TPW>::W;
-    const size_t smem = (size_t)G * NCP * 16 * sizeof(double);
+    const size_t smem = RowLds<PREC, G, NCP>::bytes;
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step_row_kernel<P, G, TPW, OCC, BK>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step_row_kernel<P, PREC, G, TPW, OCC, BK>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         if (e != hipSuccess) return e;
         attr = true;
@@ -1007,8 +1075,8 @@ static hipError_t launch_row_p(StepParams prm, const fe_mesh *m, hipStream_t s) 
                     cells *= cnt;
                 }
                 if (cells == 0) continue;
-                hipLaunchKernelGGL((step_row_kernel<P, G, TPW, OCC, BK>), dim3((unsigned)(cells * ngroups)), dim3(64 * W), smem, s,
-                                   prm);
+                hipLaunchKernelGGL((step_row_kernel<P, PREC, G, TPW, OCC, BK>), dim3((unsigned)(cells * ngroups)),
+                                   dim3(64 * W), smem, s, prm);
                 hipError_t e = hipGetLastError();
                 if (e != hipSuccess) return e;
             }
@@ -1016,141 +1084,233 @@ static hipError_t launch_row_p(StepParams prm, const fe_mesh *m, hipStream_t s) 
 }
 
 // ------------------------------------------------------------------------
-// Row-owner variant for the FP32 / BF16 cell products (16x16 MFMA shapes):
-// each lane's accumulator i holds row 4(l/16) + i of its tile for vector l%16
-// of a chunk, so each thread owns four consecutive cell rows for one vector
-// per chunk.  As in the FP64 row-owner kernel, every HBM load those outputs
-// need is issued in one round trip before the barrier, D X is staged in LDS
-// rounded to the product precision, and Y is written without re-reading it.
-// Same arithmetic, in the same order, as the other variants of the precision.
-template <int P, int PREC, int G, int OCC>
-__global__ __launch_bounds__(64 * McShape<P>::W) __attribute__((amdgpu_waves_per_eu(OCC)))
-void step_row16_kernel(StepParams k) {
-    constexpr int N1 = P + 1, NC = N1 * N1 * N1, NCP = (NC + 31) / 32 * 32;
+// Warp-specialised row-owner variant (p <= 4): persistent workgroups walk the
+// items (cell, G chunks of 16 vectors) of a colour with stride gridDim.x.  A
+// workgroup has NT compute waves (one 16-row tile of (1/2)K_c each) and NT
+// memory waves (the same rows, the same lane-to-output map as the row-owner
+// kernel).  In step j the compute waves multiply item j out of one LDS buffer
+// into an LDS accumulator buffer, while the memory waves write item j-1's
+// outputs from the other accumulator buffer and load and stage item j+1 into
+// the other D X buffer; one barrier ends the step.  The two roles never wait
+// on each other's memory operations (each wave's loads complete in its own
+// issue order), so HBM traffic overlaps the products.  Same arithmetic, in
+// the same order, as the other variants of the precision.
+template <int P, int PREC, int G> struct WsShape {
+    static constexpr int NCP = ((P + 1) * (P + 1) * (P + 1) + 31) / 32 * 32, NT = NCP / 16;
+    static constexpr int XS = RowLds<PREC, G, NCP>::XS;
+    static constexpr size_t xbytes = RowLds<PREC, G, NCP>::bytes;        // one D X buffer
+    static constexpr size_t abytes = (size_t)G * NCP * 16 * sizeof(double);  // one accumulator buffer
+    static constexpr size_t bytes = 2 * xbytes + 2 * abytes;
+};
+
+template <int P, int PREC, int G, int BK>
+__global__ __launch_bounds__((128 * WsShape<P, PREC, G>::NT)) void step_ws_kernel(StepParams k, int64_t nitems) {
+    constexpr int N1 = P + 1, NC = N1 * N1 * N1, NCP = (NC + 31) / 32 * 32, NT = NCP / 16;
     constexpr int KSTEP = PrecTraits<PREC>::KSTEP, NKS = NCP / KSTEP;
-    constexpr int TPW = McShape<P>::TPW, W = McShape<P>::W;
+    typedef WsShape<P, PREC, G> S;
+    constexpr int XS = S::XS;
     typedef typename PrecTraits<PREC>::T T;
     typedef typename FragOf<PREC>::T FragT;
-    constexpr int XS = PREC == 2 ? 16 * Bf16Stride<NCP>::value : NCP * 16;
     extern __shared__ __align__(16) unsigned char smem[];
-    T *xs = reinterpret_cast<T *>(smem);  // [G][XS]
+    // buffer b of each kind (b = item parity, a compile-time constant below)
+    auto xbuf = [&](int b) { return reinterpret_cast<T *>(smem + b * S::xbytes); };
+    auto abuf = [&](int b) { return reinterpret_cast<double *>(smem + 2 * S::xbytes + b * S::abytes); };
 
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const bool compute = wave < NT;
+    const int t = compute ? wave : wave - NT;  // the tile this wave works on
+    const int rl = PREC == 0 ? 4 * ((lane >> 2) & 3) + (lane >> 4) : (lane & 15);
+    const int vq = PREC == 0 ? 4 * (lane & 3) : 4 * (lane >> 4);
+    const int r = 16 * t + rl;  // the cell row this lane owns
     const int ngroups = (k.nchunk + G - 1) / G;
-    const int grp = blockIdx.x % ngroups;
-    const ItemCell c = item_cell(k, (int64_t)(blockIdx.x / ngroups) * k.nchunk);
-    const int64_t v0 = (int64_t)grp * G * 16 + col;
+    const int64_t J = nitems > (int64_t)blockIdx.x ? (nitems - 1 - blockIdx.x) / gridDim.x + 1 : 0;
 
-    constexpr int R = TPW * 4;  // rows owned by the thread
-    NodeRef nr[R];
-    bool fst[R];
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-        const int r = 16 * (wave + (j / 4) * W) + 4 * (lane >> 4) + (j % 4);
-        nr[j] = node_ref<P>(k, c, r);
-        fst[j] = r < NC && node_first<P>(k, c, r);
-    }
-    double xv[R][G], ov[R][G], vraw[R];
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-        const int64_t Ic = max(nr[j].I, 0);
-        const double *orow = !fst[j] ? k.Y + Ic * k.ldy : (k.Ym1 ? k.Ym1 + Ic * k.ldm : k.X + Ic * k.ldx);
+    // memory-wave state: the owned row of the item being loaded / written
+    int Iw[2] = {-1, -1};   // DoF (by item parity)
+    double dw[2] = {0, 0};  // D factor
+    double bo[2][G][4];     // base term or old Y
+    int64_t vbase[2] = {0, 0};
+
+    auto item_of = [&](int64_t j) { return (int64_t)blockIdx.x + j * gridDim.x; };
+    // load item j's rows into registers and stage D X into xbuf(j & 1)
+    auto load_stage = [&](auto bc, int64_t j) {
+        constexpr int b = decltype(bc)::value;
+        const int64_t it = item_of(j);
+        const int grp = (int)(it % ngroups);
+        const ItemCell c = item_cell(k, (it / ngroups) * k.nchunk);
+        const int64_t v0 = (int64_t)grp * G * 16 + vq;
+        const NodeRef nr = node_ref<P>(k, c, r);
+        const bool fst = r < NC && node_first<P>(k, c, r);
+        const int64_t Ic = max(nr.I, 0);
+        const double *orow = !fst ? k.Y + Ic * k.ldy : (k.Ym1 ? k.Ym1 + Ic * k.ldm : k.X + Ic * k.ldx);
         const double *xrow = k.X + Ic * k.ldx;
-        vraw[j] = k.v[Ic];
+        const double vraw = k.v[Ic];
+        double xv[G][4], ov[G][4];
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int64_t vc = min(v0 + 16 * g, k.N - 1);
-            xv[j][g] = xrow[vc];
-            ov[j][g] = orow[vc];
-        }
-    }
-    double bo[R][G], d[R];
+        for (int g = 0; g < G; ++g)
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-        const int r = 16 * (wave + (j / 4) * W) + 4 * (lane >> 4) + (j % 4);
-        const bool useo = !fst[j] || k.Ym1 != nullptr;
-        const double vI = (nr[j].I >= 0 && fst[j]) ? vraw[j] : 0.0;
+            for (int q = 0; q < 4; ++q) {
+                const int64_t vc = min(v0 + 16 * g + q, k.N - 1);
+                xv[g][q] = xrow[vc];
+                ov[g][q] = orow[vc];
+            }
+        const bool useo = !fst || k.Ym1 != nullptr;
+        const double vI = (nr.I >= 0 && fst) ? vraw : 0.0;
         const double sc = k.alpha * (vI - k.shift);
-        d[j] = node_scale(nr[j]);
+        const double dn = node_scale(nr);
+        T *xs = xbuf(b);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            const bool ok = nr[j].I >= 0 && v0 + 16 * g < k.N;
-            const double x = ok ? xv[j][g] : 0.0;
-            const double o = (ok && useo) ? ov[j][g] : 0.0;
-            double base = sc * x;
-            if (k.Ym1) base -= k.beta * o;
-            bo[j][g] = fst[j] ? base : o;
-            const double dx = d[j] * x;
-            if constexpr (PREC == 1) xs[g * XS + r * 16 + col] = (float)dx;
-            else xs[g * XS + col * Bf16Stride<NCP>::value + r] = to_bf16_bits(dx);
-        }
-    }
-    __syncthreads();
-
+            double dx[4];
 #pragma unroll
-    for (int tt = 0; tt < TPW; ++tt) {
-        const int t = wave + tt * W;
-        const FragT *A = reinterpret_cast<const FragT *>(k.A) + (size_t)t * NKS * 64 + lane;
-        double acc[G][4];
-        if constexpr (PREC == 1) {
-            f4 c4[G];
-#pragma unroll
-            for (int g = 0; g < G; ++g) c4[g] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 8
-            for (int s = 0; s < NKS; ++s) {
-                float a = A[s * 64];
-#pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    float b = xs[g * XS + (4 * s + (lane >> 4)) * 16 + col];
-                    c4[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c4[g], 0, 0, 0);
-                }
+            for (int q = 0; q < 4; ++q) {
+                const bool ok = nr.I >= 0 && v0 + 16 * g + q < k.N;
+                const double x = ok ? xv[g][q] : 0.0;
+                const double o = (ok && useo) ? ov[g][q] : 0.0;
+                double base = sc * x;
+                if (k.Ym1) base -= k.beta * o;
+                bo[b][g][q] = fst ? base : o;
+                dx[q] = dn * x;
             }
+            if constexpr (PREC == 0) {
+                double2 *dst = reinterpret_cast<double2 *>(xs + g * XS + r * 16 + vq);
+                dst[0] = double2{dx[0], dx[1]};
+                dst[1] = double2{dx[2], dx[3]};
+            } else if constexpr (PREC == 1) {
+                *reinterpret_cast<f4 *>(xs + g * XS + r * 16 + vq) =
+                    f4{(float)dx[0], (float)dx[1], (float)dx[2], (float)dx[3]};
+            } else {
 #pragma unroll
-            for (int g = 0; g < G; ++g)
-                for (int i = 0; i < 4; ++i) acc[g][i] = (double)c4[g][i];
-        } else {
-            f4 c4[G];
-#pragma unroll
-            for (int g = 0; g < G; ++g) c4[g] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
-            for (int s = 0; s < NKS; ++s) {
-                bf8 a = __builtin_bit_cast(bf8, A[s * 64]);
-#pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    const uint16_t *xrow = xs + g * XS + col * Bf16Stride<NCP>::value + 8 * (lane >> 4);
-                    bf8 b = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4 *>(xrow + 32 * s));
-                    c4[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c4[g], 0, 0, 0);
-                }
+                for (int q = 0; q < 4; ++q) xs[g * XS + (vq + q) * Bf16Stride<NCP>::value + r] = to_bf16_bits(dx[q]);
             }
-#pragma unroll
-            for (int g = 0; g < G; ++g)
-                for (int i = 0; i < 4; ++i) acc[g][i] = (double)c4[g][i];
         }
+        Iw[b] = nr.I;
+        dw[b] = dn;
+        vbase[b] = v0;
+    };
+    // write the outputs of the item of parity b from abuf(b)
+    auto emit = [&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+        if (Iw[b] < 0) return;
+        const double *ab = abuf(b);
+        double *yrow = k.Y + (int64_t)Iw[b] * k.ldy;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int j = tt * 4 + i;
-            if (nr[j].I < 0) continue;
-            double *yrow = k.Y + (int64_t)nr[j].I * k.ldy;
+        for (int g = 0; g < G; ++g) {
+            const double2 *src = reinterpret_cast<const double2 *>(ab + (g * NCP + r) * 16 + vq);
+            const double2 u = src[0], w = src[1];
+            const double acc[4] = {u.x, u.y, w.x, w.y};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t vec = vbase[b] + 16 * g + q;
+                if (vec < k.N) yrow[vec] = bo[b][g][q] + k.alpha * dw[b] * acc[q];
+            }
+        }
+    };
+    // multiply the item of parity b (compute waves): xbuf(b) -> abuf(b)
+    const FragT *A = reinterpret_cast<const FragT *>(k.A) + (size_t)t * NKS * 64 + lane;
+    constexpr int BKE = batch_size(NKS, BK), NB = NKS / BKE;
+    static_assert(NKS % BKE == 0, "k-steps must split into batches");
+    auto multiply = [&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+        const T *xs = xbuf(b);
+        typedef typename std::conditional<PREC == 0, double, f4>::type AccT;
+        AccT cacc[G][PREC == 0 ? 4 : 1];
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int q = 0; q < (PREC == 0 ? 4 : 1); ++q) {
+                if constexpr (PREC == 0) cacc[g][q] = 0.0;
+                else cacc[g][q] = f4{0.f, 0.f, 0.f, 0.f};
+            }
+        auto mul_step = [&](const FragT a, int s) {
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                const int64_t vec = v0 + 16 * g;
-                if (vec < k.N) yrow[vec] = bo[j][g] + k.alpha * d[j] * acc[g][i];
+                if constexpr (PREC == 0) {
+                    double bq[4];
+                    f64_quad_b(xs + g * XS, s, lane, bq);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) cacc[g][q] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, bq[q], cacc[g][q], 0, 0, 0);
+                } else if constexpr (PREC == 1) {
+                    const float bb = xs[g * XS + (4 * s + (lane >> 4)) * 16 + (lane & 15)];
+                    cacc[g][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(bb, a, cacc[g][0], 0, 0, 0);
+                } else {
+                    const uint16_t *xcol = xs + g * XS + (lane & 15) * Bf16Stride<NCP>::value + 8 * (lane >> 4);
+                    const bf8 bb = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4 *>(xcol + 32 * s));
+                    cacc[g][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bb, __builtin_bit_cast(bf8, a), cacc[g][0], 0, 0, 0);
+                }
+            }
+        };
+        auto load_batch = [&](FragT (&ab)[BKE], int sb) {
+#pragma unroll
+            for (int i = 0; i < BKE; ++i) ab[i] = A[(size_t)(sb * BKE + i) * 64];
+        };
+        FragT ab0[BKE], ab1[BKE];
+        load_batch(ab0, 0);
+#pragma unroll(NB <= 4 ? NB : 1)
+        for (int sb = 0; sb < NB; sb += 2) {
+            if (sb + 1 < NB) load_batch(ab1, sb + 1);
+#pragma unroll
+            for (int i = 0; i < BKE; ++i) mul_step(ab0[i], sb * BKE + i);
+            if (sb + 1 < NB) {
+                if (sb + 2 < NB) load_batch(ab0, sb + 2);
+#pragma unroll
+                for (int i = 0; i < BKE; ++i) mul_step(ab1[i], (sb + 1) * BKE + i);
             }
         }
+        double *ab = abuf(b);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            double acc[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if constexpr (PREC == 0) acc[q] = cacc[g][q];
+                else acc[q] = (double)cacc[g][0][q];
+            }
+            double2 *dst = reinterpret_cast<double2 *>(ab + (g * NCP + r) * 16 + vq);
+            dst[0] = double2{acc[0], acc[1]};
+            dst[1] = double2{acc[2], acc[3]};
+        }
+    };
+
+    // step j (buffer parity B = j & 1): compute waves multiply item j; memory
+    // waves write item j-1, then load and stage item j+1 (both of parity 1-B)
+    auto step = [&](auto bc, int64_t j) {
+        constexpr int B = decltype(bc)::value;
+        if (compute) {
+            if (j < J) multiply(bc);
+        } else {
+            if (j >= 1) emit(std::integral_constant<int, 1 - B>());
+            if (j + 1 < J) load_stage(std::integral_constant<int, 1 - B>(), j + 1);
+        }
+        __syncthreads();
+    };
+    if (J == 0) return;  // whole workgroup
+    if (!compute) load_stage(std::integral_constant<int, 0>(), 0);
+    __syncthreads();
+    for (int64_t j = 0; j <= J; j += 2) {
+        step(std::integral_constant<int, 0>(), j);
+        if (j + 1 <= J) step(std::integral_constant<int, 1>(), j + 1);
     }
 }
 
-template <int P, int PREC, int G, int OCC>
-static hipError_t launch_row16_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
-    constexpr int N1 = P + 1, NC = N1 * N1 * N1, NCP = (NC + 31) / 32 * 32, W = McShape<P>::W;
-    typedef typename PrecTraits<PREC>::T T;
-    constexpr int XS = PREC == 2 ? 16 * Bf16Stride<NCP>::value : NCP * 16;
-    const size_t smem = ((size_t)G * XS * sizeof(T) + 15) / 16 * 16;
+template <int P, int PREC, int G, int BK>
+static hipError_t launch_ws_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
+    typedef WsShape<P, PREC, G> S;
     static bool attr = false;
+    static int resident = 0;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step_row16_kernel<P, PREC, G, OCC>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step_ws_kernel<P, PREC, G, BK>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::bytes);
         if (e != hipSuccess) return e;
+        int per_cu = 0, dev = 0, cus = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(&step_ws_kernel<P, PREC, G, BK>), 128 * S::NT, S::bytes);
+        if (e != hipSuccess) return e;
+        e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        resident = std::max(1, per_cu) * std::max(1, cus);
         attr = true;
     }
     const int ngroups = (prm.nchunk + G - 1) / G;
@@ -1172,8 +1332,10 @@ static hipError_t launch_row16_p(StepParams prm, const fe_mesh *m, hipStream_t s
                     cells *= cnt;
                 }
                 if (cells == 0) continue;
-                hipLaunchKernelGGL((step_row16_kernel<P, PREC, G, OCC>), dim3((unsigned)(cells * ngroups)),
-                                   dim3(64 * W), smem, s, prm);
+                const int64_t nitems = cells * ngroups;
+                const int64_t grid = std::min<int64_t>(nitems, resident);
+                hipLaunchKernelGGL((step_ws_kernel<P, PREC, G, BK>), dim3((unsigned)grid), dim3(128 * S::NT), S::bytes,
+                                   s, prm, nitems);
                 hipError_t e = hipGetLastError();
                 if (e != hipSuccess) return e;
             }
@@ -1674,6 +1836,21 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
         if (e != hipErrorNotSupported) return e;
         // otherwise: the multi-chunk kernel below
     }
+    if (m->kernel_variant == 8) {
+#define FE_WS(PP)                                                                    \
+    case PP:                                                                         \
+        if (prec == FE_F64) return launch_ws_p<PP, 0, 2, 4>(prm, m, s);              \
+        if (prec == FE_F32) return launch_ws_p<PP, 1, 2, 4>(prm, m, s);              \
+        return launch_ws_p<PP, 2, 2, 4>(prm, m, s);
+        switch (m->p) {
+            FE_WS(1)
+            FE_WS(2)
+            FE_WS(3)
+            FE_WS(4)
+        default: break;
+        }
+#undef FE_WS
+    }
     if (m->kernel_variant == 7 && prec == FE_F64) {
         switch (m->p) {
         case 1: return launch_pipe_p<1>(prm, m, s);
@@ -1683,33 +1860,28 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
         default: break;
         }
     }
-    if (m->kernel_variant == 6 && prec != FE_F64) {
-        const bool f32 = prec == FE_F32;
-        switch (m->p) {
-        case 1: return f32 ? launch_row16_p<1, 1, 2, 6>(prm, m, s) : launch_row16_p<1, 2, 2, 6>(prm, m, s);
-        case 2: return f32 ? launch_row16_p<2, 1, 2, 6>(prm, m, s) : launch_row16_p<2, 2, 2, 6>(prm, m, s);
-        case 3: return f32 ? launch_row16_p<3, 1, 2, 6>(prm, m, s) : launch_row16_p<3, 2, 2, 6>(prm, m, s);
-        case 4: return f32 ? launch_row16_p<4, 1, 2, 6>(prm, m, s) : launch_row16_p<4, 2, 2, 6>(prm, m, s);
-        case 5: return f32 ? launch_row16_p<5, 1, 2, 6>(prm, m, s) : launch_row16_p<5, 2, 2, 6>(prm, m, s);
-        case 6: return f32 ? launch_row16_p<6, 1, 1, 5>(prm, m, s) : launch_row16_p<6, 2, 1, 5>(prm, m, s);
-        case 7: return f32 ? launch_row16_p<7, 1, 1, 5>(prm, m, s) : launch_row16_p<7, 2, 1, 5>(prm, m, s);
-        default: break;
-        }
-    }
-    if ((m->kernel_variant == 0 || m->kernel_variant == 6 || m->kernel_variant == 7) && prec == FE_F64) {
-        switch (m->p) {
+    if ((m->kernel_variant == 0 && prec == FE_F64) || m->kernel_variant == 6 || m->kernel_variant == 8 ||
+        (m->kernel_variant == 7 && prec == FE_F64)) {
         // 32 vectors per workgroup and one row tile per wave measured best
         // where the tiles fit one workgroup (p <= 5); above that two tiles
         // per wave keep the workgroup within 1024 threads
-        case 1: return launch_row_p<1, 2, 1, 5, 4>(prm, m, s);
-        case 2: return launch_row_p<2, 2, 1, 5, 4>(prm, m, s);
-        case 3: return launch_row_p<3, 2, 1, 5, 4>(prm, m, s);
-        case 4: return launch_row_p<4, 2, 1, 5, 4>(prm, m, s);
-        case 5: return launch_row_p<5, 2, 1, 5, 4>(prm, m, s);
-        case 6: return launch_row_p<6, 1, 2, 5, 2>(prm, m, s);
-        case 7: return launch_row_p<7, 1, 2, 5, 2>(prm, m, s);
+        // BK / BKL: fragment batch (k-steps) for FP64 / for FP32 and BF16
+#define FE_ROW(PP, G, TPW, OCC, BK, BKL)                                                     \
+    case PP:                                                                                 \
+        if (prec == FE_F64) return launch_row_p<PP, 0, G, TPW, OCC, BK>(prm, m, s);          \
+        if (prec == FE_F32) return launch_row_p<PP, 1, G, TPW, OCC, BKL>(prm, m, s);         \
+        return launch_row_p<PP, 2, G, TPW, OCC, BKL>(prm, m, s);
+        switch (m->p) {
+            FE_ROW(1, 2, 1, 5, 4, 4)
+            FE_ROW(2, 2, 1, 5, 4, 4)
+            FE_ROW(3, 2, 1, 5, 4, 4)
+            FE_ROW(4, 2, 1, 5, 4, 4)
+            FE_ROW(5, 2, 1, 5, 4, 4)
+            FE_ROW(6, 1, 2, 5, 2, 2)
+            FE_ROW(7, 1, 2, 5, 2, 2)
         default: break;
         }
+#undef FE_ROW
     }
     // variant 3/4: one cell x 2/4 chunks per workgroup; variant 0 picks the
     // multi-chunk kernel with the chunk count measured best for the precision
