@@ -219,6 +219,23 @@ def main():
             "launches_per_step": launches,
         },
     }
+    # density of the filtered block (Sec. 2.1) and its planar integral: HBM-bound
+    # row reductions over the same (n, N) block
+    f_occ = torch.ones(N, dtype=torch.float64, device=dev)
+    rho = gm.density(Y, f_occ)
+    gm.planar_average(rho)
+    torch.cuda.synchronize()
+    de0, de1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    de0.record(stream)
+    for _ in range(5):
+        gm.density(Y, f_occ, rho=rho)
+    de1.record(stream)
+    torch.cuda.synchronize()
+    ms_rho = de0.elapsed_time(de1) / 5
+    rho_bytes = 8.0 * n * N + 8.0 * N + 8.0 * n
+    rec["density"] = {"ms": round(ms_rho, 4), "bytes": rho_bytes, "GB/s": round(rho_bytes / (ms_rho * 1e-3) / 1e9, 1),
+                      "frac_of_hbm_peak": round(rho_bytes / (ms_rho * 1e-3) / 8e12, 4),
+                      "kernel": "density_kernel (2 sum_n f_n X[I,n]^2 / M_I, 16 lanes per DoF)"}
     if not args.no_mixed and args.prec == "f64":
         t_pot_ms = t_pot
         rec["mixed_precision"] = mixed_precision_report(gm, wl, X, Y, work, a, b, a0, args.steps, ms - t_pot_ms)

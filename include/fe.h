@@ -208,6 +208,30 @@ fe_status fe_cholqr2(fe_mesh *mesh, double *Y, int64_t N, int64_t ld, hipStream_
 fe_status fe_rayleigh_ritz(fe_mesh *mesh, const double *Q, double *X, double *P, int64_t N, int64_t ld,
                            double *theta_host, hipStream_t stream);
 
+/* Electron density at the free nodes (Sec. 2.1, rho = 2 sum_n f_n |psi_n|^2):
+ *   rho[I] = 2 sum_n f[n] X[I,n]^2 / M_I,
+ * i.e. the density of the orbitals psi_n = M^-1/2 x_n (the vectors this
+ * library filters are M^1/2-scaled nodal coefficients) at the GLL nodes,
+ * where the lumped-mass orbitals are collocated.  X: device, (n, N)
+ * row-major, leading dimension ld >= N; f: device, N occupation weights;
+ * rho: device, n doubles, overwritten.  N = 0 writes zeros (X, f may then be
+ * NULL).  The sum over n runs in a fixed order (reproducible).  Enqueued on
+ * stream.  FE_EINVAL for NULL arguments, N < 0 or ld < N. */
+fe_status fe_density(fe_mesh *mesh, const double *X, int64_t N, int64_t ld, const double *f, double *rho,
+                     hipStream_t stream);
+
+/* Planar integral (normalize = 0) or planar average (normalize = 1) of a
+ * nodal field over the x-y plane through each row of free z nodes
+ * (Sec. 3.2, rho^0(z) and V^0_bare(z)):
+ *   out[k] = s * sum_{i,j} m_x(i) m_y(j) field[i + n_x (j + n_y k)],
+ * with m_a the assembled 1-D GLL lumped masses of the free positions,
+ * s = 1 or 1 / (sum_i m_x(i) sum_j m_y(j)) (the plane area when x and y are
+ * periodic).  field: device, n doubles in DoF order; out: device, n_z
+ * doubles (one per free z position, ascending z).  Fixed reduction order.
+ * Enqueued on stream.  FE_EINVAL for NULL arguments or normalize not 0/1. */
+fe_status fe_planar_average(fe_mesh *mesh, const double *field, int32_t normalize, double *out,
+                            hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

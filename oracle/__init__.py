@@ -332,6 +332,51 @@ def apply_rows(mesh: Mesh, Vq: Optional[np.ndarray], E: float, z0: float, rows, 
     return Yr
 
 
+# ------------------------------------------------------------ observables
+
+def density(mesh: Mesh, X: np.ndarray, f: np.ndarray) -> np.ndarray:
+    """Electron density of Sec. 2.1, rho = 2 sum_n f_n |psi_n|^2, at the free
+    GLL nodes, for orbitals psi_n = M^-1/2 x_n (x_n a column of X)."""
+    M = mesh.mass()
+    return 2.0 * ((X * X) @ np.asarray(f, dtype=np.float64)) / M
+
+
+def axis_positions(mesh: Mesh, a: int):
+    """Coordinates and assembled 1-D GLL lumped masses of the free node
+    positions along axis a (Dirichlet ends dropped, periodic ends joined)."""
+    xi, w = gll(mesh.p)
+    p, nce = mesh.p, mesh.ncell[a]
+    h = mesh.L[a] / nce
+    K = nce * p
+    mass = np.zeros(K + 1)
+    coord = np.zeros(K + 1)
+    for c in range(nce):
+        for i in range(p + 1):
+            mass[c * p + i] += 0.5 * h * w[i]
+            coord[c * p + i] = c * h + 0.5 * h * (xi[i] + 1.0)
+    if mesh.bc[a] == 1:  # periodic: position K is position 0
+        mass[0] += mass[K]
+        return coord[:K], mass[:K]
+    if mesh.bc[a] == 0:  # Dirichlet
+        return coord[1:K], mass[1:K]
+    return coord, mass
+
+
+def planar_integral(mesh: Mesh, field: np.ndarray, normalize: bool = False) -> np.ndarray:
+    """Sec. 3.2 planar integral of a nodal field over the x-y plane S_z through
+    each row of free z nodes (ascending z), by GLL quadrature in x and y:
+    sum over the plane's nodes of m_x m_y F = M_I F_I / m_z.  With normalize,
+    divided by the plane area sum m_x * sum m_y (the planar average)."""
+    xyz = mesh.dof_coords()
+    M = mesh.mass()
+    zc, mz = axis_positions(mesh, 2)
+    k = np.searchsorted(zc, xyz[:, 2] - 1e-9 * mesh.L[2])
+    out = np.bincount(k, weights=M * np.asarray(field, dtype=np.float64), minlength=len(zc)) / mz
+    if normalize:
+        out = out / (axis_positions(mesh, 0)[1].sum() * axis_positions(mesh, 1)[1].sum())
+    return out
+
+
 def stiffness(mesh: Mesh):
     """Global stiffness K (no 1/2, unscaled) as scipy CSR."""
     return CSR(lib().or_assemble(C.byref(mesh._m), 0, None, 0.0, 0.0)).to_scipy()

@@ -71,6 +71,8 @@ def lib() -> C.CDLL:
         "fe_lanczos_bounds": ([vp, vp, i32, C.POINTER(dbl), C.POINTER(dbl), vp], C.c_int),
         "fe_cholqr2": ([vp, vp, i64, i64, vp], C.c_int),
         "fe_rayleigh_ritz": ([vp, vp, vp, vp, i64, i64, vp, vp], C.c_int),
+        "fe_density": ([vp, vp, i64, i64, vp, vp, vp], C.c_int),
+        "fe_planar_average": ([vp, vp, i32, vp, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -124,6 +126,9 @@ class Mesh:
         n, nce, nc = C.c_int64(), C.c_int64(), C.c_int32()
         _check(lib().fe_mesh_info(h, C.byref(n), C.byref(nce), C.byref(nc)))
         self.n, self.n_cells, self.nc = n.value, nce.value, nc.value
+        # free node positions per axis (Dirichlet faces removed, periodic ends identified)
+        self.nf = tuple(int(ncell[a]) * self.p + (1 if bc[a] == NEUMANN else 0 if bc[a] == PERIODIC else -1)
+                        for a in range(3))
 
     @classmethod
     def from_workload(cls, wl, rule: Optional[int] = None) -> "Mesh":
@@ -220,6 +225,31 @@ class Mesh:
                                         _PREC[prec], _ptr(Xb), _ptr(Vb), _ptr(Eb), int(ckpt_stride), int(col_chunk),
                                         _ptr(work), work.numel() * 8, _stream(stream)))
         return Xb, Vb, Eb
+
+    # ------------------------------------------------------------ observables
+    def density(self, X, f, rho=None, stream=None):
+        """rho_I = 2 sum_n f_n X[I,n]^2 / M_I at the free nodes (fe_density).
+        X: (n, N) float64 device block; f: N float64 device occupations."""
+        import torch
+        _check_block(X, self.n, "X")
+        N, ld = X.shape[1], X.stride(0)
+        if f.dtype != torch.float64 or not f.is_cuda or not f.is_contiguous() or f.numel() != N:
+            raise ValueError("f must be a contiguous float64 device tensor of N values")
+        if rho is None:
+            rho = torch.empty(self.n, dtype=torch.float64, device=X.device)
+        _check(lib().fe_density(self._h, _ptr(X), N, ld, _ptr(f), _ptr(rho), _stream(stream)))
+        return rho
+
+    def planar_average(self, field, normalize: bool = False, out=None, stream=None):
+        """x-y planar integral (or average) of a nodal field, one value per
+        free z node position, ascending z (fe_planar_average)."""
+        import torch
+        if field.dtype != torch.float64 or not field.is_cuda or not field.is_contiguous() or field.numel() != self.n:
+            raise ValueError("field must be a contiguous float64 device tensor of n values")
+        if out is None:
+            out = torch.empty(self.nf[2], dtype=torch.float64, device=field.device)
+        _check(lib().fe_planar_average(self._h, _ptr(field), int(bool(normalize)), _ptr(out), _stream(stream)))
+        return out
 
     def lanczos_bounds(self, v0, k: int = 10, stream=None):
         a0, b = C.c_double(), C.c_double()

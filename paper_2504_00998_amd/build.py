@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfe.so")
-SOURCES = ["fe_api.cpp", "fe_refelem.cpp", "fe_dense.cpp", "fe_adjoint.cpp", "fe_kernels.hip", "fe_nonlocal.hip"]
+SOURCES = ["fe_api.cpp", "fe_refelem.cpp", "fe_dense.cpp", "fe_adjoint.cpp", "fe_kernels.hip", "fe_nonlocal.hip",
+           "fe_density.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -242,11 +242,12 @@ fe_status fe_mesh_create(const fe_mesh_desc *d, fe_mesh **out) {
         }
         m->maxf = std::max<int>(m->maxf, (int)m->nf[a]);
     }
-    std::vector<double> axis(6 * (size_t)m->maxf, 0.0);
+    std::vector<double> axis(9 * (size_t)m->maxf, 0.0);
     for (int a = 0; a < 3; ++a)
         for (int64_t t = 0; t < m->nf[a]; ++t) {
             axis[(size_t)a * m->maxf + t] = 1.0 / std::sqrt(m->axis_mass[a][t]);
             axis[(size_t)(3 + a) * m->maxf + t] = 1.0 / m->axis_mass[a][t];
+            axis[(size_t)(6 + a) * m->maxf + t] = m->axis_mass[a][t];
         }
     std::vector<double> wrel(3 * (size_t)m->n1);
     for (int a = 0; a < 3; ++a)

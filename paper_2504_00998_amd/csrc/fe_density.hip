@@ -1,0 +1,118 @@
+// Electron density and planar integrals/averages over x-y node planes.
+//
+// rho_I = 2 sum_n f_n |psi_n(x_I)|^2 with psi_n = M^-1/2 x_n, i.e. the
+// density of the occupied orbitals (paper Sec. 2.1) evaluated at the GLL
+// nodes, where the orbitals of the lumped-mass discretisation are nodal
+// values (the collocated GLL quadrature used throughout).  The planar
+// integral over the plane S_z through a row of z nodes (paper Sec. 3.2) is
+// the x-y GLL quadrature of the nodal field: sum_ij m_x(i) m_y(j) F(i,j,k),
+// with m_a the assembled 1-D lumped masses; the planar average divides it by
+// the plane area sum_i m_x(i) sum_j m_y(j).  Reductions run in a fixed
+// order, so results are reproducible bit for bit.
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "fe_internal.h"
+
+namespace fe {
+
+namespace {
+
+// 16 lanes per DoF: lane j sums f_n X[I,n]^2 over n = j, j+16, ..., then the
+// 16 partial sums are combined in a fixed butterfly order.
+__global__ void density_kernel(const double *X, int64_t ld, int64_t N, const double *f, int64_t n, int nfx, int nfy,
+                               const double *invM, int maxf, double *rho) {
+    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t I = gid >> 4;
+    const int j = (int)(gid & 15);
+    double s = 0.0;
+    if (I < n) {
+        const double *row = X + I * ld;
+        for (int64_t c = j; c < N; c += 16) {
+            const double x = row[c];
+            s += f[c] * (x * x);
+        }
+    }
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) s += __shfl_xor(s, off, 16);
+    if (I < n && j == 0) {
+        const int tx = (int)(I % nfx);
+        const int ty = (int)((I / nfx) % nfy);
+        const int tz = (int)(I / ((int64_t)nfx * nfy));
+        const double im = (invM[tx] * invM[maxf + ty]) * invM[2 * maxf + tz];
+        rho[I] = 2.0 * s * im;
+    }
+}
+
+// one workgroup per free z plane k
+__global__ __launch_bounds__(256) void planar_kernel(const double *F, int nfx, int nfy, const double *mass, int maxf,
+                                                     double scale, double *out) {
+    __shared__ double red[256];
+    const int k = blockIdx.x;
+    const int64_t plane = (int64_t)nfx * nfy;
+    const double *Fk = F + (int64_t)k * plane;
+    double s = 0.0;
+    for (int64_t e = threadIdx.x; e < plane; e += 256) {
+        const int tx = (int)(e % nfx), ty = (int)(e / nfx);
+        s += (mass[tx] * mass[maxf + ty]) * Fk[e];
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = red[0] * scale;
+}
+
+#define FE_HIPD(call, what)                                                                          \
+    do {                                                                                             \
+        hipError_t _e = (call);                                                                      \
+        if (_e != hipSuccess) return fail(FE_EDEVICE, std::string(what) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+}  // namespace
+
+}  // namespace fe
+
+using namespace fe;
+
+extern "C" {
+
+fe_status fe_density(fe_mesh *m, const double *X, int64_t N, int64_t ld, const double *f, double *rho,
+                     hipStream_t st) {
+    if (!m || !rho) return fail(FE_EINVAL, "NULL argument");
+    if (N < 0) return fail(FE_EINVAL, "N must be >= 0");
+    if (N > 0 && (!X || !f)) return fail(FE_EINVAL, "NULL X or f");
+    if (ld < N) return fail(FE_EINVAL, "ld < N");
+    FE_HIPD(hipSetDevice(m->device), "hipSetDevice");
+    if (N == 0) {
+        FE_HIPD(launch_fill(rho, m->n, 0.0, st), "fill");
+        return FE_OK;
+    }
+    const int64_t threads = m->n * 16;
+    hipLaunchKernelGGL(density_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, X, ld, N, f, m->n,
+                       (int)m->nf[0], (int)m->nf[1], m->d_axis + 3 * m->maxf, m->maxf, rho);
+    FE_HIPD(hipGetLastError(), "density kernel");
+    return FE_OK;
+}
+
+fe_status fe_planar_average(fe_mesh *m, const double *field, int32_t normalize, double *out, hipStream_t st) {
+    if (!m || !field || !out) return fail(FE_EINVAL, "NULL argument");
+    if (normalize != 0 && normalize != 1) return fail(FE_EINVAL, "normalize must be 0 or 1");
+    FE_HIPD(hipSetDevice(m->device), "hipSetDevice");
+    double scale = 1.0;
+    if (normalize) {
+        double ax = 0.0, ay = 0.0;
+        for (double v : m->axis_mass[0]) ax += v;
+        for (double v : m->axis_mass[1]) ay += v;
+        scale = 1.0 / (ax * ay);
+    }
+    hipLaunchKernelGGL(planar_kernel, dim3((unsigned)m->nf[2]), dim3(256), 0, st, field, (int)m->nf[0], (int)m->nf[1],
+                       m->d_axis + 6 * m->maxf, m->maxf, scale, out);
+    FE_HIPD(hipGetLastError(), "planar kernel");
+    return FE_OK;
+}
+
+}  // extern "C"

@@ -67,9 +67,10 @@ struct fe_mesh {
     std::vector<double> axis_mass[3];   // assembled 1-D lumped mass per free position
 
     // device
-    double *d_axis = nullptr;     // [3][maxf] : D factors (M^-1/2 per axis)
+    // [9][maxf]: per axis a, rows a / 3 + a / 6 + a hold M^-1/2, M^-1 and M of
+    // the assembled 1-D lumped mass at each free position
+    double *d_axis = nullptr;
     double *d_zcoord = nullptr;   // [nf_z] z coordinate of free z positions
-    double *d_wq = nullptr;       // [3][maxf?] not used
     int maxf = 0;
     double *d_Af64 = nullptr;     // swizzled A fragments of 1/2 Kc (f64)
     float *d_Af32 = nullptr;      // f32

@@ -1010,7 +1010,8 @@ void step_row_kernel(StepParams k) {
 #pragma unroll
                 for (int j = 0; j < BKE; ++j) mul_step(ab[j], sb * BKE + j);
             };
-#pragma unroll(NB <= 8 ? NB : 1)
+constexpr int UNRB = NB <= 8 ? NB : 1;
+#pragma unroll UNRB
             for (int sb = 0; sb < NB; sb += 2) {
                 if (sb + 1 < NB) load_batch(ab1, sb + 1);
                 mul_batch(ab0, sb);
@@ -1246,7 +1247,8 @@ __global__ __launch_bounds__((128 * WsShape<P, PREC, G>::NT)) void step_ws_kerne
         };
         FragT ab0[BKE], ab1[BKE];
         load_batch(ab0, 0);
-#pragma unroll(NB <= 4 ? NB : 1)
+constexpr int UNRB = NB <= 4 ? NB : 1;
+#pragma unroll UNRB
         for (int sb = 0; sb < NB; sb += 2) {
             if (sb + 1 < NB) load_batch(ab1, sb + 1);
 #pragma unroll

@@ -74,3 +74,10 @@ def test_reference_cell_argument_errors():
     assert L.fe_reference_cell(3, 0, -1.0, None, None, None) == fe.FE_EINVAL
     assert L.fe_reference_cell(3, 5, 1.0, None, None, None) == fe.FE_EINVAL
     assert L.fe_reference_cell(3, 1, 1.0, None, None, None) == fe.FE_OK
+
+
+def test_density_entry_points_reject_null_without_a_device():
+    import paper_2504_00998_amd as fe
+    L = fe.lib()
+    assert L.fe_density(None, None, 4, 4, None, None, None) == fe.FE_EINVAL
+    assert L.fe_planar_average(None, None, 0, None, None) == fe.FE_EINVAL

@@ -545,3 +545,98 @@ def test_apply_rows_equals_assembled_operator():
         full = op.apply(X)[rows]
         part = O.apply_rows(m, Vq, wl.E, wl.z0, rows, X, proj, D if proj is not None else None)
         np.testing.assert_allclose(part, full, rtol=1e-13, atol=1e-13 * np.abs(full).max())
+
+
+# ------------------------------------------- density and planar averages (Sec. 2.1, Sec. 3.2)
+
+def test_density_and_planar_integral_sum_rule():
+    """int rho = sum_I M_I rho_I = 2 sum_n f_n |x_n|^2 for any block, and the
+    planar integrals integrate along z to the same total."""
+    m = _mesh((3.0, 3.0, 4.0), (3, 3, 4), 3, (1, 1, 0))
+    rng = np.random.default_rng(7)
+    X = rng.standard_normal((m.n, 9))
+    f = rng.uniform(-0.5, 2.0, 9)
+    rho = O.density(m, X, f)
+    total = 2.0 * (f * (X * X).sum(axis=0)).sum()
+    assert abs((m.mass() * rho).sum() - total) < 1e-12 * abs(total)
+    zc, mz = O.axis_positions(m, 2)
+    pl = O.planar_integral(m, rho)
+    assert pl.shape == (11,)
+    assert abs((mz * pl).sum() - total) < 1e-12 * abs(total)
+
+
+@pytest.mark.parametrize("bcz", [0, 2])
+def test_planar_integral_of_separable_orbital_closed_form(bcz):
+    """psi = a(z) with periodic x, y: rho^0(z) = 2 f a(z)^2 L_x L_y exactly (the
+    GLL weights of a periodic axis sum to its length)."""
+    L = (2.5, 3.5, 5.0)
+    m = _mesh(L, (2, 3, 4), 4, (1, 1, bcz))
+    z = m.dof_coords()[:, 2]
+    a = np.cos(0.7 * z) + 0.3 * z
+    X = (np.sqrt(m.mass()) * a)[:, None]
+    f = np.array([0.75])
+    pl = O.planar_integral(m, O.density(m, X, f))
+    zc, _ = O.axis_positions(m, 2)
+    ref = 2.0 * 0.75 * (np.cos(0.7 * zc) + 0.3 * zc) ** 2 * L[0] * L[1]
+    np.testing.assert_allclose(pl, ref, rtol=1e-13)
+
+
+def test_planar_average_of_constant_and_linear_fields():
+    """The average over a plane of a constant is the constant, of -E(z - z0)
+    is -E(z_k - z0), on any x-y boundary conditions."""
+    for bc in [(1, 1, 0), (0, 2, 2), (2, 0, 1)]:
+        m = _mesh((2.0, 3.0, 4.0), (2, 3, 4), 3, bc)
+        z = m.dof_coords()[:, 2]
+        zc, _ = O.axis_positions(m, 2)
+        np.testing.assert_allclose(O.planar_integral(m, np.full(m.n, 1.7), normalize=True), 1.7, rtol=1e-14)
+        np.testing.assert_allclose(O.planar_integral(m, -0.01 * (z - 2.0), normalize=True), -0.01 * (zc - 2.0),
+                                   rtol=1e-12, atol=1e-16)
+
+
+def test_planar_integral_brute_force_p2():
+    """p = 2 by hand: GLL weights (1/3, 4/3, 1/3) on [-1, 1], assembled masses
+    on each axis written out, plane sums by explicit loops over node positions."""
+    h = 1.5
+    m = _mesh((3 * h, 2 * h, 2 * h), (3, 2, 2), 2, (1, 0, 2))
+    w = np.array([1.0, 4.0, 1.0]) / 3.0
+
+    def masses(nce, bc):
+        mass = np.zeros(2 * nce + 1)
+        for c in range(nce):
+            for i in range(3):
+                mass[2 * c + i] += 0.5 * h * w[i]
+        if bc == 1:
+            mass[0] += mass[-1]
+            return mass[:-1]
+        if bc == 0:
+            return mass[1:-1]
+        return mass
+
+    mx, my, mz = masses(3, 1), masses(2, 0), masses(2, 2)
+    rng = np.random.default_rng(3)
+    F = rng.standard_normal(m.n)
+    xyz = m.dof_coords()
+    # node positions along each axis from the coordinates (h/2 spacing at p = 2)
+    ix = np.rint(xyz[:, 0] / (0.5 * h)).astype(int)
+    iy = np.rint(xyz[:, 1] / (0.5 * h)).astype(int) - 1  # Dirichlet: first free position is 1
+    iz = np.rint(xyz[:, 2] / (0.5 * h)).astype(int)
+    ref = np.zeros(len(mz))
+    for I in range(m.n):
+        ref[iz[I]] += mx[ix[I]] * my[iy[I]] * F[I]
+    np.testing.assert_allclose(O.planar_integral(m, F), ref, rtol=1e-13, atol=1e-14)
+
+
+def test_density_of_box_ground_state_matches_continuum():
+    """Dirichlet cube, V = 0: the lowest orbital approaches (2/L)^{3/2} prod sin,
+    so rho^0(z) -> (4/L) sin^2(pi z / L) for one doubly occupied orbital."""
+    Lb = 4.0
+    m = _mesh((Lb, Lb, Lb), (4, 4, 4), 4, (0, 0, 0))
+    op = O.Operator(m, None, 0.0, 0.5 * Lb)
+    import scipy.sparse.linalg as sla
+    A = op.A.to_scipy() if hasattr(op.A, "to_scipy") else op.A
+    vals, vecs = sla.eigsh(A, k=1, which="SA", tol=1e-12)
+    x = vecs[:, :1]
+    pl = O.planar_integral(m, O.density(m, x, np.array([1.0])))
+    zc, _ = O.axis_positions(m, 2)
+    ref = 4.0 / Lb * np.sin(np.pi * zc / Lb) ** 2
+    assert np.abs(pl - ref).max() < 1e-5 * ref.max()  # discretisation error ~3e-6 at p = 4, h = 1
