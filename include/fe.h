@@ -232,6 +232,27 @@ fe_status fe_density(fe_mesh *mesh, const double *X, int64_t N, int64_t ld, cons
 fe_status fe_planar_average(fe_mesh *mesh, const double *field, int32_t normalize, double *out,
                             hipStream_t stream);
 
+/* Electrostatic potential on the mesh's finite-element space (Sec. 2.2, the
+ * Poisson problem -lap(phi) / 4 pi = rho + b): solves K phi = 4 pi M s for
+ * the nodal charge density s, by Jacobi-preconditioned conjugate gradients
+ * on M^-1/2 (1/2 K) M^-1/2 (the step kernel with a zero diagonal term; any
+ * potential set on the mesh is ignored).  Boundary conditions are the
+ * mesh's: phi = 0 on Dirichlet faces; with no Dirichlet axis (periodic x-y
+ * and zero-Neumann z, Sec. 2.2.1) the constant null space is projected out
+ * and phi has zero mean (the charge's mean is removed, i.e. a neutral slab
+ * is assumed).  Inhomogeneous Dirichlet data (Sec. 2.2.2) are added by the
+ * caller as a lifting with zero Laplacian.  charge, phi: device, n doubles;
+ * work: device, >= fe_poisson_work_bytes(mesh) bytes.  Stops when
+ * |r| / |b| <= tol or after maxit iterations (r, b: residual and right-hand
+ * side of the scaled system in x = M^1/2 phi); *iters_host and *relres_host
+ * (may be NULL) receive the iteration count and the final |r| / |b|.  Synchronous
+ * with stream (reads back dot products).  FE_EINVAL for NULL arguments,
+ * tol <= 0 or maxit < 1; FE_ENOMEM if work is too small. */
+size_t fe_poisson_work_bytes(const fe_mesh *mesh);
+fe_status fe_poisson_solve(fe_mesh *mesh, const double *charge, double *phi, double tol, int32_t maxit,
+                           double *work, size_t work_bytes, int32_t *iters_host, double *relres_host,
+                           hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

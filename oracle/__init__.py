@@ -377,6 +377,25 @@ def planar_integral(mesh: Mesh, field: np.ndarray, normalize: bool = False) -> n
     return out
 
 
+def poisson(mesh: Mesh, s: np.ndarray) -> np.ndarray:
+    """Sec. 2.2 electrostatics on the finite-element space: -lap(phi) / 4 pi = s
+    in Galerkin form, K phi = 4 pi M s (GLL-collocated right-hand side), with
+    phi = 0 on Dirichlet faces.  With no Dirichlet axis K is singular (the
+    constants); then the charge's mean is removed and the zero-mean solution
+    (sum M phi = 0) is taken, by a bordered sparse direct solve."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+    K = stiffness(mesh).tocsc()
+    M = mesh.mass()
+    s = np.asarray(s, dtype=np.float64)
+    if 0 in mesh.bc:
+        return sla.spsolve(K, 4.0 * np.pi * M * s)
+    s0 = s - (M @ s) / M.sum()
+    A = sp.bmat([[K, sp.csc_matrix(M[:, None])], [sp.csc_matrix(M[None, :]), None]], format="csc")
+    sol = sla.spsolve(A, np.concatenate([4.0 * np.pi * M * s0, [0.0]]))
+    return sol[:-1]
+
+
 def stiffness(mesh: Mesh):
     """Global stiffness K (no 1/2, unscaled) as scipy CSR."""
     return CSR(lib().or_assemble(C.byref(mesh._m), 0, None, 0.0, 0.0)).to_scipy()

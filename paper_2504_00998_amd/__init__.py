@@ -73,6 +73,8 @@ def lib() -> C.CDLL:
         "fe_rayleigh_ritz": ([vp, vp, vp, vp, i64, i64, vp, vp], C.c_int),
         "fe_density": ([vp, vp, i64, i64, vp, vp, vp], C.c_int),
         "fe_planar_average": ([vp, vp, i32, vp, vp], C.c_int),
+        "fe_poisson_work_bytes": ([vp], C.c_size_t),
+        "fe_poisson_solve": ([vp, vp, vp, dbl, i32, vp, C.c_size_t, C.POINTER(i32), C.POINTER(dbl), vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -250,6 +252,23 @@ class Mesh:
             out = torch.empty(self.nf[2], dtype=torch.float64, device=field.device)
         _check(lib().fe_planar_average(self._h, _ptr(field), int(bool(normalize)), _ptr(out), _stream(stream)))
         return out
+
+    def poisson(self, charge, tol: float = 1e-12, maxit: int = 100000, phi=None, work=None, stream=None):
+        """Electrostatic potential of a nodal charge density on this mesh's
+        space and boundary conditions (fe_poisson_solve): K phi = 4 pi M s.
+        Returns (phi, iterations, final relative residual)."""
+        import torch
+        if charge.dtype != torch.float64 or not charge.is_cuda or not charge.is_contiguous() or charge.numel() != self.n:
+            raise ValueError("charge must be a contiguous float64 device tensor of n values")
+        if phi is None:
+            phi = torch.empty(self.n, dtype=torch.float64, device=charge.device)
+        need = int(lib().fe_poisson_work_bytes(self._h))
+        if work is None:
+            work = torch.empty((need + 7) // 8, dtype=torch.float64, device=charge.device)
+        it, rel = C.c_int32(), C.c_double()
+        _check(lib().fe_poisson_solve(self._h, _ptr(charge), _ptr(phi), float(tol), int(maxit), _ptr(work),
+                                      work.numel() * 8, C.byref(it), C.byref(rel), _stream(stream)))
+        return phi, it.value, rel.value
 
     def lanczos_bounds(self, v0, k: int = 10, stream=None):
         a0, b = C.c_double(), C.c_double()

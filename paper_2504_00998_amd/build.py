@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfe.so")
 SOURCES = ["fe_api.cpp", "fe_refelem.cpp", "fe_dense.cpp", "fe_adjoint.cpp", "fe_kernels.hip", "fe_nonlocal.hip",
-           "fe_density.hip"]
+           "fe_density.hip", "fe_poisson.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -44,6 +44,13 @@ static fe_status handle(fe_mesh *m, hipStream_t s, rocblas_handle &h) {
     return FE_OK;
 }
 
+fe_status blas_handle(fe_mesh *m, hipStream_t s, void **h) {
+    rocblas_handle hh;
+    fe_status st = handle(m, s, hh);
+    *h = hh;
+    return st;
+}
+
 // Eigenvalues of a small symmetric matrix (row-major, n x n) by cyclic Jacobi.
 static void jacobi_eigvals(std::vector<double> A, int n, std::vector<double> &ev) {
     for (int sweep = 0; sweep < 100; ++sweep) {

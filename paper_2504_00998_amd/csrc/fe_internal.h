@@ -109,6 +109,7 @@ struct StepArgs {
     int64_t ldm;
     double alpha, beta, shift;
     int64_t N;
+    const double *v = nullptr;  // diagonal term of H~; null: the mesh's potential
 };
 
 hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipStream_t s);
@@ -123,6 +124,12 @@ void cheb_coefficients(int mdeg, double a, double b, double a0, std::vector<doub
                        double &c);
 fe_status validate_filter_args(fe_mesh *m, int64_t N, int32_t mdeg, double a, double b, double a0, fe_dtype prec);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
+fe_status ensure_scratch_dense(fe_mesh *m, size_t bytes);
+fe_status blas_handle(fe_mesh *m, hipStream_t s, void **h);
+// Poisson helpers (fe_poisson.hip)
+hipError_t launch_mass_sqrt(const fe_mesh *m, double *out, hipStream_t s);
+hipError_t launch_vmul(double *z, const double *a, const double *b, int64_t n, hipStream_t s);
+hipError_t launch_xpby(double *p, const double *z, double beta, int64_t n, hipStream_t s);
 hipError_t launch_sum_partials(const double *P, int64_t nb, int64_t len, double *S, hipStream_t s);
 hipError_t launch_zero_lower(double *A, int N, hipStream_t s);
 hipError_t launch_axpby(double *Y, int64_t ldy, const double *X, int64_t ldx, int64_t n, int64_t N, double a,

@@ -1085,6 +1085,142 @@ static hipError_t launch_row_p(StepParams prm, const fe_mesh *m, hipStream_t s) 
 }
 
 // ------------------------------------------------------------------------
+// Single-vector step (N = 1, FP64): the 16 columns of the MFMA tile carry 16
+// cells of the colour instead of 16 vectors, so one cell-matrix fragment
+// multiplies 16 cells at once.  A workgroup takes 16 cells; each wave a 16-row
+// tile; lane l owns row 4((l/4)%4) + l/16 of the four cells 4(l%4) .. +3 of
+// the batch (the FP64 4x4x4 layout of the row-owner kernel with cells in
+// place of vectors).  Cells of one colour share no node, so every output is
+// written by one lane.  Same arithmetic, in the same order, as the other
+// FP64 variants at N = 1.
+template <int P, int BK>
+__global__ __launch_bounds__((64 * RowShape<P, 1>::W)) __attribute__((amdgpu_waves_per_eu(5)))
+void step_cells_kernel(StepParams k, int64_t ncells) {
+    constexpr int N1 = P + 1, NC = N1 * N1 * N1, NCP = (NC + 31) / 32 * 32, NKS = NCP / 4;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *xs = reinterpret_cast<double *>(smem);  // [NCP][16 cells], D X
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int rl = 4 * ((lane >> 2) & 3) + (lane >> 4);
+    const int cq = 4 * (lane & 3);  // first of the lane's four cells in the batch
+    const int r = 16 * wave + rl;
+    const int64_t cell0 = (int64_t)blockIdx.x * 16 + cq;
+
+    const double *A = reinterpret_cast<const double *>(k.A) + (size_t)wave * NKS * 64 + lane;
+    constexpr int BKE = batch_size(NKS, BK), NB = NKS / BKE;
+    static_assert(NKS % BKE == 0, "k-steps must split into batches");
+    auto load_batch = [&](double (&ab)[BKE], int sb) {
+#pragma unroll
+        for (int j = 0; j < BKE; ++j) ab[j] = A[(size_t)(sb * BKE + j) * 64];
+    };
+    double ab0[BKE], ab1[BKE];
+    load_batch(ab0, 0);
+
+    NodeRef nr[4];
+    bool fst[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t ci = min(cell0 + q, ncells - 1);
+        const ItemCell c = item_cell(k, ci);
+        nr[q] = node_ref<P>(k, c, r);
+        if (cell0 + q >= ncells) nr[q].I = -1;
+        fst[q] = r < NC && node_first<P>(k, c, r);
+    }
+    double xv[4], ov[4], vraw[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t Ic = max(nr[q].I, 0);
+        xv[q] = k.X[Ic * k.ldx];
+        ov[q] = !fst[q] ? k.Y[Ic * k.ldy] : (k.Ym1 ? k.Ym1[Ic * k.ldm] : 0.0);
+        vraw[q] = k.v[Ic];
+    }
+    double bo[4], d[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const bool ok = nr[q].I >= 0;
+        const bool useo = !fst[q] || k.Ym1 != nullptr;
+        const double vI = (ok && fst[q]) ? vraw[q] : 0.0;
+        const double sc = k.alpha * (vI - k.shift);
+        d[q] = node_scale(nr[q]);
+        const double x = ok ? xv[q] : 0.0;
+        const double o = (ok && useo) ? ov[q] : 0.0;
+        double base = sc * x;
+        if (k.Ym1) base -= k.beta * o;
+        bo[q] = fst[q] ? base : o;
+        xv[q] = d[q] * x;
+    }
+    {
+        double2 *dst = reinterpret_cast<double2 *>(xs + r * 16 + cq);
+        dst[0] = double2{xv[0], xv[1]};
+        dst[1] = double2{xv[2], xv[3]};
+    }
+    __syncthreads();
+
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    auto mul_batch = [&](const double (&ab)[BKE], int sb) {
+#pragma unroll
+        for (int j = 0; j < BKE; ++j) {
+            double b[4];
+            f64_quad_b(xs, sb * BKE + j, lane, b);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = __builtin_amdgcn_mfma_f64_4x4x4f64(ab[j], b[q], acc[q], 0, 0, 0);
+        }
+    };
+    constexpr int UNRB = NB <= 8 ? NB : 1;
+#pragma unroll UNRB
+    for (int sb = 0; sb < NB; sb += 2) {
+        if (sb + 1 < NB) load_batch(ab1, sb + 1);
+        mul_batch(ab0, sb);
+        if (sb + 1 < NB) {
+            if (sb + 2 < NB) load_batch(ab0, sb + 2);
+            mul_batch(ab1, sb + 1);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (nr[q].I >= 0) k.Y[(int64_t)nr[q].I * k.ldy] = bo[q] + k.alpha * d[q] * acc[q];
+}
+
+template <int P>
+static hipError_t launch_cells_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
+    constexpr int NCP = RowShape<P, 1>::NCP, W = RowShape<P, 1>::W;
+    static_assert(RowShape<P, 1>::NT <= 16, "one wave per row tile");
+    const size_t smem = (size_t)NCP * 16 * sizeof(double);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step_cells_kernel<P, 4>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    prm.nchunk = 1;
+    for (int c2 = 0; c2 < m->ncol[2]; ++c2)
+        for (int c1 = 0; c1 < m->ncol[1]; ++c1)
+            for (int c0 = 0; c0 < m->ncol[0]; ++c0) {
+                int col[3] = {c0, c1, c2};
+                int64_t cells = 1;
+                for (int a = 0; a < 3; ++a) {
+                    const AxisInfo &ax = prm.ax[a];
+                    int cnt;
+                    if (col[a] == 2) cnt = 1;
+                    else {
+                        int limit = ax.ncol == 3 ? ax.ncell - 1 : ax.ncell;
+                        cnt = limit > col[a] ? (limit - col[a] + 1) / 2 : 0;
+                    }
+                    prm.col[a] = col[a];
+                    prm.cnt[a] = cnt;
+                    cells *= cnt;
+                }
+                if (cells == 0) continue;
+                hipLaunchKernelGGL((step_cells_kernel<P, 4>), dim3((unsigned)((cells + 15) / 16)), dim3(64 * W), smem,
+                                   s, prm, cells);
+                hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+            }
+    return hipSuccess;
+}
+
+// ------------------------------------------------------------------------
 // Warp-specialised row-owner variant (p <= 4): persistent workgroups walk the
 // items (cell, G chunks of 16 vectors) of a colour with stride gridDim.x.  A
 // workgroup has NT compute waves (one 16-row tile of (1/2)K_c each) and NT
@@ -1812,7 +1948,7 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
     prm.nchunk = (int)((a.N + 15) / 16);
     prm.axisD = m->d_axis;
     prm.maxf = m->maxf;
-    prm.v = m->d_v;
+    prm.v = a.v ? a.v : m->d_v;
     prm.A = prec == FE_F64 ? (const void *)m->d_Af64 : prec == FE_F32 ? (const void *)m->d_Af32 : (const void *)m->d_Abf16;
     for (int d = 0; d < 3; ++d) {
         prm.ax[d].ncell = m->ncell[d];
@@ -1837,6 +1973,16 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
         }
         if (e != hipErrorNotSupported) return e;
         // otherwise: the multi-chunk kernel below
+    }
+    if (m->kernel_variant == 0 && prec == FE_F64 && prm.N == 1 && m->p <= 5) {
+        switch (m->p) {
+        case 1: return launch_cells_p<1>(prm, m, s);
+        case 2: return launch_cells_p<2>(prm, m, s);
+        case 3: return launch_cells_p<3>(prm, m, s);
+        case 4: return launch_cells_p<4>(prm, m, s);
+        case 5: return launch_cells_p<5>(prm, m, s);
+        default: break;
+        }
     }
     if (m->kernel_variant == 8) {
 #define FE_WS(PP)                                                                    \

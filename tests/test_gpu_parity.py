@@ -224,3 +224,23 @@ def test_lanczos_cholqr_rayleigh_ritz_on_device():
     theta, Xr = gm.rayleigh_ritz(Q)
     th_o, _ = O.rayleigh_ritz(op.apply, Qh)
     np.testing.assert_allclose(theta, th_o, atol=1e-12 * np.abs(lam).max())
+
+
+@pytest.mark.parametrize("shape,p", [((3, 5, 4), 2), ((5, 4, 7), 3), ((6, 6, 9), 4), ((3, 3, 4), 5)])
+def test_single_vector_cell_batched_kernel(shape, p):
+    """N = 1 in FP64 runs the cell-batched kernel (16 cells in the MFMA vector
+    columns): bitwise equal to the one-cell kernel, equal to the oracle, on
+    colours whose cell counts are not multiples of 16; the recurrence form
+    (beta != 0, Y_{k-1} read) through a short filter."""
+    wl = W.small_slab(shape, p=p, N=1)
+    print("case:", dict(shape=shape, p=p), flush=True)
+    op, gm, _ = _setup(wl)
+    X = torch.from_numpy(wl.X(op.n)).cuda()
+    gm.set_kernel(1)
+    Y1 = gm.hx(X)
+    F1 = gm.cheb_filter(X, 6, 2.0, 400.0, -0.5)
+    gm.set_kernel(0)
+    Y0 = gm.hx(X)
+    F0 = gm.cheb_filter(X, 6, 2.0, 400.0, -0.5)
+    assert torch.equal(Y0, Y1) and torch.equal(F0, F1)
+    assert _relerr(Y0.cpu().numpy(), op.apply(wl.X(op.n))) < 1e-13

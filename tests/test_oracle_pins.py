@@ -640,3 +640,47 @@ def test_density_of_box_ground_state_matches_continuum():
     zc, _ = O.axis_positions(m, 2)
     ref = 4.0 / Lb * np.sin(np.pi * zc / Lb) ** 2
     assert np.abs(pl - ref).max() < 1e-5 * ref.max()  # discretisation error ~3e-6 at p = 4, h = 1
+
+
+# ------------------------------------------------ electrostatics (Sec. 2.2)
+
+def test_poisson_manufactured_periodic_neumann():
+    """Periodic x, y and zero-Neumann z (the constant-field setup): phi =
+    cos(2 pi z / L_z) (zero flux at both z faces, zero mean) from
+    s = -lap(phi) / 4 pi; the FE solution matches at the nodes."""
+    L = (3.0, 3.0, 8.0)
+    m = _mesh(L, (3, 3, 8), 4, (1, 1, 2))
+    z = m.dof_coords()[:, 2]
+    k = 2 * np.pi / L[2]
+    exact = np.cos(k * z)
+    s = k * k * np.cos(k * z) / (4 * np.pi)
+    phi = O.poisson(m, s)
+    assert abs((m.mass() * phi).sum()) < 1e-10
+    assert np.abs(phi - exact).max() < 2e-5
+
+
+def test_poisson_manufactured_dirichlet_z_with_x_variation():
+    L = (4.0, 2.0, 6.0)
+    m = _mesh(L, (4, 2, 6), 4, (1, 1, 0))
+    x, z = m.dof_coords()[:, 0], m.dof_coords()[:, 2]
+    kx, kz = 2 * np.pi / L[0], np.pi / L[2]
+    exact = np.sin(kz * z) * (1 + 0.3 * np.cos(kx * x))
+    lap = -(kz ** 2) * exact - 0.3 * kx ** 2 * np.sin(kz * z) * np.cos(kx * x)
+    phi = O.poisson(m, -lap / (4 * np.pi))
+    assert np.abs(phi - exact).max() < 5e-5
+
+
+def test_poisson_residual_mean_and_neutralisation():
+    """The solve satisfies K phi = 4 pi M (s - mean) to rounding, phi has zero
+    mean, and adding a constant to s changes nothing (neutral-slab reading)."""
+    m = _mesh((3.0, 3.0, 4.0), (3, 3, 4), 3, (1, 1, 2))
+    rng = np.random.default_rng(4)
+    s = rng.standard_normal(m.n)
+    phi = O.poisson(m, s)
+    M = m.mass()
+    s0 = s - (M @ s) / M.sum()
+    K = O.stiffness(m)
+    r = K @ phi - 4 * np.pi * M * s0
+    assert np.linalg.norm(r) < 1e-10 * np.linalg.norm(4 * np.pi * M * s0)
+    assert abs(M @ phi) < 1e-10 * np.abs(phi).max()
+    np.testing.assert_allclose(O.poisson(m, s + 2.5), phi, atol=1e-9 * np.abs(phi).max())
