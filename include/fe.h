@@ -232,6 +232,17 @@ fe_status fe_density(fe_mesh *mesh, const double *X, int64_t N, int64_t ld, cons
 fe_status fe_planar_average(fe_mesh *mesh, const double *field, int32_t normalize, double *out,
                             hipStream_t stream);
 
+/* Electronic dipole about z0 (Sec. 3.1, mu_z = int rho (z - z0) for the
+ * electron density; the nuclear part is the caller's):
+ *   *mu_host = sum_I M_I rho[I] (z_I - z0),
+ * the GLL quadrature of the nodal density, computed as the z moment of the
+ * planar integrals (fe_planar_average) in a fixed order.  By the
+ * Hellmann-Feynman relation for v containing -E (z - z0), the band-energy
+ * derivative 2 sum f_n d eps_n / dE at eigenvectors equals -mu.  rho: device,
+ * n doubles.  Synchronous with stream (uses the mesh's scratch).  FE_EINVAL
+ * for NULL arguments or non-finite z0. */
+fe_status fe_dipole(fe_mesh *mesh, const double *rho, double z0, double *mu_host, hipStream_t stream);
+
 /* Electrostatic potential on the mesh's finite-element space (Sec. 2.2, the
  * Poisson problem -lap(phi) / 4 pi = rho + b): solves K phi = 4 pi M s for
  * the nodal charge density s, by Jacobi-preconditioned conjugate gradients

@@ -377,6 +377,13 @@ def planar_integral(mesh: Mesh, field: np.ndarray, normalize: bool = False) -> n
     return out
 
 
+def dipole(mesh: Mesh, rho: np.ndarray, z0: float) -> float:
+    """Sec. 3.1 electronic dipole about z0, int rho (z - z0), by the GLL
+    quadrature of the nodal density."""
+    z = mesh.dof_coords()[:, 2]
+    return float((mesh.mass() * np.asarray(rho, dtype=np.float64) * (z - z0)).sum())
+
+
 def poisson(mesh: Mesh, s: np.ndarray) -> np.ndarray:
     """Sec. 2.2 electrostatics on the finite-element space: -lap(phi) / 4 pi = s
     in Galerkin form, K phi = 4 pi M s (GLL-collocated right-hand side), with

@@ -73,6 +73,7 @@ def lib() -> C.CDLL:
         "fe_rayleigh_ritz": ([vp, vp, vp, vp, i64, i64, vp, vp], C.c_int),
         "fe_density": ([vp, vp, i64, i64, vp, vp, vp], C.c_int),
         "fe_planar_average": ([vp, vp, i32, vp, vp], C.c_int),
+        "fe_dipole": ([vp, vp, dbl, C.POINTER(dbl), vp], C.c_int),
         "fe_poisson_work_bytes": ([vp], C.c_size_t),
         "fe_poisson_solve": ([vp, vp, vp, dbl, i32, vp, C.c_size_t, C.POINTER(i32), C.POINTER(dbl), vp], C.c_int),
     }
@@ -252,6 +253,15 @@ class Mesh:
             out = torch.empty(self.nf[2], dtype=torch.float64, device=field.device)
         _check(lib().fe_planar_average(self._h, _ptr(field), int(bool(normalize)), _ptr(out), _stream(stream)))
         return out
+
+    def dipole(self, rho, z0: float, stream=None) -> float:
+        """Electronic dipole sum_I M_I rho_I (z_I - z0) (fe_dipole)."""
+        import torch
+        if rho.dtype != torch.float64 or not rho.is_cuda or not rho.is_contiguous() or rho.numel() != self.n:
+            raise ValueError("rho must be a contiguous float64 device tensor of n values")
+        mu = C.c_double()
+        _check(lib().fe_dipole(self._h, _ptr(rho), float(z0), C.byref(mu), _stream(stream)))
+        return mu.value
 
     def poisson(self, charge, tol: float = 1e-12, maxit: int = 100000, phi=None, work=None, stream=None):
         """Electrostatic potential of a nodal charge density on this mesh's

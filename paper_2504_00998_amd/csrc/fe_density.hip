@@ -11,6 +11,7 @@
 // order, so results are reproducible bit for bit.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <string>
 
 #include "fe_internal.h"
@@ -66,6 +67,22 @@ __global__ __launch_bounds__(256) void planar_kernel(const double *F, int nfx, i
     if (threadIdx.x == 0) out[k] = red[0] * scale;
 }
 
+// mu = sum_k m_z(k) (z_k - z0) P[k] over the free z positions, one workgroup,
+// fixed order
+__global__ __launch_bounds__(256) void zmoment_kernel(const double *P, int nz, const double *massz, const double *zc,
+                                                      double z0, double *out) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int kk = threadIdx.x; kk < nz; kk += 256) s += (massz[kk] * (zc[kk] - z0)) * P[kk];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
 #define FE_HIPD(call, what)                                                                          \
     do {                                                                                             \
         hipError_t _e = (call);                                                                      \
@@ -112,6 +129,25 @@ fe_status fe_planar_average(fe_mesh *m, const double *field, int32_t normalize, 
     hipLaunchKernelGGL(planar_kernel, dim3((unsigned)m->nf[2]), dim3(256), 0, st, field, (int)m->nf[0], (int)m->nf[1],
                        m->d_axis + 6 * m->maxf, m->maxf, scale, out);
     FE_HIPD(hipGetLastError(), "planar kernel");
+    return FE_OK;
+}
+
+fe_status fe_dipole(fe_mesh *m, const double *rho, double z0, double *mu_host, hipStream_t st) {
+    if (!m || !rho || !mu_host) return fail(FE_EINVAL, "NULL argument");
+    if (!std::isfinite(z0)) return fail(FE_EINVAL, "z0 must be finite");
+    FE_HIPD(hipSetDevice(m->device), "hipSetDevice");
+    const int nz = (int)m->nf[2];
+    fe_status rc = ensure_scratch_dense(m, (size_t)(nz + 8) * sizeof(double));
+    if (rc != FE_OK) return rc;
+    double *planes = m->d_scratch, *res = m->d_scratch + nz;
+    hipLaunchKernelGGL(planar_kernel, dim3((unsigned)nz), dim3(256), 0, st, rho, (int)m->nf[0], (int)m->nf[1],
+                       m->d_axis + 6 * m->maxf, m->maxf, 1.0, planes);
+    FE_HIPD(hipGetLastError(), "planar kernel");
+    hipLaunchKernelGGL(zmoment_kernel, dim3(1), dim3(256), 0, st, planes, nz, m->d_axis + 8 * m->maxf, m->d_zcoord, z0,
+                       res);
+    FE_HIPD(hipGetLastError(), "z-moment kernel");
+    FE_HIPD(hipMemcpyAsync(mu_host, res, sizeof(double), hipMemcpyDeviceToHost, st), "copy");
+    FE_HIPD(hipStreamSynchronize(st), "hipStreamSynchronize");
     return FE_OK;
 }
 

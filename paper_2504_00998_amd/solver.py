@@ -47,3 +47,34 @@ def subspace_iteration(mesh, X0, m: int, iters: int, a: float, b: float, a0: flo
         hist.append(theta)
         a, a0 = float(theta[-1]), float(theta[0])
     return hist, X
+
+
+def ground_state(mesh, Vq, E: float, z0: float, X0, v0, m: int, iters: int, prec: str = "f64", work=None):
+    """Set the potential (V_loc at the GLL points, field E about z0), bound the
+    spectrum by Lanczos from v0, and run `iters` filtered subspace iterations
+    from X0.  Returns (Ritz values of the last iteration, Ritz vectors)."""
+    mesh.set_potential(Vq, E, z0)
+    a0, b = spectrum_bounds(mesh, v0)
+    a = weyl_cut(a0, b, X0.shape[1], mesh.n)
+    hist, X = subspace_iteration(mesh, X0, m, iters, a, b, a0, prec=prec, work=work)
+    return hist[-1], X
+
+
+def polarizability(mesh, Vq, E: float, dE: float, z0: float, X0, v0, f, m: int, iters: int, prec: str = "f64"):
+    """Electronic response of the slab to the field (Sec. 3.1): ground states
+    at E - dE and E + dE, densities (fe_density) with occupations f, dipoles
+    about z0 (fe_dipole); alpha_z = (mu(E+dE) - mu(E-dE)) / (2 dE).  Also the
+    band energy 2 sum f eps at both fields, whose central difference is the
+    Hellmann-Feynman derivative -mu.  Returns a dict of host scalars."""
+    import torch
+    f = torch.as_tensor(f, dtype=torch.float64, device=X0.device)
+    out = {}
+    for tag, e in (("minus", E - dE), ("plus", E + dE)):
+        theta, X = ground_state(mesh, Vq, e, z0, X0, v0, m, iters, prec=prec)
+        rho = mesh.density(X, f)
+        out["mu_" + tag] = mesh.dipole(rho, z0)
+        out["eband_" + tag] = 2.0 * float((f.cpu().numpy() * theta).sum())
+    out["alpha"] = (out["mu_plus"] - out["mu_minus"]) / (2.0 * dE)
+    out["deband_dE"] = (out["eband_plus"] - out["eband_minus"]) / (2.0 * dE)
+    out["mu_mid"] = 0.5 * (out["mu_plus"] + out["mu_minus"])
+    return out

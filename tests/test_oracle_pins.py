@@ -684,3 +684,66 @@ def test_poisson_residual_mean_and_neutralisation():
     assert np.linalg.norm(r) < 1e-10 * np.linalg.norm(4 * np.pi * M * s0)
     assert abs(M @ phi) < 1e-10 * np.abs(phi).max()
     np.testing.assert_allclose(O.poisson(m, s + 2.5), phi, atol=1e-9 * np.abs(phi).max())
+
+
+# ------------------------------------------- dipole and polarisability (Sec. 3.1)
+
+def test_dipole_of_polynomial_profile_is_exact():
+    """psi = a(z) with a cubic: a^2 (z - z0) has degree 7, integrated exactly by
+    the p = 4 GLL rule per cell; periodic x, y give the factor L_x L_y."""
+    L = (2.0, 3.0, 6.0)
+    m = _mesh(L, (2, 3, 6), 4, (1, 1, 2))
+    z = m.dof_coords()[:, 2]
+    a = np.polynomial.Polynomial([0.3, -0.2, 0.05, 0.01])
+    X = (np.sqrt(m.mass()) * a(z))[:, None]
+    rho = O.density(m, X, np.array([1.0]))
+    z0 = 2.5
+    integrand = a * a * np.polynomial.Polynomial([-z0, 1.0])
+    exact = 2.0 * L[0] * L[1] * (integrand.integ()(L[2]) - integrand.integ()(0.0))
+    assert abs(O.dipole(m, rho, z0) - exact) < 1e-12 * abs(exact)
+
+
+@pytest.fixture(scope="module")
+def biased_box():
+    """A tiny Dirichlet box with two asymmetric wells; dense H~(E) and Z."""
+    wl = W.CFG1
+    m = O.Mesh.from_workload(wl)
+    Vq = W.wells_potential(m.quad_points(), wl.centres(), wl.depth, wl.sigma, wl.L, [b == 1 for b in wl.bc])
+    z = m.dof_coords()[:, 2] - wl.z0
+
+    def H(E):
+        return _Hdense(O.Operator(m, Vq, E, wl.z0))
+    return m, wl, H, z
+
+
+def test_hellmann_feynman_band_derivative_equals_minus_dipole(biased_box):
+    """d(2 sum_{n<4} eps_n)/dE by central differences of dense eigenvalues
+    equals -mu of the occupied eigenvectors (dH~/dE = -diag(z - z0))."""
+    m, wl, H, z = biased_box
+    E, h, nocc = 0.01, 1e-4, 4
+    lam_p = np.linalg.eigvalsh(H(E + h))[:nocc]
+    lam_m = np.linalg.eigvalsh(H(E - h))[:nocc]
+    lam, Q = np.linalg.eigh(H(E))
+    rho = O.density(m, Q[:, :nocc], np.ones(nocc))
+    mu = O.dipole(m, rho, wl.z0)
+    deb = 2.0 * (lam_p.sum() - lam_m.sum()) / (2 * h)
+    assert abs(deb + mu) < 1e-7 * max(1.0, abs(mu))
+
+
+def test_polarisability_sum_over_states_equals_dipole_derivative(biased_box):
+    """Second-order perturbation theory, alpha = 4 sum_{n occ, k virt}
+    |<x_k|Z|x_n>|^2 / (eps_k - eps_n), equals d mu / dE by central
+    differences of the dipole of the occupied eigenvectors."""
+    m, wl, H, z = biased_box
+    E, h, nocc = 0.0, 1e-4, 3
+    lam, Q = np.linalg.eigh(H(E))
+    Zm = Q.T @ (z[:, None] * Q)
+    occ, vir = slice(0, nocc), slice(nocc, None)
+    alpha_sos = 4.0 * (Zm[vir, occ] ** 2 / (lam[vir][:, None] - lam[occ][None, :])).sum()
+
+    def mu(e):
+        _, Qe = np.linalg.eigh(H(e))
+        return O.dipole(m, O.density(m, Qe[:, :nocc], np.ones(nocc)), wl.z0)
+    alpha_fd = (mu(E + h) - mu(E - h)) / (2 * h)
+    assert alpha_sos > 0
+    assert abs(alpha_fd - alpha_sos) < 1e-5 * alpha_sos
