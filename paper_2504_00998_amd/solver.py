@@ -49,28 +49,38 @@ def subspace_iteration(mesh, X0, m: int, iters: int, a: float, b: float, a0: flo
     return hist, X
 
 
-def ground_state(mesh, Vq, E: float, z0: float, X0, v0, m: int, iters: int, prec: str = "f64", work=None):
+def ground_state(mesh, Vq, E: float, z0: float, X0, v0, m: int, iters: int, prec: str = "f64", work=None,
+                 profile_q=None):
     """Set the potential (V_loc at the GLL points, field E about z0), bound the
     spectrum by Lanczos from v0, and run `iters` filtered subspace iterations
-    from X0.  Returns (Ritz values of the last iteration, Ritz vectors)."""
-    mesh.set_potential(Vq, E, z0)
+    from X0.  Returns (Ritz values of the last iteration, Ritz vectors).
+
+    profile_q: optional field shape per unit E at the GLL points (e.g. the
+    sawtooth of workloads.sawtooth divided by E); the field then enters as
+    V_loc + E profile instead of the linear -E (z - z0)."""
+    if profile_q is None:
+        mesh.set_potential(Vq, E, z0)
+    else:
+        mesh.set_potential(Vq + E * profile_q, 0.0, z0)
     a0, b = spectrum_bounds(mesh, v0)
     a = weyl_cut(a0, b, X0.shape[1], mesh.n)
     hist, X = subspace_iteration(mesh, X0, m, iters, a, b, a0, prec=prec, work=work)
     return hist[-1], X
 
 
-def polarizability(mesh, Vq, E: float, dE: float, z0: float, X0, v0, f, m: int, iters: int, prec: str = "f64"):
+def polarizability(mesh, Vq, E: float, dE: float, z0: float, X0, v0, f, m: int, iters: int, prec: str = "f64",
+                   profile_q=None):
     """Electronic response of the slab to the field (Sec. 3.1): ground states
     at E - dE and E + dE, densities (fe_density) with occupations f, dipoles
     about z0 (fe_dipole); alpha_z = (mu(E+dE) - mu(E-dE)) / (2 dE).  Also the
     band energy 2 sum f eps at both fields, whose central difference is the
-    Hellmann-Feynman derivative -mu.  Returns a dict of host scalars."""
+    Hellmann-Feynman derivative -mu (for the linear field).  Returns a dict of
+    host scalars.  profile_q: as in ground_state."""
     import torch
     f = torch.as_tensor(f, dtype=torch.float64, device=X0.device)
     out = {}
     for tag, e in (("minus", E - dE), ("plus", E + dE)):
-        theta, X = ground_state(mesh, Vq, e, z0, X0, v0, m, iters, prec=prec)
+        theta, X = ground_state(mesh, Vq, e, z0, X0, v0, m, iters, prec=prec, profile_q=profile_q)
         rho = mesh.density(X, f)
         out["mu_" + tag] = mesh.dipole(rho, z0)
         out["eband_" + tag] = 2.0 * float((f.cpu().numpy() * theta).sum())

@@ -188,6 +188,21 @@ def wells_potential_cells(axis_pts, centres: np.ndarray, depth: float, sigma: fl
     return np.ascontiguousarray(V.reshape(ncz * ncy * ncx, n1 ** 3))
 
 
+def sawtooth(z: np.ndarray, Lz: float, E: float, frac: float = 0.1) -> np.ndarray:
+    """Sawtooth form of the constant-field potential along z (Sec. 2.2.1;
+    extrema at `frac` of the box from either z face, Sec. 3.1): slope -E on
+    [frac Lz, (1 - frac) Lz], centred on Lz / 2, and the return ramp through
+    the z faces, so that V(0) = V(Lz) = 0."""
+    z = np.asarray(z, dtype=np.float64)
+    lo, hi = frac * Lz, (1.0 - frac) * Lz
+    vmax = -E * (lo - 0.5 * Lz)
+    ramp = (hi - lo) / (2.0 * lo)  # slope of the return ramp in units of E
+    mid = -E * (z - 0.5 * Lz)
+    below = vmax - ramp * E * (lo - z)
+    above = -vmax + ramp * E * (z - hi)
+    return np.where(z < lo, below, np.where(z > hi, above, mid))
+
+
 def workload_potential(wl: "Workload", quad_points: np.ndarray) -> np.ndarray:
     """V_loc of the workload at the given cell GLL points, (n_cells, (p+1)^3)."""
     periodic = [b == PERIODIC for b in wl.bc]

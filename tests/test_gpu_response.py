@@ -84,3 +84,49 @@ def test_hellmann_feynman_on_device_ground_states(response):
     assert abs(res["deband_dE"] - deb) < 1e-8 * abs(deb)
     assert abs(res["mu_mid"] - mu_mid) < 1e-10 * abs(mu_mid)
     assert abs(res["deband_dE"] + res["mu_mid"]) < 1e-4 * abs(res["mu_mid"])
+
+
+def test_sawtooth_field_filter_and_polarisability():
+    """The sawtooth V_app supplied at the GLL points: filter parity with the
+    oracle, and the polarisability to it against the dense reference and
+    second-order perturbation theory with the sawtooth as perturbation."""
+    import paper_2504_00998_amd as fe
+    from paper_2504_00998_amd import solver
+    wl = W.CFG1
+    gm = fe.Mesh.from_workload(wl)
+    om = O.Mesh.from_workload(wl)
+    Vq_h = W.workload_potential(wl, om.quad_points())
+    shape_q = W.sawtooth(om.quad_points()[:, :, 2], wl.L[2], 1.0)
+    E0 = 0.01
+    gm.set_potential(torch.from_numpy(Vq_h + E0 * shape_q).cuda(), 0.0, wl.z0)
+    op = O.Operator(om, Vq_h + E0 * shape_q, 0.0, wl.z0)
+    X = wl.X(om.n)
+    a0, b, _ = O.lanczos_bounds(op.apply, wl.lanczos_start(om.n), 10)
+    a = O.weyl_cut(a0, b, wl.N, om.n)
+    Y = gm.cheb_filter(torch.from_numpy(X).cuda(), wl.m, a, b, a0).cpu().numpy()
+    R = op.filter(X, wl.m, a, b, a0)
+    assert (np.linalg.norm(Y - R, axis=0) / np.linalg.norm(R, axis=0)).max() < 1e-12
+
+    nocc, dE = 4, 1e-3
+    f = np.zeros(wl.N)
+    f[:nocc] = 1.0
+    res = solver.polarizability(gm, torch.from_numpy(Vq_h).cuda(), 0.0, dE, wl.z0,
+                                torch.from_numpy(X).cuda(), torch.from_numpy(wl.lanczos_start(om.n)).cuda(), f,
+                                m=20, iters=25, profile_q=torch.from_numpy(shape_q).cuda())
+
+    def dense(e):
+        return np.linalg.eigh(O.Operator(om, Vq_h + e * shape_q, 0.0, wl.z0).A.to_scipy().toarray())
+
+    def mu(e):
+        _, Q = dense(e)
+        return O.dipole(om, O.density(om, Q[:, :nocc], np.ones(nocc)), wl.z0)
+    alpha_fd = (mu(dE) - mu(-dE)) / (2 * dE)
+    lam, Q = dense(0.0)
+    z = om.dof_coords()[:, 2] - wl.z0
+    s = W.sawtooth(om.dof_coords()[:, 2], wl.L[2], 1.0)
+    Zm = Q.T @ (z[:, None] * Q)
+    Sm = Q.T @ (s[:, None] * Q)
+    alpha_pt = -4.0 * (Zm[nocc:, :nocc] * Sm[nocc:, :nocc] / (lam[nocc:][:, None] - lam[:nocc][None, :])).sum()
+    print("sawtooth alpha device", res["alpha"], "dense FD", alpha_fd, "perturbation theory", alpha_pt, flush=True)
+    assert abs(res["alpha"] - alpha_fd) < 1e-7 * abs(alpha_fd)
+    assert abs(res["alpha"] - alpha_pt) < 2e-4 * abs(alpha_pt)

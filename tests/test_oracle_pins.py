@@ -747,3 +747,25 @@ def test_polarisability_sum_over_states_equals_dipole_derivative(biased_box):
     alpha_fd = (mu(E + h) - mu(E - h)) / (2 * h)
     assert alpha_sos > 0
     assert abs(alpha_fd - alpha_sos) < 1e-5 * alpha_sos
+
+
+def test_sawtooth_field_shape_and_collocation():
+    """The sawtooth V_app (Sec. 2.2.1, extrema at 0.1 of the box from the z
+    faces): zero at both faces, slope -E in the middle, extrema +-0.4 L E,
+    return slope 4 E; supplied at the GLL points it is collocated exactly into
+    the diagonal of H~."""
+    Lz, E = 8.0, 0.02
+    z = np.linspace(0.0, Lz, 801)
+    v = W.sawtooth(z, Lz, E)
+    assert abs(v[0]) < 1e-15 and abs(v[-1]) < 1e-15
+    mid = (z > 0.1 * Lz + 1e-9) & (z < 0.9 * Lz - 1e-9)
+    np.testing.assert_allclose(np.diff(v)[mid[:-1] & mid[1:]] / np.diff(z)[0], -E, rtol=1e-9)
+    assert abs(v.max() - 0.4 * Lz * E) < 1e-12 and abs(z[v.argmax()] - 0.1 * Lz) < 1e-9
+    assert abs(v.min() + 0.4 * Lz * E) < 1e-12 and abs(z[v.argmin()] - 0.9 * Lz) < 1e-9
+    np.testing.assert_allclose((v[1:40] - v[:39]) / np.diff(z)[0], 4 * E, rtol=1e-9)
+    m = _mesh((4.0, 4.0, Lz), (2, 2, 4), 3, (1, 1, 0))
+    zq = m.quad_points()[:, :, 2]
+    d = (O.Operator(m, W.sawtooth(zq, Lz, E), 0.0, 0.0).A.to_scipy()
+         - O.Operator(m, np.zeros_like(zq), 0.0, 0.0).A.to_scipy())
+    assert abs(d - sp.diags(d.diagonal())).max() < 1e-15
+    np.testing.assert_allclose(d.diagonal(), W.sawtooth(m.dof_coords()[:, 2], Lz, E), atol=1e-15)
