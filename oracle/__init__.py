@@ -66,6 +66,7 @@ def lib():
         L.or_gauss.argtypes = [C.c_int, _dp, _dp]
         L.or_lagrange_eval.argtypes = [C.c_int, C.c_double, _dp, _dp]
         L.or_cell_stiffness.argtypes = [C.c_int, C.c_int, C.c_double, _dp]
+        L.or_cell_advection.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, _dp]
         L.or_n_free.argtypes = [C.POINTER(_Mesh)]
         L.or_n_free.restype = C.c_int64
         L.or_cell_dofs.argtypes = [C.POINTER(_Mesh), _i64p]
@@ -134,6 +135,14 @@ def cell_stiffness(p: int, rule: int = 0, h: float = 1.0) -> np.ndarray:
     K = np.zeros(nc * nc)
     assert lib().or_cell_stiffness(p, rule, h, K) == 0
     return K.reshape(nc, nc)
+
+
+def cell_advection(p: int, axis: int, rule: int = 0, h: float = 1.0) -> np.ndarray:
+    """int_c N_l dN_l'/dx_axis over one cubic cell, (p+1)^3 x (p+1)^3."""
+    nc = (p + 1) ** 3
+    G = np.zeros(nc * nc)
+    assert lib().or_cell_advection(p, rule, h, axis, G) == 0
+    return G.reshape(nc, nc)
 
 
 # ------------------------------------------------------------------- the mesh
@@ -330,6 +339,58 @@ def apply_rows(mesh: Mesh, Vq: Optional[np.ndarray], E: float, z0: float, rows, 
     if rc != 0:
         raise MemoryError("or_apply_rows failed")
     return Yr
+
+
+# ------------------------------------------------------------ Bloch-k operator
+
+class BlochOperator:
+    """Bloch-periodic form of H~ (paper Sec. 2.3 with k-point sampling over
+    the periodic x-y directions): for psi = exp(i k.r) u with u periodic,
+    (1/2)(-i grad + k)^2 + V acting on u gives, on the FE space,
+        H~^k = H~ + |k|^2 / 2 - i M^-1/2 (k_x G_x + k_y G_y) M^-1/2,
+    G_a the assembled advection matrices int N_I dN_J/dx_a (real,
+    antisymmetric on periodic axes), so H~^k is Hermitian.  Complex sparse
+    (scipy); vectors are complex (n, N)."""
+
+    def __init__(self, op: "Operator", mesh: Mesh, k):
+        import scipy.sparse as sp
+        self.k = (float(k[0]), float(k[1]))
+        for a in range(2):
+            if self.k[a] != 0.0 and mesh.bc[a] != 1:
+                raise ValueError("a Bloch wave number needs a periodic axis")
+        n = op.n
+        h = mesh.L[0] / mesh.ncell[0]
+        dofs = mesh.cell_dofs()
+        M = mesh.mass()
+        rows, cols, vals = [], [], []
+        Gk = self.k[0] * cell_advection(mesh.p, 0, mesh.rule, h) + self.k[1] * cell_advection(mesh.p, 1, mesh.rule, h)
+        nc = mesh.nc
+        li, lj = np.meshgrid(np.arange(nc), np.arange(nc), indexing="ij")
+        for c in range(mesh.n_cells):
+            I, J = dofs[c][li], dofs[c][lj]
+            ok = (I >= 0) & (J >= 0)
+            rows.append(I[ok]); cols.append(J[ok]); vals.append(Gk[ok])
+        G = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+        d = 1.0 / np.sqrt(M)
+        S = sp.diags(d) @ G @ sp.diags(d)
+        kk = 0.5 * (self.k[0] ** 2 + self.k[1] ** 2)
+        self.A = (op.A.to_scipy().astype(np.complex128) + kk * sp.identity(n, dtype=np.complex128)
+                  - 1j * S.astype(np.complex128)).tocsr()
+        self.n = n
+
+    def apply(self, X: np.ndarray) -> np.ndarray:
+        return self.A @ X
+
+    def filter(self, X: np.ndarray, m: int, a: float, b: float, a0: float = float("nan")) -> np.ndarray:
+        """The same scaled / unscaled three-term recurrence as Operator.filter
+        (real coefficients), on complex vectors."""
+        al, be, c = cheb_coeffs(m, a, b, a0)
+        Ym1 = np.array(X, dtype=np.complex128)
+        Y = al[0] * (self.A @ Ym1 - c * Ym1)
+        for j in range(1, m):
+            Yn = al[j] * (self.A @ Y - c * Y) - be[j] * Ym1
+            Ym1, Y = Y, Yn
+        return Y
 
 
 # ------------------------------------------------------------ observables

@@ -171,6 +171,44 @@ int or_cell_stiffness(int p, int rule, double h, double *Kc) {
     return 0;
 }
 
+/* Cell advection matrix along axis a (0, 1, 2): G[l][l'] = int_c N_l dN_l'/dx_a
+ * over a cube of edge h, by the same direct 3-D Gauss quadrature (exact rule,
+ * p+2 points) or the GLL rule (rule 1).  The Bloch-k term of the Hamiltonian
+ * (the -i k.grad part of (-i grad + k)^2 / 2) is assembled from these. */
+int or_cell_advection(int p, int rule, double h, int axis, double *Gc) {
+    int n1 = p + 1, nc = n1 * n1 * n1;
+    double xi[16], wg[16], qx[16], qw[16];
+    int nq;
+    if (axis < 0 || axis > 2) return -1;
+    or_gll(p, xi, wg);
+    if (rule == 0) { nq = p + 2; or_gauss(nq, qx, qw); }
+    else if (rule == 1) { nq = p + 1; memcpy(qx, xi, sizeof(double) * n1); memcpy(qw, wg, sizeof(double) * n1); }
+    else return -1;
+    double *L = malloc(sizeof(double) * nq * n1), *dL = malloc(sizeof(double) * nq * n1);
+    for (int q = 0; q < nq; ++q) lagrange(p, xi, qx[q], L + q * n1, dL + q * n1);
+    double s = 2.0 / h, jac = (h / 2.0) * (h / 2.0) * (h / 2.0);
+    memset(Gc, 0, sizeof(double) * nc * nc);
+    for (int qz = 0; qz < nq; ++qz)
+    for (int qy = 0; qy < nq; ++qy)
+    for (int qx_ = 0; qx_ < nq; ++qx_) {
+        double wq = qw[qx_] * qw[qy] * qw[qz] * jac;
+        int q3[3] = {qx_, qy, qz};
+        for (int l = 0; l < nc; ++l) {
+            int il[3] = {l % n1, (l / n1) % n1, l / (n1 * n1)};
+            double v = L[q3[0] * n1 + il[0]] * L[q3[1] * n1 + il[1]] * L[q3[2] * n1 + il[2]];
+            for (int lp = 0; lp < nc; ++lp) {
+                int ip[3] = {lp % n1, (lp / n1) % n1, lp / (n1 * n1)};
+                double g = s;
+                for (int a = 0; a < 3; ++a)
+                    g *= (a == axis) ? dL[q3[a] * n1 + ip[a]] : L[q3[a] * n1 + ip[a]];
+                Gc[(size_t)l * nc + lp] += wq * v * g;
+            }
+        }
+    }
+    free(L); free(dL);
+    return 0;
+}
+
 /* ----------------------------------------------------------------- mesh */
 
 typedef struct {

@@ -769,3 +769,71 @@ def test_sawtooth_field_shape_and_collocation():
          - O.Operator(m, np.zeros_like(zq), 0.0, 0.0).A.to_scipy())
     assert abs(d - sp.diags(d.diagonal())).max() < 1e-15
     np.testing.assert_allclose(d.diagonal(), W.sawtooth(m.dof_coords()[:, 2], Lz, E), atol=1e-15)
+
+
+# ------------------------------------------------ Bloch-k operator (Sec. 2.3, k-point sampling)
+
+@pytest.mark.parametrize("p,rule", [(2, 0), (3, 0), (3, 1)])
+def test_cell_advection_is_a_kronecker_product(p, rule):
+    """int N_l dN_l'/dx over the cell = (h/2)^2 Mhat (x) Mhat (x) Chat with the
+    1-D Chat_ij = int l_i l_j' and the 1-D mass (consistent for the exact rule,
+    GLL-lumped for rule 1), from exact numpy polynomial integration."""
+    h = 1.7
+    xi, w = F.gll_numpy(p)
+    P = F.lagrange_polys(xi)
+    Ch = np.array([[F.integ(P[i] * P[j].deriv()) for j in range(p + 1)] for i in range(p + 1)])
+    Mh = np.diag(w) if rule == 1 else np.array([[F.integ(P[i] * P[j]) for j in range(p + 1)] for i in range(p + 1)])
+    for axis in range(3):
+        mats = [(h / 2) * Mh, (h / 2) * Mh, (h / 2) * Mh]
+        mats[axis] = Ch
+        ref = np.kron(mats[2], np.kron(mats[1], mats[0]))
+        np.testing.assert_allclose(O.cell_advection(p, axis, rule, h), ref, atol=1e-13)
+
+
+def test_bloch_operator_hermitian_and_reduces_at_gamma():
+    wl = W.small_slab((3, 3, 4), p=3, N=6)
+    m = O.Mesh.from_workload(wl)
+    Vq = W.workload_potential(wl, m.quad_points())
+    op = O.Operator(m, Vq, wl.E, wl.z0)
+    B = O.BlochOperator(op, m, (0.3, -0.7))
+    D = B.A - B.A.conj().T
+    assert abs(D).max() < 1e-12 * abs(B.A).max()
+    B0 = O.BlochOperator(op, m, (0.0, 0.0))
+    assert abs(B0.A - op.A.to_scipy()).max() == 0.0
+    X = wl.X(op.n)
+    np.testing.assert_allclose(B0.filter(X, 7, 2.0, 300.0, -0.5).real, op.filter(X, 7, 2.0, 300.0, -0.5), rtol=0,
+                               atol=1e-12 * np.abs(op.filter(X, 7, 2.0, 300.0, -0.5)).max())
+
+
+def test_bloch_free_particle_levels():
+    """V = 0, periodic x-y, Dirichlet z: the levels of H~^k approach
+    (k_x + 2 pi a / L_x)^2 / 2 + (k_y + 2 pi b / L_y)^2 / 2 + (pi c / L_z)^2 / 2."""
+    L = (4.0, 4.0, 6.0)
+    m = _mesh(L, (4, 4, 6), 4, (1, 1, 0))
+    op = O.Operator(m, None, 0.0, 0.0)
+    k = (0.35, -0.2)
+    B = O.BlochOperator(op, m, k)
+    lam = np.linalg.eigvalsh(B.A.toarray())[:12]
+    ref = sorted(0.5 * (k[0] + 2 * np.pi * a / L[0]) ** 2 + 0.5 * (k[1] + 2 * np.pi * b / L[1]) ** 2
+                 + 0.5 * (np.pi * c / L[2]) ** 2
+                 for a in range(-3, 4) for b in range(-3, 4) for c in range(1, 6))[:12]
+    np.testing.assert_allclose(lam, ref, rtol=2e-6)
+
+
+def test_bloch_sign_from_a_plane_wave():
+    """psi = exp(i k.r) u with u = exp(i g x) sin(pi z / Lz): the Rayleigh
+    quotient of H~^k at M^1/2 u is (k_x + g)^2/2 + k_y^2/2 + (pi/Lz)^2/2 up to
+    the FE error; the opposite sign of the k.grad term would give (k_x - g)^2/2."""
+    L = (4.0, 4.0, 6.0)
+    m = _mesh(L, (4, 4, 6), 5, (1, 1, 0))
+    op = O.Operator(m, None, 0.0, 0.0)
+    k = (0.4, 0.25)
+    g = 2 * np.pi / L[0]
+    B = O.BlochOperator(op, m, k)
+    xyz = m.dof_coords()
+    u = np.exp(1j * g * xyz[:, 0]) * np.sin(np.pi * xyz[:, 2] / L[2])
+    v = np.sqrt(m.mass()) * u
+    rq = (v.conj() @ (B.A @ v)).real / (v.conj() @ v).real
+    ref = 0.5 * (k[0] + g) ** 2 + 0.5 * k[1] ** 2 + 0.5 * (np.pi / L[2]) ** 2
+    wrong = 0.5 * (k[0] - g) ** 2 + 0.5 * k[1] ** 2 + 0.5 * (np.pi / L[2]) ** 2
+    assert abs(rq - ref) < 1e-6 < abs(wrong - ref) / 100
