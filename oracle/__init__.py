@@ -229,6 +229,7 @@ class Projectors:
 
     def __init__(self, mesh: Mesh, centres, r_cut: float, r_g: float):
         centres = np.ascontiguousarray(centres, dtype=np.float64)
+        self.centres = centres.copy()
         self.n_site = centres.shape[0]
         self._p = lib().or_projectors(C.byref(mesh._m), self.n_site, centres.reshape(-1),
                                       float(r_cut), float(r_g))
@@ -344,13 +345,17 @@ def apply_rows(mesh: Mesh, Vq: Optional[np.ndarray], E: float, z0: float, rows, 
 # ------------------------------------------------------------ Bloch-k operator
 
 class BlochOperator:
-    """Bloch-periodic form of H~ (paper Sec. 2.3 with k-point sampling over
-    the periodic x-y directions): for psi = exp(i k.r) u with u periodic,
-    (1/2)(-i grad + k)^2 + V acting on u gives, on the FE space,
-        H~^k = H~ + |k|^2 / 2 - i M^-1/2 (k_x G_x + k_y G_y) M^-1/2,
+    """Bloch form of H~ over the periodic x-y directions (paper Sec. 2.1,
+    governing equations for u = exp(-i k.r) psi): the local part
+    -1/2 lap - i k.grad + |k|^2/2 + V on the FE space is
+        H~ + |k|^2 / 2 - i M^-1/2 (k_x G_x + k_y G_y) M^-1/2,
     G_a the assembled advection matrices int N_I dN_J/dx_a (real,
-    antisymmetric on periodic axes), so H~^k is Hermitian.  Complex sparse
-    (scipy); vectors are complex (n, N)."""
+    antisymmetric on periodic axes), and the nonlocal part carries the phase
+    exp(-i k.(x - R - L_r)) on the ket side and its conjugate on the bra side,
+    i.e. C^k_I = exp(-i k.d_I) C~_I with d_I = x_I - R_s the displacement to
+    the image of the site the entry belongs to (minimum image), and
+    H~^k gains C^k diag(D) C^k^H.  Hermitian.  Complex sparse (scipy);
+    vectors are complex (n, N)."""
 
     def __init__(self, op: "Operator", mesh: Mesh, k):
         import scipy.sparse as sp
@@ -376,6 +381,17 @@ class BlochOperator:
         kk = 0.5 * (self.k[0] ** 2 + self.k[1] ** 2)
         self.A = (op.A.to_scipy().astype(np.complex128) + kk * sp.identity(n, dtype=np.complex128)
                   - 1j * S.astype(np.complex128)).tocsr()
+        if op.proj is not None:
+            Cm = op.proj.to_scipy().tocoo()
+            xyz = mesh.dof_coords()
+            site = Cm.col // 9
+            d = xyz[Cm.row] - op.proj.centres[site]
+            for a in range(3):
+                if mesh.bc[a] == 1:
+                    d[:, a] -= mesh.L[a] * np.round(d[:, a] / mesh.L[a])
+            ph = np.exp(-1j * (self.k[0] * d[:, 0] + self.k[1] * d[:, 1]))
+            Ck = sp.csr_matrix((Cm.data * ph, (Cm.row, Cm.col)), shape=Cm.shape)
+            self.A = (self.A + Ck @ sp.diags(op.Dnl.astype(np.complex128)) @ Ck.conj().T).tocsr()
         self.n = n
 
     def apply(self, X: np.ndarray) -> np.ndarray:

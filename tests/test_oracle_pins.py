@@ -837,3 +837,49 @@ def test_bloch_sign_from_a_plane_wave():
     ref = 0.5 * (k[0] + g) ** 2 + 0.5 * k[1] ** 2 + 0.5 * (np.pi / L[2]) ** 2
     wrong = 0.5 * (k[0] - g) ** 2 + 0.5 * k[1] ** 2 + 0.5 * (np.pi / L[2]) ** 2
     assert abs(rq - ref) < 1e-6 < abs(wrong - ref) / 100
+
+
+def test_bloch_band_folding_with_phase_twisted_projectors():
+    """Bloch's theorem on a supercell: for a potential and sites of period L_x,
+    the Gamma levels of the 2 L_x supercell are the union of the k_x = 0 and
+    k_x = pi / L_x levels of the L_x cell, up to the FE error of the exp(i k x)
+    factor (it shrinks from 2e-4 at p = 4 to 3e-7 at p = 6).  The site sits
+    0.3 from the periodic face, so its cutoff ball wraps and the projector
+    phase must use the minimum-image displacement; dropping the wrap, or
+    conjugating the projector phase against the -i k.grad term, moves the
+    folded levels by O(1)."""
+    import scipy.sparse as sp
+    p, Lx = 4, 3.0
+
+    def build(nx, cen):
+        m = _mesh((Lx * nx, 3.0, 4.0), (3 * nx, 3, 4), p, (1, 1, 0))
+        q = m.quad_points()
+        Vq = -1.5 * np.exp(-(q[..., 2] - 2.0) ** 2) * (1 + 0.5 * np.cos(2 * np.pi * q[..., 0] / Lx))
+        P = O.Projectors(m, np.array(cen), 1.2, 0.45)
+        D = np.tile([2.0, 0.7, 0.7, 0.7, 0.3, 0.3, 0.3, 0.3, 0.3], (len(cen), 1))
+        return m, O.Operator(m, Vq, 0.0, 0.0, P, D)
+
+    c0 = [0.3, 1.5, 2.0]
+    m1, op1 = build(1, [c0])
+    ms, ops = build(2, [c0, [c0[0] + Lx, c0[1], c0[2]]])
+    nev = 12
+    lam_sc = np.linalg.eigvalsh(O.BlochOperator(ops, ms, (0.0, 0.0)).A.toarray())[:nev]
+    l0 = np.linalg.eigvalsh(O.BlochOperator(op1, m1, (0.0, 0.0)).A.toarray())
+    k = np.pi / Lx
+    B = O.BlochOperator(op1, m1, (k, 0.0))
+
+    def folded(A):
+        return np.sort(np.concatenate([l0, np.linalg.eigvalsh(A.toarray())]))[:nev]
+
+    err = lambda lam: np.max(np.abs(lam - lam_sc) / np.abs(lam_sc))
+    assert err(folded(B.A)) < 1e-3
+    # the two plausible mistakes, planted in a copy of the operator
+    Cm = op1.proj.to_scipy().tocoo()
+    d = m1.dof_coords()[Cm.row] - op1.proj.centres[Cm.col // 9]
+    dw = d[:, 0] - Lx * np.round(d[:, 0] / Lx)
+    Dd = sp.diags(op1.Dnl.astype(complex))
+    C_ok = sp.csr_matrix((Cm.data * np.exp(-1j * k * dw), (Cm.row, Cm.col)), shape=Cm.shape)
+    base = B.A - C_ok @ Dd @ C_ok.conj().T
+    for ph in (np.exp(-1j * k * d[:, 0]), np.exp(1j * k * dw)):
+        Cb = sp.csr_matrix((Cm.data * ph, (Cm.row, Cm.col)), shape=Cm.shape)
+        assert err(folded(base + Cb @ Dd @ Cb.conj().T)) > 0.1
