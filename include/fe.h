@@ -264,6 +264,40 @@ fe_status fe_poisson_solve(fe_mesh *mesh, const double *charge, double *phi, dou
                            double *work, size_t work_bytes, int32_t *iters_host, double *relres_host,
                            hipStream_t stream);
 
+/* ---------------------------------------------------------------- Bloch-k
+ * Bloch form of the Hamiltonian over the periodic x-y directions (Sec. 2.1,
+ * governing equations for u_nk = exp(-i k.x) psi_nk): H~^k = H~ + |k|^2/2
+ * - i M^-1/2 (k_x G_x + k_y G_y) M^-1/2, G_a the assembled matrices
+ * int N_I dN_J/dx_a (antisymmetric on periodic axes, so H~^k is Hermitian),
+ * and the projectors of fe_set_nonlocal twisted to
+ * C^k_I = exp(-i k.(x_I - R_s)) C~_I (minimum-image displacement), so the
+ * nonlocal term becomes C^k diag(D) C^k^H.  Products in FP64 only.
+ *
+ * Complex blocks: device, n x N complex FP64 stored row-major as interleaved
+ * (re, im) pairs (the layout of C99 double _Complex / std::complex<double>),
+ * leading dimension ld >= N in complex elements, 8-byte aligned. */
+
+/* Set the wave vector (k_x, k_y) (bohr^-1) used by the _k entry points;
+ * (0, 0) is the Gamma point, where they equal the real entry points applied
+ * to the real and imaginary parts (bitwise).  FE_EINVAL for a non-finite k
+ * or a nonzero component along a non-periodic axis.  Waits for the device,
+ * then builds the k.G cell fragments and projector phases (synchronous). */
+fe_status fe_set_kpoint(fe_mesh *mesh, double kx, double ky);
+
+/* The current wave vector, k_host[2] (host pointer). */
+fe_status fe_get_kpoint(const fe_mesh *mesh, double *k_host);
+
+/* Y = H~^k X on complex blocks.  X, Y must not overlap.  Errors as for
+ * fe_hx_apply (FE_ESTATE without a potential).  N = 0 is a no-op. */
+fe_status fe_hx_apply_k(fe_mesh *mesh, const double *X, double *Y, int64_t N, int64_t ld, hipStream_t stream);
+
+/* Chebyshev filter of fe_cheb_filter (same coefficients, same recurrence)
+ * with H~^k on complex blocks.  work: device scratch of at least 2*n*N
+ * doubles (one complex recurrence block, leading dimension N); X, Y and work
+ * must not overlap. */
+fe_status fe_cheb_filter_k(fe_mesh *mesh, const double *X, double *Y, int64_t N, int64_t ld, int32_t m, double a,
+                           double b, double a0, double *work, size_t work_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

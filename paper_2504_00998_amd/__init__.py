@@ -76,6 +76,10 @@ def lib() -> C.CDLL:
         "fe_dipole": ([vp, vp, dbl, C.POINTER(dbl), vp], C.c_int),
         "fe_poisson_work_bytes": ([vp], C.c_size_t),
         "fe_poisson_solve": ([vp, vp, vp, dbl, i32, vp, C.c_size_t, C.POINTER(i32), C.POINTER(dbl), vp], C.c_int),
+        "fe_set_kpoint": ([vp, dbl, dbl], C.c_int),
+        "fe_get_kpoint": ([vp, vp], C.c_int),
+        "fe_hx_apply_k": ([vp, vp, vp, i64, i64, vp], C.c_int),
+        "fe_cheb_filter_k": ([vp, vp, vp, i64, i64, i32, dbl, dbl, dbl, vp, C.c_size_t, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -112,6 +116,14 @@ def _check_block(t, n: int, name: str):
     import torch
     if t.dtype != torch.float64 or not t.is_cuda:
         raise TypeError(f"{name} must be a float64 device tensor")
+    if t.dim() != 2 or t.shape[0] != n or t.stride(1) != 1:
+        raise ValueError(f"{name} must be (n={n}, N) with unit column stride")
+
+
+def _check_cblock(t, n: int, name: str):
+    import torch
+    if t.dtype != torch.complex128 or not t.is_cuda:
+        raise TypeError(f"{name} must be a complex128 device tensor")
     if t.dim() != 2 or t.shape[0] != n or t.stride(1) != 1:
         raise ValueError(f"{name} must be (n={n}, N) with unit column stride")
 
@@ -206,6 +218,45 @@ class Mesh:
             work = torch.empty(self.n * N, dtype=torch.float64, device=X.device)
         _check(lib().fe_cheb_filter(self._h, _ptr(X), _ptr(Y), N, ld, int(m), float(a), float(b), float(a0),
                                     _PREC[prec], _ptr(work), work.numel() * 8, _stream(stream)))
+        return Y
+
+    # --------------------------------------------------------------- Bloch-k
+    def set_kpoint(self, kx: float, ky: float):
+        """Bloch wave vector of the complex entry points (fe_set_kpoint)."""
+        _check(lib().fe_set_kpoint(self._h, float(kx), float(ky)))
+
+    def kpoint(self):
+        k = np.zeros(2)
+        _check(lib().fe_get_kpoint(self._h, k.ctypes.data))
+        return float(k[0]), float(k[1])
+
+    def hx_k(self, X, Y=None, stream=None):
+        """Y = H~^k X for a complex128 (n, N) device block (fe_hx_apply_k)."""
+        import torch
+        _check_cblock(X, self.n, "X")
+        N, ld = X.shape[1], X.stride(0)
+        if Y is None:
+            Y = torch.empty_strided(X.shape, X.stride(), dtype=torch.complex128, device=X.device)
+        _check_cblock(Y, self.n, "Y")
+        if Y.stride(0) != ld:
+            raise ValueError("X and Y must share the leading dimension")
+        _check(lib().fe_hx_apply_k(self._h, _ptr(X), _ptr(Y), N, ld, _stream(stream)))
+        return Y
+
+    def cheb_filter_k(self, X, m: int, a: float, b: float, a0: float = math.nan, Y=None, work=None, stream=None):
+        """Chebyshev filter with H~^k on a complex128 block (fe_cheb_filter_k)."""
+        import torch
+        _check_cblock(X, self.n, "X")
+        N, ld = X.shape[1], X.stride(0)
+        if Y is None:
+            Y = torch.empty_strided(X.shape, X.stride(), dtype=torch.complex128, device=X.device)
+        _check_cblock(Y, self.n, "Y")
+        if Y.stride(0) != ld:
+            raise ValueError("X and Y must share the leading dimension")
+        if work is None:
+            work = torch.empty(2 * self.n * N, dtype=torch.float64, device=X.device)
+        _check(lib().fe_cheb_filter_k(self._h, _ptr(X), _ptr(Y), N, ld, int(m), float(a), float(b), float(a0),
+                                      _ptr(work), work.numel() * work.element_size(), _stream(stream)))
         return Y
 
     def vjp_work_bytes(self, N: int, m: int, ckpt_stride: int = 1, col_chunk: int = 0) -> int:

@@ -130,21 +130,26 @@ static int axis_colours(int ncell, int bc) {
 // A fragments of the padded cell matrix for each MFMA shape:
 //   f64/f32 16x16x4 : frag[t][s][lane]    = A[16t + lane%16][4s + lane/16]
 //   bf16 16x16x32   : frag[t][s][lane][j] = A[16t + lane%16][32s + 8(lane/16) + j]
+void swizzle_f64(const fe_mesh *m, const std::vector<double> &A, std::vector<double> &f64) {
+    const int ncp = m->ncp, nc = m->nc, NT = ncp / 16, nks4 = ncp / 4;
+    f64.assign((size_t)NT * nks4 * 64, 0.0);
+    for (int t = 0; t < NT; ++t)
+        for (int s = 0; s < nks4; ++s)
+            for (int lane = 0; lane < 64; ++lane) {
+                const int r = 16 * t + lane % 16, c = 4 * s + lane / 16;
+                f64[((size_t)t * nks4 + s) * 64 + lane] = (r < nc && c < nc) ? A[(size_t)r * nc + c] : 0.0;
+            }
+}
+
 static void swizzle_fragments(const fe_mesh *m, std::vector<double> &f64, std::vector<float> &f32,
                               std::vector<uint16_t> &bf) {
     int ncp = m->ncp, nc = m->nc, NT = ncp / 16;
     auto A = [&](int r, int c) -> double { return (r < nc && c < nc) ? m->cellA[(size_t)r * nc + c] : 0.0; };
-    int nks4 = ncp / 4, nks32 = ncp / 32;
-    f64.assign((size_t)NT * nks4 * 64, 0.0);
-    f32.assign((size_t)NT * nks4 * 64, 0.0f);
+    int nks32 = ncp / 32;
+    swizzle_f64(m, m->cellA, f64);
+    f32.resize(f64.size());
+    for (size_t i = 0; i < f64.size(); ++i) f32[i] = (float)f64[i];
     bf.assign((size_t)NT * nks32 * 64 * 8, 0);
-    for (int t = 0; t < NT; ++t)
-        for (int s = 0; s < nks4; ++s)
-            for (int lane = 0; lane < 64; ++lane) {
-                double v = A(16 * t + lane % 16, 4 * s + lane / 16);
-                f64[((size_t)t * nks4 + s) * 64 + lane] = v;
-                f32[((size_t)t * nks4 + s) * 64 + lane] = (float)v;
-            }
     for (int t = 0; t < NT; ++t)
         for (int s = 0; s < nks32; ++s)
             for (int lane = 0; lane < 64; ++lane)
@@ -166,6 +171,7 @@ static void free_mesh(fe_mesh *m) {
     (void)hipFree(m->d_Abf16);
     (void)hipFree(m->d_v);
     (void)hipFree(m->d_wrel);
+    (void)hipFree(m->d_Sf64);
     (void)hipFree(m->d_scratch);
     nonlocal_release(m);
     if (m->blas) rocblas_destroy_handle(static_cast<rocblas_handle>(m->blas));
@@ -401,6 +407,117 @@ fe_status fe_cheb_filter(fe_mesh *m, const double *X, double *Y, int64_t N, int6
     for (int k = 1; k < mdeg; ++k) {
         st = filter_step(m, buf(k), ldb(k), buf(k + 1), ldb(k + 1), buf(k - 1), ldb(k - 1), al[k], be[k], c, N, prec,
                          s);
+        if (st != FE_OK) return st;
+    }
+    return FE_OK;
+}
+
+
+// ---------------------------------------------------------------- Bloch-k mode
+
+fe_status fe_set_kpoint(fe_mesh *m, double kx, double ky) {
+    if (!m) return fail(FE_EINVAL, "NULL mesh");
+    if (!std::isfinite(kx) || !std::isfinite(ky)) return fail(FE_EINVAL, "k must be finite");
+    if ((kx != 0.0 && m->bc[0] != FE_BC_PERIODIC) || (ky != 0.0 && m->bc[1] != FE_BC_PERIODIC))
+        return fail(FE_EINVAL, "a nonzero Bloch wave number needs a periodic axis");
+    FE_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    const double old[2] = {m->kvec[0], m->kvec[1]};
+    if (kx != 0.0 || ky != 0.0) {
+        std::vector<double> S, f;
+        cell_matrix_bloch(m->p, m->rule, m->h, kx, ky, S);
+        swizzle_f64(m, S, f);
+        if (!m->d_Sf64 && hipMalloc(&m->d_Sf64, f.size() * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            m->d_Sf64 = nullptr;
+            return fail(FE_ENOMEM, "device allocation failed in fe_set_kpoint");
+        }
+        FE_HIP(hipMemcpy(m->d_Sf64, f.data(), f.size() * sizeof(double), hipMemcpyHostToDevice), "hipMemcpy");
+    }
+    m->kvec[0] = kx;
+    m->kvec[1] = ky;
+    fe_status st = nonlocal_set_phase(m);
+    if (st != FE_OK) {
+        m->kvec[0] = old[0];
+        m->kvec[1] = old[1];
+    }
+    return st;
+}
+
+fe_status fe_get_kpoint(const fe_mesh *m, double *k_host) {
+    if (!m || !k_host) return fail(FE_EINVAL, "NULL argument");
+    k_host[0] = m->kvec[0];
+    k_host[1] = m->kvec[1];
+    return FE_OK;
+}
+
+}  // extern "C"
+
+namespace fe {
+
+// One step of the recurrence on complex blocks (n x N complex, interleaved
+// re/im, leading dimensions in complex elements): the real kernels on the
+// 2N real columns, plus the k.G product and the phase-twisted projectors
+// when k != 0.  |k|^2 / 2 enters through the shift.
+static fe_status filter_step_k(fe_mesh *m, const double *X, int64_t ldx, double *Y, int64_t ldy, const double *Ym1,
+                               int64_t ldm, double alpha, double beta, double shift, int64_t N, hipStream_t s) {
+    const bool gamma = m->kvec[0] == 0.0 && m->kvec[1] == 0.0;
+    const double kk = 0.5 * (m->kvec[0] * m->kvec[0] + m->kvec[1] * m->kvec[1]);
+    StepArgs a{X, 2 * ldx, Y, 2 * ldy, Ym1, 2 * ldm, alpha, beta, shift - kk, 2 * N};
+    a.S = gamma ? nullptr : m->d_Sf64;
+    FE_HIP(launch_step(m, a, FE_F64, s), "step kernel launch");
+    if (m->nl.n_site > 0) {
+        if (gamma) FE_HIP(launch_nonlocal(m, X, 2 * ldx, Y, 2 * ldy, 2 * N, alpha, s), "nonlocal kernel launch");
+        else FE_HIP(launch_nonlocal_k(m, X, 2 * ldx, Y, 2 * ldy, N, alpha, s), "nonlocal kernel launch");
+    }
+    return FE_OK;
+}
+
+}  // namespace fe
+
+extern "C" {
+
+fe_status fe_hx_apply_k(fe_mesh *m, const double *X, double *Y, int64_t N, int64_t ld, hipStream_t s) {
+    if (!m) return fail(FE_EINVAL, "NULL mesh");
+    if (N == 0) return FE_OK;
+    if (N < 0) return fail(FE_EINVAL, "N must be >= 0");
+    fe_status st;
+    if ((st = check_block(m, X, N, ld, "X")) != FE_OK) return st;
+    if ((st = check_block(m, Y, N, ld, "Y")) != FE_OK) return st;
+    if (overlap(X, m->n, 2 * N, 2 * ld, Y, m->n, 2 * N, 2 * ld)) return fail(FE_EINVAL, "X and Y overlap");
+    if (!m->potential_set) return fail(FE_ESTATE, "fe_set_potential has not been called");
+    return filter_step_k(m, X, ld, Y, ld, nullptr, 0, 1.0, 0.0, 0.0, N, s);
+}
+
+fe_status fe_cheb_filter_k(fe_mesh *m, const double *X, double *Y, int64_t N, int64_t ld, int32_t mdeg, double a,
+                           double b, double a0, double *work, size_t work_bytes, hipStream_t s) {
+    fe_status st = validate_filter_args(m, N, mdeg, a, b, a0, FE_F64);
+    if (st != FE_OK) return st;
+    if (N == 0) return FE_OK;
+    if ((st = check_block(m, X, N, ld, "X")) != FE_OK) return st;
+    if ((st = check_block(m, Y, N, ld, "Y")) != FE_OK) return st;
+    if (mdeg >= 2) {
+        if ((st = check_block(m, work, N, N, "work")) != FE_OK) return st;
+        if (work_bytes < (size_t)m->n * N * 2 * sizeof(double))
+            return fail(FE_ENOMEM, "work smaller than 2*n*N doubles");
+        if (overlap(X, m->n, 2 * N, 2 * ld, work, m->n, 2 * N, 2 * N) ||
+            overlap(Y, m->n, 2 * N, 2 * ld, work, m->n, 2 * N, 2 * N))
+            return fail(FE_EINVAL, "work overlaps X or Y");
+    }
+    if (overlap(X, m->n, 2 * N, 2 * ld, Y, m->n, 2 * N, 2 * ld)) return fail(FE_EINVAL, "X and Y overlap");
+    if (!m->potential_set) return fail(FE_ESTATE, "fe_set_potential has not been called");
+    std::vector<double> al, be;
+    double c;
+    cheb_coefficients(mdeg, a, b, a0, al, be, c);
+    // the buffer rotation of fe_cheb_filter: Y_m lands in Y
+    double *odd = (mdeg & 1) ? Y : work;
+    double *even = (mdeg & 1) ? work : Y;
+    int64_t ldo = (mdeg & 1) ? ld : N, lde = (mdeg & 1) ? N : ld;
+    auto buf = [&](int k) -> double * { return k == 0 ? const_cast<double *>(X) : (k & 1) ? odd : even; };
+    auto ldb = [&](int k) -> int64_t { return k == 0 ? ld : (k & 1) ? ldo : lde; };
+    st = filter_step_k(m, X, ld, buf(1), ldb(1), nullptr, 0, al[0], 0.0, c, N, s);
+    if (st != FE_OK) return st;
+    for (int k = 1; k < mdeg; ++k) {
+        st = filter_step_k(m, buf(k), ldb(k), buf(k + 1), ldb(k + 1), buf(k - 1), ldb(k - 1), al[k], be[k], c, N, s);
         if (st != FE_OK) return st;
     }
     return FE_OK;

@@ -43,6 +43,8 @@ struct NonlocalData {
     int32_t *d_entry_site = nullptr; // [nnz] site of each entry
     double *d_W = nullptr;           // projections C~^T X, grown on demand
     size_t W_cap = 0;                // doubles
+    std::vector<double> disp;        // [nnz][2] in-plane x_I - R_s of each entry (minimum image)
+    double *d_phase = nullptr;       // [nnz][2] cos, sin of k.(x_I - R_s) (Bloch mode)
 };
 
 }  // namespace fe
@@ -77,6 +79,8 @@ struct fe_mesh {
     uint16_t *d_Abf16 = nullptr;  // bf16 bits
     double *d_v = nullptr;        // [n] diagonal potential term of H~
     double *d_wrel = nullptr;     // [3][p+1]: (h/2) w_i per axis (for v and Vbar)
+    double kvec[2] = {0.0, 0.0};  // Bloch wave vector (k_x, k_y) of the complex entry points
+    double *d_Sf64 = nullptr;     // swizzled FP64 fragments of k.G_c (null while k = 0)
     bool potential_set = false;
     int kernel_variant = 0;  // 0: fastest available, 1: generic colour-pass kernel
     double E = 0.0, z0 = 0.0;
@@ -98,6 +102,7 @@ fe_status fail(fe_status s, const std::string &msg);
 void gll_rule(int p, std::vector<double> &x, std::vector<double> &w);
 void ref_matrices(int p, int rule, std::vector<double> &Khat, std::vector<double> &Mhat);
 void cell_matrix_half(int p, int rule, double h, std::vector<double> &A);
+void cell_matrix_bloch(int p, int rule, double h, double kx, double ky, std::vector<double> &S);
 
 // kernels (fe_kernels.hip)
 struct StepArgs {
@@ -110,6 +115,7 @@ struct StepArgs {
     double alpha, beta, shift;
     int64_t N;
     const double *v = nullptr;  // diagonal term of H~; null: the mesh's potential
+    const double *S = nullptr;  // Bloch mode: FP64 fragments of k.G_c (interleaved complex columns)
 };
 
 hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipStream_t s);
@@ -137,6 +143,10 @@ hipError_t launch_axpby(double *Y, int64_t ldy, const double *X, int64_t ldx, in
 hipError_t launch_nonlocal(fe_mesh *m, const double *X, int64_t ldx, double *Y, int64_t ldy, int64_t N,
                            double alpha, hipStream_t s);
 size_t nonlocal_work_doubles(const fe_mesh *m, int64_t N);
+hipError_t launch_nonlocal_k(fe_mesh *m, const double *X, int64_t ldx, double *Y, int64_t ldy, int64_t N,
+                             double alpha, hipStream_t s);
+fe_status nonlocal_set_phase(fe_mesh *m);
+void swizzle_f64(const fe_mesh *m, const std::vector<double> &A, std::vector<double> &f64);
 void nonlocal_release(fe_mesh *m);
 
 }  // namespace fe

@@ -86,6 +86,7 @@ struct StepParams {
     int maxf;
     const double *v;
     const void *A;
+    const double *S;  // FP64 fragments of k.G_c (Bloch mode), else null
     AxisInfo ax[3];
     int col[3];
     int cnt[3];
@@ -850,10 +851,19 @@ template <int PREC, int G, int NCP> struct RowLds {
 
 // G chunks of 16 vectors per workgroup, TPW row tiles per wave, OCC waves
 // per SIMD the register allocation aims at, cell-matrix fragments fetched in
-// batches of BK k-steps (0: one k-step at a time)
-template <int P, int PREC, int G, int TPW, int OCC, int BK>
+// batches of BK k-steps (0: one k-step at a time).
+// CPX (FP64 only): Bloch-k mode.  The columns are complex vectors stored as
+// interleaved (re, im) pairs, so the four consecutive columns of a lane are
+// two complex vectors, and the operator gains -i M^-1/2 (k.G) M^-1/2 with the
+// real cell matrix S_c = k.G_c (fragments in k.S, same layout as k.A).  As
+// -i S (x_r + i x_i) = S x_i - i S x_r, each k-step adds S_c times the
+// operand (x_i, -x_r, x_i', -x_r') to the same accumulators; the diagonal
+// part (v - shift, with |k|^2/2 folded into shift by the caller) acts on
+// each real column as in the real mode.
+template <int P, int PREC, int G, int TPW, int OCC, int BK, bool CPX = false>
 __global__ __launch_bounds__((64 * RowShape<P, TPW>::W)) __attribute__((amdgpu_waves_per_eu(OCC)))
 void step_row_kernel(StepParams k) {
+    static_assert(!CPX || PREC == 0, "the Bloch mode is FP64 only");
     constexpr int N1 = P + 1, NC = N1 * N1 * N1, NCP = (NC + 31) / 32 * 32;
     constexpr int KSTEP = PrecTraits<PREC>::KSTEP, NKS = NCP / KSTEP;
     constexpr int W = RowShape<P, TPW>::W, XS = RowLds<PREC, G, NCP>::XS;
@@ -876,13 +886,18 @@ void step_row_kernel(StepParams k) {
     constexpr size_t TS = (size_t)W * NKS * 64;  // fragment stride between the wave's tiles
     constexpr int BKE = batch_size(NKS, BK > 0 ? BK : 1), NB = NKS / BKE;
     static_assert(NKS % BKE == 0, "k-steps must split into batches");
-    auto load_batch = [&](FragT (&ab)[BKE][TPW], int sb) {
+    const double *Sf = CPX ? k.S + (size_t)wave * NKS * 64 + lane : nullptr;
+    constexpr int NS = CPX ? 2 : 1;  // fragment streams: (1/2)K_c, and S_c in the Bloch mode
+    auto load_batch = [&](FragT (&ab)[BKE][NS][TPW], int sb) {
 #pragma unroll
         for (int j = 0; j < BKE; ++j)
 #pragma unroll
-            for (int tt = 0; tt < TPW; ++tt) ab[j][tt] = A[tt * TS + (size_t)(sb * BKE + j) * 64];
+            for (int tt = 0; tt < TPW; ++tt) {
+                ab[j][0][tt] = A[tt * TS + (size_t)(sb * BKE + j) * 64];
+                if constexpr (CPX) ab[j][NS - 1][tt] = Sf[tt * TS + (size_t)(sb * BKE + j) * 64];
+            }
     };
-    FragT ab0[BKE][TPW], ab1[BKE][TPW];
+    FragT ab0[BKE][NS][TPW], ab1[BKE][NS][TPW];
     if constexpr (BK > 0) load_batch(ab0, 0);
 
     int I[TPW];
@@ -967,7 +982,8 @@ void step_row_kernel(StepParams k) {
                     if constexpr (PREC == 0) cacc[tt][g][q] = 0.0;
                     else cacc[tt][g][q] = f4{0.f, 0.f, 0.f, 0.f};
                 }
-        auto mul_step = [&](const FragT (&a)[TPW], int s) {
+        auto mul_step = [&](const FragT (&af)[NS][TPW], int s) {
+            const FragT(&a)[TPW] = af[0];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 if constexpr (PREC == 0) {
@@ -978,6 +994,15 @@ void step_row_kernel(StepParams k) {
 #pragma unroll
                         for (int q = 0; q < 4; ++q)
                             cacc[tt][g][q] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[tt], b[q], cacc[tt][g][q], 0, 0, 0);
+                    if constexpr (CPX) {
+                        const double bs[4] = {b[1], -b[0], b[3], -b[2]};
+#pragma unroll
+                        for (int tt = 0; tt < TPW; ++tt)
+#pragma unroll
+                            for (int q = 0; q < 4; ++q)
+                                cacc[tt][g][q] =
+                                    __builtin_amdgcn_mfma_f64_4x4x4f64(af[NS - 1][tt], bs[q], cacc[tt][g][q], 0, 0, 0);
+                    }
                 } else if constexpr (PREC == 1) {
                     const float b = xs[g * XS + (4 * s + (lane >> 4)) * 16 + (lane & 15)];
 #pragma unroll
@@ -997,16 +1022,19 @@ void step_row_kernel(StepParams k) {
             constexpr int UNR = NKS <= 40 ? NKS : 8;
 #pragma unroll UNR
             for (int s = 0; s < NKS; ++s) {
-                FragT a[TPW];
+                FragT a[NS][TPW];
 #pragma unroll
-                for (int tt = 0; tt < TPW; ++tt) a[tt] = A[tt * TS + (size_t)s * 64];
+                for (int tt = 0; tt < TPW; ++tt) {
+                    a[0][tt] = A[tt * TS + (size_t)s * 64];
+                    if constexpr (CPX) a[NS - 1][tt] = Sf[tt * TS + (size_t)s * 64];
+                }
                 mul_step(a, s);
             }
         } else {
             // batch j + 1 in flight while batch j is multiplied (loads complete
             // in issue order, so a wait for batch j leaves the later batch
             // outstanding); batch 0 was requested at the start
-            auto mul_batch = [&](const FragT (&ab)[BKE][TPW], int sb) {
+            auto mul_batch = [&](const FragT (&ab)[BKE][NS][TPW], int sb) {
 #pragma unroll
                 for (int j = 0; j < BKE; ++j) mul_step(ab[j], sb * BKE + j);
             };
@@ -1046,13 +1074,13 @@ constexpr int UNRB = NB <= 8 ? NB : 1;
     }
 }
 
-template <int P, int PREC, int G, int TPW, int OCC, int BK>
+template <int P, int PREC, int G, int TPW, int OCC, int BK, bool CPX = false>
 static hipError_t launch_row_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
     constexpr int N1 = P + 1, NC = N1 * N1 * N1, NCP = (NC + 31) / 32 * 32, W = RowShape<P, TPW>::W;
     const size_t smem = RowLds<PREC, G, NCP>::bytes;
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step_row_kernel<P, PREC, G, TPW, OCC, BK>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step_row_kernel<P, PREC, G, TPW, OCC, BK, CPX>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         if (e != hipSuccess) return e;
         attr = true;
@@ -1076,7 +1104,7 @@ static hipError_t launch_row_p(StepParams prm, const fe_mesh *m, hipStream_t s) 
                     cells *= cnt;
                 }
                 if (cells == 0) continue;
-                hipLaunchKernelGGL((step_row_kernel<P, PREC, G, TPW, OCC, BK>), dim3((unsigned)(cells * ngroups)),
+                hipLaunchKernelGGL((step_row_kernel<P, PREC, G, TPW, OCC, BK, CPX>), dim3((unsigned)(cells * ngroups)),
                                    dim3(64 * W), smem, s, prm);
                 hipError_t e = hipGetLastError();
                 if (e != hipSuccess) return e;
@@ -1950,6 +1978,7 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
     prm.maxf = m->maxf;
     prm.v = a.v ? a.v : m->d_v;
     prm.A = prec == FE_F64 ? (const void *)m->d_Af64 : prec == FE_F32 ? (const void *)m->d_Af32 : (const void *)m->d_Abf16;
+    prm.S = a.S;
     for (int d = 0; d < 3; ++d) {
         prm.ax[d].ncell = m->ncell[d];
         prm.ax[d].nfree = (int)m->nf[d];
@@ -1958,6 +1987,21 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
     }
     prm.nfx = m->nf[0];
     prm.nfy = m->nf[1];
+    if (a.S) {
+        // Bloch mode: FP64 row-owner kernel in the configurations of the real
+        // mode, with one wave less per SIMD for the second fragment stream
+        if (prec != FE_F64) return hipErrorInvalidValue;
+        switch (m->p) {
+        case 1: return launch_row_p<1, 0, 2, 1, 4, 4, true>(prm, m, s);
+        case 2: return launch_row_p<2, 0, 2, 1, 4, 4, true>(prm, m, s);
+        case 3: return launch_row_p<3, 0, 2, 1, 4, 4, true>(prm, m, s);
+        case 4: return launch_row_p<4, 0, 2, 1, 4, 4, true>(prm, m, s);
+        case 5: return launch_row_p<5, 0, 2, 1, 4, 4, true>(prm, m, s);
+        case 6: return launch_row_p<6, 0, 1, 2, 4, 2, true>(prm, m, s);
+        case 7: return launch_row_p<7, 0, 1, 2, 4, 2, true>(prm, m, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
     if (m->kernel_variant == 5) {
         hipError_t e = hipErrorNotSupported;
         switch (m->p * 3 + (int)prec) {

@@ -46,6 +46,7 @@ void free_nl(NonlocalData &nl) {
     (void)hipFree(nl.d_inc_entry);
     (void)hipFree(nl.d_entry_site);
     (void)hipFree(nl.d_W);
+    (void)hipFree(nl.d_phase);
     nl = NonlocalData();
 }
 
@@ -91,6 +92,68 @@ __global__ void nl_expand_kernel(double *Y, int64_t ldy, int64_t N, double alpha
     Y[(int64_t)node[u] * ldy + j] += alpha * acc;
 }
 
+// Bloch mode (paper Sec. 2.3 with k-point sampling): with u = exp(-i k.r) psi
+// the projectors become C^k_I = exp(-i k.d_I) C~_I, d_I = x_I - R_s the
+// minimum-image displacement (the cutoff ball never wraps onto itself, so one
+// image per entry), and H~^k gains C^k diag(D) C^k^H.  Complex columns are
+// interleaved (re, im); ph[e] = (cos k.d_e, sin k.d_e).
+// W[(s*9+beta)][j] = D_{s,beta} sum_e exp(+i k.d_e) C~[e][beta] X[dof(e)][j]
+__global__ void nl_project_k_kernel(const double *X, int64_t ldx, int64_t N, const int64_t *supp_ptr,
+                                    const int32_t *supp_dof, const double *vals, const double *ph, const double *D,
+                                    double *W) {
+    const int s = blockIdx.x;
+    const int64_t j = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    double ar[9], ai[9];
+#pragma unroll
+    for (int b = 0; b < 9; ++b) ar[b] = ai[b] = 0.0;
+    for (int64_t e = supp_ptr[s]; e < supp_ptr[s + 1]; ++e) {
+        const double *x = X + (int64_t)supp_dof[e] * ldx + 2 * j;
+        const double c = ph[2 * e], sn = ph[2 * e + 1];
+        const double tr = c * x[0] - sn * x[1], ti = sn * x[0] + c * x[1];
+        const double *v = vals + e * 9;
+#pragma unroll
+        for (int b = 0; b < 9; ++b) {
+            ar[b] += v[b] * tr;
+            ai[b] += v[b] * ti;
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < 9; ++b) {
+        double *w = W + ((int64_t)s * 9 + b) * 2 * N + 2 * j;
+        w[0] = D[s * 9 + b] * ar[b];
+        w[1] = D[s * 9 + b] * ai[b];
+    }
+}
+
+// Y[node][j] += alpha sum_e exp(-i k.d_e) sum_beta C~[e][beta] W[(site(e)*9+beta)][j]
+__global__ void nl_expand_k_kernel(double *Y, int64_t ldy, int64_t N, double alpha, const int32_t *node,
+                                   const int64_t *inc_ptr, const int64_t *inc_entry, const int32_t *entry_site,
+                                   const double *vals, const double *ph, const double *W) {
+    const int64_t u = blockIdx.x;
+    const int64_t j = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    double yr = 0.0, yi = 0.0;
+    for (int64_t q = inc_ptr[u]; q < inc_ptr[u + 1]; ++q) {
+        const int64_t e = inc_entry[q];
+        const int s = entry_site[e];
+        const double *v = vals + e * 9;
+        const double *w = W + (int64_t)s * 9 * 2 * N + 2 * j;
+        double tr = 0.0, ti = 0.0;
+#pragma unroll
+        for (int b = 0; b < 9; ++b) {
+            tr += v[b] * w[(int64_t)b * 2 * N];
+            ti += v[b] * w[(int64_t)b * 2 * N + 1];
+        }
+        const double c = ph[2 * e], sn = ph[2 * e + 1];
+        yr += c * tr + sn * ti;
+        yi += c * ti - sn * tr;
+    }
+    double *y = Y + (int64_t)node[u] * ldy + 2 * j;
+    y[0] += alpha * yr;
+    y[1] += alpha * yi;
+}
+
 size_t nonlocal_work_doubles(const fe_mesh *m, int64_t N) { return (size_t)m->nl.n_site * 9 * (size_t)N; }
 
 static hipError_t ensure_nl_work(fe_mesh *m, int64_t N) {
@@ -129,6 +192,50 @@ hipError_t launch_nonlocal(fe_mesh *m, const double *X, int64_t ldx, double *Y, 
     return hipGetLastError();
 }
 
+// complex blocks: N complex columns, ldx / ldy in doubles
+hipError_t launch_nonlocal_k(fe_mesh *m, const double *X, int64_t ldx, double *Y, int64_t ldy, int64_t N,
+                             double alpha, hipStream_t s) {
+    if (m->nl.n_site == 0) return hipSuccess;
+    if (!m->nl.d_phase) return hipErrorInvalidValue;
+    hipError_t e = ensure_nl_work(m, 2 * N);
+    if (e != hipSuccess) return e;
+    const int TB = 128;
+    dim3 g1((unsigned)m->nl.n_site, (unsigned)((N + TB - 1) / TB));
+    hipLaunchKernelGGL(nl_project_k_kernel, g1, dim3(TB), 0, s, X, ldx, N, (const int64_t *)m->nl.d_supp_ptr,
+                       (const int32_t *)m->nl.d_supp_dof, (const double *)m->nl.d_vals,
+                       (const double *)m->nl.d_phase, (const double *)m->nl.d_D, m->nl.d_W);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (m->nl.n_node == 0) return hipSuccess;
+    dim3 g2((unsigned)m->nl.n_node, (unsigned)((N + TB - 1) / TB));
+    hipLaunchKernelGGL(nl_expand_k_kernel, g2, dim3(TB), 0, s, Y, ldy, N, alpha, (const int32_t *)m->nl.d_node,
+                       (const int64_t *)m->nl.d_inc_ptr, (const int64_t *)m->nl.d_inc_entry,
+                       (const int32_t *)m->nl.d_entry_site, (const double *)m->nl.d_vals,
+                       (const double *)m->nl.d_phase, (const double *)m->nl.d_W);
+    return hipGetLastError();
+}
+
+// (cos, sin) of k.d for every support entry, for the mesh's current k
+// (host build, synchronous upload; nothing to do without sites).
+fe_status nonlocal_set_phase(fe_mesh *m) {
+    NonlocalData &nl = m->nl;
+    if (nl.n_site == 0 || nl.nnz == 0) return FE_OK;
+    std::vector<double> ph(2 * (size_t)nl.nnz);
+    for (int64_t e = 0; e < nl.nnz; ++e) {
+        const double t = m->kvec[0] * nl.disp[2 * e] + m->kvec[1] * nl.disp[2 * e + 1];
+        ph[2 * e] = std::cos(t);
+        ph[2 * e + 1] = std::sin(t);
+    }
+    if (!nl.d_phase && hipMalloc(&nl.d_phase, ph.size() * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        nl.d_phase = nullptr;
+        return fail(FE_ENOMEM, "device allocation failed for the projector phases");
+    }
+    if (hipMemcpy(nl.d_phase, ph.data(), ph.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(FE_EDEVICE, "hipMemcpy of the projector phases failed");
+    return FE_OK;
+}
+
 }  // namespace fe
 
 using namespace fe;
@@ -154,7 +261,7 @@ fe_status fe_set_nonlocal(fe_mesh *m, int32_t n_site, const double *centres, con
     // per-axis free positions within r_cut of each centre coordinate
     std::vector<int64_t> supp_ptr(1, 0);
     std::vector<int32_t> supp_dof;
-    std::vector<double> vals;
+    std::vector<double> vals, disp;
     for (int s = 0; s < n_site; ++s) {
         std::vector<std::pair<int64_t, double>> cand[3];  // (free index, signed offset)
         for (int a = 0; a < 3; ++a) {
@@ -164,8 +271,8 @@ fe_status fe_set_nonlocal(fe_mesh *m, int32_t n_site, const double *centres, con
                 if (std::fabs(d) < r_cut) cand[a].push_back({t, d});
             }
         }
-        std::vector<std::pair<int32_t, double>> pts;  // (dof, offsets encoded below)
-        std::vector<double> pv;
+        std::vector<std::pair<int32_t, double>> pts;  // (dof, M_I)
+        std::vector<double> pv, pd;                   // projector values; in-plane offsets
         double nrm[9] = {0};
         for (auto &z : cand[2])
             for (auto &y : cand[1])
@@ -176,6 +283,8 @@ fe_status fe_set_nonlocal(fe_mesh *m, int32_t n_site, const double *centres, con
                     double M = m->axis_mass[0][x.first] * m->axis_mass[1][y.first] * m->axis_mass[2][z.first];
                     double rad = std::exp(-r2 / (2.0 * r_g * r_g));
                     pts.push_back({(int32_t)I, M});
+                    pd.push_back(x.second);
+                    pd.push_back(y.second);
                     for (int b = 0; b < 9; ++b) {
                         double p = solid_harmonic(b, x.second, y.second, z.second) * rad;
                         pv.push_back(p);
@@ -188,6 +297,8 @@ fe_status fe_set_nonlocal(fe_mesh *m, int32_t n_site, const double *centres, con
         std::sort(order.begin(), order.end(), [&](size_t u, size_t v) { return pts[u].first < pts[v].first; });
         for (size_t oi : order) {
             supp_dof.push_back(pts[oi].first);
+            disp.push_back(pd[2 * oi]);
+            disp.push_back(pd[2 * oi + 1]);
             double sq = std::sqrt(pts[oi].second);
             for (int b = 0; b < 9; ++b) {
                 double sc = nrm[b] > 0.0 ? 1.0 / std::sqrt(nrm[b]) : 0.0;
@@ -237,7 +348,10 @@ fe_status fe_set_nonlocal(fe_mesh *m, int32_t n_site, const double *centres, con
     nl.n_site = n_site;
     nl.nnz = (int64_t)supp_dof.size();
     nl.n_node = (int64_t)node.size();
-    return FE_OK;
+    nl.disp.swap(disp);
+    const fe_status ps = nonlocal_set_phase(m);
+    if (ps != FE_OK) free_nl(nl);
+    return ps;
 }
 
 }  // extern "C"

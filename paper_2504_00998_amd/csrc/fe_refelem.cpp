@@ -144,3 +144,36 @@ void cell_matrix_half(int p, int rule, double h, std::vector<double> &A) {
 }
 
 }  // namespace fe
+
+namespace fe {
+
+// S = kx G_x + ky G_y with the cell advection matrices
+//   G_a[l][l'] = int_c N_l dN_l'/dx_a
+// of a cube of edge h (the Bloch-k term of Sec. 2.3 is -i M^-1/2 (k.G) M^-1/2
+// after assembly).  Per axis the integral factors into 1-D ones: the
+// derivative axis contributes Chat_ij = int l_i l_j' (degree 2p-1, so the
+// (p+1)-point GLL rule is exact and Chat_ij = w_i l_j'(x_i) under either
+// rule), the others (h/2) Mhat; the 2/h of the derivative cancels one h/2.
+void cell_matrix_bloch(int p, int rule, double h, double kx, double ky, std::vector<double> &S) {
+    std::vector<double> K, M, x, w;
+    ref_matrices(p, rule, K, M);
+    gll_rule(p, x, w);
+    std::vector<double> D = Barycentric(x).diff_matrix();
+    const int n = p + 1, nc = n * n * n;
+    std::vector<double> Ch(n * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Ch[i * n + j] = w[i] * D[i * n + j];
+    const double s = 0.25 * h * h;  // (h/2)^2
+    S.assign((size_t)nc * nc, 0.0);
+    for (int l = 0; l < nc; ++l) {
+        const int i = l % n, j = (l / n) % n, k = l / (n * n);
+        for (int lp = 0; lp < nc; ++lp) {
+            const int ip = lp % n, jp = (lp / n) % n, kp = lp / (n * n);
+            const double mz = M[k * n + kp];
+            const double v = kx * Ch[i * n + ip] * M[j * n + jp] * mz + ky * M[i * n + ip] * Ch[j * n + jp] * mz;
+            S[(size_t)l * nc + lp] = s * v;
+        }
+    }
+}
+
+}  // namespace fe

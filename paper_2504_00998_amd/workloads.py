@@ -97,6 +97,16 @@ class Workload:
             out[:, t] = np.random.default_rng([self.seed(2), int(j)]).standard_normal(n)
         return out
 
+    def Xc(self, n: Optional[int] = None, cols=None) -> np.ndarray:
+        """Complex random block for the Bloch-k operator: real part `X`, imaginary
+        part i.i.d. N(0,1) from the streams (seed(7), j)."""
+        n = self.n_free() if n is None else n
+        cols = list(range(self.N) if cols is None else cols)
+        im = np.empty((n, len(cols)), dtype=np.float64)
+        for t, j in enumerate(cols):
+            im[:, t] = np.random.default_rng([self.seed(7), int(j)]).standard_normal(n)
+        return self.X(n, cols) + 1j * im
+
     def X_device(self, n: Optional[int] = None, N: Optional[int] = None, device="cuda"):
         """Random block (n, N), i.i.d. N(0,1), drawn on the device by torch's
         seeded generator (seed(2)).  Used where the host recipe `X` would be

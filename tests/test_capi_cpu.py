@@ -88,3 +88,12 @@ def test_poisson_entry_points_reject_null_without_a_device():
     L = fe.lib()
     assert L.fe_poisson_work_bytes(None) == 0
     assert L.fe_poisson_solve(None, None, None, 1e-8, 10, None, 0, None, None, None) == fe.FE_EINVAL
+
+
+def test_bloch_entry_points_reject_null_without_a_device():
+    import paper_2504_00998_amd as fe
+    L = fe.lib()
+    assert L.fe_set_kpoint(None, 0.1, 0.2) == fe.FE_EINVAL
+    assert L.fe_get_kpoint(None, None) == fe.FE_EINVAL
+    assert L.fe_hx_apply_k(None, None, None, 4, 4, None) == fe.FE_EINVAL
+    assert L.fe_cheb_filter_k(None, None, None, 4, 4, 5, 1.0, 2.0, float("nan"), None, 0, None) == fe.FE_EINVAL

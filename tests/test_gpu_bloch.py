@@ -1,0 +1,139 @@
+"""GPU parity of the Bloch-k operator (complex H~^k over the periodic x-y
+directions, with phase-twisted projectors) against the oracle's complex
+sparse operator.  Complex blocks are interleaved (re, im) FP64, so the bar is
+the FP64 one: 1e-13 relative per vector for one application, 1e-12 for the
+filter.  At k = 0 the complex entry points must equal the real ones applied
+to the real and imaginary parts bit for bit."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2504_00998_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _fe():
+    import paper_2504_00998_amd as fe
+    return fe
+
+
+def _print_case(**kw):
+    print("case:", kw, flush=True)
+
+
+def _relerr(Y, R):
+    return (np.linalg.norm(Y - R, axis=0) / np.maximum(np.linalg.norm(R, axis=0), 1e-300)).max()
+
+
+def _setup(wl, nonlocal_=False):
+    fe = _fe()
+    om = O.Mesh.from_workload(wl)
+    Vq = W.workload_potential(wl, om.quad_points())
+    gm = fe.Mesh.from_workload(wl)
+    gm.set_potential(torch.from_numpy(Vq).cuda(), wl.E, wl.z0)
+    if nonlocal_:
+        cen, D = wl.centres(), wl.nonlocal_coupling()
+        op = O.Operator(om, Vq, wl.E, wl.z0, O.Projectors(om, cen, wl.r_cut, wl.r_g), D.reshape(-1))
+        gm.set_nonlocal(cen, D, wl.r_cut, wl.r_g)
+    else:
+        op = O.Operator(om, Vq, wl.E, wl.z0)
+    return om, op, gm
+
+
+CASES = [
+    # (label, workload, k, nonlocal): several tiles per axis, ragged column groups
+    ("p4-kx-N7", W.small_slab((3, 3, 4), p=4, N=7), (0.37, 0.0), False),
+    ("p4-kxy-N20-nl", W.small_slab((5, 5, 6), p=3, N=20, cfg=5), (0.21, -0.45), True),
+    ("p1-ky-N17", W.small_slab((4, 4, 5), p=1, N=17), (0.0, 0.9), False),
+    ("p2-kxy-N16", W.small_slab((2, 3, 4), p=2, N=16), (-0.6, 0.3), False),
+    ("p3-gll-kxy-N9", W.small_slab((3, 2, 3), p=3, N=9, rule=W.RULE_GLL), (0.5, 0.5), False),
+    ("p5-kxy-N18", W.small_slab((2, 2, 3), p=5, N=18), (0.8, -0.2), False),
+    ("p6-kx-N8", W.small_slab((2, 2, 2), p=6, N=8), (1.1, 0.0), False),
+    ("p7-kxy-N5", W.small_slab((2, 2, 2), p=7, N=5), (0.4, 0.7), False),
+    ("p4-odd-periodic-N1-nl", W.small_slab((5, 5, 6), p=4, N=1, cfg=5), (0.3, 0.6), True),
+]
+
+
+@pytest.mark.parametrize("label,wl,k,nl", CASES, ids=[c[0] for c in CASES])
+def test_hx_k_matches_oracle(label, wl, k, nl):
+    _print_case(test="hx_k", label=label, ncell=wl.ncell, p=wl.p, N=wl.N, k=k, nonlocal_=nl)
+    om, op, gm = _setup(wl, nl)
+    gm.set_kpoint(*k)
+    assert gm.kpoint() == k
+    X = wl.Xc(op.n)
+    Y = gm.hx_k(torch.from_numpy(X).cuda()).cpu().numpy()
+    R = O.BlochOperator(op, om, k).apply(X)
+    assert _relerr(Y, R) < 1e-13
+
+
+@pytest.mark.parametrize("label,wl,k,nl", [CASES[0], CASES[1], CASES[3]], ids=[CASES[i][0] for i in (0, 1, 3)])
+@pytest.mark.parametrize("scaled", [True, False])
+def test_filter_k_matches_oracle(label, wl, k, nl, scaled):
+    _print_case(test="filter_k", label=label, k=k, scaled=scaled)
+    om, op, gm = _setup(wl, nl)
+    gm.set_kpoint(*k)
+    B = O.BlochOperator(op, om, k)
+    # interval from the real operator's Lanczos bounds moved by |k|^2 / 2
+    # (both sides evaluate the same polynomial; the interval only sets scale)
+    a0r, br, _ = O.lanczos_bounds(op.apply, wl.lanczos_start(op.n), 10)
+    kk = 0.5 * (k[0] ** 2 + k[1] ** 2)
+    a0, b = a0r - 0.5, br + kk + 1.0
+    a = O.weyl_cut(a0r, br, wl.N, op.n) + kk
+    X = wl.Xc(op.n)
+    a0 = a0 if scaled else float("nan")
+    Y = gm.cheb_filter_k(torch.from_numpy(X).cuda(), wl.m, a, b, a0).cpu().numpy()
+    assert _relerr(Y, B.filter(X, wl.m, a, b, a0)) < 1e-12
+
+
+def test_gamma_point_equals_real_path_bitwise():
+    """k = 0: H~^0 X = H~ Re X + i H~ Im X with identical rounding, for the
+    application and the filter, nonlocal term included."""
+    wl = W.small_slab((5, 5, 6), p=3, N=12, cfg=5)
+    _print_case(test="gamma_bitwise", ncell=wl.ncell, p=wl.p, N=wl.N)
+    _, op, gm = _setup(wl, True)
+    gm.set_kpoint(0.0, 0.0)
+    X = torch.from_numpy(wl.Xc(op.n)).cuda()
+    Xr, Xi = X.real.contiguous(), X.imag.contiguous()
+    Y = gm.hx_k(X)
+    assert torch.equal(Y.real, gm.hx(Xr)) and torch.equal(Y.imag, gm.hx(Xi))
+    Yf = gm.cheb_filter_k(X, 6, 3.0, 40.0, -0.5)
+    assert torch.equal(Yf.real, gm.cheb_filter(Xr, 6, 3.0, 40.0, -0.5))
+    assert torch.equal(Yf.imag, gm.cheb_filter(Xi, 6, 3.0, 40.0, -0.5))
+
+
+def test_kpoint_changes_and_hermiticity():
+    """Switching k rebuilds fragments and phases (a second k matches the
+    oracle too); <U, H~^k V> = <H~^k U, V> on the device result."""
+    wl = W.small_slab((5, 5, 6), p=3, N=6, cfg=5)
+    om, op, gm = _setup(wl, True)
+    X = wl.Xc(op.n)
+    Xd = torch.from_numpy(X).cuda()
+    for k in ((0.5, 0.1), (-0.2, 0.9)):
+        _print_case(test="k_switch", k=k)
+        gm.set_kpoint(*k)
+        Y = gm.hx_k(Xd)
+        assert _relerr(Y.cpu().numpy(), O.BlochOperator(op, om, k).apply(X)) < 1e-13
+        U, V = Xd[:, :3], Xd[:, 3:]
+        HU, HV = gm.hx_k(U.contiguous()), gm.hx_k(V.contiguous())
+        lhs = U.conj().T @ HV
+        rhs = HU.conj().T @ V
+        assert float((lhs - rhs).abs().max()) < 1e-12 * float(lhs.abs().max())
+
+
+def test_kpoint_argument_errors():
+    fe = _fe()
+    wl = W.small_slab((3, 3, 4), p=2, N=4, bc=(W.DIRICHLET, W.PERIODIC, W.DIRICHLET))
+    _print_case(test="kpoint_errors")
+    _, op, gm = _setup(wl)
+    with pytest.raises(fe.FEError):
+        gm.set_kpoint(0.3, 0.0)  # x is not periodic
+    with pytest.raises(fe.FEError):
+        gm.set_kpoint(float("inf"), 0.0)
+    gm.set_kpoint(0.0, 0.4)
+    X = torch.from_numpy(wl.Xc(op.n)).cuda()
+    with pytest.raises(fe.FEError):
+        gm.cheb_filter_k(X, 4, 1.0, 10.0, work=torch.empty(op.n * wl.N, dtype=torch.float64, device="cuda"))
+    with pytest.raises(TypeError):
+        gm.hx_k(X.real.contiguous())
