@@ -409,6 +409,26 @@ class BlochOperator:
         return Y
 
 
+def bloch_advection_rows(mesh: Mesh, k, rows, X: np.ndarray) -> np.ndarray:
+    """Rows `rows` of M^-1/2 (k_x G_x + k_y G_y) M^-1/2 X, summed cell by cell
+    from the cell advection matrices (the -i k.grad term of the Bloch form is
+    -i times this); X is the full (n, N) block, real or complex.  No
+    nonlocal term."""
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    h = mesh.L[0] / mesh.ncell[0]
+    Gk = k[0] * cell_advection(mesh.p, 0, mesh.rule, h) + k[1] * cell_advection(mesh.p, 1, mesh.rule, h)
+    dofs = mesh.cell_dofs()
+    d = 1.0 / np.sqrt(mesh.mass())
+    pos = {int(I): t for t, I in enumerate(rows)}
+    out = np.zeros((rows.size, X.shape[1]), dtype=np.result_type(X.dtype, np.float64))
+    for c, l in zip(*np.nonzero(np.isin(dofs, rows))):
+        I = int(dofs[c, l])
+        J = dofs[c]
+        ok = J >= 0
+        out[pos[I]] += d[I] * (Gk[l, ok] @ (d[J[ok], None] * X[J[ok]]))
+    return out
+
+
 # ------------------------------------------------------------ observables
 
 def density(mesh: Mesh, X: np.ndarray, f: np.ndarray) -> np.ndarray:

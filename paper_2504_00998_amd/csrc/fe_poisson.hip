@@ -10,11 +10,15 @@
 // constant-field setup of Sec. 2.2.1) H0 has the null vector M^1/2 1, which is
 // projected out of the right-hand side and of every search direction, so the
 // solution has zero mean (integral of phi = 0).  Conjugate gradients with a
-// Jacobi preconditioner (the assembled diagonal of H0); dot products by
-// rocBLAS.
+// Jacobi preconditioner (the assembled diagonal of H0).  The iteration runs on
+// the device: its dot products are fixed-order two-pass reductions whose
+// results, and the CG scalars computed from them, stay in device memory; the
+// host reads the convergence state once per batch of iterations, and
+// iterations queued after convergence leave the iterate untouched.
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 
+#include <algorithm>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -53,6 +57,132 @@ __global__ void xpby_kernel(double *p, const double *z, double beta, int64_t n) 
 }
 
 inline unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+// ---------------------------------------------------------------- device CG
+// Scalars of the device iteration (doubles in the work buffer).
+enum : int {
+    S_RZ = 0,     // r.z of the current iterate (z = projected P r)
+    S_ALPHA,      // rz / p.Hp
+    S_BETA,       // rz_new / rz
+    S_EZ,         // e.(P r): the null-space component removed from z
+    S_BNRM,       // |b|
+    S_REL,        // |r| / |b| after the last update
+    S_DONE,       // 1 once converged (or broken down): later iterations do nothing
+    S_IT,         // updates made
+    S_TOL,
+    S_SING,       // 1 when e spans the null space
+    S_BREAK,      // 1 when p.Hp <= 0 was met
+    S_COUNT
+};
+constexpr int kRedThreads = 256;
+constexpr int kRedBlocks = 1024;  // partial sums per reduction (fixed: the summation order does not depend on timing)
+
+// Fixed-order sum of the block's per-thread values for C components.
+template <int C> __device__ __forceinline__ void block_sum(double (&v)[C], double *lds) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < C; ++c) lds[c * kRedThreads + t] = v[c];
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if (t < w)
+#pragma unroll
+            for (int c = 0; c < C; ++c) lds[c * kRedThreads + t] += lds[c * kRedThreads + t + w];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) v[c] = lds[c * kRedThreads];
+}
+
+// part[blk] = sum over the block's grid-stride elements of p_i q_i
+__global__ __launch_bounds__(kRedThreads) void cg_pq_kernel(const double *p, const double *q, int64_t n,
+                                                            const double *sc, double *part) {
+    __shared__ double lds[kRedThreads];
+    if (sc[S_DONE] != 0.0) return;
+    double v[1] = {0.0};
+    for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRedThreads)
+        v[0] += p[i] * q[i];
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+// alpha = rz / p.Hp (one block); a non-positive p.Hp stops the iteration
+__global__ __launch_bounds__(kRedThreads) void cg_alpha_kernel(const double *part, int nb, double *sc) {
+    __shared__ double lds[kRedThreads];
+    if (sc[S_DONE] != 0.0) return;
+    double v[1] = {0.0};
+    for (int b = threadIdx.x; b < nb; b += kRedThreads) v[0] += part[b];
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) {
+        const double pq = v[0];
+        if (!(pq > 0.0)) {
+            sc[S_BREAK] = 1.0;
+            sc[S_DONE] = 1.0;
+            sc[S_ALPHA] = 0.0;
+        } else {
+            sc[S_ALPHA] = sc[S_RZ] / pq;
+        }
+    }
+}
+
+// x += alpha p, r -= alpha q, and the partial sums r.r, r.z, e.z, r.e with
+// z = pinv r (before the null-space projection)
+__global__ __launch_bounds__(kRedThreads) void cg_update_kernel(double *x, double *r, const double *p,
+                                                                const double *q, const double *pinv,
+                                                                const double *e, int64_t n, const double *sc,
+                                                                double *part) {
+    __shared__ double lds[4 * kRedThreads];
+    if (sc[S_DONE] != 0.0) return;
+    const double al = sc[S_ALPHA];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRedThreads) {
+        x[i] += al * p[i];
+        const double ri = r[i] - al * q[i];
+        r[i] = ri;
+        const double zi = pinv[i] * ri;
+        v[0] += ri * ri;
+        v[1] += ri * zi;
+        v[2] += e[i] * zi;
+        v[3] += ri * e[i];
+    }
+    block_sum<4>(v, lds);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 4; ++c) part[c * kRedBlocks + blockIdx.x] = v[c];
+}
+
+// |r| / |b|, convergence, and beta with the projected z:
+//   z' = z - (e.z) e,  r.z' = r.z - (e.z)(r.e)
+__global__ __launch_bounds__(kRedThreads) void cg_beta_kernel(const double *part, int nb, double *sc) {
+    __shared__ double lds[4 * kRedThreads];
+    if (sc[S_DONE] != 0.0) return;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += kRedThreads)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[c] += part[c * kRedBlocks + b];
+    block_sum<4>(v, lds);
+    if (threadIdx.x == 0) {
+        sc[S_IT] += 1.0;
+        const double rel = sqrt(v[0]) / sc[S_BNRM];
+        sc[S_REL] = rel;
+        if (rel <= sc[S_TOL]) {
+            sc[S_DONE] = 1.0;
+            return;
+        }
+        const double ez = sc[S_SING] != 0.0 ? v[2] : 0.0;
+        const double rz = v[1] - ez * (sc[S_SING] != 0.0 ? v[3] : 0.0);
+        sc[S_EZ] = ez;
+        sc[S_BETA] = rz / sc[S_RZ];
+        sc[S_RZ] = rz;
+    }
+}
+
+// p = (pinv r - ez e) + beta p
+__global__ void cg_direction_kernel(double *p, const double *r, const double *pinv, const double *e, int64_t n,
+                                    const double *sc) {
+    if (sc[S_DONE] != 0.0) return;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    p[i] = (pinv[i] * r[i] - sc[S_EZ] * e[i]) + sc[S_BETA] * p[i];
+}
 
 #define FE_HIPP(call, what)                                                                          \
     do {                                                                                             \
@@ -128,7 +258,7 @@ extern "C" {
 
 size_t fe_poisson_work_bytes(const fe_mesh *m) {
     if (!m) return 0;
-    return (size_t)8 * (size_t)m->n * sizeof(double);
+    return ((size_t)8 * (size_t)m->n + 4 * (size_t)kRedBlocks + 16) * sizeof(double);
 }
 
 fe_status fe_poisson_solve(fe_mesh *m, const double *charge, double *phi, double tol, int32_t maxit,
@@ -184,28 +314,36 @@ fe_status fe_poisson_solve(fe_mesh *m, const double *charge, double *phi, double
         FE_HIPP(hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
         double rz = 0.0;
         FE_BLASP(rocblas_ddot(h, ni, r, 1, z, 1, &rz), "ddot");
-        rel = 1.0;
-        while (it < maxit) {
-            StepArgs a{p, 1, q, 1, nullptr, 0, 1.0, 0.0, 0.0, 1, zero};
-            FE_HIPP(launch_step(m, a, FE_F64, st), "step kernel launch");
-            double pq = 0.0;
-            FE_BLASP(rocblas_ddot(h, ni, p, 1, q, 1, &pq), "ddot");
-            if (!(pq > 0.0)) return fail(FE_EDEVICE, "CG breakdown: p^T H0 p <= 0");
-            double al = rz / pq, mal = -al;
-            FE_BLASP(rocblas_daxpy(h, ni, &al, p, 1, x, 1), "daxpy");
-            FE_BLASP(rocblas_daxpy(h, ni, &mal, q, 1, r, 1), "daxpy");
-            ++it;
-            double rn = 0.0;
-            FE_BLASP(rocblas_dnrm2(h, ni, r, 1, &rn), "dnrm2");
-            rel = rn / bnrm;
-            if (rel <= tol) break;
-            FE_HIPP(launch_vmul(z, pinv, r, n, st), "precondition");
-            if ((stt = project(z)) != FE_OK) return stt;
-            double rz2 = 0.0;
-            FE_BLASP(rocblas_ddot(h, ni, r, 1, z, 1, &rz2), "ddot");
-            FE_HIPP(launch_xpby(p, z, rz2 / rz, n, st), "xpby");
-            rz = rz2;
+        // the iteration itself on the device; the host looks at its state
+        // once per batch
+        double *part = zero + n, *sc = part + 4 * kRedBlocks;
+        const double sc0[S_COUNT] = {rz, 0.0, 0.0, 0.0, bnrm, 1.0, 0.0, 0.0, tol, singular ? 1.0 : 0.0, 0.0};
+        FE_HIPP(hipMemcpyAsync(sc, sc0, sizeof(sc0), hipMemcpyHostToDevice, st), "copy scalars");
+        const int nb = (int)std::min<int64_t>(kRedBlocks, (n + kRedThreads - 1) / kRedThreads);
+        constexpr int kBatch = 8;
+        double sh[S_COUNT] = {};
+        int queued = 0;
+        while (queued < maxit) {
+            const int nbatch = std::min(kBatch, maxit - queued);
+            for (int j = 0; j < nbatch; ++j) {
+                StepArgs a{p, 1, q, 1, nullptr, 0, 1.0, 0.0, 0.0, 1, zero};
+                FE_HIPP(launch_step(m, a, FE_F64, st), "step kernel launch");
+                hipLaunchKernelGGL(cg_pq_kernel, dim3(nb), dim3(kRedThreads), 0, st, p, q, n, sc, part);
+                hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(kRedThreads), 0, st, part, nb, sc);
+                hipLaunchKernelGGL(cg_update_kernel, dim3(nb), dim3(kRedThreads), 0, st, x, r, p, q, pinv, e, n, sc,
+                                   part);
+                hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(kRedThreads), 0, st, part, nb, sc);
+                hipLaunchKernelGGL(cg_direction_kernel, dim3(blocks(n)), dim3(256), 0, st, p, r, pinv, e, n, sc);
+                FE_HIPP(hipGetLastError(), "CG kernel launch");
+            }
+            queued += nbatch;
+            FE_HIPP(hipMemcpyAsync(sh, sc, sizeof(sh), hipMemcpyDeviceToHost, st), "read CG state");
+            FE_HIPP(hipStreamSynchronize(st), "hipStreamSynchronize");
+            if (sh[S_DONE] != 0.0) break;
         }
+        if (sh[S_BREAK] != 0.0) return fail(FE_EDEVICE, "CG breakdown: p^T H0 p <= 0");
+        it = (int)sh[S_IT];
+        rel = sh[S_REL];
         if ((stt = project(x)) != FE_OK) return stt;
     }
     // phi = M^-1/2 x

@@ -42,6 +42,22 @@ def test_fullsize_filter_f64_sampled_columns(cfg2):
     assert torch.isfinite(Y).all()
 
 
+def test_fullsize_kernel_variants_bitwise(cfg2):
+    """At the benchmark's size every FP64 variant but the register-resident
+    one (16x16x4 blocks) gives the default's bits, including the persistent
+    pipelined kernel, whose workgroups each walk about 108 items per pass."""
+    wl, op, gm, X, R, (a, b, a0) = cfg2
+    gm.set_kernel(0)
+    Y0 = gm.hx(X)
+    try:
+        for var in (1, 6, 7):
+            print("case: fullsize variant", var, flush=True)
+            gm.set_kernel(var)
+            assert torch.equal(gm.hx(X), Y0), var
+    finally:
+        gm.set_kernel(0)
+
+
 @pytest.mark.parametrize("prec,tol", [("f32", 1e-4), ("bf16", 1.0)])
 def test_fullsize_filter_mixed_precision_error_report(cfg2, prec, tol):
     """Mixed-precision cell products: per-vector error of Y against the FP64
@@ -51,3 +67,42 @@ def test_fullsize_filter_mixed_precision_error_report(cfg2, prec, tol):
     err = np.linalg.norm(Y - R, axis=0) / np.linalg.norm(R, axis=0)
     print(f"{prec} per-vector rel err vs FP64 oracle", err, flush=True)
     assert err.max() < tol
+
+
+def test_fullsize_bloch_sampled_rows_and_gamma():
+    """Bloch mode at the benchmark's size and launch configuration: the same
+    storage as 128 complex vectors at the wave vector the benchmark uses.
+    Sampled rows of one H~^k application against the oracle (real part of
+    H~ row by row, the k.G term cell by cell); at k = 0 the complex filter
+    equals the real filter on the real and imaginary parts bit for bit."""
+    import math
+    import paper_2504_00998_amd as fe
+    wl = W.CFG2
+    om = O.Mesh.from_workload(wl)
+    Vq = W.workload_potential(wl, om.quad_points())
+    gm = fe.Mesh.from_workload(wl)
+    gm.set_potential(torch.from_numpy(Vq).cuda(), wl.E, wl.z0)
+    Nc = wl.N // 2
+    k = (0.5 * math.pi / wl.L[0], 0.25 * math.pi / wl.L[1])
+    print("case: bloch full size", wl.name, "Nc", Nc, "k", k, flush=True)
+    Xh = wl.Xc(om.n, cols=range(Nc))
+    X = torch.from_numpy(Xh).cuda()
+    gm.set_kpoint(*k)
+    Y = gm.hx_k(X)
+    rows = np.unique(np.concatenate([np.linspace(0, om.n - 1, 40).astype(np.int64), [1, 95, 96 * 96, om.n - 2]]))
+    Ys = Y[torch.from_numpy(rows).cuda()].cpu().numpy()
+    kk = 0.5 * (k[0] ** 2 + k[1] ** 2)
+    R = (O.apply_rows(om, Vq, wl.E, wl.z0, rows, Xh.real.copy())
+         + 1j * O.apply_rows(om, Vq, wl.E, wl.z0, rows, Xh.imag.copy())
+         + kk * Xh[rows] - 1j * O.bloch_advection_rows(om, k, rows, Xh))
+    err = np.linalg.norm(Ys - R, axis=1) / np.linalg.norm(R, axis=1)
+    print("per-row rel err max", err.max(), flush=True)
+    assert err.max() < 1e-13
+    # Gamma: the degree-30 complex filter is the real one, bit for bit
+    gm.set_kpoint(0.0, 0.0)
+    Yk = gm.cheb_filter_k(X, wl.m, 5.66, 315.0, 4.8)
+    Yr = gm.cheb_filter(X.real.contiguous(), wl.m, 5.66, 315.0, 4.8)
+    assert torch.equal(Yk.real, Yr)
+    del Yr
+    Yi = gm.cheb_filter(X.imag.contiguous(), wl.m, 5.66, 315.0, 4.8)
+    assert torch.equal(Yk.imag, Yi)
