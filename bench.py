@@ -31,13 +31,13 @@ METRIC = "H·X GDoF·vec/s in Chebyshev filter, FP64 vs FP32/BF16 at ≤1e-7 Ha 
 UNIT = "GDoF·vec/s"
 PEAK = {"f64": (78.6, "mfma"), "f32": (157.3, "mfma"), "bf16": (2500.0, "mfma")}  # TFLOP/s, dense MFMA
 # sustained rate of the instruction each default step kernel multiplies with,
-# measured on the box with a register-only loop (FP64: 4x4x4 blocks, FP32:
+# measured on an MI355X with a register-only loop (FP64: 4x4x4 blocks, FP32:
 # 16x16x4); see paper_2504_00998_amd/microbench/mfma_rate.hip
 MEASURED_PEAK = {"f64": 74.2, "f32": 155.0}
 # HBM bytes per colour launch of the default step kernel on the p=4 slab
 # (N=256), from FETCH_SIZE/WRITE_SIZE counters scaled by a plain copy of known
 # size; valid for this kernel build only
-COUNTED_TRAFFIC = {("slab-p4-24x24x48", 256, "f64"): (2.229e9, "step_row_kernel<4,0,2,1,5,4>"),
+COUNTED_TRAFFIC = {("slab-p4-24x24x48", 256, "f64"): (2.228e9, "step_pipe_kernel<4,2>"),
                    ("slab-p4-24x24x48", 256, "f32"): (2.631e9, "step_mc_kernel<4,1,2>"),
                    ("slab-p4-24x24x48", 256, "bf16"): (2.670e9, "step_mc_kernel<4,2,4>")}
 
@@ -255,6 +255,37 @@ def main():
                       "iterations": p_it, "relres": p_rel, "s": round(p_s, 4),
                       "ms_per_iteration": round(1e3 * p_s / max(p_it, 1), 4),
                       "solver": "Jacobi-preconditioned CG; product = cell-batched single-vector step kernel"}
+    # Bloch form (Sec. 2.1): the same filter with complex H~^k at an in-plane
+    # wave vector, on the same storage read as N/2 complex vectors
+    # (interleaved re/im), FP64 only
+    if args.prec == "f64" and wl.bc[0] == W.PERIODIC and wl.bc[1] == W.PERIODIC and N % 2 == 0:
+        kb = (0.5 * math.pi / wl.L[0], 0.25 * math.pi / wl.L[1])
+        gm.set_kpoint(*kb)
+        kk = 0.5 * (kb[0] ** 2 + kb[1] ** 2)
+        Xc, Yc = X.view(torch.complex128), Y.view(torch.complex128)
+        gm.cheb_filter_k(Xc, m, a + kk, b + kk + 1.0, a0 + kk, Y=Yc, work=work)
+        torch.cuda.synchronize()
+        be0, be1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        nb = max(1, min(args.steps, 3))
+        be0.record(stream)
+        for _ in range(nb):
+            gm.cheb_filter_k(Xc, m, a + kk, b + kk + 1.0, a0 + kk, Y=Yc, work=work)
+        be1.record(stream)
+        torch.cuda.synchronize()
+        ms_k = be0.elapsed_time(be1) / nb
+        gm.set_kpoint(0.0, 0.0)
+        if not torch.isfinite(Y).all():
+            raise RuntimeError("non-finite Bloch filter output")
+        Nc = N // 2
+        # per colour launch: (1/2)K_c and k.G_c products on 2 Nc real columns
+        fl_k = 2.0 * 2.0 * nc * nc * (cells / ncol) * (2 * Nc)
+        lk_ms = ms_k / launches
+        rec["bloch"] = {"k": list(kb), "complex_vectors": Nc, "ms_per_filter": round(ms_k, 4),
+                        "GDoF_cvec_per_s": round(m * n * Nc / (ms_k * 1e-3) / 1e9, 3),
+                        "avg_launch_ms": round(lk_ms, 5), "flops_per_launch": fl_k,
+                        "achieved_TFLOPs": round(fl_k / (lk_ms * 1e-3) / 1e12, 3),
+                        "frac_of_fp64_peak": round(fl_k / (lk_ms * 1e-3) / 1e12 / PEAK["f64"][0], 4),
+                        "kernel": f"step_row_kernel<{wl.p},0,...,CPX> (complex H~^k, one colour pass)"}
     if not args.no_mixed and args.prec == "f64":
         t_pot_ms = t_pot
         rec["mixed_precision"] = mixed_precision_report(gm, wl, X, Y, work, a, b, a0, args.steps, ms - t_pot_ms)

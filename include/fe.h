@@ -100,8 +100,10 @@ fe_status fe_mesh_destroy(fe_mesh *mesh);
  * would exceed the LDS); 5 = tiles of cells accumulated in LDS (p = 3, 4 and,
  * below FP64, 5; else 3); 6 = row-owner kernel (each thread loads
  * everything its outputs need in one round trip before the cell product;
- * the FP64 default); 7 = FP64 persistent pipelined row-owner kernel with the
- * cell matrix in registers (p <= 4; else 6; below FP64, 3); 8 = persistent
+ * the FP64 default except at p = 4); 7 = FP64 persistent pipelined
+ * row-owner kernel with the cell matrix in registers and the loads of the
+ * next two items in flight during each cell product (p <= 4, the FP64
+ * default at p = 4; else 6; below FP64, 3); 8 = persistent
  * warp-specialised row-owner kernel, compute waves and memory waves
  * exchanging double-buffered LDS tiles (p <= 4; else 6).  Variants 0-4 and
  * 6-8 give bitwise-identical results, except that in FP64 variant 2 multiplies with
@@ -256,8 +258,10 @@ fe_status fe_dipole(fe_mesh *mesh, const double *rho, double z0, double *mu_host
  * work: device, >= fe_poisson_work_bytes(mesh) bytes.  Stops when
  * |r| / |b| <= tol or after maxit iterations (r, b: residual and right-hand
  * side of the scaled system in x = M^1/2 phi); *iters_host and *relres_host
- * (may be NULL) receive the iteration count and the final |r| / |b|.  Synchronous
- * with stream (reads back dot products).  FE_EINVAL for NULL arguments,
+ * (may be NULL) receive the iteration count and the final |r| / |b|.  The
+ * iteration runs on the device (fixed-order reductions, so results are
+ * reproducible); the host reads its state once per 8 iterations and returns
+ * after the stream has drained.  FE_EINVAL for NULL arguments,
  * tol <= 0 or maxit < 1; FE_ENOMEM if work is too small. */
 size_t fe_poisson_work_bytes(const fe_mesh *mesh);
 fe_status fe_poisson_solve(fe_mesh *mesh, const double *charge, double *phi, double tol, int32_t maxit,

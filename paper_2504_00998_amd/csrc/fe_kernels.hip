@@ -1510,159 +1510,224 @@ static hipError_t launch_ws_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
 
 // ------------------------------------------------------------------------
 // Pipelined row-owner variant (FP64, p <= 4): persistent workgroups walk the
-// items (cell, chunk of 16 vectors) of a colour with stride gridDim.x.  Each
-// wave owns two row tiles of (1/2)K_c, held in registers for the whole
-// launch, so one LDS read of B feeds eight 4x4x4 products; each thread owns
-// one row of each tile for four consecutive vectors.  While the cell product
-// of item i runs from one LDS buffer, the HBM loads of item i + gridDim.x
-// (X, the previous iterate or the old Y, v) are in flight into registers --
-// the product loop issues no vector-memory instruction, so nothing waits on
-// them -- and they are staged into the other buffer after item i's outputs
-// are written.  Same arithmetic, in the same order, as the other FP64
-// variants.
+// items (cell, group of G chunks of 16 vectors) of a colour with stride
+// gridDim.x, one wave per 16-row tile of (1/2)K_c with the tile's fragments
+// held in registers for the whole launch, each thread owning one row for four
+// consecutive vectors per chunk (the 4x4x4 layout of the row-owner kernel).
+// The product loop issues no vector-memory instruction, so the HBM loads of
+// the next item (X, the previous iterate or the old Y, v; branch-free from
+// clamped addresses) stay in flight while it runs.  After the product the
+// next item is staged into the other LDS buffer -- the only wait on those
+// loads -- and only then are the current item's outputs stored, so the wait
+// never includes the stores.  B is read from LDS one k-step ahead of its
+// products.  Same arithmetic, in the same order, as the other FP64 variants.
 template <int P> struct PipeShape {
-    static constexpr int NCP = ((P + 1) * (P + 1) * (P + 1) + 31) / 32 * 32, NT = NCP / 16;
-    static constexpr int TPW = 2, W = NT / TPW;
+    static constexpr int NCP = ((P + 1) * (P + 1) * (P + 1) + 31) / 32 * 32, NT = NCP / 16, NKS = NCP / 4;
+    static constexpr int W = NT, G = 2, XS = NCP * 16;  // waves; chunks per item; doubles per chunk buffer
+    static constexpr size_t bytes = (size_t)2 * G * XS * sizeof(double);
 };
 
-struct RowItem {
+// Whether local node i of cell c is not shared, along this axis, with a cell
+// of a lower colour: node_first for one axis, as selects only (no branches).
+__device__ __forceinline__ bool axis_first_sel(const AxisInfo &a, int p, int c, int i) {
+    const bool lo = i == 0, hi = i == p;
+    const bool wrap_lo = lo && c == 0, wrap_hi = hi && c == a.ncell - 1;
+    int nb = lo ? c - 1 : c + 1;
+    nb = wrap_lo ? a.ncell - 1 : nb;
+    nb = wrap_hi ? 0 : nb;
+    const bool exists = (lo || hi) && (!(wrap_lo || wrap_hi) || a.bc == FE_BC_PERIODIC);
+    const int cn = (a.ncol == 3 && nb == a.ncell - 1) ? 2 : (nb & 1);
+    const int cc = (a.ncol == 3 && c == a.ncell - 1) ? 2 : (c & 1);
+    return !(exists && cn < cc);
+}
+
+// The loads of one thread for one item, and what the epilogue needs.
+template <int G> struct PipeRow {
     NodeRef n;
     bool fst;
-    double vI;
-    double x[4], o[4];
+    double vraw;
+    double x[G][4], o[G][4];
+    int64_t v0;
 };
 
 template <int P>
-__device__ __forceinline__ void pipe_load(const StepParams &k, int64_t item, int wave, int lane, RowItem (&L)[2]) {
-    constexpr int N1 = P + 1, NC = N1 * N1 * N1, W = PipeShape<P>::W;
-    const ItemCell c = item_cell(k, item);
+__device__ __forceinline__ void pipe_issue(const StepParams &k, int64_t item, int ngroups, int wave, int lane,
+                                           PipeRow<PipeShape<P>::G> &L) {
+    constexpr int N1 = P + 1, NC = N1 * N1 * N1, G = PipeShape<P>::G;
+    const int grp = (int)(item % ngroups);
+    const ItemCell c = item_cell(k, (item / ngroups) * k.nchunk);
     const int rl = 4 * ((lane >> 2) & 3) + (lane >> 4);
-    const int64_t v0 = (int64_t)c.chunk * 16 + 4 * (lane & 3);
+    const int r = 16 * wave + rl;
+    L.v0 = (int64_t)grp * G * 16 + 4 * (lane & 3);
+    L.n = node_ref<P>(k, c, r);
+    const int l = min(r, NC - 1);
+    const bool f0 = axis_first_sel(k.ax[0], P, c.cx, l % N1);
+    const bool f1 = axis_first_sel(k.ax[1], P, c.cy, (l / N1) % N1);
+    const bool f2 = axis_first_sel(k.ax[2], P, c.cz, l / (N1 * N1));
+    L.fst = (r < NC) & f0 & f1 & f2;
+    const int64_t Ic = max(L.n.I, 0);
+    // the old value: Y where an earlier colour has written the node, else the
+    // previous iterate (or X when there is none, unused then); the two base
+    // pointers are uniform, only the choice between them is per lane
+    const double *ob = k.Ym1 ? k.Ym1 : k.X;
+    const int64_t ol = k.Ym1 ? k.ldm : k.ldx;
+    const double *orow = L.fst ? ob + Ic * ol : k.Y + Ic * k.ldy;
+    const double *xrow = k.X + Ic * k.ldx;
+    L.vraw = k.v[Ic];
 #pragma unroll
-    for (int tt = 0; tt < 2; ++tt) {
-        const int r = 16 * (wave + tt * W) + rl;
-        L[tt].n = node_ref<P>(k, c, r);
-        const int I = L[tt].n.I;
-        L[tt].fst = r < NC && node_first<P>(k, c, r);
-        L[tt].vI = (I >= 0 && L[tt].fst) ? k.v[I] : 0.0;
+    for (int g = 0; g < G; ++g)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int64_t vec = v0 + q;
-            double x = 0.0, o = 0.0;
-            if (I >= 0 && vec < k.N) {
-                x = k.X[(int64_t)I * k.ldx + vec];
-                if (!L[tt].fst) o = k.Y[(int64_t)I * k.ldy + vec];
-                else if (k.Ym1) o = k.Ym1[(int64_t)I * k.ldm + vec];
-            }
-            L[tt].x[q] = x;
-            L[tt].o[q] = o;
+            const int64_t vc = min(L.v0 + 16 * g + q, k.N - 1);
+            L.x[g][q] = xrow[vc];
+            L.o[g][q] = orow[vc];
         }
+}
+
+// D X of the item into an LDS buffer; per output the first writer's base term
+// alpha (v - c) X - beta Y_{k-1}, or the old Y, into bo.
+template <int P>
+__device__ __forceinline__ void pipe_stage(const StepParams &k, const PipeRow<PipeShape<P>::G> &L, double *xs,
+                                           int wave, int lane, double (&bo)[PipeShape<P>::G][4], int &I, double &d,
+                                           int64_t &v0) {
+    constexpr int G = PipeShape<P>::G, XS = PipeShape<P>::XS;
+    const int rl = 4 * ((lane >> 2) & 3) + (lane >> 4);
+    const int r = 16 * wave + rl;
+    const int vq = 4 * (lane & 3);
+    const bool useo = !L.fst || k.Ym1 != nullptr;
+    const double vI = (L.n.I >= 0 && L.fst) ? L.vraw : 0.0;
+    const double sc = k.alpha * (vI - k.shift);
+    d = node_scale(L.n);
+    I = L.n.I;
+    v0 = L.v0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        double dx[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const bool ok = L.n.I >= 0 && L.v0 + 16 * g + q < k.N;
+            const double x = ok ? L.x[g][q] : 0.0;
+            const double o = (ok && useo) ? L.o[g][q] : 0.0;
+            double base = sc * x;
+            if (k.Ym1) base -= k.beta * o;
+            bo[g][q] = L.fst ? base : o;
+            dx[q] = d * x;
+        }
+        double2 *dst = reinterpret_cast<double2 *>(xs + g * XS + r * 16 + vq);
+        dst[0] = double2{dx[0], dx[1]};
+        dst[1] = double2{dx[2], dx[3]};
     }
 }
 
-// D X of the item into an LDS buffer; the first writer's base term (or the
-// old Y) into bo; the row's DoF and D factor kept for the epilogue.
-template <int P>
-__device__ __forceinline__ void pipe_stage(const StepParams &k, const RowItem (&L)[2], double *xs, int wave, int lane,
-                                           double (&bo)[2][4], int (&I)[2], double (&d)[2]) {
-    constexpr int W = PipeShape<P>::W;
-    const int rl = 4 * ((lane >> 2) & 3) + (lane >> 4);
-#pragma unroll
-    for (int tt = 0; tt < 2; ++tt) {
-        const int r = 16 * (wave + tt * W) + rl;
-        const double sc = k.alpha * (L[tt].vI - k.shift);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            double base = sc * L[tt].x[q];
-            if (k.Ym1) base -= k.beta * L[tt].o[q];
-            bo[tt][q] = L[tt].fst ? base : L[tt].o[q];
-        }
-        const double dn = node_scale(L[tt].n);
-        double2 *dst = reinterpret_cast<double2 *>(xs + r * 16 + 4 * (lane & 3));
-        dst[0] = double2{dn * L[tt].x[0], dn * L[tt].x[1]};
-        dst[1] = double2{dn * L[tt].x[2], dn * L[tt].x[3]};
-        I[tt] = L[tt].n.I;
-        d[tt] = dn;
-    }
-}
-
-template <int P>
-__global__ __launch_bounds__(64 * PipeShape<P>::W) void step_pipe_kernel(StepParams k, int64_t nitems) {
-    constexpr int NCP = PipeShape<P>::NCP, NKS = NCP / 4, W = PipeShape<P>::W;
+template <int P, int PD>
+__global__ __launch_bounds__(64 * PipeShape<P>::W) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void step_pipe_kernel(StepParams k, int64_t nitems) {
+    constexpr int NKS = PipeShape<P>::NKS, G = PipeShape<P>::G, XS = PipeShape<P>::XS;
     extern __shared__ __align__(16) unsigned char smem[];
-    double *xbuf = reinterpret_cast<double *>(smem);  // [2][NCP][16]
+    double *xbuf = reinterpret_cast<double *>(smem);  // [2][G][XS]
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int ngroups = (k.nchunk + G - 1) / G;
+    const int64_t stride = gridDim.x;
     int64_t item = blockIdx.x;
     if (item >= nitems) return;  // whole workgroup
-    RowItem L[2];
-    double bo[2][4], d[2];
-    int I[2];
-    pipe_load<P>(k, item, wave, lane, L);
-    pipe_stage<P>(k, L, xbuf, wave, lane, bo, I, d);
-    __syncthreads();
-    int cur = 0;
-    double ar[2][NKS];  // fragments of row tiles wave and wave + W
+    // the wave's row tile of (1/2)K_c, resident for the launch
+    double ar[NKS];
     {
-        const double *A0 = reinterpret_cast<const double *>(k.A) + (size_t)wave * NKS * 64 + lane;
-        const double *A1 = A0 + (size_t)W * NKS * 64;
+        const double *A = reinterpret_cast<const double *>(k.A) + (size_t)wave * NKS * 64 + lane;
 #pragma unroll
-        for (int s = 0; s < NKS; ++s) {
-            ar[0][s] = A0[s * 64];
-            ar[1][s] = A1[s * 64];
-        }
+        for (int s = 0; s < NKS; ++s) ar[s] = A[s * 64];
     }
-    for (;;) {
-        const int64_t next = item + gridDim.x;
-        const bool more = next < nitems;  // uniform over the workgroup
-        if (more) pipe_load<P>(k, next, wave, lane, L);
-
-        const double *xs = xbuf + cur * NCP * 16;
-        double acc[2][4];
+    double bo[G][4], d;
+    int I;
+    int64_t v0;
+    int cur = 0;
+    // One item: product from xbuf[cur]; the next item (loaded into Ln) staged
+    // into the other buffer; with PD = 2 the item after it is requested into
+    // Lf first (index clamped to the last item, so the loads are
+    // unconditional and the wait for Ln's loads leaves them in flight);
+    // then this item's outputs are stored.  Returns false after the last item.
+    auto body = [&](PipeRow<G> &Ln, PipeRow<G> &Lf) -> bool {
+        const bool more = item + stride < nitems;  // uniform over the workgroup
+        if constexpr (PD == 2) pipe_issue<P>(k, min(item + 2 * stride, nitems - 1), ngroups, wave, lane, Lf);
+        else if (more) pipe_issue<P>(k, item + stride, ngroups, wave, lane, Ln);
+        const double *xs = xbuf + cur * G * XS;
+        double acc[G][4];
 #pragma unroll
-        for (int tt = 0; tt < 2; ++tt)
-            for (int q = 0; q < 4; ++q) acc[tt][q] = 0.0;
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[g][q] = 0.0;
+        double bc[G][4], bn[G][4];
+#pragma unroll
+        for (int g = 0; g < G; ++g) f64_quad_b(xs + g * XS, 0, lane, bc[g]);
 #pragma unroll
         for (int s = 0; s < NKS; ++s) {
-            double b[4];
-            f64_quad_b(xs, s, lane, b);
+            if (s + 1 < NKS)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                acc[0][q] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[0][s], b[q], acc[0][q], 0, 0, 0);
-                acc[1][q] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[1][s], b[q], acc[1][q], 0, 0, 0);
-            }
+                for (int g = 0; g < G; ++g) f64_quad_b(xs + g * XS, s + 1, lane, bn[g]);
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    acc[g][q] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[s], bc[g][q], acc[g][q], 0, 0, 0);
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) bc[g][q] = bn[g][q];
         }
-        const int64_t v0 = (int64_t)(item % k.nchunk) * 16 + 4 * (lane & 3);
+        // outputs of this item, kept while the next one is staged
+        double out[G][4];
 #pragma unroll
-        for (int tt = 0; tt < 2; ++tt) {
-            if (I[tt] < 0) continue;
-            double *yrow = k.Y + (int64_t)I[tt] * k.ldy;
+        for (int g = 0; g < G; ++g)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t vec = v0 + q;
-                if (vec < k.N) yrow[vec] = bo[tt][q] + k.alpha * d[tt] * acc[tt][q];
-            }
+            for (int q = 0; q < 4; ++q) out[g][q] = bo[g][q] + k.alpha * d * acc[g][q];
+        const int Io = I;
+        const int64_t v0o = v0;
+        if (more) pipe_stage<P>(k, Ln, xbuf + (cur ^ 1) * G * XS, wave, lane, bo, I, d, v0);
+        if (Io >= 0) {
+            double *yrow = k.Y + (int64_t)Io * k.ldy;
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t vec = v0o + 16 * g + q;
+                    if (vec < k.N) yrow[vec] = out[g][q];
+                }
         }
-        if (!more) break;
+        if (!more) return false;
         cur ^= 1;
-        pipe_stage<P>(k, L, xbuf + cur * NCP * 16, wave, lane, bo, I, d);
         __syncthreads();
-        item = next;
+        item += stride;
+        return true;
+    };
+    PipeRow<G> LA, LB;
+    pipe_issue<P>(k, item, ngroups, wave, lane, LA);
+    pipe_stage<P>(k, LA, xbuf, wave, lane, bo, I, d, v0);
+    __syncthreads();
+    if constexpr (PD == 2) {
+        pipe_issue<P>(k, min(item + stride, nitems - 1), ngroups, wave, lane, LA);
+        for (;;) {
+            if (!body(LA, LB)) break;
+            if (!body(LB, LA)) break;
+        }
+    } else {
+        while (body(LA, LB)) {
+        }
     }
 }
 
-template <int P>
+template <int P, int PD = 1>
 static hipError_t launch_pipe_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
-    constexpr int NCP = PipeShape<P>::NCP, W = PipeShape<P>::W;
-    const size_t smem = (size_t)2 * NCP * 16 * sizeof(double);
+    constexpr int W = PipeShape<P>::W, G = PipeShape<P>::G;
+    const size_t smem = PipeShape<P>::bytes;
     static bool attr = false;
     static int resident = 0;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step_pipe_kernel<P>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step_pipe_kernel<P, PD>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         if (e != hipSuccess) return e;
         int per_cu = 0, dev = 0, cus = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&step_pipe_kernel<P>),
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&step_pipe_kernel<P, PD>),
                                                          64 * W, smem);
         if (e != hipSuccess) return e;
         e = hipGetDevice(&dev);
@@ -1672,6 +1737,7 @@ static hipError_t launch_pipe_p(StepParams prm, const fe_mesh *m, hipStream_t s)
         resident = std::max(1, per_cu) * std::max(1, cus);
         attr = true;
     }
+    const int ngroups = (prm.nchunk + G - 1) / G;
     for (int c2 = 0; c2 < m->ncol[2]; ++c2)
         for (int c1 = 0; c1 < m->ncol[1]; ++c1)
             for (int c0 = 0; c0 < m->ncol[0]; ++c0) {
@@ -1690,9 +1756,9 @@ static hipError_t launch_pipe_p(StepParams prm, const fe_mesh *m, hipStream_t s)
                     cells *= cnt;
                 }
                 if (cells == 0) continue;
-                const int64_t nitems = cells * prm.nchunk;
+                const int64_t nitems = cells * ngroups;
                 const int64_t grid = std::min<int64_t>(nitems, resident);
-                hipLaunchKernelGGL((step_pipe_kernel<P>), dim3((unsigned)grid), dim3(64 * W), smem, s, prm, nitems);
+                hipLaunchKernelGGL((step_pipe_kernel<P, PD>), dim3((unsigned)grid), dim3(64 * W), smem, s, prm, nitems);
                 hipError_t e = hipGetLastError();
                 if (e != hipSuccess) return e;
             }
@@ -2043,12 +2109,15 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
         }
 #undef FE_WS
     }
-    if (m->kernel_variant == 7 && prec == FE_F64) {
+    // the pipelined kernel with two items in flight is the FP64 default at
+    // p = 4, where it was measured fastest (6.1 against 6.8 ms per H~X on
+    // the 24x24x48-cell slab, 256 vectors)
+    if ((m->kernel_variant == 7 || (m->kernel_variant == 0 && m->p == 4)) && prec == FE_F64) {
         switch (m->p) {
-        case 1: return launch_pipe_p<1>(prm, m, s);
-        case 2: return launch_pipe_p<2>(prm, m, s);
-        case 3: return launch_pipe_p<3>(prm, m, s);
-        case 4: return launch_pipe_p<4>(prm, m, s);
+        case 1: return launch_pipe_p<1, 2>(prm, m, s);
+        case 2: return launch_pipe_p<2, 2>(prm, m, s);
+        case 3: return launch_pipe_p<3, 2>(prm, m, s);
+        case 4: return launch_pipe_p<4, 2>(prm, m, s);
         default: break;
         }
     }
