@@ -1521,11 +1521,22 @@ static hipError_t launch_ws_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
 // loads -- and only then are the current item's outputs stored, so the wait
 // never includes the stores.  B is read from LDS one k-step ahead of its
 // products.  Same arithmetic, in the same order, as the other FP64 variants.
-template <int P> struct PipeShape {
+template <int P, int PREC = 0> struct PipeShape {
+    typedef typename PrecTraits<PREC>::T T;
     static constexpr int NCP = ((P + 1) * (P + 1) * (P + 1) + 31) / 32 * 32, NT = NCP / 16, NKS = NCP / 4;
-    static constexpr int W = NT, G = 2, XS = NCP * 16;  // waves; chunks per item; doubles per chunk buffer
-    static constexpr size_t bytes = (size_t)2 * G * XS * sizeof(double);
+    static constexpr int W = NT, G = 2, XS = NCP * 16;  // waves; chunks per item; elements per chunk buffer
+    static constexpr size_t bytes = (size_t)2 * G * XS * sizeof(T);
 };
+
+// Row within the 16-row tile and first of the four vectors a lane owns: the
+// FP64 4x4x4 layout, or (FP32) the transposed 16x16x4 product of the
+// row-owner kernel (lane l owns row l%16, vectors 4(l/16) .. +3).
+template <int PREC> __device__ __forceinline__ int pipe_row(int lane) {
+    return PREC == 0 ? 4 * ((lane >> 2) & 3) + (lane >> 4) : (lane & 15);
+}
+template <int PREC> __device__ __forceinline__ int pipe_vec(int lane) {
+    return PREC == 0 ? 4 * (lane & 3) : 4 * (lane >> 4);
+}
 
 // Whether local node i of cell c is not shared, along this axis, with a cell
 // of a lower colour: node_first for one axis, as selects only (no branches).
@@ -1550,15 +1561,14 @@ template <int G> struct PipeRow {
     int64_t v0;
 };
 
-template <int P>
+template <int P, int PREC>
 __device__ __forceinline__ void pipe_issue(const StepParams &k, int64_t item, int ngroups, int wave, int lane,
                                            PipeRow<PipeShape<P>::G> &L) {
     constexpr int N1 = P + 1, NC = N1 * N1 * N1, G = PipeShape<P>::G;
     const int grp = (int)(item % ngroups);
     const ItemCell c = item_cell(k, (item / ngroups) * k.nchunk);
-    const int rl = 4 * ((lane >> 2) & 3) + (lane >> 4);
-    const int r = 16 * wave + rl;
-    L.v0 = (int64_t)grp * G * 16 + 4 * (lane & 3);
+    const int r = 16 * wave + pipe_row<PREC>(lane);
+    L.v0 = (int64_t)grp * G * 16 + pipe_vec<PREC>(lane);
     L.n = node_ref<P>(k, c, r);
     const int l = min(r, NC - 1);
     const bool f0 = axis_first_sel(k.ax[0], P, c.cx, l % N1);
@@ -1586,14 +1596,13 @@ __device__ __forceinline__ void pipe_issue(const StepParams &k, int64_t item, in
 
 // D X of the item into an LDS buffer; per output the first writer's base term
 // alpha (v - c) X - beta Y_{k-1}, or the old Y, into bo.
-template <int P>
-__device__ __forceinline__ void pipe_stage(const StepParams &k, const PipeRow<PipeShape<P>::G> &L, double *xs,
-                                           int wave, int lane, double (&bo)[PipeShape<P>::G][4], int &I, double &d,
-                                           int64_t &v0) {
+template <int P, int PREC>
+__device__ __forceinline__ void pipe_stage(const StepParams &k, const PipeRow<PipeShape<P>::G> &L,
+                                           typename PipeShape<P, PREC>::T *xs, int wave, int lane,
+                                           double (&bo)[PipeShape<P>::G][4], int &I, double &d, int64_t &v0) {
     constexpr int G = PipeShape<P>::G, XS = PipeShape<P>::XS;
-    const int rl = 4 * ((lane >> 2) & 3) + (lane >> 4);
-    const int r = 16 * wave + rl;
-    const int vq = 4 * (lane & 3);
+    const int r = 16 * wave + pipe_row<PREC>(lane);
+    const int vq = pipe_vec<PREC>(lane);
     const bool useo = !L.fst || k.Ym1 != nullptr;
     const double vI = (L.n.I >= 0 && L.fst) ? L.vraw : 0.0;
     const double sc = k.alpha * (vI - k.shift);
@@ -1613,18 +1622,24 @@ __device__ __forceinline__ void pipe_stage(const StepParams &k, const PipeRow<Pi
             bo[g][q] = L.fst ? base : o;
             dx[q] = d * x;
         }
-        double2 *dst = reinterpret_cast<double2 *>(xs + g * XS + r * 16 + vq);
-        dst[0] = double2{dx[0], dx[1]};
-        dst[1] = double2{dx[2], dx[3]};
+        if constexpr (PREC == 0) {
+            double2 *dst = reinterpret_cast<double2 *>(xs + g * XS + r * 16 + vq);
+            dst[0] = double2{dx[0], dx[1]};
+            dst[1] = double2{dx[2], dx[3]};
+        } else {
+            *reinterpret_cast<f4 *>(xs + g * XS + r * 16 + vq) = f4{(float)dx[0], (float)dx[1], (float)dx[2], (float)dx[3]};
+        }
     }
 }
 
-template <int P, int PD>
+template <int P, int PREC, int PD>
 __global__ __launch_bounds__(64 * PipeShape<P>::W) __attribute__((amdgpu_waves_per_eu(1, 2)))
 void step_pipe_kernel(StepParams k, int64_t nitems) {
+    static_assert(PREC == 0 || PREC == 1, "FP64 or FP32 cell products");
     constexpr int NKS = PipeShape<P>::NKS, G = PipeShape<P>::G, XS = PipeShape<P>::XS;
+    typedef typename PipeShape<P, PREC>::T T;
     extern __shared__ __align__(16) unsigned char smem[];
-    double *xbuf = reinterpret_cast<double *>(smem);  // [2][G][XS]
+    T *xbuf = reinterpret_cast<T *>(smem);  // [2][G][XS]
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int ngroups = (k.nchunk + G - 1) / G;
@@ -1632,9 +1647,9 @@ void step_pipe_kernel(StepParams k, int64_t nitems) {
     int64_t item = blockIdx.x;
     if (item >= nitems) return;  // whole workgroup
     // the wave's row tile of (1/2)K_c, resident for the launch
-    double ar[NKS];
+    T ar[NKS];
     {
-        const double *A = reinterpret_cast<const double *>(k.A) + (size_t)wave * NKS * 64 + lane;
+        const T *A = reinterpret_cast<const T *>(k.A) + (size_t)wave * NKS * 64 + lane;
 #pragma unroll
         for (int s = 0; s < NKS; ++s) ar[s] = A[s * 64];
     }
@@ -1649,31 +1664,57 @@ void step_pipe_kernel(StepParams k, int64_t nitems) {
     // then this item's outputs are stored.  Returns false after the last item.
     auto body = [&](PipeRow<G> &Ln, PipeRow<G> &Lf) -> bool {
         const bool more = item + stride < nitems;  // uniform over the workgroup
-        if constexpr (PD == 2) pipe_issue<P>(k, min(item + 2 * stride, nitems - 1), ngroups, wave, lane, Lf);
-        else if (more) pipe_issue<P>(k, item + stride, ngroups, wave, lane, Ln);
-        const double *xs = xbuf + cur * G * XS;
+        if constexpr (PD == 2) pipe_issue<P, PREC>(k, min(item + 2 * stride, nitems - 1), ngroups, wave, lane, Lf);
+        else if (more) pipe_issue<P, PREC>(k, item + stride, ngroups, wave, lane, Ln);
+        const T *xs = xbuf + cur * G * XS;
         double acc[G][4];
-#pragma unroll
-        for (int g = 0; g < G; ++g)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[g][q] = 0.0;
-        double bc[G][4], bn[G][4];
-#pragma unroll
-        for (int g = 0; g < G; ++g) f64_quad_b(xs + g * XS, 0, lane, bc[g]);
-#pragma unroll
-        for (int s = 0; s < NKS; ++s) {
-            if (s + 1 < NKS)
-#pragma unroll
-                for (int g = 0; g < G; ++g) f64_quad_b(xs + g * XS, s + 1, lane, bn[g]);
+        if constexpr (PREC == 0) {
 #pragma unroll
             for (int g = 0; g < G; ++g)
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    acc[g][q] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[s], bc[g][q], acc[g][q], 0, 0, 0);
+                for (int q = 0; q < 4; ++q) acc[g][q] = 0.0;
+            double bc[G][4], bn[G][4];
+#pragma unroll
+            for (int g = 0; g < G; ++g) f64_quad_b(xs + g * XS, 0, lane, bc[g]);
+#pragma unroll
+            for (int s = 0; s < NKS; ++s) {
+                if (s + 1 < NKS)
+#pragma unroll
+                    for (int g = 0; g < G; ++g) f64_quad_b(xs + g * XS, s + 1, lane, bn[g]);
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        acc[g][q] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[s], bc[g][q], acc[g][q], 0, 0, 0);
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) bc[g][q] = bn[g][q];
+            }
+        } else {
+            // transposed 16x16x4 products: X slice first, cell-matrix fragment second
+            f4 c4[G];
+            float bc[G], bn[G];
+            const int bo0 = (lane >> 4) * 16 + (lane & 15);
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                c4[g] = f4{0.f, 0.f, 0.f, 0.f};
+                bc[g] = xs[g * XS + bo0];
+            }
+#pragma unroll
+            for (int s = 0; s < NKS; ++s) {
+                if (s + 1 < NKS)
+#pragma unroll
+                    for (int g = 0; g < G; ++g) bn[g] = xs[g * XS + (4 * (s + 1)) * 16 + bo0];
+#pragma unroll
+                for (int g = 0; g < G; ++g) c4[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(bc[g], ar[s], c4[g], 0, 0, 0);
+#pragma unroll
+                for (int g = 0; g < G; ++g) bc[g] = bn[g];
+            }
 #pragma unroll
             for (int g = 0; g < G; ++g)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) bc[g][q] = bn[g][q];
+                for (int q = 0; q < 4; ++q) acc[g][q] = (double)c4[g][q];
         }
         // outputs of this item, kept while the next one is staged
         double out[G][4];
@@ -1683,7 +1724,7 @@ void step_pipe_kernel(StepParams k, int64_t nitems) {
             for (int q = 0; q < 4; ++q) out[g][q] = bo[g][q] + k.alpha * d * acc[g][q];
         const int Io = I;
         const int64_t v0o = v0;
-        if (more) pipe_stage<P>(k, Ln, xbuf + (cur ^ 1) * G * XS, wave, lane, bo, I, d, v0);
+        if (more) pipe_stage<P, PREC>(k, Ln, xbuf + (cur ^ 1) * G * XS, wave, lane, bo, I, d, v0);
         if (Io >= 0) {
             double *yrow = k.Y + (int64_t)Io * k.ldy;
 #pragma unroll
@@ -1701,11 +1742,11 @@ void step_pipe_kernel(StepParams k, int64_t nitems) {
         return true;
     };
     PipeRow<G> LA, LB;
-    pipe_issue<P>(k, item, ngroups, wave, lane, LA);
-    pipe_stage<P>(k, LA, xbuf, wave, lane, bo, I, d, v0);
+    pipe_issue<P, PREC>(k, item, ngroups, wave, lane, LA);
+    pipe_stage<P, PREC>(k, LA, xbuf, wave, lane, bo, I, d, v0);
     __syncthreads();
     if constexpr (PD == 2) {
-        pipe_issue<P>(k, min(item + stride, nitems - 1), ngroups, wave, lane, LA);
+        pipe_issue<P, PREC>(k, min(item + stride, nitems - 1), ngroups, wave, lane, LA);
         for (;;) {
             if (!body(LA, LB)) break;
             if (!body(LB, LA)) break;
@@ -1716,18 +1757,18 @@ void step_pipe_kernel(StepParams k, int64_t nitems) {
     }
 }
 
-template <int P, int PD = 1>
+template <int P, int PREC, int PD>
 static hipError_t launch_pipe_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
     constexpr int W = PipeShape<P>::W, G = PipeShape<P>::G;
-    const size_t smem = PipeShape<P>::bytes;
+    const size_t smem = PipeShape<P, PREC>::bytes;
     static bool attr = false;
     static int resident = 0;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step_pipe_kernel<P, PD>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step_pipe_kernel<P, PREC, PD>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         if (e != hipSuccess) return e;
         int per_cu = 0, dev = 0, cus = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&step_pipe_kernel<P, PD>),
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&step_pipe_kernel<P, PREC, PD>),
                                                          64 * W, smem);
         if (e != hipSuccess) return e;
         e = hipGetDevice(&dev);
@@ -1758,7 +1799,7 @@ static hipError_t launch_pipe_p(StepParams prm, const fe_mesh *m, hipStream_t s)
                 if (cells == 0) continue;
                 const int64_t nitems = cells * ngroups;
                 const int64_t grid = std::min<int64_t>(nitems, resident);
-                hipLaunchKernelGGL((step_pipe_kernel<P, PD>), dim3((unsigned)grid), dim3(64 * W), smem, s, prm, nitems);
+                hipLaunchKernelGGL((step_pipe_kernel<P, PREC, PD>), dim3((unsigned)grid), dim3(64 * W), smem, s, prm, nitems);
                 hipError_t e = hipGetLastError();
                 if (e != hipSuccess) return e;
             }
@@ -2114,10 +2155,19 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
     // the 24x24x48-cell slab, 256 vectors)
     if ((m->kernel_variant == 7 || (m->kernel_variant == 0 && m->p == 4)) && prec == FE_F64) {
         switch (m->p) {
-        case 1: return launch_pipe_p<1, 2>(prm, m, s);
-        case 2: return launch_pipe_p<2, 2>(prm, m, s);
-        case 3: return launch_pipe_p<3, 2>(prm, m, s);
-        case 4: return launch_pipe_p<4, 2>(prm, m, s);
+        case 1: return launch_pipe_p<1, 0, 2>(prm, m, s);
+        case 2: return launch_pipe_p<2, 0, 2>(prm, m, s);
+        case 3: return launch_pipe_p<3, 0, 2>(prm, m, s);
+        case 4: return launch_pipe_p<4, 0, 2>(prm, m, s);
+        default: break;
+        }
+    }
+    if (m->kernel_variant == 7 && prec == FE_F32) {
+        switch (m->p) {
+        case 1: return launch_pipe_p<1, 1, 2>(prm, m, s);
+        case 2: return launch_pipe_p<2, 1, 2>(prm, m, s);
+        case 3: return launch_pipe_p<3, 1, 2>(prm, m, s);
+        case 4: return launch_pipe_p<4, 1, 2>(prm, m, s);
         default: break;
         }
     }

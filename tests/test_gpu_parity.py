@@ -246,16 +246,17 @@ def test_single_vector_cell_batched_kernel(shape, p):
     assert _relerr(Y0.cpu().numpy(), op.apply(wl.X(op.n))) < 1e-13
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("p", [2, 3, 4])
-def test_pipelined_variant_several_items_per_workgroup(p):
-    """The persistent pipelined kernel (variant 7) walks several items per
+def test_pipelined_variant_several_items_per_workgroup(p, prec):
+    """The persistent pipelined kernel (variant 7, FP64 and FP32) walks several items per
     workgroup only when a colour pass has more items than resident
     workgroups: 24 x 24 x 16 cells and 64 vectors give 2304 items per pass
     (about 9 per workgroup at p = 4).  Bitwise equal to the one-cell kernel
     for one application and for the filter (previous-iterate path)."""
     wl = W.small_slab((24, 24, 16), p=p, N=64)
     fe = _fe()
-    _print_case(test="pipelined_multi_item", p=p, ncell=wl.ncell, N=wl.N)
+    _print_case(test="pipelined_multi_item", p=p, prec=prec, ncell=wl.ncell, N=wl.N)
     gm = fe.Mesh.from_workload(wl)
     Vq = W.workload_potential(wl, gm.quad_points())
     gm.set_potential(torch.from_numpy(Vq).cuda(), wl.E, wl.z0)
@@ -263,8 +264,8 @@ def test_pipelined_variant_several_items_per_workgroup(p):
     g.manual_seed(wl.seed(2))
     X = torch.randn(gm.n, wl.N, generator=g, dtype=torch.float64, device="cuda")
     gm.set_kernel(1)
-    Y1 = gm.hx(X)
-    F1 = gm.cheb_filter(X, 6, 2.0, 400.0, -0.5)
+    Y1 = gm.hx(X, prec=prec)
+    F1 = gm.cheb_filter(X, 6, 2.0, 400.0, -0.5, prec=prec)
     gm.set_kernel(7)
-    assert torch.equal(gm.hx(X), Y1)
-    assert torch.equal(gm.cheb_filter(X, 6, 2.0, 400.0, -0.5), F1)
+    assert torch.equal(gm.hx(X, prec=prec), Y1)
+    assert torch.equal(gm.cheb_filter(X, 6, 2.0, 400.0, -0.5, prec=prec), F1)
