@@ -100,10 +100,10 @@ fe_status fe_mesh_destroy(fe_mesh *mesh);
  * would exceed the LDS); 5 = tiles of cells accumulated in LDS (p = 3, 4 and,
  * below FP64, 5; else 3); 6 = row-owner kernel (each thread loads
  * everything its outputs need in one round trip before the cell product;
- * the FP64 default except at p = 4); 7 = persistent pipelined row-owner
+ * the FP64 default for p != 4); 7 = persistent pipelined row-owner
  * kernel with the cell matrix in registers and the loads of the next two
- * items in flight during each cell product (FP64 and FP32, p <= 4; the FP64
- * default at p = 4; else 6; BF16: 3); 8 = persistent
+ * items in flight during each cell product (FP64 and FP32, p <= 4; the
+ * default for both at p = 4; else 6; BF16: 3); 8 = persistent
  * warp-specialised row-owner kernel, compute waves and memory waves
  * exchanging double-buffered LDS tiles (p <= 4; else 6).  Variants 0-4 and
  * 6-8 give bitwise-identical results, except that in FP64 variant 2 multiplies with

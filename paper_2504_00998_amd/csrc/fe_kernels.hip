@@ -1552,6 +1552,16 @@ __device__ __forceinline__ bool axis_first_sel(const AxisInfo &a, int p, int c, 
     return !(exists && cn < cc);
 }
 
+// Whether the G chunks of 16 vectors starting at column c0 lie inside N and
+// every block the pipelined kernel touches allows 16-byte accesses (same for
+// all lanes of an item).
+__device__ __forceinline__ bool pipe_wide(const StepParams &k, int64_t c0) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(k.X) | reinterpret_cast<uintptr_t>(k.Y) |
+                        reinterpret_cast<uintptr_t>(k.Ym1 ? k.Ym1 : k.X);
+    const int64_t ld = k.ldx | k.ldy | (k.Ym1 ? k.ldm : k.ldx);
+    return (a & 15) == 0 && (ld & 1) == 0 && c0 + 32 <= k.N;
+}
+
 // The loads of one thread for one item, and what the epilogue needs.
 template <int G> struct PipeRow {
     NodeRef n;
@@ -1584,14 +1594,27 @@ __device__ __forceinline__ void pipe_issue(const StepParams &k, int64_t item, in
     const double *orow = L.fst ? ob + Ic * ol : k.Y + Ic * k.ldy;
     const double *xrow = k.X + Ic * k.ldx;
     L.vraw = k.v[Ic];
+    if (pipe_wide(k, (int64_t)grp * G * 16)) {
+        // the item's columns are all inside N and the blocks 16-byte aligned:
+        // each lane's four consecutive values as two 16-byte loads
 #pragma unroll
-    for (int g = 0; g < G; ++g)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t vc = min(L.v0 + 16 * g + q, k.N - 1);
-            L.x[g][q] = xrow[vc];
-            L.o[g][q] = orow[vc];
+        for (int g = 0; g < G; ++g) {
+            const double2 *xp = reinterpret_cast<const double2 *>(xrow + L.v0 + 16 * g);
+            const double2 *op = reinterpret_cast<const double2 *>(orow + L.v0 + 16 * g);
+            const double2 x01 = xp[0], x23 = xp[1], o01 = op[0], o23 = op[1];
+            L.x[g][0] = x01.x; L.x[g][1] = x01.y; L.x[g][2] = x23.x; L.x[g][3] = x23.y;
+            L.o[g][0] = o01.x; L.o[g][1] = o01.y; L.o[g][2] = o23.x; L.o[g][3] = o23.y;
         }
+    } else {
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t vc = min(L.v0 + 16 * g + q, k.N - 1);
+                L.x[g][q] = xrow[vc];
+                L.o[g][q] = orow[vc];
+            }
+    }
 }
 
 // D X of the item into an LDS buffer; per output the first writer's base term
@@ -1727,13 +1750,22 @@ void step_pipe_kernel(StepParams k, int64_t nitems) {
         if (more) pipe_stage<P, PREC>(k, Ln, xbuf + (cur ^ 1) * G * XS, wave, lane, bo, I, d, v0);
         if (Io >= 0) {
             double *yrow = k.Y + (int64_t)Io * k.ldy;
+            if (pipe_wide(k, v0o - pipe_vec<PREC>(lane))) {
 #pragma unroll
-            for (int g = 0; g < G; ++g)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int64_t vec = v0o + 16 * g + q;
-                    if (vec < k.N) yrow[vec] = out[g][q];
+                for (int g = 0; g < G; ++g) {
+                    double2 *yp = reinterpret_cast<double2 *>(yrow + v0o + 16 * g);
+                    yp[0] = double2{out[g][0], out[g][1]};
+                    yp[1] = double2{out[g][2], out[g][3]};
                 }
+            } else {
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int64_t vec = v0o + 16 * g + q;
+                        if (vec < k.N) yrow[vec] = out[g][q];
+                    }
+            }
         }
         if (!more) return false;
         cur ^= 1;
@@ -2150,9 +2182,10 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
         }
 #undef FE_WS
     }
-    // the pipelined kernel with two items in flight is the FP64 default at
-    // p = 4, where it was measured fastest (6.1 against 6.8 ms per H~X on
-    // the 24x24x48-cell slab, 256 vectors)
+    // the pipelined kernel with two items in flight is the FP64 and FP32
+    // default at p = 4, where it was measured fastest (FP64 6.1 against 6.8,
+    // FP32 6.08 against 6.17 ms per H~X on the 24x24x48-cell slab, 256
+    // vectors)
     if ((m->kernel_variant == 7 || (m->kernel_variant == 0 && m->p == 4)) && prec == FE_F64) {
         switch (m->p) {
         case 1: return launch_pipe_p<1, 0, 2>(prm, m, s);
@@ -2162,7 +2195,7 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
         default: break;
         }
     }
-    if (m->kernel_variant == 7 && prec == FE_F32) {
+    if ((m->kernel_variant == 7 || (m->kernel_variant == 0 && m->p == 4)) && prec == FE_F32) {
         switch (m->p) {
         case 1: return launch_pipe_p<1, 1, 2>(prm, m, s);
         case 2: return launch_pipe_p<2, 1, 2>(prm, m, s);
