@@ -345,6 +345,27 @@ __device__ __forceinline__ double node_scale(const NodeRef &n) {
     return n.I >= 0 ? (n.f[0] * n.f[1]) * n.f[2] : 0.0;
 }
 
+// Whether columns [c0, c0 + ncols) lie inside N and every block a step
+// touches (X, Y, the previous iterate) allows 16-byte accesses at any row:
+// then each lane's four consecutive values move as two 16-byte loads or
+// stores.  The same for all lanes of a workgroup item.
+__device__ __forceinline__ bool wide_ok(const StepParams &k, int64_t c0, int ncols) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(k.X) | reinterpret_cast<uintptr_t>(k.Y) |
+                        reinterpret_cast<uintptr_t>(k.Ym1 ? k.Ym1 : k.X);
+    const int64_t ld = k.ldx | k.ldy | (k.Ym1 ? k.ldm : k.ldx);
+    return (a & 15) == 0 && (ld & 1) == 0 && c0 + ncols <= k.N;
+}
+
+__device__ __forceinline__ void load4(const double *p, double (&v)[4]) {
+    const double2 a = reinterpret_cast<const double2 *>(p)[0], b = reinterpret_cast<const double2 *>(p)[1];
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+
+__device__ __forceinline__ void store4(double *p, double v0, double v1, double v2, double v3) {
+    reinterpret_cast<double2 *>(p)[0] = double2{v0, v1};
+    reinterpret_cast<double2 *>(p)[1] = double2{v2, v3};
+}
+
 template <int P>
 __device__ __forceinline__ bool node_first(const StepParams &k, const ItemCell &c, int l) {
     constexpr int N1 = P + 1;
@@ -916,6 +937,7 @@ void step_row_kernel(StepParams k) {
         fst[tt] = r < NC && node_first<P>(k, c, r);
     }
     double xv[TPW][G][4], ov[TPW][G][4], vraw[TPW];
+    const bool wide = wide_ok(k, (int64_t)grp * G * 16, 16 * G);
 #pragma unroll
     for (int tt = 0; tt < TPW; ++tt) {
         const int64_t Ic = max(nr[tt].I, 0);
@@ -923,14 +945,22 @@ void step_row_kernel(StepParams k) {
             !fst[tt] ? k.Y + Ic * k.ldy : (k.Ym1 ? k.Ym1 + Ic * k.ldm : k.X + Ic * k.ldx);
         const double *xrow = k.X + Ic * k.ldx;
         vraw[tt] = k.v[Ic];
+        if (wide) {
 #pragma unroll
-        for (int g = 0; g < G; ++g)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t vc = min(v0 + 16 * g + q, k.N - 1);
-                xv[tt][g][q] = xrow[vc];
-                ov[tt][g][q] = orow[vc];
+            for (int g = 0; g < G; ++g) {
+                load4(xrow + v0 + 16 * g, xv[tt][g]);
+                load4(orow + v0 + 16 * g, ov[tt][g]);
             }
+        } else {
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t vc = min(v0 + 16 * g + q, k.N - 1);
+                    xv[tt][g][q] = xrow[vc];
+                    ov[tt][g][q] = orow[vc];
+                }
+        }
     }
 #pragma unroll
     for (int tt = 0; tt < TPW; ++tt) {
@@ -1063,6 +1093,16 @@ constexpr int UNRB = NB <= 8 ? NB : 1;
     for (int tt = 0; tt < TPW; ++tt) {
         if (I[tt] < 0) continue;
         double *yrow = k.Y + (int64_t)I[tt] * k.ldy;
+        if (wide) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                double o4[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) o4[q] = bo[tt][g][q] + k.alpha * d[tt] * acc[tt][g][q];
+                store4(yrow + v0 + 16 * g, o4[0], o4[1], o4[2], o4[3]);
+            }
+            continue;
+        }
 #pragma unroll
         for (int g = 0; g < G; ++g)
 #pragma unroll
@@ -1552,16 +1592,6 @@ __device__ __forceinline__ bool axis_first_sel(const AxisInfo &a, int p, int c, 
     return !(exists && cn < cc);
 }
 
-// Whether the G chunks of 16 vectors starting at column c0 lie inside N and
-// every block the pipelined kernel touches allows 16-byte accesses (same for
-// all lanes of an item).
-__device__ __forceinline__ bool pipe_wide(const StepParams &k, int64_t c0) {
-    const uintptr_t a = reinterpret_cast<uintptr_t>(k.X) | reinterpret_cast<uintptr_t>(k.Y) |
-                        reinterpret_cast<uintptr_t>(k.Ym1 ? k.Ym1 : k.X);
-    const int64_t ld = k.ldx | k.ldy | (k.Ym1 ? k.ldm : k.ldx);
-    return (a & 15) == 0 && (ld & 1) == 0 && c0 + 32 <= k.N;
-}
-
 // The loads of one thread for one item, and what the epilogue needs.
 template <int G> struct PipeRow {
     NodeRef n;
@@ -1594,7 +1624,7 @@ __device__ __forceinline__ void pipe_issue(const StepParams &k, int64_t item, in
     const double *orow = L.fst ? ob + Ic * ol : k.Y + Ic * k.ldy;
     const double *xrow = k.X + Ic * k.ldx;
     L.vraw = k.v[Ic];
-    if (pipe_wide(k, (int64_t)grp * G * 16)) {
+    if (wide_ok(k, (int64_t)grp * G * 16, 16 * G)) {
         // the item's columns are all inside N and the blocks 16-byte aligned:
         // each lane's four consecutive values as two 16-byte loads
 #pragma unroll
@@ -1750,7 +1780,7 @@ void step_pipe_kernel(StepParams k, int64_t nitems) {
         if (more) pipe_stage<P, PREC>(k, Ln, xbuf + (cur ^ 1) * G * XS, wave, lane, bo, I, d, v0);
         if (Io >= 0) {
             double *yrow = k.Y + (int64_t)Io * k.ldy;
-            if (pipe_wide(k, v0o - pipe_vec<PREC>(lane))) {
+            if (wide_ok(k, v0o - pipe_vec<PREC>(lane), 16 * G)) {
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
                     double2 *yp = reinterpret_cast<double2 *>(yrow + v0o + 16 * g);
