@@ -115,7 +115,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32/BF16 report")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the domain split across GPUs is a design, not built)", file=sys.stderr)
         sys.exit(2)
 
