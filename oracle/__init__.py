@@ -545,29 +545,32 @@ def weyl_cut(a0: float, b: float, N: int, n: int) -> float:
 
 
 def cholqr2(Y: np.ndarray):
-    """Two passes of Cholesky-QR: Q = Y R^-1 with Q^T Q = I."""
+    """Two passes of Cholesky-QR: Q = Y R^-1 with Q^H Q = I (real or complex
+    blocks; for real ones the conjugations are the identity)."""
     Q = Y
-    R = np.eye(Y.shape[1])
+    R = np.eye(Y.shape[1], dtype=Y.dtype)
     for _ in range(2):
-        S = Q.T @ Q
-        Rk = np.linalg.cholesky(S).T          # S = Rk^T Rk
+        S = Q.conj().T @ Q
+        Rk = np.linalg.cholesky(S).conj().T   # S = Rk^H Rk
         Q = np.linalg.solve(Rk.T, Q.T).T      # Q Rk^-1
         R = Rk @ R
     return Q, R
 
 
 def rayleigh_ritz(apply, Q: np.ndarray):
-    """Ritz values/vectors of the operator on span(Q) (Q orthonormal)."""
+    """Ritz values/vectors of the operator on span(Q) (Q orthonormal, real or
+    complex): the Hermitian part of Q^H A Q."""
     P = apply(Q)
-    Hs = Q.T @ P
-    Hs = 0.5 * (Hs + Hs.T)
+    Hs = Q.conj().T @ P
+    Hs = 0.5 * (Hs + Hs.conj().T)
     theta, W = np.linalg.eigh(Hs)
     return theta, Q @ W
 
 
-def subspace_iteration(op: Operator, X0: np.ndarray, m: int, iters: int, a: float, b: float, a0: float):
+def subspace_iteration(op, X0: np.ndarray, m: int, iters: int, a: float, b: float, a0: float):
     """Chebyshev-filtered subspace iteration: filter, CholQR2, Rayleigh-Ritz;
-    the cut a and the scaling point a0 follow the current Ritz values."""
+    the cut a and the scaling point a0 follow the current Ritz values.  op is
+    an Operator, or a BlochOperator with complex X0."""
     X = X0
     hist = []
     for _ in range(iters):

@@ -901,3 +901,42 @@ def test_bloch_advection_rows_match_the_assembled_operator():
          + kk * X[rows] - 1j * S)
     ref = O.BlochOperator(op, m, k).apply(X)[rows]
     np.testing.assert_allclose(R, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def test_complex_cholqr2_and_rayleigh_ritz_on_a_known_hermitian_matrix():
+    """Complex CholQR2 gives orthonormal columns spanning Y (Y = Q R, R upper
+    triangular); Rayleigh-Ritz of a Hermitian matrix with known spectrum on an
+    invariant subspace returns those eigenvalues and eigenvectors."""
+    rng = np.random.default_rng(3)
+    n, N = 60, 7
+    Y = rng.standard_normal((n, N)) + 1j * rng.standard_normal((n, N))
+    Q, R = O.cholqr2(Y)
+    np.testing.assert_allclose(Q.conj().T @ Q, np.eye(N), atol=1e-13)
+    np.testing.assert_allclose(Q @ R, Y, atol=1e-12)
+    assert np.allclose(np.tril(R, -1), 0.0)
+    # H = U diag(lam) U^H with a random unitary U
+    U, _ = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    lam = np.sort(rng.uniform(-3, 5, n))
+    H = (U * lam) @ U.conj().T
+    idx = [1, 4, 9, 20, 33, 41, 57]
+    V = U[:, idx] @ np.linalg.qr(rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N)))[0]
+    theta, X = O.rayleigh_ritz(lambda Z: H @ Z, V)
+    np.testing.assert_allclose(theta, lam[idx], atol=1e-12)
+    np.testing.assert_allclose(H @ X, X * theta, atol=1e-11)
+
+
+def test_bloch_subspace_iteration_converges_to_the_dense_levels():
+    """Filtered subspace iteration with the Bloch operator (complex filter,
+    complex CholQR2, Rayleigh-Ritz) converges to the lowest eigenvalues of the
+    assembled complex matrix."""
+    wl = W.small_slab((3, 3, 4), p=3, N=8)
+    m = O.Mesh.from_workload(wl)
+    op = O.Operator(m, W.workload_potential(wl, m.quad_points()), wl.E, wl.z0)
+    k = (0.45, -0.3)
+    B = O.BlochOperator(op, m, k)
+    ev = np.linalg.eigvalsh(B.A.toarray())
+    X0 = wl.Xc(op.n)
+    a0, b = ev[0] - 0.1, ev[-1] + 0.1
+    a = ev[12]
+    hist, _ = O.subspace_iteration(B, X0, 12, 25, a, b, a0)
+    np.testing.assert_allclose(hist[-1][:5], ev[:5], rtol=0, atol=1e-9)
