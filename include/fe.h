@@ -302,6 +302,23 @@ fe_status fe_hx_apply_k(fe_mesh *mesh, const double *X, double *Y, int64_t N, in
 fe_status fe_cheb_filter_k(fe_mesh *mesh, const double *X, double *Y, int64_t N, int64_t ld, int32_t m, double a,
                            double b, double a0, double *work, size_t work_bytes, hipStream_t stream);
 
+/* Two passes of Cholesky-QR on a complex block: Y <- Y R^-1 with
+ * Y^H Y = R^H R, so that the columns become orthonormal in the complex inner
+ * product (the dense step of subspace iteration at a k-point; the real
+ * fe_cholqr2 for Bloch vectors).  Y: device complex n x N, ld >= N (complex
+ * elements), overwritten.  FE_EDEVICE if the Gram matrix is not positive
+ * definite; synchronous with stream. */
+fe_status fe_cholqr2_k(fe_mesh *mesh, double *Y, int64_t N, int64_t ld, hipStream_t stream);
+
+/* Rayleigh-Ritz with H~^k on span(Q) (Q complex n x N with orthonormal
+ * columns): P = H~^k Q, the Hermitian projection (Q^H P + P^H Q) / 2 =
+ * W diag(theta) W^H, X = Q W.  Q, X, P: device complex n x N with leading
+ * dimension ld (X and P caller-owned outputs, P scratch); theta_host: N
+ * doubles, ascending.  Synchronous with stream.  FE_ESTATE without a
+ * potential. */
+fe_status fe_rayleigh_ritz_k(fe_mesh *mesh, const double *Q, double *X, double *P, int64_t N, int64_t ld,
+                             double *theta_host, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -80,6 +80,8 @@ def lib() -> C.CDLL:
         "fe_get_kpoint": ([vp, vp], C.c_int),
         "fe_hx_apply_k": ([vp, vp, vp, i64, i64, vp], C.c_int),
         "fe_cheb_filter_k": ([vp, vp, vp, i64, i64, i32, dbl, dbl, dbl, vp, C.c_size_t, vp], C.c_int),
+        "fe_cholqr2_k": ([vp, vp, i64, i64, vp], C.c_int),
+        "fe_rayleigh_ritz_k": ([vp, vp, vp, vp, i64, i64, vp, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -258,6 +260,30 @@ class Mesh:
         _check(lib().fe_cheb_filter_k(self._h, _ptr(X), _ptr(Y), N, ld, int(m), float(a), float(b), float(a0),
                                       _ptr(work), work.numel() * work.element_size(), _stream(stream)))
         return Y
+
+    def cholqr2_k(self, Y, stream=None):
+        """Complex CholQR2 in place (fe_cholqr2_k)."""
+        _check_cblock(Y, self.n, "Y")
+        _check(lib().fe_cholqr2_k(self._h, _ptr(Y), Y.shape[1], Y.stride(0), _stream(stream)))
+        return Y
+
+    def rayleigh_ritz_k(self, Q, X=None, P=None, stream=None):
+        """(theta, X) of H~^k on span(Q) (fe_rayleigh_ritz_k)."""
+        import torch
+        _check_cblock(Q, self.n, "Q")
+        N, ld = Q.shape[1], Q.stride(0)
+        if X is None:
+            X = torch.empty_strided(Q.shape, Q.stride(), dtype=torch.complex128, device=Q.device)
+        if P is None:
+            P = torch.empty_strided(Q.shape, Q.stride(), dtype=torch.complex128, device=Q.device)
+        for t, name in ((X, "X"), (P, "P")):
+            _check_cblock(t, self.n, name)
+            if t.stride(0) != ld:
+                raise ValueError(f"{name} must share Q's leading dimension")
+        theta = np.zeros(N)
+        _check(lib().fe_rayleigh_ritz_k(self._h, _ptr(Q), _ptr(X), _ptr(P), N, ld, theta.ctypes.data,
+                                        _stream(stream)))
+        return theta, X
 
     def vjp_work_bytes(self, N: int, m: int, ckpt_stride: int = 1, col_chunk: int = 0) -> int:
         return int(lib().fe_cheb_filter_vjp_work_bytes(self._h, N, m, ckpt_stride, col_chunk))

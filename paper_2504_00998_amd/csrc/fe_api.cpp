@@ -458,8 +458,8 @@ namespace fe {
 // re/im, leading dimensions in complex elements): the real kernels on the
 // 2N real columns, plus the k.G product and the phase-twisted projectors
 // when k != 0.  |k|^2 / 2 enters through the shift.
-static fe_status filter_step_k(fe_mesh *m, const double *X, int64_t ldx, double *Y, int64_t ldy, const double *Ym1,
-                               int64_t ldm, double alpha, double beta, double shift, int64_t N, hipStream_t s) {
+fe_status filter_step_k(fe_mesh *m, const double *X, int64_t ldx, double *Y, int64_t ldy, const double *Ym1,
+                        int64_t ldm, double alpha, double beta, double shift, int64_t N, hipStream_t s) {
     const bool gamma = m->kvec[0] == 0.0 && m->kvec[1] == 0.0;
     const double kk = 0.5 * (m->kvec[0] * m->kvec[0] + m->kvec[1] * m->kvec[1]);
     StepArgs a{X, 2 * ldx, Y, 2 * ldy, Ym1, 2 * ldm, alpha, beta, shift - kk, 2 * N};

@@ -129,6 +129,31 @@ static fe_status tsgram(rocblas_handle h, const double *A, const double *B, int6
 
 static size_t tsgram_doubles(int64_t n, int64_t N) { return (size_t)(n / kSliceRows + 1) * N * N; }
 
+// Complex blocks (interleaved re/im, ld in complex elements): out (N x N,
+// column-major complex) = Acm Bcm^H, which is conj(A^H B) for the row-major
+// blocks; the same deterministic split-K as tsgram.  part: scratch of
+// 2 * tsgram_doubles(n, N) doubles.
+static fe_status tsgram_z(rocblas_handle h, const double *A, const double *B, int64_t n, int64_t N, int64_t ld,
+                          double *part, double *out, hipStream_t s) {
+    int64_t nfull = n / kSliceRows, rem = n - nfull * kSliceRows;
+    const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
+    int Ni = (int)N, ldi = (int)ld, kb = (int)kSliceRows;
+    auto z = [](const double *p) { return reinterpret_cast<const rocblas_double_complex *>(p); };
+    auto zw = [](double *p) { return reinterpret_cast<rocblas_double_complex *>(p); };
+    if (nfull > 0)
+        FE_BLAS(rocblas_zgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_conjugate_transpose, Ni, Ni,
+                                              kb, &one, z(A), ldi, kSliceRows * ld, z(B), ldi, kSliceRows * ld, &zero,
+                                              zw(part), Ni, N * N, (int)nfull),
+                "zgemm_strided_batched (gram)");
+    if (rem > 0)
+        FE_BLAS(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_conjugate_transpose, Ni, Ni, (int)rem, &one,
+                              z(A + 2 * nfull * kSliceRows * ld), ldi, z(B + 2 * nfull * kSliceRows * ld), ldi, &zero,
+                              zw(part + 2 * nfull * N * N), Ni),
+                "zgemm (gram tail)");
+    FE_HIPD(launch_sum_partials(part, nfull + (rem > 0 ? 1 : 0), 2 * N * N, out, s), "sum partials");
+    return FE_OK;
+}
+
 }  // namespace fe
 
 using namespace fe;
@@ -263,6 +288,88 @@ fe_status fe_rayleigh_ritz(fe_mesh *m, const double *Q, double *X, double *P, in
     FE_BLAS(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, Ni, ni, Ni, &one, Ht, Ni, Q, ldi,
                           &zero, X, ldi),
             "dgemm QW");
+    return FE_OK;
+}
+
+// ------------------------------------------------------------ Bloch-k blocks
+
+fe_status fe_cholqr2_k(fe_mesh *m, double *Y, int64_t N, int64_t ld, hipStream_t s) {
+    if (!m || !Y) return fail(FE_EINVAL, "NULL argument");
+    if (N < 1 || ld < N) return fail(FE_EINVAL, "need N >= 1 and ld >= N");
+    if (N > m->n) return fail(FE_EINVAL, "N exceeds the number of DoFs");
+    int64_t n = m->n;
+    int64_t nb = std::min(kBlockRows, n);
+    // scratch: [1024 reserved][D: N*N complex][partials][T: nb*N complex][info]
+    size_t need = (1024 + 2 * (size_t)N * N + 2 * tsgram_doubles(n, N) + 2 * (size_t)nb * N + 64) * sizeof(double);
+    fe_status st = ensure_scratch_dense(m, need);
+    if (st != FE_OK) return st;
+    double *D = m->d_scratch + 1024, *part = D + 2 * (size_t)N * N, *T = part + 2 * tsgram_doubles(n, N);
+    rocblas_int *info = reinterpret_cast<rocblas_int *>(T + 2 * (size_t)nb * N);
+    rocblas_handle h;
+    if ((st = handle(m, s, h)) != FE_OK) return st;
+    int Ni = (int)N, ldi = (int)ld;
+    auto zw = [](double *p) { return reinterpret_cast<rocblas_double_complex *>(p); };
+    for (int pass = 0; pass < 2; ++pass) {
+        // D = conj(Y^H Y) = U^H U (Cholesky); with R = conj(U), Y^H Y = R^H R and
+        // Y R^-1 in column-major form is Ycm <- (U^-1)^H Ycm
+        if ((st = tsgram_z(h, Y, Y, n, N, ld, part, D, s)) != FE_OK) return st;
+        FE_BLAS(rocsolver_zpotrf(h, rocblas_fill_upper, Ni, zw(D), Ni, info), "zpotrf");
+        rocblas_int hinfo = 0;
+        FE_HIPD(hipMemcpyAsync(&hinfo, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, s), "copy info");
+        FE_HIPD(hipStreamSynchronize(s), "sync");
+        if (hinfo != 0) return fail(FE_EDEVICE, "Gram matrix not positive definite (potrf info " + std::to_string(hinfo) + ")");
+        FE_BLAS(rocsolver_ztrtri(h, rocblas_fill_upper, rocblas_diagonal_non_unit, Ni, zw(D), Ni, info), "ztrtri");
+        FE_HIPD(launch_zero_lower_z(D, Ni, s), "zero lower");
+        const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
+        for (int64_t r0 = 0; r0 < n; r0 += nb) {
+            int64_t rows = std::min(nb, n - r0);
+            double *Yb = Y + 2 * r0 * ld;
+            FE_HIPD(hipMemcpy2DAsync(T, 2 * N * sizeof(double), Yb, 2 * ld * sizeof(double), 2 * N * sizeof(double),
+                                     rows, hipMemcpyDeviceToDevice, s),
+                    "stage block");
+            FE_BLAS(rocblas_zgemm(h, rocblas_operation_conjugate_transpose, rocblas_operation_none, Ni, (int)rows, Ni,
+                                  &one, zw(D), Ni, zw(T), Ni, &zero, zw(Yb), ldi),
+                    "zgemm (Y R^-1)");
+        }
+    }
+    return FE_OK;
+}
+
+fe_status fe_rayleigh_ritz_k(fe_mesh *m, const double *Q, double *X, double *P, int64_t N, int64_t ld, double *theta,
+                             hipStream_t s) {
+    if (!m || !Q || !X || !P || !theta) return fail(FE_EINVAL, "NULL argument");
+    if (N < 1 || ld < N) return fail(FE_EINVAL, "need N >= 1 and ld >= N");
+    if (!m->potential_set) return fail(FE_ESTATE, "fe_set_potential has not been called");
+    int64_t n = m->n;
+    // P = H~^k Q
+    fe_status st = filter_step_k(m, Q, ld, P, ld, nullptr, 0, 1.0, 0.0, 0.0, N, s);
+    if (st != FE_OK) return st;
+    size_t need = (1024 + 4 * (size_t)N * N + 2 * (size_t)N + 64 + 2 * tsgram_doubles(n, N)) * sizeof(double);
+    if ((st = ensure_scratch_dense(m, need)) != FE_OK) return st;
+    double *Hs = m->d_scratch + 1024, *Ht = Hs + 2 * (size_t)N * N, *d = Ht + 2 * (size_t)N * N, *e = d + N;
+    rocblas_int *info = reinterpret_cast<rocblas_int *>(e + N);
+    double *part = reinterpret_cast<double *>(info + 128);
+    rocblas_handle h;
+    if ((st = handle(m, s, h)) != FE_OK) return st;
+    int Ni = (int)N, ni = (int)n, ldi = (int)ld;
+    auto z = [](const double *p) { return reinterpret_cast<const rocblas_double_complex *>(p); };
+    auto zw = [](double *p) { return reinterpret_cast<rocblas_double_complex *>(p); };
+    const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0}, half = {0.5, 0.0};
+    // Hs = conj(Q^H P); Ht = (Hs + Hs^H) / 2 = conj of the Hermitian projected matrix
+    if ((st = tsgram_z(h, Q, P, n, N, ld, part, Hs, s)) != FE_OK) return st;
+    FE_BLAS(rocblas_zgeam(h, rocblas_operation_none, rocblas_operation_conjugate_transpose, Ni, Ni, &half, z(Hs), Ni,
+                          &half, z(Hs), Ni, zw(Ht), Ni),
+            "zgeam");
+    FE_BLAS(rocsolver_zheevd(h, rocblas_evect_original, rocblas_fill_upper, Ni, zw(Ht), Ni, d, e, info), "zheevd");
+    rocblas_int hinfo = 0;
+    FE_HIPD(hipMemcpyAsync(&hinfo, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, s), "copy info");
+    FE_HIPD(hipMemcpyAsync(theta, d, N * sizeof(double), hipMemcpyDeviceToHost, s), "copy theta");
+    FE_HIPD(hipStreamSynchronize(s), "sync");
+    if (hinfo != 0) return fail(FE_EDEVICE, "heevd failed (info " + std::to_string(hinfo) + ")");
+    // the eigenvectors W' of conj(H) are conj(W); X = Q W, i.e. Xcm = W'^H Qcm
+    FE_BLAS(rocblas_zgemm(h, rocblas_operation_conjugate_transpose, rocblas_operation_none, Ni, ni, Ni, &one, z(Ht),
+                          Ni, z(Q), ldi, &zero, zw(X), ldi),
+            "zgemm QW");
     return FE_OK;
 }
 

@@ -138,6 +138,11 @@ hipError_t launch_vmul(double *z, const double *a, const double *b, int64_t n, h
 hipError_t launch_xpby(double *p, const double *z, double beta, int64_t n, hipStream_t s);
 hipError_t launch_sum_partials(const double *P, int64_t nb, int64_t len, double *S, hipStream_t s);
 hipError_t launch_zero_lower(double *A, int N, hipStream_t s);
+hipError_t launch_zero_lower_z(double *A, int N, hipStream_t s);
+// one Bloch-mode recurrence step on complex blocks (leading dimensions in
+// complex elements); fe_api.cpp
+fe_status filter_step_k(fe_mesh *m, const double *X, int64_t ldx, double *Y, int64_t ldy, const double *Ym1,
+                        int64_t ldm, double alpha, double beta, double shift, int64_t N, hipStream_t s);
 hipError_t launch_axpby(double *Y, int64_t ldy, const double *X, int64_t ldx, int64_t n, int64_t N, double a,
                         double b, hipStream_t s);
 hipError_t launch_nonlocal(fe_mesh *m, const double *X, int64_t ldx, double *Y, int64_t ldy, int64_t N,

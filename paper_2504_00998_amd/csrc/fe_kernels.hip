@@ -2532,6 +2532,23 @@ __global__ void zero_lower_kernel(double *A, int N) {
     if (row > col) A[e] = 0.0;
 }
 
+// complex N x N column-major matrix stored as (re, im) pairs
+__global__ void zero_lower_z_kernel(double *A, int N) {
+    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= (int64_t)N * N) return;
+    int col = (int)(e / N), row = (int)(e % N);
+    if (row > col) {
+        A[2 * e] = 0.0;
+        A[2 * e + 1] = 0.0;
+    }
+}
+
+hipError_t launch_zero_lower_z(double *A, int N, hipStream_t s) {
+    int64_t tot = (int64_t)N * N;
+    hipLaunchKernelGGL(zero_lower_z_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, A, N);
+    return hipGetLastError();
+}
+
 hipError_t launch_zero_lower(double *A, int N, hipStream_t s) {
     int64_t tot = (int64_t)N * N;
     hipLaunchKernelGGL(zero_lower_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, A, N);

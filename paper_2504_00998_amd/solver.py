@@ -49,6 +49,29 @@ def subspace_iteration(mesh, X0, m: int, iters: int, a: float, b: float, a0: flo
     return hist, X
 
 
+def subspace_iteration_k(mesh, X0, m: int, iters: int, a: float, b: float, a0: float,
+                         work=None) -> Tuple[List[np.ndarray], "object"]:
+    """Filtered subspace iteration with the Bloch operator H~^k at the mesh's
+    current wave vector (fe_set_kpoint): complex filter, complex CholQR2 and
+    Rayleigh-Ritz, all on the device.  X0: complex128 (n, N) device block,
+    not modified.  Returns the Ritz values of every iteration and the final
+    Ritz vectors."""
+    import torch
+    X = X0.clone()
+    Y = torch.empty_like(X)
+    P = torch.empty_like(X)
+    if work is None:
+        work = torch.empty(2 * X.numel(), dtype=torch.float64, device=X.device)
+    hist = []
+    for _ in range(iters):
+        mesh.cheb_filter_k(X, m, a, b, a0, Y=Y, work=work)
+        mesh.cholqr2_k(Y)
+        theta, X = mesh.rayleigh_ritz_k(Y, X=X, P=P)
+        hist.append(theta)
+        a, a0 = float(theta[-1]), float(theta[0])
+    return hist, X
+
+
 def ground_state(mesh, Vq, E: float, z0: float, X0, v0, m: int, iters: int, prec: str = "f64", work=None,
                  profile_q=None):
     """Set the potential (V_loc at the GLL points, field E about z0), bound the

@@ -97,3 +97,5 @@ def test_bloch_entry_points_reject_null_without_a_device():
     assert L.fe_get_kpoint(None, None) == fe.FE_EINVAL
     assert L.fe_hx_apply_k(None, None, None, 4, 4, None) == fe.FE_EINVAL
     assert L.fe_cheb_filter_k(None, None, None, 4, 4, 5, 1.0, 2.0, float("nan"), None, 0, None) == fe.FE_EINVAL
+    assert L.fe_cholqr2_k(None, None, 4, 4, None) == fe.FE_EINVAL
+    assert L.fe_rayleigh_ritz_k(None, None, None, None, 4, 4, None, None) == fe.FE_EINVAL
