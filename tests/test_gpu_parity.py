@@ -269,3 +269,35 @@ def test_pipelined_variant_several_items_per_workgroup(p, prec):
     gm.set_kernel(7)
     assert torch.equal(gm.hx(X, prec=prec), Y1)
     assert torch.equal(gm.cheb_filter(X, 6, 2.0, 400.0, -0.5, prec=prec), F1)
+
+
+def test_empty_blocks_and_the_one_dof_mesh():
+    """N = 0 is a no-op for every apply / filter entry point (the output is
+    left untouched); a single Dirichlet cell of degree 2 has one free DoF,
+    and H~X and the filter on it match the oracle."""
+    fe = _fe()
+    wl = W.small_slab((3, 3, 4), p=2, N=4)
+    _print_case(test="empty_and_one_dof")
+    op, gm, _ = _setup(wl)
+    L = fe.lib()
+    Y = torch.full((op.n, 4), 7.0, dtype=torch.float64, device="cuda")
+    X = torch.ones_like(Y)
+    W0 = torch.empty(8 * op.n, dtype=torch.float64, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    assert L.fe_hx_apply(gm._h, X.data_ptr(), Y.data_ptr(), 0, 4, fe._PREC["f64"], s) == fe.FE_OK
+    assert L.fe_cheb_filter(gm._h, X.data_ptr(), Y.data_ptr(), 0, 4, 5, 1.0, 9.0, float("nan"), fe._PREC["f64"],
+                            W0.data_ptr(), W0.numel() * 8, s) == fe.FE_OK
+    assert L.fe_hx_apply_k(gm._h, X.data_ptr(), Y.data_ptr(), 0, 2, s) == fe.FE_OK
+    assert L.fe_cheb_filter_k(gm._h, X.data_ptr(), Y.data_ptr(), 0, 2, 5, 1.0, 9.0, float("nan"), W0.data_ptr(),
+                              W0.numel() * 8, s) == fe.FE_OK
+    torch.cuda.synchronize()
+    assert bool((Y == 7.0).all())
+    # one free DoF: a single cube, Dirichlet on every face, p = 2
+    one = W.small_slab((1, 1, 1), p=2, N=3, bc=(W.DIRICHLET, W.DIRICHLET, W.DIRICHLET))
+    op1, gm1, _ = _setup(one)
+    assert op1.n == 1 and gm1.n == 1
+    X1 = one.X(1)
+    assert _relerr(gm1.hx(torch.from_numpy(X1).cuda()).cpu().numpy(), op1.apply(X1)) < 1e-13
+    lam = float(op1.apply(np.ones((1, 1)))[0, 0])
+    Yf = gm1.cheb_filter(torch.from_numpy(X1).cuda(), 4, lam + 1.0, lam + 3.0, lam - 1.0).cpu().numpy()
+    assert _relerr(Yf, op1.filter(X1, 4, lam + 1.0, lam + 3.0, lam - 1.0)) < 1e-13
