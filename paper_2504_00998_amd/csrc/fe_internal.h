@@ -119,6 +119,9 @@ struct StepArgs {
 };
 
 hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipStream_t s);
+// single-vector FP64 product in two launches (cell products, then nodal sums)
+size_t assembled_scratch_doubles(const fe_mesh *m);
+hipError_t launch_step_assembled(const fe_mesh *m, const StepArgs &a, double *Zc, hipStream_t s);
 hipError_t launch_potential(const fe_mesh *m, const double *Vq, double E, double z0, hipStream_t s);
 hipError_t launch_potential_vjp(const fe_mesh *m, const double *g, double z0, double *Vbar, double *Ebar,
                                 hipStream_t s);

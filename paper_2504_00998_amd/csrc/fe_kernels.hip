@@ -1249,6 +1249,167 @@ void step_cells_kernel(StepParams k, int64_t ncells) {
         if (nr[q].I >= 0) k.Y[(int64_t)nr[q].I * k.ldy] = bo[q] + k.alpha * d[q] * acc[q];
 }
 
+// ------------------------------------------------------------------------
+// Single-vector product in two launches (the CG iteration of the Poisson
+// solve): every cell's product at once into a cell-local buffer, then each
+// free DoF sums its (at most eight) cell rows in a fixed order.  No colour
+// passes, so one launch covers all cells; deterministic, but the nodal sums
+// are associated differently from the colour-pass kernels.
+//   cell_apply_kernel: 16 cells per workgroup (the MFMA vector columns carry
+//   cells, as in step_cells_kernel); Zc[cell][r] = d_r ((1/2)K_c (D x)_c)_r.
+template <int P, int BK>
+__global__ __launch_bounds__((64 * RowShape<P, 1>::W)) __attribute__((amdgpu_waves_per_eu(5)))
+void cell_apply_kernel(StepParams k, int64_t ncells, double *Zc) {
+    constexpr int N1 = P + 1, NC = N1 * N1 * N1, NCP = (NC + 31) / 32 * 32, NKS = NCP / 4;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *xs = reinterpret_cast<double *>(smem);  // [NCP][16 cells], D x
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int rl = 4 * ((lane >> 2) & 3) + (lane >> 4);
+    const int cq = 4 * (lane & 3);
+    const int r = 16 * wave + rl;
+    const int64_t cell0 = (int64_t)blockIdx.x * 16 + cq;
+
+    const double *A = reinterpret_cast<const double *>(k.A) + (size_t)wave * NKS * 64 + lane;
+    constexpr int BKE = batch_size(NKS, BK), NB = NKS / BKE;
+    static_assert(NKS % BKE == 0, "k-steps must split into batches");
+    auto load_batch = [&](double (&ab)[BKE], int sb) {
+#pragma unroll
+        for (int j = 0; j < BKE; ++j) ab[j] = A[(size_t)(sb * BKE + j) * 64];
+    };
+    double ab0[BKE], ab1[BKE];
+    load_batch(ab0, 0);
+
+    NodeRef nr[4];
+    const int ncx = k.ax[0].ncell, ncy = k.ax[1].ncell;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int ci = (int)min(cell0 + q, ncells - 1);
+        ItemCell c;
+        c.cx = ci % ncx;
+        c.cy = (ci / ncx) % ncy;
+        c.cz = ci / (ncx * ncy);
+        c.chunk = 0;
+        nr[q] = node_ref<P>(k, c, r);
+        if (cell0 + q >= ncells) nr[q].I = -1;
+    }
+    double xv[4], d[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) xv[q] = k.X[(int64_t)max(nr[q].I, 0) * k.ldx];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        d[q] = node_scale(nr[q]);
+        xv[q] = nr[q].I >= 0 ? d[q] * xv[q] : 0.0;
+    }
+    {
+        double2 *dst = reinterpret_cast<double2 *>(xs + r * 16 + cq);
+        dst[0] = double2{xv[0], xv[1]};
+        dst[1] = double2{xv[2], xv[3]};
+    }
+    __syncthreads();
+
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    auto mul_batch = [&](const double (&ab)[BKE], int sb) {
+#pragma unroll
+        for (int j = 0; j < BKE; ++j) {
+            double b[4];
+            f64_quad_b(xs, sb * BKE + j, lane, b);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = __builtin_amdgcn_mfma_f64_4x4x4f64(ab[j], b[q], acc[q], 0, 0, 0);
+        }
+    };
+    constexpr int UNRB = NB <= 8 ? NB : 1;
+#pragma unroll UNRB
+    for (int sb = 0; sb < NB; sb += 2) {
+        if (sb + 1 < NB) load_batch(ab1, sb + 1);
+        mul_batch(ab0, sb);
+        if (sb + 1 < NB) {
+            if (sb + 2 < NB) load_batch(ab0, sb + 2);
+            mul_batch(ab1, sb + 1);
+        }
+    }
+    if (r < NC) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (cell0 + q < ncells) Zc[(cell0 + q) * NCP + r] = d[q] * acc[q];
+    }
+}
+
+// Cells containing global node position g along an axis (left one first) and
+// the node's local index in each; returns how many (1 or 2).
+__device__ __forceinline__ int axis_cells(const AxisInfo &a, int p, int g, int (&c)[2], int (&l)[2]) {
+    const int K = a.ncell * p;
+    if (g % p != 0) {
+        c[0] = g / p;
+        l[0] = g % p;
+        return 1;
+    }
+    int n = 0;
+    if (g > 0) {
+        c[n] = g / p - 1;
+        l[n++] = p;
+    } else if (a.bc == FE_BC_PERIODIC) {
+        c[n] = a.ncell - 1;
+        l[n++] = p;
+    }
+    if (g < K) {
+        c[n] = g / p;
+        l[n++] = 0;
+    }
+    return n;
+}
+
+// y_I = alpha ((v_I - shift) x_I + sum over the cells containing I of Zc)
+//       - beta Ym1_I,  summed over the cells z-, y-, x-outermost, left first.
+template <int P>
+__global__ void assemble_kernel(StepParams k, const double *Zc) {
+    constexpr int N1 = P + 1, NC = N1 * N1 * N1, NCP = (NC + 31) / 32 * 32;
+    const int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t n = k.nfx * k.nfy * (int64_t)k.ax[2].nfree;
+    if (I >= n) return;
+    const int t[3] = {(int)(I % k.nfx), (int)((I / k.nfx) % k.nfy), (int)(I / (k.nfx * k.nfy))};
+    int cs[3][2], ls[3][2], nc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int g = k.ax[a].bc == FE_BC_DIRICHLET ? t[a] + 1 : t[a];
+        nc[a] = axis_cells(k.ax[a], P, g, cs[a], ls[a]);
+    }
+    const int ncx = k.ax[0].ncell, ncy = k.ax[1].ncell;
+    double sum = 0.0;
+    for (int iz = 0; iz < nc[2]; ++iz)
+        for (int iy = 0; iy < nc[1]; ++iy)
+            for (int ix = 0; ix < nc[0]; ++ix) {
+                const int64_t cell = cs[0][ix] + (int64_t)ncx * (cs[1][iy] + (int64_t)ncy * cs[2][iz]);
+                const int l = ls[0][ix] + N1 * (ls[1][iy] + N1 * ls[2][iz]);
+                sum += Zc[cell * NCP + l];
+            }
+    double base = k.alpha * (k.v[I] - k.shift) * k.X[I * k.ldx];
+    if (k.Ym1) base -= k.beta * k.Ym1[I * k.ldm];
+    k.Y[I * k.ldy] = base + k.alpha * sum;
+}
+
+template <int P>
+static hipError_t launch_assembled_p(StepParams prm, const fe_mesh *m, double *Zc, hipStream_t s) {
+    constexpr int NCP = RowShape<P, 1>::NCP, W = RowShape<P, 1>::W;
+    static_assert(RowShape<P, 1>::NT <= 16, "one wave per row tile");
+    const size_t smem = (size_t)NCP * 16 * sizeof(double);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&cell_apply_kernel<P, 4>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int64_t ncells = m->ncells;
+    hipLaunchKernelGGL((cell_apply_kernel<P, 4>), dim3((unsigned)((ncells + 15) / 16)), dim3(64 * W), smem, s, prm,
+                       ncells, Zc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((assemble_kernel<P>), dim3((unsigned)((m->n + 255) / 256)), dim3(256), 0, s, prm,
+                       (const double *)Zc);
+    return hipGetLastError();
+}
+
 template <int P>
 static hipError_t launch_cells_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
     constexpr int NCP = RowShape<P, 1>::NCP, W = RowShape<P, 1>::W;
@@ -2133,6 +2294,45 @@ static hipError_t launch_tile_p(StepParams prm, const fe_mesh *m, hipStream_t s)
                 if (e != hipSuccess) return e;
             }
     return hipSuccess;
+}
+
+size_t assembled_scratch_doubles(const fe_mesh *m) {
+    return m->p <= 5 ? (size_t)m->ncells * (size_t)padded_nc(m->p) : 0;
+}
+
+// N = 1, FP64: the two-launch form above for p <= 5 (Zc: device scratch of
+// assembled_scratch_doubles), the colour passes otherwise.
+hipError_t launch_step_assembled(const fe_mesh *m, const StepArgs &a, double *Zc, hipStream_t s) {
+    if (a.N != 1 || m->p > 5 || !Zc) return launch_step(m, a, FE_F64, s);
+    StepParams prm;
+    prm.X = a.X; prm.ldx = a.ldx;
+    prm.Y = a.Y; prm.ldy = a.ldy;
+    prm.Ym1 = a.Ym1; prm.ldm = a.ldm;
+    prm.alpha = a.alpha; prm.beta = a.beta; prm.shift = a.shift;
+    prm.N = 1;
+    prm.nchunk = 1;
+    prm.axisD = m->d_axis;
+    prm.maxf = m->maxf;
+    prm.v = a.v ? a.v : m->d_v;
+    prm.A = m->d_Af64;
+    prm.S = nullptr;
+    for (int d = 0; d < 3; ++d) {
+        prm.ax[d].ncell = m->ncell[d];
+        prm.ax[d].nfree = (int)m->nf[d];
+        prm.ax[d].bc = m->bc[d];
+        prm.ax[d].ncol = m->ncol[d];
+        prm.col[d] = 0;
+        prm.cnt[d] = m->ncell[d];
+    }
+    prm.nfx = m->nf[0];
+    prm.nfy = m->nf[1];
+    switch (m->p) {
+    case 1: return launch_assembled_p<1>(prm, m, Zc, s);
+    case 2: return launch_assembled_p<2>(prm, m, Zc, s);
+    case 3: return launch_assembled_p<3>(prm, m, Zc, s);
+    case 4: return launch_assembled_p<4>(prm, m, Zc, s);
+    default: return launch_assembled_p<5>(prm, m, Zc, s);
+    }
 }
 
 hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipStream_t s) {

@@ -10,7 +10,9 @@
 // constant-field setup of Sec. 2.2.1) H0 has the null vector M^1/2 1, which is
 // projected out of the right-hand side and of every search direction, so the
 // solution has zero mean (integral of phi = 0).  Conjugate gradients with a
-// Jacobi preconditioner (the assembled diagonal of H0).  The iteration runs on
+// Jacobi preconditioner (the assembled diagonal of H0); the product is the
+// two-launch single-vector form (all cell products, then fixed-order nodal
+// sums) for p <= 5.  The iteration runs on
 // the device: its dot products are fixed-order two-pass reductions whose
 // results, and the CG scalars computed from them, stay in device memory; the
 // host reads the convergence state once per batch of iterations, and
@@ -258,7 +260,7 @@ extern "C" {
 
 size_t fe_poisson_work_bytes(const fe_mesh *m) {
     if (!m) return 0;
-    return ((size_t)8 * (size_t)m->n + 4 * (size_t)kRedBlocks + 16) * sizeof(double);
+    return ((size_t)8 * (size_t)m->n + 4 * (size_t)kRedBlocks + 16 + assembled_scratch_doubles(m)) * sizeof(double);
 }
 
 fe_status fe_poisson_solve(fe_mesh *m, const double *charge, double *phi, double tol, int32_t maxit,
@@ -316,7 +318,7 @@ fe_status fe_poisson_solve(fe_mesh *m, const double *charge, double *phi, double
         FE_BLASP(rocblas_ddot(h, ni, r, 1, z, 1, &rz), "ddot");
         // the iteration itself on the device; the host looks at its state
         // once per batch
-        double *part = zero + n, *sc = part + 4 * kRedBlocks;
+        double *part = zero + n, *sc = part + 4 * kRedBlocks, *Zc = sc + 16;
         const double sc0[S_COUNT] = {rz, 0.0, 0.0, 0.0, bnrm, 1.0, 0.0, 0.0, tol, singular ? 1.0 : 0.0, 0.0};
         FE_HIPP(hipMemcpyAsync(sc, sc0, sizeof(sc0), hipMemcpyHostToDevice, st), "copy scalars");
         const int nb = (int)std::min<int64_t>(kRedBlocks, (n + kRedThreads - 1) / kRedThreads);
@@ -327,7 +329,7 @@ fe_status fe_poisson_solve(fe_mesh *m, const double *charge, double *phi, double
             const int nbatch = std::min(kBatch, maxit - queued);
             for (int j = 0; j < nbatch; ++j) {
                 StepArgs a{p, 1, q, 1, nullptr, 0, 1.0, 0.0, 0.0, 1, zero};
-                FE_HIPP(launch_step(m, a, FE_F64, st), "step kernel launch");
+                FE_HIPP(launch_step_assembled(m, a, Zc, st), "product launch");
                 hipLaunchKernelGGL(cg_pq_kernel, dim3(nb), dim3(kRedThreads), 0, st, p, q, n, sc, part);
                 hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(kRedThreads), 0, st, part, nb, sc);
                 hipLaunchKernelGGL(cg_update_kernel, dim3(nb), dim3(kRedThreads), 0, st, x, r, p, q, pinv, e, n, sc,
