@@ -320,6 +320,17 @@ class Mesh:
         _check(lib().fe_density(self._h, _ptr(X), N, ld, _ptr(f), _ptr(rho), _stream(stream)))
         return rho
 
+    def density_k(self, X, f, rho=None, stream=None):
+        """rho_I = 2 sum_n f_n |u_nk(x_I)|^2 / M_I for the complex Bloch vectors of
+        one k-point (the k-point's term of the Brillouin-zone average): the same
+        fe_density on the (n, 2N) real view of the interleaved block, each
+        occupation applied to the real and the imaginary column."""
+        import torch
+        _check_cblock(X, self.n, "X")
+        if f.dtype != torch.float64 or not f.is_cuda or not f.is_contiguous() or f.numel() != X.shape[1]:
+            raise ValueError("f must be a contiguous float64 device tensor of N values")
+        return self.density(X.view(torch.float64), f.repeat_interleave(2), rho, stream)
+
     def planar_average(self, field, normalize: bool = False, out=None, stream=None):
         """x-y planar integral (or average) of a nodal field, one value per
         free z node position, ascending z (fe_planar_average)."""

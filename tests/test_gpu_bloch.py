@@ -207,3 +207,15 @@ def test_band_folding_on_the_device():
     np.testing.assert_allclose(hist[-1][:nev], evs[:nev], rtol=0, atol=1e-8)
     folded = np.sort(np.concatenate([levels[0.0], levels[math.pi / Lx]]))[:nev]
     assert np.max(np.abs(folded - hist[-1][:nev]) / np.abs(hist[-1][:nev])) < 1e-3
+
+
+def test_density_of_bloch_vectors():
+    """rho_I = 2 sum_n f_n |u_n(x_I)|^2 / M_I for complex vectors, against the
+    oracle's density of the real and imaginary parts."""
+    wl = W.small_slab((3, 3, 4), p=3, N=6)
+    om, op, gm = _setup(wl)
+    X = wl.Xc(op.n)
+    f = np.linspace(1.0, 0.25, wl.N)
+    rho = gm.density_k(torch.from_numpy(X).cuda(), torch.from_numpy(f).cuda()).cpu().numpy()
+    ref = O.density(om, X.real.copy(), f) + O.density(om, X.imag.copy(), f)
+    np.testing.assert_allclose(rho, ref, rtol=1e-13, atol=0)
