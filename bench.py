@@ -37,8 +37,8 @@ MEASURED_PEAK = {"f64": 74.2, "f32": 155.0}
 # HBM bytes per colour launch of the default step kernel on the p=4 slab
 # (N=256), from FETCH_SIZE/WRITE_SIZE counters scaled by a plain copy of known
 # size; valid for this kernel build only
-COUNTED_TRAFFIC = {("slab-p4-24x24x48", 256, "f64"): (2.228e9, "step_pipe_kernel<4,0,2>"),
-                   ("slab-p4-24x24x48", 256, "f32"): (2.234e9, "step_pipe_kernel<4,1,2>"),
+COUNTED_TRAFFIC = {("slab-p4-24x24x48", 256, "f64"): (1.779e9, "step_pipe_kernel<4,0,2,true>"),
+                   ("slab-p4-24x24x48", 256, "f32"): (1.779e9, "step_pipe_kernel<4,1,2,true>"),
                    ("slab-p4-24x24x48", 256, "bf16"): (2.670e9, "step_mc_kernel<4,2,4>")}
 
 
@@ -113,6 +113,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cols", type=int, default=24)
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32/BF16 report")
+    ap.add_argument("--variant", type=int, default=0,
+                    help="step-kernel variant (fe_mesh_set_kernel; 0 = the fastest measured)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -130,6 +132,7 @@ def main():
     torch.cuda.set_device(dev)
     t0 = time.time()
     gm = fe.Mesh.from_workload(wl)
+    gm.set_kernel(args.variant)
     n, N, m = gm.n, wl.N, wl.m
     Vq = torch.from_numpy(W.workload_potential(wl, gm.quad_points())).to(dev)
     gm.set_potential(Vq, wl.E, wl.z0)
@@ -184,7 +187,8 @@ def main():
     launch_ms = (ms - t_pot) / launches
     achieved = flops_per_launch / (launch_ms * 1e-3) / 1e12
     peak, bound = PEAK[args.prec]
-    traffic = COUNTED_TRAFFIC.get((wl.name, N, args.prec))
+    # the counters belong to the default kernel
+    traffic = COUNTED_TRAFFIC.get((wl.name, N, args.prec)) if args.variant == 0 else None
     # measured copy bandwidth of the same block (read + write), the practical
     # HBM ceiling the counted traffic is compared with
     W2 = work.view(n, N)
@@ -213,14 +217,15 @@ def main():
         "config": {"workload": f"{wl.name} (box {wl.L[0]:g}x{wl.L[1]:g}x{wl.L[2]:g} bohr, cells "
                                f"{wl.ncell[0]}x{wl.ncell[1]}x{wl.ncell[2]}, GLL p={wl.p}, n={n} free DoFs, "
                                f"N={N}, filter degree m={m}, cell products {args.prec})",
-                   "n_dof": n, "N": N, "m": m, "p": wl.p, "cells": list(wl.ncell), "prec": args.prec},
+                   "n_dof": n, "N": N, "m": m, "p": wl.p, "cells": list(wl.ncell), "prec": args.prec,
+                   "kernel_variant": args.variant},
         "roofline": {
             "bound": bound,
             "achieved": round(achieved, 3),
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4),
-            "traffic": traffic[0] if traffic else None,
+            "traffic": traffic[0] if traffic and traffic[0] else None,
             "traffic_unit": "B per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "algorithmic_bytes_per_launch": 24.0 * n * N / ncol,
             "kernel": (traffic[1] if traffic else f"step kernel p={wl.p} {args.prec}") + " (one colour pass)",
@@ -229,10 +234,10 @@ def main():
             "flops_per_launch": flops_per_launch,
             "avg_launch_ms": round(launch_ms, 5),
             "launches_per_step": launches,
-            "hbm_GBps": round(traffic[0] / (launch_ms * 1e-3) / 1e9, 1) if traffic else None,
-            "hbm_frac_of_8TBps": round(traffic[0] / (launch_ms * 1e-3) / 8e12, 4) if traffic else None,
+            "hbm_GBps": round(traffic[0] / (launch_ms * 1e-3) / 1e9, 1) if traffic and traffic[0] else None,
+            "hbm_frac_of_8TBps": round(traffic[0] / (launch_ms * 1e-3) / 8e12, 4) if traffic and traffic[0] else None,
             "copy_GBps_measured": round(copy_GBps, 1),
-            "hbm_frac_of_measured_copy": round(traffic[0] / (launch_ms * 1e-3) / 1e9 / copy_GBps, 4) if traffic else None,
+            "hbm_frac_of_measured_copy": round(traffic[0] / (launch_ms * 1e-3) / 1e9 / copy_GBps, 4) if traffic and traffic[0] else None,
         },
     }
     # density of the filtered block (Sec. 2.1) and its planar integral: HBM-bound

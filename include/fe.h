@@ -102,14 +102,19 @@ fe_status fe_mesh_destroy(fe_mesh *mesh);
  * everything its outputs need in one round trip before the cell product;
  * the FP64 default for p != 4); 7 = persistent pipelined row-owner
  * kernel with the cell matrix in registers and the loads of the next two
- * items in flight during each cell product (FP64 and FP32, p <= 4; the
- * default for both at p = 4; else 6; BF16: 3); 8 = persistent
- * warp-specialised row-owner kernel, compute waves and memory waves
- * exchanging double-buffered LDS tiles (p <= 4; else 6).  Variants 0-4 and
- * 6-8 give bitwise-identical results, except that in FP64 variant 2 multiplies with
- * 16x16x4 MFMA blocks where the others use 4x4x4 blocks (equal to rounding);
- * variant 5 sums each node's contributions in another fixed order (equal to
- * rounding, reproducible).  FE_EINVAL for other values. */
+ * items in flight during each cell product (FP64 and FP32, p <= 4; else 6;
+ * BF16: 3); 8 = persistent warp-specialised row-owner kernel, compute waves
+ * and memory waves exchanging double-buffered LDS tiles (p <= 4; else 6);
+ * 9 = the pipelined kernel of 7 walking z segments of up to 6 cells (the
+ * largest length that divides the z cell count, at least two segments on a
+ * periodic z axis), the faces shared inside a segment kept in LDS instead of
+ * being read and written in HBM (FP64 and FP32, p <= 4, the default for both
+ * at p = 4; else as 7).  Variants 0-4 and 6-8 give bitwise-identical results
+ * (variant 0 wherever it is not variant 9), except that in FP64 variant 2
+ * multiplies with 16x16x4 MFMA blocks where the others use 4x4x4 blocks
+ * (equal to rounding); variants 5 and 9 sum each node's contributions in
+ * other fixed orders (equal to rounding, reproducible).  FE_EINVAL for other
+ * values. */
 fe_status fe_mesh_set_kernel(fe_mesh *mesh, int32_t variant);
 
 /* Sizes: free DoFs n, cells, and points per cell n_c = (p+1)^3.  Any output

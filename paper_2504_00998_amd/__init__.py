@@ -164,7 +164,7 @@ class Mesh:
 
     def set_kernel(self, variant: int):
         """Step-kernel implementation (``fe_mesh_set_kernel``): 0 = fastest
-        measured (default), 1 = one cell x 16 vectors per workgroup, 2-7 =
+        measured (default), 1 = one cell x 16 vectors per workgroup, 2-9 =
         the alternatives declared in ``include/fe.h``."""
         _check(lib().fe_mesh_set_kernel(self._h, int(variant)))
 

@@ -310,7 +310,7 @@ fe_status fe_mesh_destroy(fe_mesh *mesh) {
 
 fe_status fe_mesh_set_kernel(fe_mesh *m, int32_t variant) {
     if (!m) return fail(FE_EINVAL, "NULL mesh");
-    if (variant < 0 || variant > 8) return fail(FE_EINVAL, "kernel variant must be in 0..8");
+    if (variant < 0 || variant > 9) return fail(FE_EINVAL, "kernel variant must be in 0..9");
     m->kernel_variant = variant;
     return FE_OK;
 }

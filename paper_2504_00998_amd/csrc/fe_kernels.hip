@@ -31,6 +31,7 @@ namespace fe {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 // ---------------------------------------------------------------- helpers
@@ -91,6 +92,8 @@ struct StepParams {
     int col[3];
     int cnt[3];
     int64_t nfx, nfy;
+    AxisInfo zs;  // z axis in segments of zl cells (the pipelined kernel's z segments; zl = 1: cells)
+    int zl;
 };
 
 template <int PREC> struct PrecTraits;
@@ -1729,14 +1732,37 @@ template <int P, int PREC = 0> struct PipeShape {
     static constexpr size_t bytes = (size_t)2 * G * XS * sizeof(T);
 };
 
-// Row within the 16-row tile and first of the four vectors a lane owns: the
-// FP64 4x4x4 layout, or (FP32) the transposed 16x16x4 product of the
-// row-owner kernel (lane l owns row l%16, vectors 4(l/16) .. +3).
+// Row within the 16-row tile and the vectors a lane owns.  The four lanes
+// sharing a row own the vector pairs {2j, 2j+1} and {8+2j, 9+2j} of each
+// 16-vector chunk (j = 0..3), so that each 16-byte load or store of the four
+// covers one contiguous 64-byte run of the row.  FP64: 4x4x4 blocks, lane l
+// owns row 4((l/4)%4) + l/16 with j = l%4; instruction q multiplies the
+// B slice of vectors {pipe_off(q) + 2j}.  FP32: the transposed 16x16x4
+// product, lane l owns row l%16 with j = l/16, the X operand's vector
+// index permuted to match (pipe_perm).
 template <int PREC> __device__ __forceinline__ int pipe_row(int lane) {
     return PREC == 0 ? 4 * ((lane >> 2) & 3) + (lane >> 4) : (lane & 15);
 }
 template <int PREC> __device__ __forceinline__ int pipe_vec(int lane) {
-    return PREC == 0 ? 4 * (lane & 3) : 4 * (lane >> 4);
+    return PREC == 0 ? 2 * (lane & 3) : 2 * (lane >> 4);
+}
+// Offset of a lane's q-th owned vector from pipe_vec: q = 0, 1 the first
+// pair, q = 2, 3 the pair 8 vectors on.
+__device__ __forceinline__ constexpr int pipe_off(int q) { return (q & 1) + 8 * (q >> 1); }
+// Vector carried by row i of the transposed FP32 product's X operand, so that
+// lane l's accumulator q holds vector pipe_vec(l) + pipe_off(q).
+__device__ __forceinline__ int pipe_perm(int i) { return 2 * (i >> 2) + pipe_off(i & 3); }
+
+// B operand of the FP64 4x4x4 product at k-step s for the pipelined layout:
+// row 4s + l/16 of the chunk, vectors 2(l%4) + pipe_off(q), as two 16-byte
+// LDS reads.
+__device__ __forceinline__ void f64_pair_b(const double *xs, int s, int lane, double b[4]) {
+    const double *row = xs + (4 * s + (lane >> 4)) * 16 + 2 * (lane & 3);
+    const double2 u = reinterpret_cast<const double2 *>(row)[0], v = reinterpret_cast<const double2 *>(row + 8)[0];
+    b[0] = u.x;
+    b[1] = u.y;
+    b[2] = v.x;
+    b[3] = v.y;
 }
 
 // Whether local node i of cell c is not shared, along this axis, with a cell
@@ -1753,28 +1779,61 @@ __device__ __forceinline__ bool axis_first_sel(const AxisInfo &a, int p, int c, 
     return !(exists && cn < cc);
 }
 
-// The loads of one thread for one item, and what the epilogue needs.
+// The loads of one thread for one cell of an item, and what the epilogue
+// needs.  With z segments (ZS), bot marks a row on the bottom face of a cell
+// after the segment's first: it loads nothing (X comes from the previous
+// cell's staged top face, the old value from the LDS hold); top marks a row on
+// the top face of a cell before the segment's last, whose output goes to the
+// hold instead of Y.
 template <int G> struct PipeRow {
     NodeRef n;
-    bool fst;
+    bool fst, bot, top;
     double vraw;
     double x[G][4], o[G][4];
     int64_t v0;
 };
 
-template <int P, int PREC>
-__device__ __forceinline__ void pipe_issue(const StepParams &k, int64_t item, int ngroups, int wave, int lane,
+// Cell of cell index ci of the launch's colour: along z, segment s of the
+// colour and cell c within it (c = 0 without segments).
+__device__ __forceinline__ ItemCell seg_cell(const StepParams &k, int ci, int c, int &seg) {
+    ItemCell r;
+    r.chunk = 0;
+    const int ix = ci % k.cnt[0];
+    ci /= k.cnt[0];
+    const int iy = ci % k.cnt[1];
+    const int iz = ci / k.cnt[1];
+    r.cx = colour_cell(k.ax[0], k.col[0], ix);
+    r.cy = colour_cell(k.ax[1], k.col[1], iy);
+    seg = colour_cell(k.zs, k.col[2], iz);
+    r.cz = seg * k.zl + c;
+    return r;
+}
+
+template <int P, int PREC, bool ZS>
+__device__ __forceinline__ void pipe_issue(const StepParams &k, int64_t item, int c, int ngroups, int wave, int lane,
                                            PipeRow<PipeShape<P>::G> &L) {
     constexpr int N1 = P + 1, NC = N1 * N1 * N1, G = PipeShape<P>::G;
     const int grp = (int)(item % ngroups);
-    const ItemCell c = item_cell(k, (item / ngroups) * k.nchunk);
+    int seg;
+    const ItemCell cc = seg_cell(k, (int)(item / ngroups), c, seg);
     const int r = 16 * wave + pipe_row<PREC>(lane);
     L.v0 = (int64_t)grp * G * 16 + pipe_vec<PREC>(lane);
-    L.n = node_ref<P>(k, c, r);
+    L.n = node_ref<P>(k, cc, r);
     const int l = min(r, NC - 1);
-    const bool f0 = axis_first_sel(k.ax[0], P, c.cx, l % N1);
-    const bool f1 = axis_first_sel(k.ax[1], P, c.cy, (l / N1) % N1);
-    const bool f2 = axis_first_sel(k.ax[2], P, c.cz, l / (N1 * N1));
+    const int lz = l / (N1 * N1);
+    const bool f0 = axis_first_sel(k.ax[0], P, cc.cx, l % N1);
+    const bool f1 = axis_first_sel(k.ax[1], P, cc.cy, (l / N1) % N1);
+    bool f2;
+    if constexpr (ZS) {
+        // along z only the segment's end faces meet other workgroups
+        const int iz = lz == 0 ? (c == 0 ? 0 : -1) : lz == P ? (c == k.zl - 1 ? P : -1) : -1;
+        f2 = axis_first_sel(k.zs, P, seg, iz);
+        L.bot = r < NC && lz == 0 && c > 0;
+        L.top = r < NC && lz == P && c < k.zl - 1;
+    } else {
+        f2 = axis_first_sel(k.ax[2], P, cc.cz, lz);
+        L.bot = L.top = false;
+    }
     L.fst = (r < NC) & f0 & f1 & f2;
     const int64_t Ic = max(L.n.I, 0);
     // the old value: Y where an earlier colour has written the node, else the
@@ -1785,14 +1844,21 @@ __device__ __forceinline__ void pipe_issue(const StepParams &k, int64_t item, in
     const double *orow = L.fst ? ob + Ic * ol : k.Y + Ic * k.ldy;
     const double *xrow = k.X + Ic * k.ldx;
     L.vraw = k.v[Ic];
+    // a bottom-face row of a segment's later cell loads nothing; its x and o
+    // are left unset (never read), so that no register a load in flight
+    // targets is written by the other lanes
+    const bool skip = ZS && L.bot;
     if (wide_ok(k, (int64_t)grp * G * 16, 16 * G)) {
         // the item's columns are all inside N and the blocks 16-byte aligned:
-        // each lane's four consecutive values as two 16-byte loads
+        // each lane's four values as two 16-byte loads
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            const double2 *xp = reinterpret_cast<const double2 *>(xrow + L.v0 + 16 * g);
-            const double2 *op = reinterpret_cast<const double2 *>(orow + L.v0 + 16 * g);
-            const double2 x01 = xp[0], x23 = xp[1], o01 = op[0], o23 = op[1];
+            if (skip) continue;
+            const double *xp = xrow + L.v0 + 16 * g, *op = orow + L.v0 + 16 * g;
+            const double2 x01 = *reinterpret_cast<const double2 *>(xp);
+            const double2 x23 = *reinterpret_cast<const double2 *>(xp + 8);
+            const double2 o01 = *reinterpret_cast<const double2 *>(op);
+            const double2 o23 = *reinterpret_cast<const double2 *>(op + 8);
             L.x[g][0] = x01.x; L.x[g][1] = x01.y; L.x[g][2] = x23.x; L.x[g][3] = x23.y;
             L.o[g][0] = o01.x; L.o[g][1] = o01.y; L.o[g][2] = o23.x; L.o[g][3] = o23.y;
         }
@@ -1801,20 +1867,27 @@ __device__ __forceinline__ void pipe_issue(const StepParams &k, int64_t item, in
         for (int g = 0; g < G; ++g)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int64_t vc = min(L.v0 + 16 * g + q, k.N - 1);
+                if (skip) continue;
+                const int64_t vc = min(L.v0 + 16 * g + pipe_off(q), k.N - 1);
                 L.x[g][q] = xrow[vc];
                 L.o[g][q] = orow[vc];
             }
     }
 }
 
-// D X of the item into an LDS buffer; per output the first writer's base term
-// alpha (v - c) X - beta Y_{k-1}, or the old Y, into bo.
-template <int P, int PREC>
+// D X of the cell into an LDS buffer; per output the first writer's base term
+// alpha (v - c) X - beta Y_{k-1}, or the old Y, into bo.  A bottom-face row of
+// a segment's later cell copies D X from the previous cell's top face in xp
+// (the same node) and takes its base from the hold later (hf bit 0); hf bit 1
+// sends the row's output to the hold.
+template <int P, int PREC, bool ZS>
 __device__ __forceinline__ void pipe_stage(const StepParams &k, const PipeRow<PipeShape<P>::G> &L,
-                                           typename PipeShape<P, PREC>::T *xs, int wave, int lane,
-                                           double (&bo)[PipeShape<P>::G][4], int &I, double &d, int64_t &v0) {
-    constexpr int G = PipeShape<P>::G, XS = PipeShape<P>::XS;
+                                           typename PipeShape<P, PREC>::T *xs,
+                                           const typename PipeShape<P, PREC>::T *xp, int wave, int lane,
+                                           double (&bo)[PipeShape<P>::G][4], int &I, double &d, int64_t &v0,
+                                           int &hf) {
+    constexpr int N1 = P + 1, G = PipeShape<P>::G, XS = PipeShape<P>::XS;
+    typedef typename PipeShape<P, PREC>::T T;
     const int r = 16 * wave + pipe_row<PREC>(lane);
     const int vq = pipe_vec<PREC>(lane);
     const bool useo = !L.fst || k.Ym1 != nullptr;
@@ -1823,12 +1896,27 @@ __device__ __forceinline__ void pipe_stage(const StepParams &k, const PipeRow<Pi
     d = node_scale(L.n);
     I = L.n.I;
     v0 = L.v0;
+    hf = (L.bot ? 1 : 0) | (L.top ? 2 : 0);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
+        if (ZS && L.bot) {
+            const T *src = xp + g * XS + (r + P * N1 * N1) * 16 + vq;
+            T *dst = xs + g * XS + r * 16 + vq;
+            if constexpr (PREC == 0) {
+                *reinterpret_cast<double2 *>(dst) = *reinterpret_cast<const double2 *>(src);
+                *reinterpret_cast<double2 *>(dst + 8) = *reinterpret_cast<const double2 *>(src + 8);
+            } else {
+                *reinterpret_cast<f2 *>(dst) = *reinterpret_cast<const f2 *>(src);
+                *reinterpret_cast<f2 *>(dst + 8) = *reinterpret_cast<const f2 *>(src + 8);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) bo[g][q] = 0.0;
+            continue;
+        }
         double dx[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const bool ok = L.n.I >= 0 && L.v0 + 16 * g + q < k.N;
+            const bool ok = L.n.I >= 0 && L.v0 + 16 * g + pipe_off(q) < k.N;
             const double x = ok ? L.x[g][q] : 0.0;
             const double o = (ok && useo) ? L.o[g][q] : 0.0;
             double base = sc * x;
@@ -1836,30 +1924,46 @@ __device__ __forceinline__ void pipe_stage(const StepParams &k, const PipeRow<Pi
             bo[g][q] = L.fst ? base : o;
             dx[q] = d * x;
         }
+        T *dst = xs + g * XS + r * 16 + vq;
         if constexpr (PREC == 0) {
-            double2 *dst = reinterpret_cast<double2 *>(xs + g * XS + r * 16 + vq);
-            dst[0] = double2{dx[0], dx[1]};
-            dst[1] = double2{dx[2], dx[3]};
+            *reinterpret_cast<double2 *>(dst) = double2{dx[0], dx[1]};
+            *reinterpret_cast<double2 *>(dst + 8) = double2{dx[2], dx[3]};
         } else {
-            *reinterpret_cast<f4 *>(xs + g * XS + r * 16 + vq) = f4{(float)dx[0], (float)dx[1], (float)dx[2], (float)dx[3]};
+            *reinterpret_cast<f2 *>(dst) = f2{(float)dx[0], (float)dx[1]};
+            *reinterpret_cast<f2 *>(dst + 8) = f2{(float)dx[2], (float)dx[3]};
         }
     }
 }
 
-template <int P, int PREC, int PD>
+// Walk of a workgroup: its items blockIdx.x, blockIdx.x + gridDim.x, ...,
+// each taken as ZL consecutive cells of a z segment (ZL = 1 without
+// segments); position t of the walk is cell t % ZL of the workgroup's item
+// t / ZL.  One body call handles one position: the product from xbuf[cur];
+// the next position (loaded into Ln) staged into the other buffer, with the
+// loads of the position after it requested into Lf first (index clamped to
+// the last position, so the loads are unconditional and the wait for Ln's
+// loads leaves them in flight); then this position's outputs are stored (to
+// the hold for the top face of a segment's non-last cell).
+template <int P, int PREC, int PD, bool ZS>
 __global__ __launch_bounds__(64 * PipeShape<P>::W) __attribute__((amdgpu_waves_per_eu(1, 2)))
 void step_pipe_kernel(StepParams k, int64_t nitems) {
     static_assert(PREC == 0 || PREC == 1, "FP64 or FP32 cell products");
-    constexpr int NKS = PipeShape<P>::NKS, G = PipeShape<P>::G, XS = PipeShape<P>::XS;
+    static_assert(PD == 2 || !ZS, "z segments need the two-deep pipeline");
+    constexpr int N1 = P + 1, NKS = PipeShape<P>::NKS, G = PipeShape<P>::G, XS = PipeShape<P>::XS;
+    constexpr int HS = N1 * N1 * 16 * G;  // doubles per hold buffer
     typedef typename PipeShape<P, PREC>::T T;
     extern __shared__ __align__(16) unsigned char smem[];
-    T *xbuf = reinterpret_cast<T *>(smem);  // [2][G][XS]
+    T *xbuf = reinterpret_cast<T *>(smem);                                      // [2][G][XS]
+    double *hold = reinterpret_cast<double *>(smem + PipeShape<P, PREC>::bytes);  // [2][N1*N1][16G] (ZS)
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int ngroups = (k.nchunk + G - 1) / G;
     const int64_t stride = gridDim.x;
-    int64_t item = blockIdx.x;
-    if (item >= nitems) return;  // whole workgroup
+    if ((int64_t)blockIdx.x >= nitems) return;  // whole workgroup
+    const int zl = ZS ? k.zl : 1;
+    const int npos = (int)((nitems - 1 - blockIdx.x) / stride + 1) * zl;  // < 2^31, as items per launch
+    auto item_of = [&](int t) { return (int64_t)blockIdx.x + (int64_t)(ZS ? t / zl : t) * stride; };
+    auto cell_of = [&](int t) { return ZS ? t % zl : 0; };
     // the wave's row tile of (1/2)K_c, resident for the launch
     T ar[NKS];
     {
@@ -1867,19 +1971,21 @@ void step_pipe_kernel(StepParams k, int64_t nitems) {
 #pragma unroll
         for (int s = 0; s < NKS; ++s) ar[s] = A[s * 64];
     }
+    const int r = 16 * wave + pipe_row<PREC>(lane);
+    const int vq = pipe_vec<PREC>(lane);
     double bo[G][4], d;
-    int I;
+    int I, hf = 0;
     int64_t v0;
     int cur = 0;
-    // One item: product from xbuf[cur]; the next item (loaded into Ln) staged
-    // into the other buffer; with PD = 2 the item after it is requested into
-    // Lf first (index clamped to the last item, so the loads are
-    // unconditional and the wait for Ln's loads leaves them in flight);
-    // then this item's outputs are stored.  Returns false after the last item.
+    int t = 0;
     auto body = [&](PipeRow<G> &Ln, PipeRow<G> &Lf) -> bool {
-        const bool more = item + stride < nitems;  // uniform over the workgroup
-        if constexpr (PD == 2) pipe_issue<P, PREC>(k, min(item + 2 * stride, nitems - 1), ngroups, wave, lane, Lf);
-        else if (more) pipe_issue<P, PREC>(k, item + stride, ngroups, wave, lane, Ln);
+        const bool more = t + 1 < npos;  // uniform over the workgroup
+        if constexpr (PD == 2) {
+            const int tf = min(t + 2, npos - 1);
+            pipe_issue<P, PREC, ZS>(k, item_of(tf), cell_of(tf), ngroups, wave, lane, Lf);
+        } else if (more) {
+            pipe_issue<P, PREC, ZS>(k, item_of(t + 1), cell_of(t + 1), ngroups, wave, lane, Ln);
+        }
         const T *xs = xbuf + cur * G * XS;
         double acc[G][4];
         if constexpr (PREC == 0) {
@@ -1889,12 +1995,12 @@ void step_pipe_kernel(StepParams k, int64_t nitems) {
                 for (int q = 0; q < 4; ++q) acc[g][q] = 0.0;
             double bc[G][4], bn[G][4];
 #pragma unroll
-            for (int g = 0; g < G; ++g) f64_quad_b(xs + g * XS, 0, lane, bc[g]);
+            for (int g = 0; g < G; ++g) f64_pair_b(xs + g * XS, 0, lane, bc[g]);
 #pragma unroll
             for (int s = 0; s < NKS; ++s) {
                 if (s + 1 < NKS)
 #pragma unroll
-                    for (int g = 0; g < G; ++g) f64_quad_b(xs + g * XS, s + 1, lane, bn[g]);
+                    for (int g = 0; g < G; ++g) f64_pair_b(xs + g * XS, s + 1, lane, bn[g]);
 #pragma unroll
                 for (int g = 0; g < G; ++g)
 #pragma unroll
@@ -1909,7 +2015,7 @@ void step_pipe_kernel(StepParams k, int64_t nitems) {
             // transposed 16x16x4 products: X slice first, cell-matrix fragment second
             f4 c4[G];
             float bc[G], bn[G];
-            const int bo0 = (lane >> 4) * 16 + (lane & 15);
+            const int bo0 = (lane >> 4) * 16 + pipe_perm(lane & 15);
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 c4[g] = f4{0.f, 0.f, 0.f, 0.f};
@@ -1930,30 +2036,51 @@ void step_pipe_kernel(StepParams k, int64_t nitems) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) acc[g][q] = (double)c4[g][q];
         }
-        // outputs of this item, kept while the next one is staged
+        if constexpr (ZS) {
+            // a bottom-face row of a later cell continues the previous cell's
+            // output for the same node, left in the hold
+            if (hf & 1) {
+                const double *h = hold + ((t - 1) & 1) * HS + r * 16 * G + vq;
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const double2 u = *reinterpret_cast<const double2 *>(h + 16 * g);
+                    const double2 w = *reinterpret_cast<const double2 *>(h + 16 * g + 8);
+                    bo[g][0] = u.x; bo[g][1] = u.y; bo[g][2] = w.x; bo[g][3] = w.y;
+                }
+            }
+        }
+        // outputs of this position, kept while the next one is staged
         double out[G][4];
 #pragma unroll
         for (int g = 0; g < G; ++g)
 #pragma unroll
             for (int q = 0; q < 4; ++q) out[g][q] = bo[g][q] + k.alpha * d * acc[g][q];
-        const int Io = I;
+        const int Io = I, hfo = hf;
         const int64_t v0o = v0;
-        if (more) pipe_stage<P, PREC>(k, Ln, xbuf + (cur ^ 1) * G * XS, wave, lane, bo, I, d, v0);
-        if (Io >= 0) {
+        if (more)
+            pipe_stage<P, PREC, ZS>(k, Ln, xbuf + (cur ^ 1) * G * XS, xs, wave, lane, bo, I, d, v0, hf);
+        if (ZS && (hfo & 2)) {
+            double *h = hold + (t & 1) * HS + (r - P * N1 * N1) * 16 * G + vq;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                *reinterpret_cast<double2 *>(h + 16 * g) = double2{out[g][0], out[g][1]};
+                *reinterpret_cast<double2 *>(h + 16 * g + 8) = double2{out[g][2], out[g][3]};
+            }
+        } else if (Io >= 0) {
             double *yrow = k.Y + (int64_t)Io * k.ldy;
-            if (wide_ok(k, v0o - pipe_vec<PREC>(lane), 16 * G)) {
+            if (wide_ok(k, v0o - vq, 16 * G)) {
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
-                    double2 *yp = reinterpret_cast<double2 *>(yrow + v0o + 16 * g);
-                    yp[0] = double2{out[g][0], out[g][1]};
-                    yp[1] = double2{out[g][2], out[g][3]};
+                    double *yp = yrow + v0o + 16 * g;
+                    *reinterpret_cast<double2 *>(yp) = double2{out[g][0], out[g][1]};
+                    *reinterpret_cast<double2 *>(yp + 8) = double2{out[g][2], out[g][3]};
                 }
             } else {
 #pragma unroll
                 for (int g = 0; g < G; ++g)
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        const int64_t vec = v0o + 16 * g + q;
+                        const int64_t vec = v0o + 16 * g + pipe_off(q);
                         if (vec < k.N) yrow[vec] = out[g][q];
                     }
             }
@@ -1961,15 +2088,16 @@ void step_pipe_kernel(StepParams k, int64_t nitems) {
         if (!more) return false;
         cur ^= 1;
         __syncthreads();
-        item += stride;
+        ++t;
         return true;
     };
     PipeRow<G> LA, LB;
-    pipe_issue<P, PREC>(k, item, ngroups, wave, lane, LA);
-    pipe_stage<P, PREC>(k, LA, xbuf, wave, lane, bo, I, d, v0);
+    pipe_issue<P, PREC, ZS>(k, item_of(0), 0, ngroups, wave, lane, LA);
+    pipe_stage<P, PREC, ZS>(k, LA, xbuf, xbuf, wave, lane, bo, I, d, v0, hf);  // cell 0: no bottom copy
     __syncthreads();
     if constexpr (PD == 2) {
-        pipe_issue<P, PREC>(k, min(item + stride, nitems - 1), ngroups, wave, lane, LA);
+        const int t1 = min(1, npos - 1);
+        pipe_issue<P, PREC, ZS>(k, item_of(t1), cell_of(t1), ngroups, wave, lane, LA);
         for (;;) {
             if (!body(LA, LB)) break;
             if (!body(LB, LA)) break;
@@ -1980,19 +2108,29 @@ void step_pipe_kernel(StepParams k, int64_t nitems) {
     }
 }
 
-template <int P, int PREC, int PD>
+// Cells per z segment for the segmented pipelined kernel: the largest length
+// up to 6 that divides the cell count along z and leaves a periodic axis at
+// least two segments; 1 (no segments) when there is none above 1.
+static int zseg_length(const fe_mesh *m) {
+    const int nz = m->ncell[2];
+    for (int L = 6; L >= 2; --L)
+        if (nz % L == 0 && (m->bc[2] != FE_BC_PERIODIC || nz / L >= 2)) return L;
+    return 1;
+}
+
+template <int P, int PREC, int PD, bool ZS>
 static hipError_t launch_pipe_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
-    constexpr int W = PipeShape<P>::W, G = PipeShape<P>::G;
-    const size_t smem = PipeShape<P, PREC>::bytes;
+    constexpr int W = PipeShape<P>::W, G = PipeShape<P>::G, N1 = P + 1;
+    const size_t smem = PipeShape<P, PREC>::bytes + (ZS ? (size_t)2 * N1 * N1 * 16 * G * sizeof(double) : 0);
     static bool attr = false;
     static int resident = 0;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step_pipe_kernel<P, PREC, PD>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step_pipe_kernel<P, PREC, PD, ZS>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         if (e != hipSuccess) return e;
         int per_cu = 0, dev = 0, cus = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&step_pipe_kernel<P, PREC, PD>),
-                                                         64 * W, smem);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(&step_pipe_kernel<P, PREC, PD, ZS>), 64 * W, smem);
         if (e != hipSuccess) return e;
         e = hipGetDevice(&dev);
         if (e != hipSuccess) return e;
@@ -2001,14 +2139,20 @@ static hipError_t launch_pipe_p(StepParams prm, const fe_mesh *m, hipStream_t s)
         resident = std::max(1, per_cu) * std::max(1, cus);
         attr = true;
     }
+    // along z the colours are those of segments of zl cells (of cells when
+    // zl = 1): segments of one colour share no node, as cells do
+    prm.zl = ZS ? zseg_length(m) : 1;
+    prm.zs = prm.ax[2];
+    prm.zs.ncell = prm.ax[2].ncell / prm.zl;
+    prm.zs.ncol = (prm.zs.bc == FE_BC_PERIODIC && (prm.zs.ncell & 1)) ? 3 : prm.zs.ncell >= 2 ? 2 : 1;
     const int ngroups = (prm.nchunk + G - 1) / G;
-    for (int c2 = 0; c2 < m->ncol[2]; ++c2)
+    for (int c2 = 0; c2 < prm.zs.ncol; ++c2)
         for (int c1 = 0; c1 < m->ncol[1]; ++c1)
             for (int c0 = 0; c0 < m->ncol[0]; ++c0) {
                 int col[3] = {c0, c1, c2};
                 int64_t cells = 1;
                 for (int a = 0; a < 3; ++a) {
-                    const AxisInfo &ax = prm.ax[a];
+                    const AxisInfo &ax = a == 2 ? prm.zs : prm.ax[a];
                     int cnt;
                     if (col[a] == 2) cnt = 1;
                     else {
@@ -2022,7 +2166,8 @@ static hipError_t launch_pipe_p(StepParams prm, const fe_mesh *m, hipStream_t s)
                 if (cells == 0) continue;
                 const int64_t nitems = cells * ngroups;
                 const int64_t grid = std::min<int64_t>(nitems, resident);
-                hipLaunchKernelGGL((step_pipe_kernel<P, PREC, PD>), dim3((unsigned)grid), dim3(64 * W), smem, s, prm, nitems);
+                hipLaunchKernelGGL((step_pipe_kernel<P, PREC, PD, ZS>), dim3((unsigned)grid), dim3(64 * W), smem, s,
+                                   prm, nitems);
                 hipError_t e = hipGetLastError();
                 if (e != hipSuccess) return e;
             }
@@ -2356,6 +2501,8 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
     }
     prm.nfx = m->nf[0];
     prm.nfy = m->nf[1];
+    prm.zs = prm.ax[2];
+    prm.zl = 1;
     if (a.S) {
         // Bloch mode: FP64 row-owner kernel in the configurations of the real
         // mode, with one wave less per SIMD for the second fragment stream
@@ -2412,30 +2559,41 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
         }
 #undef FE_WS
     }
-    // the pipelined kernel with two items in flight is the FP64 and FP32
-    // default at p = 4, where it was measured fastest (FP64 6.1 against 6.8,
-    // FP32 6.08 against 6.17 ms per H~X on the 24x24x48-cell slab, 256
-    // vectors)
-    if ((m->kernel_variant == 7 || (m->kernel_variant == 0 && m->p == 4)) && prec == FE_F64) {
+    // the pipelined kernel walking z segments is the FP64 and FP32 default at
+    // p = 4, where it was measured fastest (FP64 5.7 against 6.0 for the
+    // one-cell pipelined kernel, FP32 4.24 against 5.8 ms per H~X on the
+    // 24x24x48-cell slab, 256 vectors)
+    const bool zseg = m->kernel_variant == 9 || (m->kernel_variant == 0 && m->p == 4);
+    if (m->kernel_variant == 7 && prec != FE_BF16) {
+#define FE_PIPE(PP)                                                                       \
+    case PP:                                                                              \
+        return prec == FE_F64 ? launch_pipe_p<PP, 0, 2, false>(prm, m, s) : launch_pipe_p<PP, 1, 2, false>(prm, m, s);
         switch (m->p) {
-        case 1: return launch_pipe_p<1, 0, 2>(prm, m, s);
-        case 2: return launch_pipe_p<2, 0, 2>(prm, m, s);
-        case 3: return launch_pipe_p<3, 0, 2>(prm, m, s);
-        case 4: return launch_pipe_p<4, 0, 2>(prm, m, s);
+            FE_PIPE(1)
+            FE_PIPE(2)
+            FE_PIPE(3)
+            FE_PIPE(4)
         default: break;
         }
+#undef FE_PIPE
     }
-    if ((m->kernel_variant == 7 || (m->kernel_variant == 0 && m->p == 4)) && prec == FE_F32) {
+    // variant 9: the pipelined kernel walking z segments of cells, the shared
+    // faces inside a segment kept in LDS
+    if (zseg && prec != FE_BF16) {
+#define FE_ZSEG(PP)                                                                       \
+    case PP:                                                                              \
+        return prec == FE_F64 ? launch_pipe_p<PP, 0, 2, true>(prm, m, s) : launch_pipe_p<PP, 1, 2, true>(prm, m, s);
         switch (m->p) {
-        case 1: return launch_pipe_p<1, 1, 2>(prm, m, s);
-        case 2: return launch_pipe_p<2, 1, 2>(prm, m, s);
-        case 3: return launch_pipe_p<3, 1, 2>(prm, m, s);
-        case 4: return launch_pipe_p<4, 1, 2>(prm, m, s);
+            FE_ZSEG(1)
+            FE_ZSEG(2)
+            FE_ZSEG(3)
+            FE_ZSEG(4)
         default: break;
         }
+#undef FE_ZSEG
     }
     if ((m->kernel_variant == 0 && prec == FE_F64) || m->kernel_variant == 6 || m->kernel_variant == 8 ||
-        (m->kernel_variant == 7 && prec == FE_F64)) {
+        ((m->kernel_variant == 7 || m->kernel_variant == 9) && prec == FE_F64)) {
         // 32 vectors per workgroup and one row tile per wave measured best
         // where the tiles fit one workgroup (p <= 5); above that two tiles
         // per wave keep the workgroup within 1024 threads
