@@ -39,7 +39,7 @@ MEASURED_PEAK = {"f64": 74.2, "f32": 155.0}
 # size; valid for this kernel build only
 COUNTED_TRAFFIC = {("slab-p4-24x24x48", 256, "f64"): (1.779e9, "step_pipe_kernel<4,0,2,true>"),
                    ("slab-p4-24x24x48", 256, "f32"): (1.779e9, "step_pipe_kernel<4,1,2,true>"),
-                   ("slab-p4-24x24x48", 256, "bf16"): (2.670e9, "step_mc_kernel<4,2,4>")}
+                   ("slab-p4-24x24x48", 256, "bf16"): (1.779e9, "step_pipe_kernel<4,2,2,true>")}
 
 
 def log(*a):

@@ -108,13 +108,13 @@ fe_status fe_mesh_destroy(fe_mesh *mesh);
  * 9 = the pipelined kernel of 7 walking z segments of up to 6 cells (the
  * largest length that divides the z cell count, at least two segments on a
  * periodic z axis), the faces shared inside a segment kept in LDS instead of
- * being read and written in HBM (FP64 and FP32, p <= 4, the default for both
- * at p = 4; else as 7).  Variants 0-4 and 6-8 give bitwise-identical results
- * (variant 0 wherever it is not variant 9), except that in FP64 variant 2
- * multiplies with 16x16x4 MFMA blocks where the others use 4x4x4 blocks
- * (equal to rounding); variants 5 and 9 sum each node's contributions in
- * other fixed orders (equal to rounding, reproducible).  FE_EINVAL for other
- * values. */
+ * being read and written in HBM (FP64, FP32 and BF16 products, p <= 4, the
+ * default for all three at p = 4; else as 7).  Variants 0-4 and 6-8 give
+ * bitwise-identical results (variant 0 wherever it is not variant 9), except
+ * that in FP64 variant 2 multiplies with 16x16x4 MFMA blocks where the others
+ * use 4x4x4 blocks (equal to rounding); variants 5 and 9 sum each node's
+ * contributions in other fixed orders (equal to rounding, reproducible).
+ * FE_EINVAL for other values. */
 fe_status fe_mesh_set_kernel(fe_mesh *mesh, int32_t variant);
 
 /* Sizes: free DoFs n, cells, and points per cell n_c = (p+1)^3.  Any output

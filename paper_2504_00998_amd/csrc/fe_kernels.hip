@@ -1713,23 +1713,30 @@ static hipError_t launch_ws_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------------
-// Pipelined row-owner variant (FP64, p <= 4): persistent workgroups walk the
-// items (cell, group of G chunks of 16 vectors) of a colour with stride
-// gridDim.x, one wave per 16-row tile of (1/2)K_c with the tile's fragments
-// held in registers for the whole launch, each thread owning one row for four
-// consecutive vectors per chunk (the 4x4x4 layout of the row-owner kernel).
-// The product loop issues no vector-memory instruction, so the HBM loads of
-// the next item (X, the previous iterate or the old Y, v; branch-free from
-// clamped addresses) stay in flight while it runs.  After the product the
-// next item is staged into the other LDS buffer -- the only wait on those
-// loads -- and only then are the current item's outputs stored, so the wait
-// never includes the stores.  B is read from LDS one k-step ahead of its
-// products.  Same arithmetic, in the same order, as the other FP64 variants.
+// Pipelined row-owner variant (p <= 4): persistent workgroups walk the items
+// (cell or z segment of cells, group of G chunks of 16 vectors) of a colour
+// with stride gridDim.x, one wave per 16-row tile of (1/2)K_c with the tile's
+// fragments held in registers for the whole launch, each thread owning one
+// row for four vectors per chunk.  Products: FP64 on 4x4x4 blocks, FP32 on
+// transposed 16x16x4 and BF16 on transposed 16x16x32 products (X operand
+// first), FP32 accumulation below FP64.  The product loop issues no
+// vector-memory instruction, so the HBM loads of the next cells (X, the
+// previous iterate or the old Y, v; from clamped addresses) stay in flight
+// while it runs.  After the product the next cell is staged into the other
+// LDS buffer -- the only wait on those loads -- and only then are the
+// current cell's outputs stored, so the wait never includes the stores.  The
+// B (FP64) or X (FP32) operand is read from LDS one k-step ahead of its
+// products.  Without z segments: the same arithmetic, in the same order, as
+// the other FP64 and FP32 variants.
 template <int P, int PREC = 0> struct PipeShape {
     typedef typename PrecTraits<PREC>::T T;
-    static constexpr int NCP = ((P + 1) * (P + 1) * (P + 1) + 31) / 32 * 32, NT = NCP / 16, NKS = NCP / 4;
-    static constexpr int W = NT, G = 2, XS = NCP * 16;  // waves; chunks per item; elements per chunk buffer
-    static constexpr size_t bytes = (size_t)2 * G * XS * sizeof(T);
+    static constexpr int NCP = ((P + 1) * (P + 1) * (P + 1) + 31) / 32 * 32, NT = NCP / 16;
+    static constexpr int NKS = NCP / PrecTraits<PREC>::KSTEP;  // k-steps of the product
+    // BF16 keeps each chunk transposed (vector-major, rows padded to
+    // Bf16Stride) for the 8-element operand reads of the 16x16x32 product
+    static constexpr int STR = PREC == 2 ? Bf16Stride<NCP>::value : 16;
+    static constexpr int W = NT, G = 2, XS = PREC == 2 ? 16 * STR : NCP * 16;  // waves; chunks; elements per chunk
+    static constexpr size_t bytes = ((size_t)2 * G * XS * sizeof(T) + 15) / 16 * 16;
 };
 
 // Row within the 16-row tile and the vectors a lane owns.  The four lanes
@@ -1886,7 +1893,7 @@ __device__ __forceinline__ void pipe_stage(const StepParams &k, const PipeRow<Pi
                                            const typename PipeShape<P, PREC>::T *xp, int wave, int lane,
                                            double (&bo)[PipeShape<P>::G][4], int &I, double &d, int64_t &v0,
                                            int &hf) {
-    constexpr int N1 = P + 1, G = PipeShape<P>::G, XS = PipeShape<P>::XS;
+    constexpr int N1 = P + 1, G = PipeShape<P>::G, XS = PipeShape<P, PREC>::XS, STR = PipeShape<P, PREC>::STR;
     typedef typename PipeShape<P, PREC>::T T;
     const int r = 16 * wave + pipe_row<PREC>(lane);
     const int vq = pipe_vec<PREC>(lane);
@@ -1900,14 +1907,22 @@ __device__ __forceinline__ void pipe_stage(const StepParams &k, const PipeRow<Pi
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         if (ZS && L.bot) {
-            const T *src = xp + g * XS + (r + P * N1 * N1) * 16 + vq;
-            T *dst = xs + g * XS + r * 16 + vq;
-            if constexpr (PREC == 0) {
-                *reinterpret_cast<double2 *>(dst) = *reinterpret_cast<const double2 *>(src);
-                *reinterpret_cast<double2 *>(dst + 8) = *reinterpret_cast<const double2 *>(src + 8);
+            if constexpr (PREC == 2) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int v = vq + pipe_off(q);
+                    xs[g * XS + v * STR + r] = xp[g * XS + v * STR + r + P * N1 * N1];
+                }
             } else {
-                *reinterpret_cast<f2 *>(dst) = *reinterpret_cast<const f2 *>(src);
-                *reinterpret_cast<f2 *>(dst + 8) = *reinterpret_cast<const f2 *>(src + 8);
+                const T *src = xp + g * XS + (r + P * N1 * N1) * 16 + vq;
+                T *dst = xs + g * XS + r * 16 + vq;
+                if constexpr (PREC == 0) {
+                    *reinterpret_cast<double2 *>(dst) = *reinterpret_cast<const double2 *>(src);
+                    *reinterpret_cast<double2 *>(dst + 8) = *reinterpret_cast<const double2 *>(src + 8);
+                } else {
+                    *reinterpret_cast<f2 *>(dst) = *reinterpret_cast<const f2 *>(src);
+                    *reinterpret_cast<f2 *>(dst + 8) = *reinterpret_cast<const f2 *>(src + 8);
+                }
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) bo[g][q] = 0.0;
@@ -1924,13 +1939,19 @@ __device__ __forceinline__ void pipe_stage(const StepParams &k, const PipeRow<Pi
             bo[g][q] = L.fst ? base : o;
             dx[q] = d * x;
         }
-        T *dst = xs + g * XS + r * 16 + vq;
-        if constexpr (PREC == 0) {
-            *reinterpret_cast<double2 *>(dst) = double2{dx[0], dx[1]};
-            *reinterpret_cast<double2 *>(dst + 8) = double2{dx[2], dx[3]};
+        if constexpr (PREC == 2) {
+            // transposed: element (row r, vector v) at v * STR + r
+#pragma unroll
+            for (int q = 0; q < 4; ++q) xs[g * XS + (vq + pipe_off(q)) * STR + r] = to_bf16_bits(dx[q]);
         } else {
-            *reinterpret_cast<f2 *>(dst) = f2{(float)dx[0], (float)dx[1]};
-            *reinterpret_cast<f2 *>(dst + 8) = f2{(float)dx[2], (float)dx[3]};
+            T *dst = xs + g * XS + r * 16 + vq;
+            if constexpr (PREC == 0) {
+                *reinterpret_cast<double2 *>(dst) = double2{dx[0], dx[1]};
+                *reinterpret_cast<double2 *>(dst + 8) = double2{dx[2], dx[3]};
+            } else {
+                *reinterpret_cast<f2 *>(dst) = f2{(float)dx[0], (float)dx[1]};
+                *reinterpret_cast<f2 *>(dst + 8) = f2{(float)dx[2], (float)dx[3]};
+            }
         }
     }
 }
@@ -1947,11 +1968,11 @@ __device__ __forceinline__ void pipe_stage(const StepParams &k, const PipeRow<Pi
 template <int P, int PREC, int PD, bool ZS>
 __global__ __launch_bounds__(64 * PipeShape<P>::W) __attribute__((amdgpu_waves_per_eu(1, 2)))
 void step_pipe_kernel(StepParams k, int64_t nitems) {
-    static_assert(PREC == 0 || PREC == 1, "FP64 or FP32 cell products");
     static_assert(PD == 2 || !ZS, "z segments need the two-deep pipeline");
-    constexpr int N1 = P + 1, NKS = PipeShape<P>::NKS, G = PipeShape<P>::G, XS = PipeShape<P>::XS;
+    constexpr int N1 = P + 1, NKS = PipeShape<P, PREC>::NKS, G = PipeShape<P>::G, XS = PipeShape<P, PREC>::XS;
     constexpr int HS = N1 * N1 * 16 * G;  // doubles per hold buffer
     typedef typename PipeShape<P, PREC>::T T;
+    typedef typename FragOf<PREC>::T FragT;
     extern __shared__ __align__(16) unsigned char smem[];
     T *xbuf = reinterpret_cast<T *>(smem);                                      // [2][G][XS]
     double *hold = reinterpret_cast<double *>(smem + PipeShape<P, PREC>::bytes);  // [2][N1*N1][16G] (ZS)
@@ -1965,9 +1986,9 @@ void step_pipe_kernel(StepParams k, int64_t nitems) {
     auto item_of = [&](int t) { return (int64_t)blockIdx.x + (int64_t)(ZS ? t / zl : t) * stride; };
     auto cell_of = [&](int t) { return ZS ? t % zl : 0; };
     // the wave's row tile of (1/2)K_c, resident for the launch
-    T ar[NKS];
+    FragT ar[NKS];
     {
-        const T *A = reinterpret_cast<const T *>(k.A) + (size_t)wave * NKS * 64 + lane;
+        const FragT *A = reinterpret_cast<const FragT *>(k.A) + (size_t)wave * NKS * 64 + lane;
 #pragma unroll
         for (int s = 0; s < NKS; ++s) ar[s] = A[s * 64];
     }
@@ -2011,6 +2032,25 @@ void step_pipe_kernel(StepParams k, int64_t nitems) {
 #pragma unroll
                     for (int q = 0; q < 4; ++q) bc[g][q] = bn[g][q];
             }
+        } else if constexpr (PREC == 2) {
+            // transposed 16x16x32 products: 8 consecutive rows of one vector of
+            // X from the vector-major buffer, the cell-matrix fragment second
+            constexpr int STR = PipeShape<P, PREC>::STR;
+            const T *xa = xs + pipe_perm(lane & 15) * STR + 8 * (lane >> 4);
+            f4 c4[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) c4[g] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < NKS; ++s)
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const bf8 a = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4 *>(xa + g * XS + 32 * s));
+                    c4[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf8, ar[s]), c4[g], 0, 0, 0);
+                }
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[g][q] = (double)c4[g][q];
         } else {
             // transposed 16x16x4 products: X slice first, cell-matrix fragment second
             f4 c4[G];
@@ -2559,10 +2599,11 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
         }
 #undef FE_WS
     }
-    // the pipelined kernel walking z segments is the FP64 and FP32 default at
-    // p = 4, where it was measured fastest (FP64 5.7 against 6.0 for the
-    // one-cell pipelined kernel, FP32 4.24 against 5.8 ms per H~X on the
-    // 24x24x48-cell slab, 256 vectors)
+    // the pipelined kernel walking z segments is the default at p = 4 for all
+    // three product precisions, where it was measured fastest (FP64 5.7-6.0
+    // against 5.9-6.1 for the one-cell pipelined kernel, FP32 4.24 against
+    // 5.8, BF16 3.84 against 5.0 for the multi-chunk kernel, ms per H~X on
+    // the 24x24x48-cell slab, 256 vectors)
     const bool zseg = m->kernel_variant == 9 || (m->kernel_variant == 0 && m->p == 4);
     if (m->kernel_variant == 7 && prec != FE_BF16) {
 #define FE_PIPE(PP)                                                                       \
@@ -2579,10 +2620,12 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
     }
     // variant 9: the pipelined kernel walking z segments of cells, the shared
     // faces inside a segment kept in LDS
-    if (zseg && prec != FE_BF16) {
+    if (zseg) {
 #define FE_ZSEG(PP)                                                                       \
     case PP:                                                                              \
-        return prec == FE_F64 ? launch_pipe_p<PP, 0, 2, true>(prm, m, s) : launch_pipe_p<PP, 1, 2, true>(prm, m, s);
+        if (prec == FE_F64) return launch_pipe_p<PP, 0, 2, true>(prm, m, s);              \
+        if (prec == FE_F32) return launch_pipe_p<PP, 1, 2, true>(prm, m, s);              \
+        return launch_pipe_p<PP, 2, 2, true>(prm, m, s);
         switch (m->p) {
             FE_ZSEG(1)
             FE_ZSEG(2)
