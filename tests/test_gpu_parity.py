@@ -121,7 +121,8 @@ def test_kernel_variants_bitwise_equal(prec, p):
     gm.set_kernel(1)
     Y1 = gm.cheb_filter(X, 5, 2.0, 400.0, -0.5, prec=prec)
     zseg_default = p == 4
-    for var in (0, 2, 3, 4, 6, 7, 8):
+    # above p = 4 variant 9 runs what variant 7 runs (one-cell kernels)
+    for var in (0, 2, 3, 4, 6, 7, 8) + ((9,) if p > 4 else ()):
         gm.set_kernel(var)
         Y0 = gm.cheb_filter(X, 5, 2.0, 400.0, -0.5, prec=prec)
         if (var == 2 and prec == "f64") or (var == 0 and zseg_default):
