@@ -1820,9 +1820,10 @@ template <int P, int PREC, bool ZS>
 __device__ __forceinline__ void pipe_issue(const StepParams &k, int64_t item, int c, int ngroups, int wave, int lane,
                                            PipeRow<PipeShape<P>::G> &L) {
     constexpr int N1 = P + 1, NC = N1 * N1 * N1, G = PipeShape<P>::G;
-    const int grp = (int)(item % ngroups);
+    const int it = (int)item;  // items per launch < 2^31: 32-bit division
+    const int grp = it % ngroups;
     int seg;
-    const ItemCell cc = seg_cell(k, (int)(item / ngroups), c, seg);
+    const ItemCell cc = seg_cell(k, it / ngroups, c, seg);
     const int r = 16 * wave + pipe_row<PREC>(lane);
     L.v0 = (int64_t)grp * G * 16 + pipe_vec<PREC>(lane);
     L.n = node_ref<P>(k, cc, r);
