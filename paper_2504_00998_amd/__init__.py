@@ -204,8 +204,8 @@ class Mesh:
         if Y is None:
             Y = torch.empty_strided(X.shape, X.stride(), dtype=torch.float64, device=X.device)
         _check_block(Y, self.n, "Y")
-        if Y.stride(0) != ld:
-            raise ValueError("X and Y must share the leading dimension")
+        if Y.shape[1] != N or Y.stride(0) != ld:
+            raise ValueError("Y must have X's shape and leading dimension")
         _check(lib().fe_hx_apply(self._h, _ptr(X), _ptr(Y), N, ld, _PREC[prec], _stream(stream)))
         return Y
 
@@ -216,6 +216,9 @@ class Mesh:
         N, ld = X.shape[1], X.stride(0)
         if Y is None:
             Y = torch.empty_strided(X.shape, X.stride(), dtype=torch.float64, device=X.device)
+        _check_block(Y, self.n, "Y")
+        if Y.shape[1] != N or Y.stride(0) != ld:
+            raise ValueError("Y must have X's shape and leading dimension")
         if work is None:
             work = torch.empty(self.n * N, dtype=torch.float64, device=X.device)
         _check(lib().fe_cheb_filter(self._h, _ptr(X), _ptr(Y), N, ld, int(m), float(a), float(b), float(a0),
@@ -240,8 +243,8 @@ class Mesh:
         if Y is None:
             Y = torch.empty_strided(X.shape, X.stride(), dtype=torch.complex128, device=X.device)
         _check_cblock(Y, self.n, "Y")
-        if Y.stride(0) != ld:
-            raise ValueError("X and Y must share the leading dimension")
+        if Y.shape[1] != N or Y.stride(0) != ld:
+            raise ValueError("Y must have X's shape and leading dimension")
         _check(lib().fe_hx_apply_k(self._h, _ptr(X), _ptr(Y), N, ld, _stream(stream)))
         return Y
 
@@ -253,8 +256,8 @@ class Mesh:
         if Y is None:
             Y = torch.empty_strided(X.shape, X.stride(), dtype=torch.complex128, device=X.device)
         _check_cblock(Y, self.n, "Y")
-        if Y.stride(0) != ld:
-            raise ValueError("X and Y must share the leading dimension")
+        if Y.shape[1] != N or Y.stride(0) != ld:
+            raise ValueError("Y must have X's shape and leading dimension")
         if work is None:
             work = torch.empty(2 * self.n * N, dtype=torch.float64, device=X.device)
         _check(lib().fe_cheb_filter_k(self._h, _ptr(X), _ptr(Y), N, ld, int(m), float(a), float(b), float(a0),
@@ -278,8 +281,8 @@ class Mesh:
             P = torch.empty_strided(Q.shape, Q.stride(), dtype=torch.complex128, device=Q.device)
         for t, name in ((X, "X"), (P, "P")):
             _check_cblock(t, self.n, name)
-            if t.stride(0) != ld:
-                raise ValueError(f"{name} must share Q's leading dimension")
+            if t.shape[1] != N or t.stride(0) != ld:
+                raise ValueError(f"{name} must have Q's shape and leading dimension")
         theta = np.zeros(N)
         _check(lib().fe_rayleigh_ritz_k(self._h, _ptr(Q), _ptr(X), _ptr(P), N, ld, theta.ctypes.data,
                                         _stream(stream)))
@@ -295,6 +298,8 @@ class Mesh:
         _check_block(X, self.n, "X")
         _check_block(G, self.n, "G")
         N, ld = X.shape[1], X.stride(0)
+        if G.shape[1] != N or G.stride(0) != ld:
+            raise ValueError("G must have X's shape and leading dimension")
         Xb = torch.empty_strided(X.shape, X.stride(), dtype=torch.float64, device=X.device)
         Vb = torch.empty((self.n_cells, self.nc), dtype=torch.float64, device=X.device)
         Eb = torch.empty((), dtype=torch.float64, device=X.device)
@@ -386,6 +391,10 @@ class Mesh:
             X = torch.empty_strided(Q.shape, Q.stride(), dtype=torch.float64, device=Q.device)
         if P is None:
             P = torch.empty_strided(Q.shape, Q.stride(), dtype=torch.float64, device=Q.device)
+        for t, name in ((X, "X"), (P, "P")):
+            _check_block(t, self.n, name)
+            if t.shape[1] != N or t.stride(0) != ld:
+                raise ValueError(f"{name} must have Q's shape and leading dimension")
         theta = np.zeros(N)
         _check(lib().fe_rayleigh_ritz(self._h, _ptr(Q), _ptr(X), _ptr(P), N, ld, theta.ctypes.data,
                                       _stream(stream)))

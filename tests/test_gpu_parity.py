@@ -321,6 +321,8 @@ def test_empty_blocks_and_the_one_dof_mesh():
     ((3, 2, 8), 4, (W.DIRICHLET, W.PERIODIC, W.PERIODIC), 4),  # periodic z, 2 segments
     ((2, 3, 10), 3, (W.NEUMANN, W.NEUMANN, W.NEUMANN), 5),    # Neumann z
     ((3, 3, 7), 2, None, 1),                                  # no divisor: plain cells
+    ((2, 2, 18), 4, (W.PERIODIC, W.PERIODIC, W.PERIODIC), 6),  # p = 4, periodic z, 3 segment colours
+    ((3, 2, 10), 4, (W.PERIODIC, W.DIRICHLET, W.NEUMANN), 5),  # p = 4, Neumann z
 ])
 def test_zsegment_variant_matches_oracle_and_is_reproducible(prec, shape, p, bc, zl):
     """Variant 9 walks z segments of zl cells (the largest length up to 6 that
@@ -389,4 +391,33 @@ def test_zsegment_variant_several_items_per_workgroup(p, N, prec):
     for A, B in ((Y9, Y1), (F9, F1)):
         rel = ((A - B).norm(dim=0) / B.norm(dim=0)).max().item()
         assert rel < tol, rel
+    gm.set_kernel(0)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("N", [1, 17])
+def test_zsegment_variant_ragged_blocks(prec, N):
+    """Blocks of 1 and 17 vectors through the z-segment kernel (p = 4): the
+    second 16-vector chunk of every item is wholly or partly outside N, so
+    those lanes load clamped columns, and their outputs (and holds) must not
+    leak into the block.  Equal to the one-cell kernel to rounding; columns
+    past N of the wider buffers untouched.  X and Y share one leading
+    dimension (N + 3 here); a Y of another layout is refused."""
+    wl = W.small_slab((3, 3, 12), p=4, N=N)
+    _print_case(test="zsegment_ragged", prec=prec, N=N)
+    op, gm, _ = _setup(wl)
+    Xb = torch.full((op.n, N + 3), float("nan"), dtype=torch.float64, device="cuda")
+    Xb[:, :N] = torch.from_numpy(wl.X(op.n)).cuda()
+    X = Xb[:, :N]
+    gm.set_kernel(1)
+    Y1 = gm.cheb_filter(X, 5, 2.0, 400.0, -0.5, prec=prec)
+    gm.set_kernel(9)
+    Yb = torch.full((op.n, N + 3), float("nan"), dtype=torch.float64, device="cuda")
+    gm.cheb_filter(X, 5, 2.0, 400.0, -0.5, prec=prec, Y=Yb[:, :N])
+    Y9 = Yb[:, :N]
+    with pytest.raises(ValueError):
+        gm.cheb_filter(X, 5, 2.0, 400.0, -0.5, prec=prec, Y=torch.empty((op.n, N), dtype=torch.float64, device="cuda"))
+    rel = ((Y9 - Y1).norm(dim=0) / Y1.norm(dim=0)).max().item()
+    assert rel < {"f32": 1e-6, "bf16": 1e-5}[prec], rel
+    assert torch.isnan(Yb[:, N:]).all()
     gm.set_kernel(0)
