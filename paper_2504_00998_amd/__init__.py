@@ -122,6 +122,20 @@ def _check_block(t, n: int, name: str):
         raise ValueError(f"{name} must be (n={n}, N) with unit column stride")
 
 
+def _check_vec(t, n: int, name: str):
+    """A contiguous float64 device vector of exactly n values."""
+    import torch
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name} must be a contiguous float64 device tensor of {n} values")
+
+
+def _work_bytes(t) -> int:
+    """Size in bytes of a caller's scratch buffer (any dtype, contiguous, on the device)."""
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("work must be a contiguous device tensor")
+    return t.numel() * t.element_size()
+
+
 def _check_cblock(t, n: int, name: str):
     import torch
     if t.dtype != torch.complex128 or not t.is_cuda:
@@ -222,7 +236,7 @@ class Mesh:
         if work is None:
             work = torch.empty(self.n * N, dtype=torch.float64, device=X.device)
         _check(lib().fe_cheb_filter(self._h, _ptr(X), _ptr(Y), N, ld, int(m), float(a), float(b), float(a0),
-                                    _PREC[prec], _ptr(work), work.numel() * 8, _stream(stream)))
+                                    _PREC[prec], _ptr(work), _work_bytes(work), _stream(stream)))
         return Y
 
     # --------------------------------------------------------------- Bloch-k
@@ -261,7 +275,7 @@ class Mesh:
         if work is None:
             work = torch.empty(2 * self.n * N, dtype=torch.float64, device=X.device)
         _check(lib().fe_cheb_filter_k(self._h, _ptr(X), _ptr(Y), N, ld, int(m), float(a), float(b), float(a0),
-                                      _ptr(work), work.numel() * work.element_size(), _stream(stream)))
+                                      _ptr(work), _work_bytes(work), _stream(stream)))
         return Y
 
     def cholqr2_k(self, Y, stream=None):
@@ -308,7 +322,7 @@ class Mesh:
             work = torch.empty(max(1, (nb + 7) // 8), dtype=torch.float64, device=X.device)
         _check(lib().fe_cheb_filter_vjp(self._h, _ptr(X), _ptr(G), N, ld, int(m), float(a), float(b), float(a0),
                                         _PREC[prec], _ptr(Xb), _ptr(Vb), _ptr(Eb), int(ckpt_stride), int(col_chunk),
-                                        _ptr(work), work.numel() * 8, _stream(stream)))
+                                        _ptr(work), _work_bytes(work), _stream(stream)))
         return Xb, Vb, Eb
 
     # ------------------------------------------------------------ observables
@@ -322,6 +336,7 @@ class Mesh:
             raise ValueError("f must be a contiguous float64 device tensor of N values")
         if rho is None:
             rho = torch.empty(self.n, dtype=torch.float64, device=X.device)
+        _check_vec(rho, self.n, "rho")
         _check(lib().fe_density(self._h, _ptr(X), N, ld, _ptr(f), _ptr(rho), _stream(stream)))
         return rho
 
@@ -344,6 +359,7 @@ class Mesh:
             raise ValueError("field must be a contiguous float64 device tensor of n values")
         if out is None:
             out = torch.empty(self.nf[2], dtype=torch.float64, device=field.device)
+        _check_vec(out, int(self.nf[2]), "out")
         _check(lib().fe_planar_average(self._h, _ptr(field), int(bool(normalize)), _ptr(out), _stream(stream)))
         return out
 
@@ -365,15 +381,19 @@ class Mesh:
             raise ValueError("charge must be a contiguous float64 device tensor of n values")
         if phi is None:
             phi = torch.empty(self.n, dtype=torch.float64, device=charge.device)
+        _check_vec(phi, self.n, "phi")
         need = int(lib().fe_poisson_work_bytes(self._h))
         if work is None:
             work = torch.empty((need + 7) // 8, dtype=torch.float64, device=charge.device)
         it, rel = C.c_int32(), C.c_double()
         _check(lib().fe_poisson_solve(self._h, _ptr(charge), _ptr(phi), float(tol), int(maxit), _ptr(work),
-                                      work.numel() * 8, C.byref(it), C.byref(rel), _stream(stream)))
+                                      _work_bytes(work), C.byref(it), C.byref(rel), _stream(stream)))
         return phi, it.value, rel.value
 
     def lanczos_bounds(self, v0, k: int = 10, stream=None):
+        """(a0, b): lowest Ritz value and upper spectral bound from k Lanczos
+        steps started at the device vector v0 (fe_lanczos_bounds)."""
+        _check_vec(v0, self.n, "v0")
         a0, b = C.c_double(), C.c_double()
         _check(lib().fe_lanczos_bounds(self._h, _ptr(v0), int(k), C.byref(a0), C.byref(b), _stream(stream)))
         return a0.value, b.value

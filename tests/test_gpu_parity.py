@@ -421,3 +421,43 @@ def test_zsegment_variant_ragged_blocks(prec, N):
     assert rel < {"f32": 1e-6, "bf16": 1e-5}[prec], rel
     assert torch.isnan(Yb[:, N:]).all()
     gm.set_kernel(0)
+
+
+def test_binding_rejects_mismatched_buffers():
+    """The binding refuses, before any library call, buffers whose layout the
+    C entry points would misread: an output block of another leading
+    dimension or width, a start vector or output vector of the wrong length
+    or type, a scratch buffer that is not contiguous on the device."""
+    wl = W.small_slab((3, 3, 4), p=2, N=4)
+    _print_case(test="binding_checks")
+    op, gm, _ = _setup(wl)
+    n = op.n
+    dev = "cuda"
+    X = torch.from_numpy(wl.X(n)).cuda()
+    f64 = dict(dtype=torch.float64, device=dev)
+    bad_ld = torch.empty((n, 6), **f64)[:, :4]
+    with pytest.raises(ValueError):
+        gm.hx(X, bad_ld)
+    with pytest.raises(ValueError):
+        gm.cheb_filter(X, 3, 2.0, 40.0, Y=bad_ld)
+    with pytest.raises(ValueError):
+        gm.cheb_filter(X, 3, 2.0, 40.0, Y=torch.empty((n, 3), **f64))
+    with pytest.raises(ValueError):
+        gm.cheb_filter(X, 3, 2.0, 40.0, work=torch.empty(2 * n * 4, **f64)[::2])
+    with pytest.raises(ValueError):
+        gm.cheb_filter_vjp(X, bad_ld, 3, 2.0, 40.0)
+    with pytest.raises(ValueError):
+        gm.lanczos_bounds(torch.ones(n - 1, **f64))
+    with pytest.raises(ValueError):
+        gm.lanczos_bounds(torch.ones(n, dtype=torch.float32, device=dev))
+    f = torch.ones(4, **f64)
+    with pytest.raises(ValueError):
+        gm.density(X, f, rho=torch.empty(n + 1, **f64))
+    with pytest.raises(ValueError):
+        gm.planar_average(torch.ones(n, **f64), out=torch.empty(1, **f64))
+    with pytest.raises(ValueError):
+        gm.rayleigh_ritz(X, X=bad_ld)
+    # a float32 scratch buffer is sized by its own element size (half the
+    # bytes of as many doubles): too small here, so the library refuses it
+    with pytest.raises(RuntimeError):
+        gm.cheb_filter(X, 3, 2.0, 40.0, work=torch.empty(n * 4, dtype=torch.float32, device=dev))
