@@ -323,6 +323,8 @@ def test_empty_blocks_and_the_one_dof_mesh():
     ((3, 3, 7), 2, None, 1),                                  # no divisor: plain cells
     ((2, 2, 18), 4, (W.PERIODIC, W.PERIODIC, W.PERIODIC), 6),  # p = 4, periodic z, 3 segment colours
     ((3, 2, 10), 4, (W.PERIODIC, W.DIRICHLET, W.NEUMANN), 5),  # p = 4, Neumann z
+    ((3, 3, 12), 1, None, 6),                                 # p = 1: 4-node faces, 32-row padded tile
+    ((4, 3, 8), 1, (W.PERIODIC, W.PERIODIC, W.PERIODIC), 4),  # p = 1, periodic z
 ])
 def test_zsegment_variant_matches_oracle_and_is_reproducible(prec, shape, p, bc, zl):
     """Variant 9 walks z segments of zl cells (the largest length up to 6 that
