@@ -275,7 +275,7 @@ def main():
     rec["poisson"] = {"n_dof": em.n, "bc": "periodic x,y / zero-Neumann z (zero-mean)", "tol": 1e-10,
                       "iterations": p_it, "relres": p_rel, "s": round(p_s, 4),
                       "ms_per_iteration": round(1e3 * p_s / max(p_it, 1), 4),
-                      "solver": "Jacobi-preconditioned CG on the device; product = all cell products, then fixed-order nodal sums"}
+                      "solver": "Jacobi-preconditioned CG on the device; product = all cell products, then fixed-order nodal sums; batches of 8 iterations replayed from a HIP graph"}
     # Bloch form (Sec. 2.1): the same filter with complex H~^k at an in-plane
     # wave vector, on the same storage read as N/2 complex vectors
     # (interleaved re/im), FP64 only

@@ -266,8 +266,12 @@ fe_status fe_dipole(fe_mesh *mesh, const double *rho, double z0, double *mu_host
  * (may be NULL) receive the iteration count and the final |r| / |b|.  The
  * iteration runs on the device (fixed-order reductions, so results are
  * reproducible); the host reads its state once per 8 iterations and returns
- * after the stream has drained.  FE_EINVAL for NULL arguments,
- * tol <= 0 or maxit < 1; FE_ENOMEM if work is too small. */
+ * after the stream has drained.  Full batches of 8 after the first are
+ * replayed from a HIP graph (captured once per call on a private stream,
+ * kernel nodes only; direct launches if the capture fails), so the stream
+ * may be the null stream.  FE_EINVAL for NULL arguments, tol <= 0 or
+ * maxit < 1; FE_ENOMEM if work is too small; FE_EDEVICE for a failed
+ * launch. */
 size_t fe_poisson_work_bytes(const fe_mesh *mesh);
 fe_status fe_poisson_solve(fe_mesh *mesh, const double *charge, double *phi, double tol, int32_t maxit,
                            double *work, size_t work_bytes, int32_t *iters_host, double *relres_host,

@@ -323,26 +323,65 @@ fe_status fe_poisson_solve(fe_mesh *m, const double *charge, double *phi, double
         FE_HIPP(hipMemcpyAsync(sc, sc0, sizeof(sc0), hipMemcpyHostToDevice, st), "copy scalars");
         const int nb = (int)std::min<int64_t>(kRedBlocks, (n + kRedThreads - 1) / kRedThreads);
         constexpr int kBatch = 8;
+        // one CG iteration: seven launches on fixed buffers
+        auto iteration = [&](hipStream_t ss) -> hipError_t {
+            StepArgs a{p, 1, q, 1, nullptr, 0, 1.0, 0.0, 0.0, 1, zero};
+            hipError_t e2 = launch_step_assembled(m, a, Zc, ss);
+            if (e2 != hipSuccess) return e2;
+            hipLaunchKernelGGL(cg_pq_kernel, dim3(nb), dim3(kRedThreads), 0, ss, p, q, n, sc, part);
+            hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(kRedThreads), 0, ss, part, nb, sc);
+            hipLaunchKernelGGL(cg_update_kernel, dim3(nb), dim3(kRedThreads), 0, ss, x, r, p, q, pinv, e, n, sc, part);
+            hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(kRedThreads), 0, ss, part, nb, sc);
+            hipLaunchKernelGGL(cg_direction_kernel, dim3(blocks(n)), dim3(256), 0, ss, p, r, pinv, e, n, sc);
+            return hipGetLastError();
+        };
+        // After the first batch (direct launches, which also set the kernels'
+        // launch attributes) a full batch is captured once, on a private
+        // stream so that the caller's stream may be the null stream, into a
+        // HIP graph of kernel nodes only, and replayed on the caller's stream:
+        // the same launches in the same order, without the per-launch host
+        // overhead of 56 short kernels.  If the capture or instantiation
+        // fails the batches stay direct launches.
+        hipGraphExec_t exec = nullptr;
+        bool graph_tried = false;
+        auto capture = [&]() {
+            graph_tried = true;
+            hipStream_t cs = nullptr;
+            if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return;
+            hipGraph_t graph = nullptr;
+            bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) == hipSuccess;
+            if (ok) {
+                for (int j = 0; j < kBatch && ok; ++j) ok = iteration(cs) == hipSuccess;
+                ok = (hipStreamEndCapture(cs, &graph) == hipSuccess) && ok && graph;
+            }
+            if (ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) exec = nullptr;
+            if (graph) (void)hipGraphDestroy(graph);
+            (void)hipStreamDestroy(cs);
+            (void)hipGetLastError();  // a failed capture leaves no error behind
+        };
         double sh[S_COUNT] = {};
         int queued = 0;
+        fe_status loop_st = FE_OK;
         while (queued < maxit) {
             const int nbatch = std::min(kBatch, maxit - queued);
-            for (int j = 0; j < nbatch; ++j) {
-                StepArgs a{p, 1, q, 1, nullptr, 0, 1.0, 0.0, 0.0, 1, zero};
-                FE_HIPP(launch_step_assembled(m, a, Zc, st), "product launch");
-                hipLaunchKernelGGL(cg_pq_kernel, dim3(nb), dim3(kRedThreads), 0, st, p, q, n, sc, part);
-                hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(kRedThreads), 0, st, part, nb, sc);
-                hipLaunchKernelGGL(cg_update_kernel, dim3(nb), dim3(kRedThreads), 0, st, x, r, p, q, pinv, e, n, sc,
-                                   part);
-                hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(kRedThreads), 0, st, part, nb, sc);
-                hipLaunchKernelGGL(cg_direction_kernel, dim3(blocks(n)), dim3(256), 0, st, p, r, pinv, e, n, sc);
-                FE_HIPP(hipGetLastError(), "CG kernel launch");
+            if (queued > 0 && nbatch == kBatch && !graph_tried) capture();
+            if (exec && nbatch == kBatch) {
+                if (hipGraphLaunch(exec, st) != hipSuccess) { loop_st = fail(FE_EDEVICE, "CG graph launch"); break; }
+            } else {
+                for (int j = 0; j < nbatch; ++j)
+                    if (iteration(st) != hipSuccess) { loop_st = fail(FE_EDEVICE, "CG kernel launch"); break; }
+                if (loop_st != FE_OK) break;
             }
             queued += nbatch;
-            FE_HIPP(hipMemcpyAsync(sh, sc, sizeof(sh), hipMemcpyDeviceToHost, st), "read CG state");
-            FE_HIPP(hipStreamSynchronize(st), "hipStreamSynchronize");
+            if (hipMemcpyAsync(sh, sc, sizeof(sh), hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess) {
+                loop_st = fail(FE_EDEVICE, "read CG state");
+                break;
+            }
             if (sh[S_DONE] != 0.0) break;
         }
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (loop_st != FE_OK) return loop_st;
         if (sh[S_BREAK] != 0.0) return fail(FE_EDEVICE, "CG breakdown: p^T H0 p <= 0");
         it = (int)sh[S_IT];
         rel = sh[S_REL];
