@@ -87,10 +87,12 @@ def test_filter_k_matches_oracle(label, wl, k, nl, scaled):
     assert _relerr(Y, B.filter(X, wl.m, a, b, a0)) < 1e-12
 
 
-def test_gamma_point_equals_real_path_bitwise():
+@pytest.mark.parametrize("p", [3, 4])
+def test_gamma_point_equals_real_path_bitwise(p):
     """k = 0: H~^0 X = H~ Re X + i H~ Im X with identical rounding, for the
-    application and the filter, nonlocal term included."""
-    wl = W.small_slab((5, 5, 6), p=3, N=12, cfg=5)
+    application and the filter, nonlocal term included (p = 4: the z-segment
+    step kernel on the 2N interleaved columns against N columns)."""
+    wl = W.small_slab((5, 5, 6), p=p, N=12, cfg=5)
     _print_case(test="gamma_bitwise", ncell=wl.ncell, p=wl.p, N=wl.N)
     _, op, gm = _setup(wl, True)
     gm.set_kpoint(0.0, 0.0)

@@ -11,10 +11,14 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-@pytest.fixture(scope="module")
-def nl_case():
+@pytest.fixture(scope="module", params=[3, 4])
+def nl_case(request):
+    """p = 3 runs the row-owner step kernel, p = 4 the z-segment one (one
+    segment of 6 cells per column here), each followed by the projector
+    kernels."""
     import paper_2504_00998_amd as fe
-    wl = W.small_slab((5, 5, 6), p=3, N=20, m=8, cfg=5)
+    wl = W.small_slab((5, 5, 6), p=request.param, N=20, m=8, cfg=5)
+    print("case: nonlocal p =", request.param, flush=True)
     om = O.Mesh.from_workload(wl)
     Vq = W.workload_potential(wl, om.quad_points())
     cen = wl.centres()
