@@ -99,3 +99,18 @@ def test_bloch_entry_points_reject_null_without_a_device():
     assert L.fe_cheb_filter_k(None, None, None, 4, 4, 5, 1.0, 2.0, float("nan"), None, 0, None) == fe.FE_EINVAL
     assert L.fe_cholqr2_k(None, None, 4, 4, None) == fe.FE_EINVAL
     assert L.fe_rayleigh_ritz_k(None, None, None, None, 4, 4, None, None) == fe.FE_EINVAL
+
+
+def test_header_compiles_as_c(tmp_path):
+    """include/fe.h is a C header: a C11 translation unit that includes it and
+    calls an entry point compiles warning-free."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("needs gcc")
+    src = tmp_path / "use_fe.c"
+    src.write_text('#include "fe.h"\nint main(void) { fe_mesh *m = 0; return (int)fe_mesh_destroy(m); }\n')
+    r = subprocess.run(["gcc", "-std=c11", "-Wall", "-Wextra", "-Werror", "-fsyntax-only",
+                        "-I" + os.path.join(ROOT, "include"), "-I/opt/rocm/include", "-D__HIP_PLATFORM_AMD__",
+                        str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
