@@ -71,11 +71,13 @@ def cpu_baseline(wl, a, b, a0, ncols: int = 4):
     }
 
 
-def mixed_precision_report(gm, wl, X, Y, work, a, b, a0, steps, ms_f64):
+def mixed_precision_report(gm, wl, X, Y, work, a, b, a0, steps, ms_f64, launches, flops_per_launch, variant):
     """FP32 / BF16 cell products on the same workload: filter throughput,
-    speedup over FP64, and the Ritz values after 5 subspace iterations
-    (filter in the given precision; CholQR2 and Rayleigh-Ritz in FP64)
-    against the same iteration with FP64 cell products."""
+    speedup over FP64, the step kernel's launch time against the MFMA peak of
+    the precision (and its counted HBM rate where the counters of the kernel
+    are known), and the Ritz values after 5 subspace iterations (filter in the
+    given precision; CholQR2 and Rayleigh-Ritz in FP64) against the same
+    iteration with FP64 cell products."""
     import numpy as np
     import torch
     from paper_2504_00998_amd import solver
@@ -96,8 +98,15 @@ def mixed_precision_report(gm, wl, X, Y, work, a, b, a0, steps, ms_f64):
         ms = e0.elapsed_time(e1) / steps
         hist, _ = solver.subspace_iteration(gm, X, m, 5, a, b, a0, prec=prec, work=work)
         d = np.abs(hist[-1] - hist64[-1])
+        launch_ms = ms / launches
+        tf = flops_per_launch / (launch_ms * 1e-3) / 1e12
+        traffic = COUNTED_TRAFFIC.get((wl.name, N, prec)) if variant == 0 else None
         out[prec] = {"value": round(m * n * N / (ms * 1e-3) / 1e9, 4), "ms_per_filter": round(ms, 4),
                      "speedup_vs_f64": round(ms_f64 / ms, 3),
+                     "avg_launch_ms": round(launch_ms, 5), "achieved_TFLOPs": round(tf, 3),
+                     "frac_of_mfma_peak": round(tf / PEAK[prec][0], 4),
+                     "hbm_GBps": round(traffic[0] / (launch_ms * 1e-3) / 1e9, 1) if traffic and traffic[0] else None,
+                     "kernel": traffic[1] if traffic else None,
                      "ritz_err_max_Ha": float(d.max()), "ritz_err_lowest_half_Ha": float(d[: N // 2].max()),
                      "ritz_ok_1e-7": bool(d[: N // 2].max() <= 1e-7)}
     return out
@@ -309,7 +318,8 @@ def main():
                         "kernel": f"step_row_kernel<{wl.p},0,...,CPX> (complex H~^k, one colour pass)"}
     if not args.no_mixed and args.prec == "f64":
         t_pot_ms = t_pot
-        rec["mixed_precision"] = mixed_precision_report(gm, wl, X, Y, work, a, b, a0, args.steps, ms - t_pot_ms)
+        rec["mixed_precision"] = mixed_precision_report(gm, wl, X, Y, work, a, b, a0, args.steps, ms - t_pot_ms,
+                                                        launches, flops_per_launch, args.variant)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(wl, a, b, a0, args.cpu_cols)
     print(json.dumps(rec), flush=True)
