@@ -1756,8 +1756,9 @@ template <int PREC> __device__ __forceinline__ int pipe_vec(int lane) {
 // Offset of a lane's q-th owned vector from pipe_vec: q = 0, 1 the first
 // pair, q = 2, 3 the pair 8 vectors on.
 __device__ __forceinline__ constexpr int pipe_off(int q) { return (q & 1) + 8 * (q >> 1); }
-// Vector carried by row i of the transposed FP32 product's X operand, so that
-// lane l's accumulator q holds vector pipe_vec(l) + pipe_off(q).
+// Vector carried by row i of the X operand of the transposed FP32 and BF16
+// products, so that lane l's accumulator q holds vector pipe_vec(l) +
+// pipe_off(q).
 __device__ __forceinline__ int pipe_perm(int i) { return 2 * (i >> 2) + pipe_off(i & 3); }
 
 // B operand of the FP64 4x4x4 product at k-step s for the pipelined layout:
@@ -1774,6 +1775,8 @@ __device__ __forceinline__ void f64_pair_b(const double *xs, int s, int lane, do
 
 // Whether local node i of cell c is not shared, along this axis, with a cell
 // of a lower colour: node_first for one axis, as selects only (no branches).
+// An i outside [0, p] (the z-segment kernel passes -1 for a face inside a
+// segment) counts as interior: true.
 __device__ __forceinline__ bool axis_first_sel(const AxisInfo &a, int p, int c, int i) {
     const bool lo = i == 0, hi = i == p;
     const bool wrap_lo = lo && c == 0, wrap_hi = hi && c == a.ncell - 1;
