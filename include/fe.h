@@ -93,28 +93,25 @@ fe_status fe_mesh_destroy(fe_mesh *mesh);
 
 /* Select the implementation of the step kernel: 0 = the fastest measured
  * for the degree and precision (default); 1 = one cell x 16 vectors per
- * workgroup, cell matrix streamed from L2; 2 = persistent workgroups with the
- * cell matrix resident in registers (degrees/precisions where it fits, else
- * 1); 3 / 4 = one cell x 32 / 64 vectors per workgroup, so each cell-matrix
+ * workgroup, cell matrix streamed from L2 (the plain reference form);
+ * 3 / 4 = one cell x 32 / 64 vectors per workgroup, so each cell-matrix
  * fragment read from L2 feeds 2 / 4 products (falls back to 1 when the block
- * would exceed the LDS); 5 = tiles of cells accumulated in LDS (p = 3, 4 and,
- * below FP64, 5; else 3); 6 = row-owner kernel (each thread loads
+ * would exceed the LDS); 6 = row-owner kernel (each thread loads
  * everything its outputs need in one round trip before the cell product;
  * the FP64 default for p != 4); 7 = persistent pipelined row-owner
  * kernel with the cell matrix in registers and the loads of the next two
  * items in flight during each cell product (FP64 and FP32, p <= 4; else 6;
- * BF16: 3); 8 = persistent warp-specialised row-owner kernel, compute waves
- * and memory waves exchanging double-buffered LDS tiles (p <= 4; else 6);
- * 9 = the pipelined kernel of 7 walking z segments of up to 6 cells (the
- * largest length that divides the z cell count, at least two segments on a
- * periodic z axis), the faces shared inside a segment kept in LDS instead of
- * being read and written in HBM (FP64, FP32 and BF16 products, p <= 4, the
- * default for all three at p = 4; else as 7).  Variants 0-4 and 6-8 give
- * bitwise-identical results (variant 0 wherever it is not variant 9), except
- * that in FP64 variant 2 multiplies with 16x16x4 MFMA blocks where the others
- * use 4x4x4 blocks (equal to rounding); variants 5 and 9 sum each node's
- * contributions in other fixed orders (equal to rounding, reproducible).
- * FE_EINVAL for other values. */
+ * BF16: 3); 9 = the pipelined kernel of 7 walking z segments of up to 6
+ * cells (the largest length that divides the z cell count, at least two
+ * segments on a periodic z axis), the faces shared inside a segment kept in
+ * LDS instead of being read and written in HBM (FP64, FP32 and BF16
+ * products, p <= 4, the default for all three at p = 4; else as 7).
+ * Variants 0, 1, 3, 4, 6 and 7 give bitwise-identical results (variant 0
+ * wherever it is not variant 9); variant 9 sums each node's contributions in
+ * another fixed order (equal to rounding, reproducible).  Variants 2
+ * (register-resident), 5 (tiles of cells) and 8 (warp-specialised), slower
+ * than the defaults everywhere, were removed: FE_EINVAL for them and for
+ * values outside 0..9. */
 fe_status fe_mesh_set_kernel(fe_mesh *mesh, int32_t variant);
 
 /* Sizes: free DoFs n, cells, and points per cell n_c = (p+1)^3.  Any output
@@ -211,7 +208,8 @@ fe_status fe_cholqr2(fe_mesh *mesh, double *Y, int64_t N, int64_t ld, hipStream_
 /* Rayleigh-Ritz on an orthonormal block Q (n x N, ld): Hs = Q^T H~ Q
  * (symmetrised, FP64 products), Hs = W diag(theta) W^T, X <- Q W.
  * theta_host receives the N Ritz values ascending; P is caller scratch of n x N
- * doubles (ld).  Synchronises the stream. */
+ * doubles (ld).  Q, X and P must not overlap (FE_EINVAL).  Synchronises the
+ * stream. */
 fe_status fe_rayleigh_ritz(fe_mesh *mesh, const double *Q, double *X, double *P, int64_t N, int64_t ld,
                            double *theta_host, hipStream_t stream);
 
@@ -324,7 +322,7 @@ fe_status fe_cholqr2_k(fe_mesh *mesh, double *Y, int64_t N, int64_t ld, hipStrea
  * W diag(theta) W^H, X = Q W.  Q, X, P: device complex n x N with leading
  * dimension ld (X and P caller-owned outputs, P scratch); theta_host: N
  * doubles, ascending.  Synchronous with stream.  FE_ESTATE without a
- * potential. */
+ * potential; FE_EINVAL if Q, X and P overlap. */
 fe_status fe_rayleigh_ritz_k(fe_mesh *mesh, const double *Q, double *X, double *P, int64_t N, int64_t ld,
                              double *theta_host, hipStream_t stream);
 

@@ -433,8 +433,9 @@ def _autograd_function():
         """
 
         @staticmethod
-        def forward(ctx, X, Vq, E, mesh, m, a, b, a0, z0, prec, ckpt_stride, col_chunk):
-            Ev = float(E.item()) if torch.is_tensor(E) else float(E)
+        def forward(ctx, X, Vq, E, mesh, m, a, b, a0=math.nan, prec="f64", z0=0.0, ckpt_stride=1, col_chunk=0):
+            ctx.E_tensor = torch.is_tensor(E)
+            Ev = float(E.item()) if ctx.E_tensor else float(E)
             mesh.set_potential(Vq.detach().contiguous(), Ev, z0)
             Y = mesh.cheb_filter(X.detach().contiguous(), m, a, b, a0, prec=prec)
             ctx.save_for_backward(X.detach(), Vq.detach())
@@ -448,7 +449,9 @@ def _autograd_function():
             mesh.set_potential(Vq.contiguous(), Ev, z0)
             Xb, Vb, Eb = mesh.cheb_filter_vjp(X.contiguous(), G.contiguous(), m, a, b, a0, prec=prec,
                                               ckpt_stride=ckpt_stride, col_chunk=col_chunk)
-            return Xb, Vb, Eb, None, None, None, None, None, None, None, None, None
+            # dL/dV in the caller's layout of V_quad; no gradient for a plain-number E
+            Eb = Eb.reshape(()) if ctx.E_tensor else None
+            return Xb, Vb.view_as(Vq), Eb, None, None, None, None, None, None, None, None, None
 
     return ChebFilter
 
@@ -462,5 +465,18 @@ def cheb_filter(X, Vq, E, mesh: "Mesh", m: int, a: float, b: float, a0: float = 
     global _CHEB
     if _CHEB is None:
         _CHEB = _autograd_function()
-    return _CHEB.apply(X, Vq, E, mesh, int(m), float(a), float(b), float(a0), float(z0), prec, int(ckpt_stride),
+    return _CHEB.apply(X, Vq, E, mesh, int(m), float(a), float(b), float(a0), prec, float(z0), int(ckpt_stride),
                        int(col_chunk))
+
+
+def __getattr__(name):
+    """`ChebFilter`, the torch.autograd.Function behind cheb_filter, created on
+    first use (so that importing the package does not import torch):
+    ChebFilter.apply(X, Vq, E, mesh, m, a, b[, a0, prec, z0, ckpt_stride,
+    col_chunk])."""
+    global _CHEB
+    if name == "ChebFilter":
+        if _CHEB is None:
+            _CHEB = _autograd_function()
+        return _CHEB
+    raise AttributeError(f"module {__name__!r} has no attribute {name!r}")

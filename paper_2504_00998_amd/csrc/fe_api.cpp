@@ -42,8 +42,8 @@ static void block_range(const double *p, int64_t n, int64_t N, int64_t ld, uintp
     hi = lo + (uintptr_t)(((n - 1) * ld + N) * (int64_t)sizeof(double));
 }
 
-static bool overlap(const double *a, int64_t na, int64_t Na, int64_t lda, const double *b, int64_t nb, int64_t Nb,
-                    int64_t ldb) {
+bool overlap(const double *a, int64_t na, int64_t Na, int64_t lda, const double *b, int64_t nb, int64_t Nb,
+             int64_t ldb) {
     uintptr_t a0, a1, b0, b1;
     block_range(a, na, Na, lda, a0, a1);
     block_range(b, nb, Nb, ldb, b0, b1);
@@ -310,7 +310,8 @@ fe_status fe_mesh_destroy(fe_mesh *mesh) {
 
 fe_status fe_mesh_set_kernel(fe_mesh *m, int32_t variant) {
     if (!m) return fail(FE_EINVAL, "NULL mesh");
-    if (variant < 0 || variant > 9) return fail(FE_EINVAL, "kernel variant must be in 0..9");
+    if (variant < 0 || variant > 9 || variant == 2 || variant == 5 || variant == 8)
+        return fail(FE_EINVAL, "kernel variant must be 0, 1, 3, 4, 6, 7 or 9 (2, 5 and 8 were removed)");
     m->kernel_variant = variant;
     return FE_OK;
 }

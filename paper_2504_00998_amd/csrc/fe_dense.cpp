@@ -257,6 +257,9 @@ fe_status fe_rayleigh_ritz(fe_mesh *m, const double *Q, double *X, double *P, in
                            hipStream_t s) {
     if (!m || !Q || !X || !P || !theta) return fail(FE_EINVAL, "NULL argument");
     if (N < 1 || ld < N) return fail(FE_EINVAL, "need N >= 1 and ld >= N");
+    if (overlap(Q, m->n, N, ld, X, m->n, N, ld) || overlap(Q, m->n, N, ld, P, m->n, N, ld) ||
+        overlap(X, m->n, N, ld, P, m->n, N, ld))
+        return fail(FE_EINVAL, "Q, X and P must not overlap");
     if (!m->potential_set) return fail(FE_ESTATE, "fe_set_potential has not been called");
     int64_t n = m->n;
     // P = H~ Q (FP64 cell products)
@@ -339,6 +342,9 @@ fe_status fe_rayleigh_ritz_k(fe_mesh *m, const double *Q, double *X, double *P, 
                              hipStream_t s) {
     if (!m || !Q || !X || !P || !theta) return fail(FE_EINVAL, "NULL argument");
     if (N < 1 || ld < N) return fail(FE_EINVAL, "need N >= 1 and ld >= N");
+    if (overlap(Q, m->n, 2 * N, 2 * ld, X, m->n, 2 * N, 2 * ld) || overlap(Q, m->n, 2 * N, 2 * ld, P, m->n, 2 * N, 2 * ld) ||
+        overlap(X, m->n, 2 * N, 2 * ld, P, m->n, 2 * N, 2 * ld))
+        return fail(FE_EINVAL, "Q, X and P must not overlap");
     if (!m->potential_set) return fail(FE_ESTATE, "fe_set_potential has not been called");
     int64_t n = m->n;
     // P = H~^k Q

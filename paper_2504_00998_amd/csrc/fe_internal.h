@@ -97,6 +97,9 @@ namespace fe {
 // thread-local error message
 void set_error(const std::string &msg);
 fe_status fail(fe_status s, const std::string &msg);
+// whether two row-major blocks (n x N doubles, leading dimension ld) share a byte
+bool overlap(const double *a, int64_t na, int64_t Na, int64_t lda, const double *b, int64_t nb, int64_t Nb,
+             int64_t ldb);
 
 // reference element (host, FP64)
 void gll_rule(int p, std::vector<double> &x, std::vector<double> &w);

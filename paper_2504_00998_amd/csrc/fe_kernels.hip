@@ -262,12 +262,8 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams k) {
 }
 
 // ------------------------------------------------------------------------
-// Register-resident variant: each wave keeps the MFMA A fragments of its row
-// tiles of the cell matrix in VGPRs for the whole launch, and persistent
-// workgroups walk over (cell, 16-vector chunk) items of one colour.  The
-// next item's (D Y_k)_c is prefetched into registers while the current one
-// is multiplied, then written to the other LDS buffer.  Same arithmetic,
-// colouring and epilogue as step_kernel.
+// Helpers of the persistent kernels: the A-fragment type per precision, the
+// cell of a work item, node references and first-writer tests.
 template <int PREC> struct FragOf;
 template <> struct FragOf<0> { typedef double T; };
 template <> struct FragOf<1> { typedef float T; };
@@ -379,235 +375,6 @@ __device__ __forceinline__ bool node_first(const StepParams &k, const ItemCell &
         if (nb >= 0 && axis_colour(k.ax[a], nb) < axis_colour(k.ax[a], cc[a])) return false;
     }
     return true;
-}
-
-template <int P, int PREC, int W>
-__global__ __launch_bounds__(64 * W, (W <= 8 ? 4 : 1)) void step_kreg_kernel(StepParams k, int64_t nitems) {
-    constexpr int N1 = P + 1, NC = N1 * N1 * N1, NCP = (NC + 31) / 32 * 32, NT = NCP / 16;
-    constexpr int KSTEP = PrecTraits<PREC>::KSTEP, NKS = NCP / KSTEP;
-    constexpr int NTHR = 64 * W, TPW = NT / W, EPT = NCP * 16 / NTHR;
-    static_assert(NT % W == 0, "row tiles must divide evenly among waves");
-    static_assert((NCP * 16) % NTHR == 0, "staging must divide evenly among threads");
-    typedef typename PrecTraits<PREC>::T T;
-    typedef typename FragOf<PREC>::T FragT;
-    constexpr int XS = PREC == 2 ? 16 * Bf16Stride<NCP>::value : NCP * 16;  // elements per buffer
-    __shared__ __align__(16) T xs[2][XS];
-    __shared__ int32_t dof[3][NCP];
-    __shared__ double dsc[3][NCP];
-    __shared__ unsigned char first[3][NCP];
-
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15;
-
-    // cell-matrix fragments of this wave's row tiles, resident for the launch
-    FragT kreg[TPW][NKS];
-    {
-        const FragT *A = reinterpret_cast<const FragT *>(k.A);
-#pragma unroll
-        for (int tt = 0; tt < TPW; ++tt)
-#pragma unroll
-            for (int s = 0; s < NKS; ++s) kreg[tt][s] = A[((size_t)(wave + tt * W) * NKS + s) * 64 + lane];
-    }
-
-    int64_t item = blockIdx.x;
-    if (item >= nitems) return;
-
-    auto stage_tables = [&](int64_t it, int buf) {
-        const ItemCell c = item_cell(k, it);
-        for (int l = tid; l < NCP; l += NTHR) {
-            double d = 0.0;
-            int I = l < NC ? node_dof<P>(k, c, l, d) : -1;
-            dof[buf][l] = I;
-            dsc[buf][l] = d;
-            first[buf][l] = (l < NC && node_first<P>(k, c, l)) ? 1 : 0;
-        }
-    };
-    // (D Y_k)_c of an item from its node table
-    auto load_x = [&](int64_t it, int tb, double (&pre)[EPT]) {
-        const int64_t vec0 = (it % k.nchunk) * 16;
-#pragma unroll
-        for (int q = 0; q < EPT; ++q) {
-            int e = tid + q * NTHR;
-            int l = e >> 4, cc = e & 15;
-            int I = dof[tb][l];
-            double x = 0.0;
-            if (I >= 0 && vec0 + cc < k.N) x = dsc[tb][l] * k.X[(int64_t)I * k.ldx + vec0 + cc];
-            pre[q] = x;
-        }
-    };
-    auto store_x = [&](const double (&pre)[EPT], int buf) {
-#pragma unroll
-        for (int q = 0; q < EPT; ++q) {
-            int e = tid + q * NTHR;
-            if constexpr (PREC == 0) xs[buf][e] = pre[q];
-            else if constexpr (PREC == 1) xs[buf][e] = (float)pre[q];
-            else xs[buf][(e & 15) * Bf16Stride<NCP>::value + (e >> 4)] = to_bf16_bits(pre[q]);
-        }
-    };
-
-    // prologue: tables of the first two items, operand of the first
-    stage_tables(item, 0);
-    if (item + gridDim.x < nitems) stage_tables(item + gridDim.x, 1);
-    __syncthreads();
-    {
-        double pre[EPT];
-        load_x(item, 0, pre);
-        store_x(pre, 0);
-    }
-    __syncthreads();
-
-    int cur = 0, tb = 0;
-    // k-steps between scheduling barriers: bounds how many B fragments the
-    // compiler keeps in flight (VGPR pressure) without starving the MFMA pipe
-    constexpr int GROUP = PREC == 2 ? 2 : 4;
-    for (; item < nitems; item += gridDim.x) {
-        const int64_t next = item + gridDim.x, next2 = next + gridDim.x;
-        const bool has_next = next < nitems;
-        const int tbn = tb == 2 ? 0 : tb + 1, tbn2 = tbn == 2 ? 0 : tbn + 1;
-        const ItemCell c = item_cell(k, item);
-        double pre[EPT];
-        if (has_next) load_x(next, tbn, pre);
-        if (next2 < nitems) stage_tables(next2, tbn2);
-
-        // epilogue operands of this item, loaded before the product so that
-        // their latency hides under the MFMA chain
-        const int64_t vec = (int64_t)c.chunk * 16 + col;
-        const bool vec_ok = vec < k.N;
-        int32_t oI[TPW][4];
-        double o1[TPW][4], o2[TPW][4];
-#pragma unroll
-        for (int tt = 0; tt < TPW; ++tt) {
-            const int t = wave + tt * W;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                int r = 16 * t + (PREC == 0 ? (lane >> 4) + 4 * i : 4 * (lane >> 4) + i);
-                int32_t I = (vec_ok && r < NC) ? dof[tb][r] : -1;
-                oI[tt][i] = I;
-                o1[tt][i] = 0.0;
-                o2[tt][i] = 0.0;
-                if (I >= 0) {
-                    if (first[tb][r]) {
-                        o1[tt][i] = k.alpha * (k.v[I] - k.shift) * k.X[(int64_t)I * k.ldx + vec];
-                        if (k.Ym1) o2[tt][i] = k.beta * k.Ym1[(int64_t)I * k.ldm + vec];
-                    } else {
-                        o1[tt][i] = k.Y[(int64_t)I * k.ldy + vec];
-                    }
-                }
-            }
-        }
-
-        // dense cell product on MFMA: A fragments from registers, B from LDS
-        double acc[TPW][4];
-        if constexpr (PREC == 0) {
-            d4 c4[TPW];
-#pragma unroll
-            for (int tt = 0; tt < TPW; ++tt) c4[tt] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int s = 0; s < NKS; ++s) {
-                double b = xs[cur][(4 * s + (lane >> 4)) * 16 + col];
-#pragma unroll
-                for (int tt = 0; tt < TPW; ++tt)
-                    c4[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(kreg[tt][s], b, c4[tt], 0, 0, 0);
-                if ((s % GROUP) == GROUP - 1) __builtin_amdgcn_sched_barrier(0);
-            }
-#pragma unroll
-            for (int tt = 0; tt < TPW; ++tt)
-                for (int i = 0; i < 4; ++i) acc[tt][i] = c4[tt][i];
-        } else if constexpr (PREC == 1) {
-            f4 c4[TPW];
-#pragma unroll
-            for (int tt = 0; tt < TPW; ++tt) c4[tt] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int s = 0; s < NKS; ++s) {
-                float b = xs[cur][(4 * s + (lane >> 4)) * 16 + col];
-#pragma unroll
-                for (int tt = 0; tt < TPW; ++tt)
-                    c4[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(kreg[tt][s], b, c4[tt], 0, 0, 0);
-                if ((s % GROUP) == GROUP - 1) __builtin_amdgcn_sched_barrier(0);
-            }
-#pragma unroll
-            for (int tt = 0; tt < TPW; ++tt)
-                for (int i = 0; i < 4; ++i) acc[tt][i] = (double)c4[tt][i];
-        } else {
-            f4 c4[TPW];
-#pragma unroll
-            for (int tt = 0; tt < TPW; ++tt) c4[tt] = f4{0.f, 0.f, 0.f, 0.f};
-            const uint16_t *xrow = xs[cur] + col * Bf16Stride<NCP>::value + 8 * (lane >> 4);
-#pragma unroll
-            for (int s = 0; s < NKS; ++s) {
-                uint4 bv = *reinterpret_cast<const uint4 *>(xrow + 32 * s);
-                bf8 b = __builtin_bit_cast(bf8, bv);
-#pragma unroll
-                for (int tt = 0; tt < TPW; ++tt)
-                    c4[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, kreg[tt][s]), b, c4[tt], 0,
-                                                                    0, 0);
-                if ((s % GROUP) == GROUP - 1) __builtin_amdgcn_sched_barrier(0);
-            }
-#pragma unroll
-            for (int tt = 0; tt < TPW; ++tt)
-                for (int i = 0; i < 4; ++i) acc[tt][i] = (double)c4[tt][i];
-        }
-
-        // scatter with the recurrence epilogue (first writer: base - beta Y_{k-1}
-        // + contribution; later colours: running value + contribution)
-#pragma unroll
-        for (int tt = 0; tt < TPW; ++tt) {
-            const int t = wave + tt * W;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                int32_t I = oI[tt][i];
-                if (I < 0) continue;
-                int r = 16 * t + (PREC == 0 ? (lane >> 4) + 4 * i : 4 * (lane >> 4) + i);
-                double contrib = k.alpha * dsc[tb][r] * acc[tt][i];
-                k.Y[(int64_t)I * k.ldy + vec] = (o1[tt][i] - o2[tt][i]) + contrib;
-            }
-        }
-        if (has_next) store_x(pre, cur ^ 1);
-        __syncthreads();
-        cur ^= 1;
-        tb = tbn;
-    }
-}
-
-template <int P, int PREC, int W>
-static hipError_t launch_kreg_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
-    static int grid_cap = 0;
-    if (grid_cap == 0) {
-        int per_cu = 0, dev = 0, ncu = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(&step_kreg_kernel<P, PREC, W>), 64 * W, 0);
-        if (e != hipSuccess) return e;
-        e = hipGetDevice(&dev);
-        if (e != hipSuccess) return e;
-        e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e != hipSuccess) return e;
-        grid_cap = std::max(1, per_cu) * std::max(1, ncu);
-    }
-    for (int c2 = 0; c2 < m->ncol[2]; ++c2)
-        for (int c1 = 0; c1 < m->ncol[1]; ++c1)
-            for (int c0 = 0; c0 < m->ncol[0]; ++c0) {
-                int col[3] = {c0, c1, c2};
-                int64_t cells = 1;
-                for (int a = 0; a < 3; ++a) {
-                    const AxisInfo &ax = prm.ax[a];
-                    int cnt;
-                    if (col[a] == 2) cnt = 1;
-                    else {
-                        int limit = ax.ncol == 3 ? ax.ncell - 1 : ax.ncell;
-                        cnt = limit > col[a] ? (limit - col[a] + 1) / 2 : 0;
-                    }
-                    prm.col[a] = col[a];
-                    prm.cnt[a] = cnt;
-                    cells *= cnt;
-                }
-                if (cells == 0) continue;
-                int64_t items = cells * prm.nchunk;
-                int64_t grid = std::min<int64_t>(items, grid_cap);
-                hipLaunchKernelGGL((step_kreg_kernel<P, PREC, W>), dim3((unsigned)grid), dim3(64 * W), 0, s, prm,
-                                   items);
-                hipError_t e = hipGetLastError();
-                if (e != hipSuccess) return e;
-            }
-    return hipSuccess;
 }
 
 template <int P, int PREC>
@@ -1453,266 +1220,6 @@ static hipError_t launch_cells_p(StepParams prm, const fe_mesh *m, hipStream_t s
 }
 
 // ------------------------------------------------------------------------
-// Warp-specialised row-owner variant (p <= 4): persistent workgroups walk the
-// items (cell, G chunks of 16 vectors) of a colour with stride gridDim.x.  A
-// workgroup has NT compute waves (one 16-row tile of (1/2)K_c each) and NT
-// memory waves (the same rows, the same lane-to-output map as the row-owner
-// kernel).  In step j the compute waves multiply item j out of one LDS buffer
-// into an LDS accumulator buffer, while the memory waves write item j-1's
-// outputs from the other accumulator buffer and load and stage item j+1 into
-// the other D X buffer; one barrier ends the step.  The two roles never wait
-// on each other's memory operations (each wave's loads complete in its own
-// issue order), so HBM traffic overlaps the products.  Same arithmetic, in
-// the same order, as the other variants of the precision.
-template <int P, int PREC, int G> struct WsShape {
-    static constexpr int NCP = ((P + 1) * (P + 1) * (P + 1) + 31) / 32 * 32, NT = NCP / 16;
-    static constexpr int XS = RowLds<PREC, G, NCP>::XS;
-    static constexpr size_t xbytes = RowLds<PREC, G, NCP>::bytes;        // one D X buffer
-    static constexpr size_t abytes = (size_t)G * NCP * 16 * sizeof(double);  // one accumulator buffer
-    static constexpr size_t bytes = 2 * xbytes + 2 * abytes;
-};
-
-template <int P, int PREC, int G, int BK>
-__global__ __launch_bounds__((128 * WsShape<P, PREC, G>::NT)) void step_ws_kernel(StepParams k, int64_t nitems) {
-    constexpr int N1 = P + 1, NC = N1 * N1 * N1, NCP = (NC + 31) / 32 * 32, NT = NCP / 16;
-    constexpr int KSTEP = PrecTraits<PREC>::KSTEP, NKS = NCP / KSTEP;
-    typedef WsShape<P, PREC, G> S;
-    constexpr int XS = S::XS;
-    typedef typename PrecTraits<PREC>::T T;
-    typedef typename FragOf<PREC>::T FragT;
-    extern __shared__ __align__(16) unsigned char smem[];
-    // buffer b of each kind (b = item parity, a compile-time constant below)
-    auto xbuf = [&](int b) { return reinterpret_cast<T *>(smem + b * S::xbytes); };
-    auto abuf = [&](int b) { return reinterpret_cast<double *>(smem + 2 * S::xbytes + b * S::abytes); };
-
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const bool compute = wave < NT;
-    const int t = compute ? wave : wave - NT;  // the tile this wave works on
-    const int rl = PREC == 0 ? 4 * ((lane >> 2) & 3) + (lane >> 4) : (lane & 15);
-    const int vq = PREC == 0 ? 4 * (lane & 3) : 4 * (lane >> 4);
-    const int r = 16 * t + rl;  // the cell row this lane owns
-    const int ngroups = (k.nchunk + G - 1) / G;
-    const int64_t J = nitems > (int64_t)blockIdx.x ? (nitems - 1 - blockIdx.x) / gridDim.x + 1 : 0;
-
-    // memory-wave state: the owned row of the item being loaded / written
-    int Iw[2] = {-1, -1};   // DoF (by item parity)
-    double dw[2] = {0, 0};  // D factor
-    double bo[2][G][4];     // base term or old Y
-    int64_t vbase[2] = {0, 0};
-
-    auto item_of = [&](int64_t j) { return (int64_t)blockIdx.x + j * gridDim.x; };
-    // load item j's rows into registers and stage D X into xbuf(j & 1)
-    auto load_stage = [&](auto bc, int64_t j) {
-        constexpr int b = decltype(bc)::value;
-        const int64_t it = item_of(j);
-        const int grp = (int)(it % ngroups);
-        const ItemCell c = item_cell(k, (it / ngroups) * k.nchunk);
-        const int64_t v0 = (int64_t)grp * G * 16 + vq;
-        const NodeRef nr = node_ref<P>(k, c, r);
-        const bool fst = r < NC && node_first<P>(k, c, r);
-        const int64_t Ic = max(nr.I, 0);
-        const double *orow = !fst ? k.Y + Ic * k.ldy : (k.Ym1 ? k.Ym1 + Ic * k.ldm : k.X + Ic * k.ldx);
-        const double *xrow = k.X + Ic * k.ldx;
-        const double vraw = k.v[Ic];
-        double xv[G][4], ov[G][4];
-#pragma unroll
-        for (int g = 0; g < G; ++g)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t vc = min(v0 + 16 * g + q, k.N - 1);
-                xv[g][q] = xrow[vc];
-                ov[g][q] = orow[vc];
-            }
-        const bool useo = !fst || k.Ym1 != nullptr;
-        const double vI = (nr.I >= 0 && fst) ? vraw : 0.0;
-        const double sc = k.alpha * (vI - k.shift);
-        const double dn = node_scale(nr);
-        T *xs = xbuf(b);
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            double dx[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const bool ok = nr.I >= 0 && v0 + 16 * g + q < k.N;
-                const double x = ok ? xv[g][q] : 0.0;
-                const double o = (ok && useo) ? ov[g][q] : 0.0;
-                double base = sc * x;
-                if (k.Ym1) base -= k.beta * o;
-                bo[b][g][q] = fst ? base : o;
-                dx[q] = dn * x;
-            }
-            if constexpr (PREC == 0) {
-                double2 *dst = reinterpret_cast<double2 *>(xs + g * XS + r * 16 + vq);
-                dst[0] = double2{dx[0], dx[1]};
-                dst[1] = double2{dx[2], dx[3]};
-            } else if constexpr (PREC == 1) {
-                *reinterpret_cast<f4 *>(xs + g * XS + r * 16 + vq) =
-                    f4{(float)dx[0], (float)dx[1], (float)dx[2], (float)dx[3]};
-            } else {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) xs[g * XS + (vq + q) * Bf16Stride<NCP>::value + r] = to_bf16_bits(dx[q]);
-            }
-        }
-        Iw[b] = nr.I;
-        dw[b] = dn;
-        vbase[b] = v0;
-    };
-    // write the outputs of the item of parity b from abuf(b)
-    auto emit = [&](auto bc) {
-        constexpr int b = decltype(bc)::value;
-        if (Iw[b] < 0) return;
-        const double *ab = abuf(b);
-        double *yrow = k.Y + (int64_t)Iw[b] * k.ldy;
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const double2 *src = reinterpret_cast<const double2 *>(ab + (g * NCP + r) * 16 + vq);
-            const double2 u = src[0], w = src[1];
-            const double acc[4] = {u.x, u.y, w.x, w.y};
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t vec = vbase[b] + 16 * g + q;
-                if (vec < k.N) yrow[vec] = bo[b][g][q] + k.alpha * dw[b] * acc[q];
-            }
-        }
-    };
-    // multiply the item of parity b (compute waves): xbuf(b) -> abuf(b)
-    const FragT *A = reinterpret_cast<const FragT *>(k.A) + (size_t)t * NKS * 64 + lane;
-    constexpr int BKE = batch_size(NKS, BK), NB = NKS / BKE;
-    static_assert(NKS % BKE == 0, "k-steps must split into batches");
-    auto multiply = [&](auto bc) {
-        constexpr int b = decltype(bc)::value;
-        const T *xs = xbuf(b);
-        typedef typename std::conditional<PREC == 0, double, f4>::type AccT;
-        AccT cacc[G][PREC == 0 ? 4 : 1];
-#pragma unroll
-        for (int g = 0; g < G; ++g)
-#pragma unroll
-            for (int q = 0; q < (PREC == 0 ? 4 : 1); ++q) {
-                if constexpr (PREC == 0) cacc[g][q] = 0.0;
-                else cacc[g][q] = f4{0.f, 0.f, 0.f, 0.f};
-            }
-        auto mul_step = [&](const FragT a, int s) {
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                if constexpr (PREC == 0) {
-                    double bq[4];
-                    f64_quad_b(xs + g * XS, s, lane, bq);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) cacc[g][q] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, bq[q], cacc[g][q], 0, 0, 0);
-                } else if constexpr (PREC == 1) {
-                    const float bb = xs[g * XS + (4 * s + (lane >> 4)) * 16 + (lane & 15)];
-                    cacc[g][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(bb, a, cacc[g][0], 0, 0, 0);
-                } else {
-                    const uint16_t *xcol = xs + g * XS + (lane & 15) * Bf16Stride<NCP>::value + 8 * (lane >> 4);
-                    const bf8 bb = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4 *>(xcol + 32 * s));
-                    cacc[g][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bb, __builtin_bit_cast(bf8, a), cacc[g][0], 0, 0, 0);
-                }
-            }
-        };
-        auto load_batch = [&](FragT (&ab)[BKE], int sb) {
-#pragma unroll
-            for (int i = 0; i < BKE; ++i) ab[i] = A[(size_t)(sb * BKE + i) * 64];
-        };
-        FragT ab0[BKE], ab1[BKE];
-        load_batch(ab0, 0);
-constexpr int UNRB = NB <= 4 ? NB : 1;
-#pragma unroll UNRB
-        for (int sb = 0; sb < NB; sb += 2) {
-            if (sb + 1 < NB) load_batch(ab1, sb + 1);
-#pragma unroll
-            for (int i = 0; i < BKE; ++i) mul_step(ab0[i], sb * BKE + i);
-            if (sb + 1 < NB) {
-                if (sb + 2 < NB) load_batch(ab0, sb + 2);
-#pragma unroll
-                for (int i = 0; i < BKE; ++i) mul_step(ab1[i], (sb + 1) * BKE + i);
-            }
-        }
-        double *ab = abuf(b);
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            double acc[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if constexpr (PREC == 0) acc[q] = cacc[g][q];
-                else acc[q] = (double)cacc[g][0][q];
-            }
-            double2 *dst = reinterpret_cast<double2 *>(ab + (g * NCP + r) * 16 + vq);
-            dst[0] = double2{acc[0], acc[1]};
-            dst[1] = double2{acc[2], acc[3]};
-        }
-    };
-
-    // step j (buffer parity B = j & 1): compute waves multiply item j; memory
-    // waves write item j-1, then load and stage item j+1 (both of parity 1-B)
-    auto step = [&](auto bc, int64_t j) {
-        constexpr int B = decltype(bc)::value;
-        if (compute) {
-            if (j < J) multiply(bc);
-        } else {
-            if (j >= 1) emit(std::integral_constant<int, 1 - B>());
-            if (j + 1 < J) load_stage(std::integral_constant<int, 1 - B>(), j + 1);
-        }
-        __syncthreads();
-    };
-    if (J == 0) return;  // whole workgroup
-    if (!compute) load_stage(std::integral_constant<int, 0>(), 0);
-    __syncthreads();
-    for (int64_t j = 0; j <= J; j += 2) {
-        step(std::integral_constant<int, 0>(), j);
-        if (j + 1 <= J) step(std::integral_constant<int, 1>(), j + 1);
-    }
-}
-
-template <int P, int PREC, int G, int BK>
-static hipError_t launch_ws_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
-    typedef WsShape<P, PREC, G> S;
-    static bool attr = false;
-    static int resident = 0;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step_ws_kernel<P, PREC, G, BK>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::bytes);
-        if (e != hipSuccess) return e;
-        int per_cu = 0, dev = 0, cus = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(&step_ws_kernel<P, PREC, G, BK>), 128 * S::NT, S::bytes);
-        if (e != hipSuccess) return e;
-        e = hipGetDevice(&dev);
-        if (e != hipSuccess) return e;
-        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e != hipSuccess) return e;
-        resident = std::max(1, per_cu) * std::max(1, cus);
-        attr = true;
-    }
-    const int ngroups = (prm.nchunk + G - 1) / G;
-    for (int c2 = 0; c2 < m->ncol[2]; ++c2)
-        for (int c1 = 0; c1 < m->ncol[1]; ++c1)
-            for (int c0 = 0; c0 < m->ncol[0]; ++c0) {
-                int col[3] = {c0, c1, c2};
-                int64_t cells = 1;
-                for (int a = 0; a < 3; ++a) {
-                    const AxisInfo &ax = prm.ax[a];
-                    int cnt;
-                    if (col[a] == 2) cnt = 1;
-                    else {
-                        int limit = ax.ncol == 3 ? ax.ncell - 1 : ax.ncell;
-                        cnt = limit > col[a] ? (limit - col[a] + 1) / 2 : 0;
-                    }
-                    prm.col[a] = col[a];
-                    prm.cnt[a] = cnt;
-                    cells *= cnt;
-                }
-                if (cells == 0) continue;
-                const int64_t nitems = cells * ngroups;
-                const int64_t grid = std::min<int64_t>(nitems, resident);
-                hipLaunchKernelGGL((step_ws_kernel<P, PREC, G, BK>), dim3((unsigned)grid), dim3(128 * S::NT), S::bytes,
-                                   s, prm, nitems);
-                hipError_t e = hipGetLastError();
-                if (e != hipSuccess) return e;
-            }
-    return hipSuccess;
-}
-
-// ------------------------------------------------------------------------
 // Pipelined row-owner variant (p <= 4): persistent workgroups walk the items
 // (cell or z segment of cells, group of G chunks of 16 vectors) of a colour
 // with stride gridDim.x, one wave per 16-row tile of (1/2)K_c with the tile's
@@ -2218,273 +1725,6 @@ static hipError_t launch_pipe_p(StepParams prm, const fe_mesh *m, hipStream_t s)
     return hipSuccess;
 }
 
-// ------------------------------------------------------------------------
-// Tile variant: a workgroup owns a column of TXY x TXY cells in x-y and TZ
-// layers in z for one chunk of 16 vectors, with the cell matrix resident in
-// VGPRs.  It marches up the column, accumulating each cell's product rows in
-// an LDS ring of p+1 node planes (FP64), and emits a plane with the
-// recurrence epilogue once every cell touching it inside the tile is done.
-// Only nodes on tile boundaries are shared with other workgroups; tiles are
-// coloured per axis (as cells are in the other variants) and the first
-// colour to reach such a node writes the base term.  Inside a tile the
-// partial sums follow a fixed cell order, so results are reproducible run to
-// run (the association differs from the one-cell variants by rounding).
-struct TileParams {
-    StepParams k;
-    int tz;        // layers per tile (z)
-    int ntile[3];  // tiles per axis
-    int tcol[3];   // tile colour of this launch
-    int tcnt[3];   // tiles of this colour per axis
-    int tncol[3];  // tile colours per axis
-};
-
-__device__ __forceinline__ int tile_colour(int t, int nt, int ncol) { return (ncol == 3 && t == nt - 1) ? 2 : (t & 1); }
-
-// Neighbouring tile sharing a node at the tile's low (side = 0) or high
-// (side = 1) boundary, or -1.
-__device__ __forceinline__ int tile_neighbour(int t, int nt, int bc, int side) {
-    if (side == 0) return t > 0 ? t - 1 : (bc == FE_BC_PERIODIC ? nt - 1 : -1);
-    return t < nt - 1 ? t + 1 : (bc == FE_BC_PERIODIC ? 0 : -1);
-}
-
-template <int P, int PREC, int W, int TXY>
-__global__ __launch_bounds__(64 * W, (W <= 8 ? 4 : 1)) void step_tile_kernel(TileParams tp) {
-    const StepParams &k = tp.k;
-    constexpr int N1 = P + 1, NC = N1 * N1 * N1, NCP = (NC + 31) / 32 * 32, NT = NCP / 16;
-    constexpr int KSTEP = PrecTraits<PREC>::KSTEP, NKS = NCP / KSTEP;
-    constexpr int NTHR = 64 * W, TPW = NT / W, EPT = NCP * 16 / NTHR;
-    constexpr int CW = TXY * P + 1;  // closure width (nodes) in x and y
-    static_assert(NT % W == 0, "row tiles must divide evenly among waves");
-    static_assert((NCP * 16) % NTHR == 0, "staging must divide evenly among threads");
-    typedef typename PrecTraits<PREC>::T T;
-    typedef typename FragOf<PREC>::T FragT;
-    constexpr int XS = PREC == 2 ? 16 * Bf16Stride<NCP>::value : NCP * 16;
-    __shared__ __align__(16) T xs[XS];
-    __shared__ double ring[N1 * CW * CW * 16];
-
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15;
-
-    FragT kreg[TPW][NKS];
-    {
-        const FragT *A = reinterpret_cast<const FragT *>(k.A);
-#pragma unroll
-        for (int tt = 0; tt < TPW; ++tt)
-#pragma unroll
-            for (int s = 0; s < NKS; ++s) kreg[tt][s] = A[((size_t)(wave + tt * W) * NKS + s) * 64 + lane];
-    }
-
-    // which tile and chunk
-    const int chunk = blockIdx.x % k.nchunk;
-    int tix = blockIdx.x / k.nchunk;
-    int tc[3];
-    for (int a = 0; a < 3; ++a) {
-        int i = tix % tp.tcnt[a];
-        tix /= tp.tcnt[a];
-        tc[a] = tp.tcol[a] == 2 ? tp.ntile[a] - 1 : tp.tcol[a] + 2 * i;
-    }
-    const int c0x = tc[0] * TXY, c0y = tc[1] * TXY, c0z = tc[2] * tp.tz;
-    const int ncx = min(TXY, k.ax[0].ncell - c0x), ncy = min(TXY, k.ax[1].ncell - c0y);
-    const int ncz = min(tp.tz, k.ax[2].ncell - c0z);
-    const int64_t vec0 = (int64_t)chunk * 16;
-
-    for (int e = tid; e < N1 * CW * CW * 16; e += NTHR) ring[e] = 0.0;
-
-    auto load_x = [&](int cell, double (&pre)[EPT]) {
-        ItemCell c;
-        c.cx = c0x + cell % ncx;
-        c.cy = c0y + (cell / ncx) % ncy;
-        c.cz = c0z + cell / (ncx * ncy);
-#pragma unroll
-        for (int q = 0; q < EPT; ++q) {
-            int e = tid + q * NTHR;
-            int l = e >> 4, cc = e & 15;
-            double x = 0.0;
-            if (l < NC && vec0 + cc < k.N) {
-                double d;
-                int I = node_dof<P>(k, c, l, d);
-                if (I >= 0) x = d * k.X[(int64_t)I * k.ldx + vec0 + cc];
-            }
-            pre[q] = x;
-        }
-    };
-    auto store_x = [&](const double (&pre)[EPT]) {
-#pragma unroll
-        for (int q = 0; q < EPT; ++q) {
-            int e = tid + q * NTHR;
-            if constexpr (PREC == 0) xs[e] = pre[q];
-            else if constexpr (PREC == 1) xs[e] = (float)pre[q];
-            else xs[(e & 15) * Bf16Stride<NCP>::value + (e >> 4)] = to_bf16_bits(pre[q]);
-        }
-    };
-    // emit one completed plane (local z index gzl) of the tile closure
-    auto emit_plane = [&](int gzl) {
-        const int slot = gzl % N1;
-        const int gz = c0z * P + gzl;
-        const int tzv = axis_free_index32(k.ax[2], P, gz);
-        const int zside = gzl == 0 ? 0 : (gzl == ncz * P ? 1 : -1);
-        for (int e = tid; e < CW * CW * 16; e += NTHR) {
-            const int cc = e & 15, node = e >> 4;
-            const int a = node % CW, b = node / CW;
-            double *rp = &ring[(slot * CW * CW + node) * 16 + cc];
-            if (a > ncx * P || b > ncy * P) continue;
-            const double acc = *rp;
-            *rp = 0.0;
-            const int64_t v = vec0 + cc;
-            if (tzv < 0 || v >= k.N) continue;
-            const int tx = axis_free_index32(k.ax[0], P, c0x * P + a);
-            const int ty = axis_free_index32(k.ax[1], P, c0y * P + b);
-            if (tx < 0 || ty < 0) continue;
-            // first writer among the tiles sharing this node?
-            bool first = true;
-            const int side[3] = {a == 0 ? 0 : (a == ncx * P ? 1 : -1), b == 0 ? 0 : (b == ncy * P ? 1 : -1), zside};
-            for (int ax = 0; ax < 3; ++ax) {
-                if (side[ax] < 0) continue;
-                int nb = tile_neighbour(tc[ax], tp.ntile[ax], k.ax[ax].bc, side[ax]);
-                if (nb >= 0 && tile_colour(nb, tp.ntile[ax], tp.tncol[ax]) <
-                                   tile_colour(tc[ax], tp.ntile[ax], tp.tncol[ax]))
-                    first = false;
-            }
-            const int I = tx + (int)k.nfx * (ty + (int)k.nfy * tzv);
-            const double d = k.axisD[tx] * k.axisD[k.maxf + ty] * k.axisD[2 * k.maxf + tzv];
-            double *y = k.Y + (int64_t)I * k.ldy + v;
-            const double contrib = k.alpha * d * acc;
-            if (first) {
-                double base = k.alpha * (k.v[I] - k.shift) * k.X[(int64_t)I * k.ldx + v];
-                if (k.Ym1) base -= k.beta * k.Ym1[(int64_t)I * k.ldm + v];
-                *y = base + contrib;
-            } else {
-                *y += contrib;
-            }
-        }
-    };
-
-    const int ncell_t = ncx * ncy * ncz;
-    {
-        double pre[EPT];
-        load_x(0, pre);
-        store_x(pre);
-    }
-    __syncthreads();
-    constexpr int GROUP = PREC == 2 ? 2 : 4;
-    for (int cell = 0; cell < ncell_t; ++cell) {
-        const bool has_next = cell + 1 < ncell_t;
-        double pre[EPT];
-        if (has_next) load_x(cell + 1, pre);
-
-        double acc[TPW][4];
-        if constexpr (PREC == 0) {
-            d4 c4[TPW];
-#pragma unroll
-            for (int tt = 0; tt < TPW; ++tt) c4[tt] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int s = 0; s < NKS; ++s) {
-                double b = xs[(4 * s + (lane >> 4)) * 16 + col];
-#pragma unroll
-                for (int tt = 0; tt < TPW; ++tt)
-                    c4[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(kreg[tt][s], b, c4[tt], 0, 0, 0);
-                if ((s % GROUP) == GROUP - 1) __builtin_amdgcn_sched_barrier(0);
-            }
-#pragma unroll
-            for (int tt = 0; tt < TPW; ++tt)
-                for (int i = 0; i < 4; ++i) acc[tt][i] = c4[tt][i];
-        } else if constexpr (PREC == 1) {
-            f4 c4[TPW];
-#pragma unroll
-            for (int tt = 0; tt < TPW; ++tt) c4[tt] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int s = 0; s < NKS; ++s) {
-                float b = xs[(4 * s + (lane >> 4)) * 16 + col];
-#pragma unroll
-                for (int tt = 0; tt < TPW; ++tt)
-                    c4[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(kreg[tt][s], b, c4[tt], 0, 0, 0);
-                if ((s % GROUP) == GROUP - 1) __builtin_amdgcn_sched_barrier(0);
-            }
-#pragma unroll
-            for (int tt = 0; tt < TPW; ++tt)
-                for (int i = 0; i < 4; ++i) acc[tt][i] = (double)c4[tt][i];
-        } else {
-            f4 c4[TPW];
-#pragma unroll
-            for (int tt = 0; tt < TPW; ++tt) c4[tt] = f4{0.f, 0.f, 0.f, 0.f};
-            const uint16_t *xrow = xs + col * Bf16Stride<NCP>::value + 8 * (lane >> 4);
-#pragma unroll
-            for (int s = 0; s < NKS; ++s) {
-                bf8 b = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4 *>(xrow + 32 * s));
-#pragma unroll
-                for (int tt = 0; tt < TPW; ++tt)
-                    c4[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, kreg[tt][s]), b, c4[tt], 0,
-                                                                    0, 0);
-                if ((s % GROUP) == GROUP - 1) __builtin_amdgcn_sched_barrier(0);
-            }
-#pragma unroll
-            for (int tt = 0; tt < TPW; ++tt)
-                for (int i = 0; i < 4; ++i) acc[tt][i] = (double)c4[tt][i];
-        }
-
-        // accumulate the rows into the ring (cells in a fixed order)
-        const int cxl = cell % ncx, cyl = (cell / ncx) % ncy, lz = cell / (ncx * ncy);
-#pragma unroll
-        for (int tt = 0; tt < TPW; ++tt) {
-            const int t = wave + tt * W;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                int r = 16 * t + (PREC == 0 ? (lane >> 4) + 4 * i : 4 * (lane >> 4) + i);
-                if (r >= NC) continue;
-                int li = r % N1, lj = (r / N1) % N1, lk = r / (N1 * N1);
-                int slot = (lz * P + lk) % N1;
-                int node = (cyl * P + lj) * CW + cxl * P + li;
-                ring[(slot * CW * CW + node) * 16 + col] += acc[tt][i];
-            }
-        }
-        __syncthreads();  // products of this cell are in the ring; xs is free
-        if (has_next) store_x(pre);
-        const bool layer_done = (cell + 1) % (ncx * ncy) == 0;
-        if (layer_done) {
-            // planes lz*P .. lz*P + P-1 are complete (and the top plane after the last layer)
-            for (int kz = 0; kz < P; ++kz) emit_plane(lz * P + kz);
-            if (lz == ncz - 1) emit_plane(ncz * P);
-        }
-        __syncthreads();
-    }
-}
-
-template <int P, int PREC, int W, int TXY>
-static hipError_t launch_tile_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
-    TileParams tp;
-    tp.k = prm;
-    tp.tz = 8;
-    const int tl[3] = {TXY, TXY, tp.tz};
-    for (int a = 0; a < 3; ++a) {
-        tp.ntile[a] = (m->ncell[a] + tl[a] - 1) / tl[a];
-        // a periodic axis needs two tiles (a tile may not wrap onto itself)
-        if (m->bc[a] == FE_BC_PERIODIC && tp.ntile[a] < 2) return hipErrorNotSupported;
-        tp.tncol[a] = (m->bc[a] == FE_BC_PERIODIC && (tp.ntile[a] & 1)) ? 3 : (tp.ntile[a] >= 2 ? 2 : 1);
-    }
-    for (int c2 = 0; c2 < tp.tncol[2]; ++c2)
-        for (int c1 = 0; c1 < tp.tncol[1]; ++c1)
-            for (int c0 = 0; c0 < tp.tncol[0]; ++c0) {
-                int col[3] = {c0, c1, c2};
-                int64_t tiles = 1;
-                for (int a = 0; a < 3; ++a) {
-                    int cnt;
-                    if (col[a] == 2) cnt = 1;
-                    else {
-                        int limit = tp.tncol[a] == 3 ? tp.ntile[a] - 1 : tp.ntile[a];
-                        cnt = limit > col[a] ? (limit - col[a] + 1) / 2 : 0;
-                    }
-                    tp.tcol[a] = col[a];
-                    tp.tcnt[a] = cnt;
-                    tiles *= cnt;
-                }
-                if (tiles == 0) continue;
-                hipLaunchKernelGGL((step_tile_kernel<P, PREC, W, TXY>), dim3((unsigned)(tiles * prm.nchunk)),
-                                   dim3(64 * W), 0, s, tp);
-                hipError_t e = hipGetLastError();
-                if (e != hipSuccess) return e;
-            }
-    return hipSuccess;
-}
-
 size_t assembled_scratch_doubles(const fe_mesh *m) {
     return m->p <= 5 ? (size_t)m->ncells * (size_t)padded_nc(m->p) : 0;
 }
@@ -2562,22 +1802,6 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
         default: return hipErrorInvalidValue;
         }
     }
-    if (m->kernel_variant == 5) {
-        hipError_t e = hipErrorNotSupported;
-        switch (m->p * 3 + (int)prec) {
-        case 3 * 3 + 0: e = launch_tile_p<3, 0, 4, 2>(prm, m, s); break;
-        case 4 * 3 + 0: e = launch_tile_p<4, 0, 8, 2>(prm, m, s); break;
-        case 3 * 3 + 1: e = launch_tile_p<3, 1, 4, 2>(prm, m, s); break;
-        case 4 * 3 + 1: e = launch_tile_p<4, 1, 8, 2>(prm, m, s); break;
-        case 5 * 3 + 1: e = launch_tile_p<5, 1, 14, 1>(prm, m, s); break;
-        case 3 * 3 + 2: e = launch_tile_p<3, 2, 4, 2>(prm, m, s); break;
-        case 4 * 3 + 2: e = launch_tile_p<4, 2, 8, 2>(prm, m, s); break;
-        case 5 * 3 + 2: e = launch_tile_p<5, 2, 14, 1>(prm, m, s); break;
-        default: break;
-        }
-        if (e != hipErrorNotSupported) return e;
-        // otherwise: the multi-chunk kernel below
-    }
     if (m->kernel_variant == 0 && prec == FE_F64 && prm.N == 1 && m->p <= 5) {
         switch (m->p) {
         case 1: return launch_cells_p<1>(prm, m, s);
@@ -2587,21 +1811,6 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
         case 5: return launch_cells_p<5>(prm, m, s);
         default: break;
         }
-    }
-    if (m->kernel_variant == 8) {
-#define FE_WS(PP)                                                                    \
-    case PP:                                                                         \
-        if (prec == FE_F64) return launch_ws_p<PP, 0, 2, 4>(prm, m, s);              \
-        if (prec == FE_F32) return launch_ws_p<PP, 1, 2, 4>(prm, m, s);              \
-        return launch_ws_p<PP, 2, 2, 4>(prm, m, s);
-        switch (m->p) {
-            FE_WS(1)
-            FE_WS(2)
-            FE_WS(3)
-            FE_WS(4)
-        default: break;
-        }
-#undef FE_WS
     }
     // the pipelined kernel walking z segments is the default at p = 4 for all
     // three product precisions, where it was measured fastest (FP64 5.7-6.0
@@ -2639,7 +1848,7 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
         }
 #undef FE_ZSEG
     }
-    if ((m->kernel_variant == 0 && prec == FE_F64) || m->kernel_variant == 6 || m->kernel_variant == 8 ||
+    if ((m->kernel_variant == 0 && prec == FE_F64) || m->kernel_variant == 6 ||
         ((m->kernel_variant == 7 || m->kernel_variant == 9) && prec == FE_F64)) {
         // 32 vectors per workgroup and one row tile per wave measured best
         // where the tiles fit one workgroup (p <= 5); above that two tiles
@@ -2666,7 +1875,7 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
     // multi-chunk kernel with the chunk count measured best for the precision
     // (bf16 with p >= 6 is fastest with one chunk per workgroup)
     if ((m->kernel_variant == 0 && !(prec == FE_BF16 && m->p >= 6)) || m->kernel_variant == 3 ||
-        m->kernel_variant == 4 || m->kernel_variant >= 5) {
+        m->kernel_variant == 4 || m->kernel_variant == 7 || m->kernel_variant == 9) {
         const int G = m->kernel_variant == 4 ? 4 : m->kernel_variant == 3 ? 2 : (prec == FE_BF16 ? 4 : 2);
 #define FE_MC(PP)                                                                                   \
     case PP:                                                                                        \
@@ -2684,27 +1893,6 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
         default: break;
         }
 #undef FE_MC
-    }
-    if (m->kernel_variant == 2) {
-        // register-resident cell matrix where it fits in the VGPR file
-        switch (m->p * 3 + (int)prec) {
-        case 1 * 3 + 0: return launch_kreg_p<1, 0, 2>(prm, m, s);
-        case 2 * 3 + 0: return launch_kreg_p<2, 0, 2>(prm, m, s);
-        case 3 * 3 + 0: return launch_kreg_p<3, 0, 4>(prm, m, s);
-        case 4 * 3 + 0: return launch_kreg_p<4, 0, 8>(prm, m, s);
-        case 1 * 3 + 1: return launch_kreg_p<1, 1, 2>(prm, m, s);
-        case 2 * 3 + 1: return launch_kreg_p<2, 1, 2>(prm, m, s);
-        case 3 * 3 + 1: return launch_kreg_p<3, 1, 4>(prm, m, s);
-        case 4 * 3 + 1: return launch_kreg_p<4, 1, 8>(prm, m, s);
-        case 5 * 3 + 1: return launch_kreg_p<5, 1, 14>(prm, m, s);
-        case 1 * 3 + 2: return launch_kreg_p<1, 2, 2>(prm, m, s);
-        case 2 * 3 + 2: return launch_kreg_p<2, 2, 2>(prm, m, s);
-        case 3 * 3 + 2: return launch_kreg_p<3, 2, 4>(prm, m, s);
-        case 4 * 3 + 2: return launch_kreg_p<4, 2, 8>(prm, m, s);
-        case 5 * 3 + 2: return launch_kreg_p<5, 2, 14>(prm, m, s);
-        case 6 * 3 + 2: return launch_kreg_p<6, 2, 11>(prm, m, s);
-        default: break;
-        }
     }
 #define FE_DISPATCH(PP)                                                        \
     case PP:                                                                   \

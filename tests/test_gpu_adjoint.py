@@ -119,3 +119,31 @@ def test_vjp_work_size_errors():
     assert e.value.status == fe.FE_ENOMEM
     assert gm.vjp_work_bytes(8, 4, 1, 0) == (3 + 3) * op.n * 8 * 8 + op.n * 8
     assert gm.vjp_work_bytes(8, 20, 5, 4) == (2 * 4 + 5 + 3) * op.n * 4 * 8 + op.n * 8
+
+
+def test_autograd_float_E_and_flat_potential():
+    """The autograd function accepts E as a plain number (no gradient for it)
+    and V_quad in any shape set_potential accepts (here flat); dL/dV comes
+    back in V's own shape and equals the 2-D form's."""
+    import paper_2504_00998_amd as fe
+    wl = W.small_slab((2, 3, 3), p=3, N=8, m=5)
+    op, gm, Vq = _setup(wl)
+    X = torch.from_numpy(wl.X(op.n)).cuda()
+    w = torch.from_numpy(wl.weights()).cuda()
+    a0, b, _ = O.lanczos_bounds(op.apply, wl.lanczos_start(op.n), 10)
+    a = O.weyl_cut(a0, b, wl.N, op.n)
+    grads = []
+    for shape in ((-1,), Vq.shape):
+        V = torch.from_numpy(Vq.reshape(shape)).cuda().requires_grad_(True)
+        Xr = X.clone().requires_grad_(True)
+        Y = fe.cheb_filter(Xr, V, float(wl.E), gm, wl.m, a, b, a0, z0=wl.z0)
+        (w * (Xr * Y).sum(0)).sum().backward()
+        assert V.grad.shape == V.shape
+        grads.append((V.grad.reshape(-1).clone(), Xr.grad.clone()))
+    assert torch.equal(grads[0][0], grads[1][0]) and torch.equal(grads[0][1], grads[1][1])
+    # the Function itself, in the argument order of the binding's docstring
+    V = torch.from_numpy(Vq).cuda().requires_grad_(True)
+    E = torch.tensor(wl.E, dtype=torch.float64, device="cuda", requires_grad=True)
+    Y = fe.ChebFilter.apply(X, V, E, gm, wl.m, a, b, a0, "f64", wl.z0)
+    Y.sum().backward()
+    assert E.grad is not None and V.grad.shape == V.shape

@@ -115,3 +115,43 @@ def test_fullsize_bloch_sampled_rows_and_gamma():
     del Yr
     Yi = gm.cheb_filter(X.imag.contiguous(), wl.m, 5.66, 315.0, 4.8)
     assert torch.equal(Yk.imag, Yi)
+
+
+def _oracle_ritz():
+    """Bounds and Ritz values of the oracle's 5-iteration subspace iteration on
+    the cfg-3 block (tests/golden/cfg3_ritz_oracle.txt, written by
+    make_cfg3_ritz.py from the CPU oracle alone)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg3_ritz_oracle.txt")
+    bounds, hist = None, {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        t = line.split()
+        if t[0] == "bounds":
+            bounds = tuple(float(x) for x in t[1:4])  # a0, b, a
+        else:
+            hist.setdefault(int(t[0]), []).append((int(t[1]), float(t[2])))
+    return bounds, [np.array([v for _, v in sorted(hist[k])]) for k in sorted(hist)]
+
+
+def test_cfg3_fp64_ritz_values_match_oracle():
+    """The device's FP64 subspace iteration at the benchmark's size (p = 4
+    slab, N = 256, degree 30, 5 iterations, cfg-3 seeds) against the
+    oracle's, both from the same start block and the oracle's Lanczos
+    bounds, each updating its own cut: every Ritz value of every iteration
+    within 1e-9 Ha (the mixed-precision bar is 1e-7 Ha)."""
+    import paper_2504_00998_amd as fe
+    from paper_2504_00998_amd import solver
+    (a0, b, a), ref = _oracle_ritz()
+    wl = W.CFG3
+    gm = fe.Mesh.from_workload(wl)
+    Vq = W.workload_potential(wl, gm.quad_points())
+    gm.set_potential(torch.from_numpy(Vq).cuda(), wl.E, wl.z0)
+    X0 = torch.from_numpy(wl.X(gm.n)).cuda()
+    print(f"case: cfg3 FP64 subspace iteration, bounds a0={a0} a={a} b={b}", flush=True)
+    hist, _ = solver.subspace_iteration(gm, X0, wl.m, len(ref), a, b, a0, prec="f64")
+    for t, (h, r) in enumerate(zip(hist, ref)):
+        err = np.abs(h - r).max()
+        print(f"iteration {t + 1}: max |Ritz - oracle| = {err:.3e} Ha", flush=True)
+        assert err < 1e-9, (t, err)

@@ -164,3 +164,45 @@ def test_cfg4_autograd_fullsize():
             an = (X.grad * dXt).sum().item() + (V.grad * dVt).sum().item() + E.grad.item() * dE
             print(f"cfg4 FD direction {t}: fd {fd:.12e} adjoint {an:.12e}", flush=True)
             assert abs(fd - an) < 1e-6 * max(1.0, abs(an))
+
+
+CFG4_COLS = [0, 41, 90, 127]
+
+
+def test_cfg4_fullsize_against_oracle():
+    """cfg4 at its full size and launch configuration (p = 6, 16x16x32
+    cells, 1,760,256 DoFs, N = 128, degree 20, FP64, default kernel) against
+    the oracle: sampled rows of one H~X (summed from their own cell
+    contributions), then the degree-20 scaled filter of the whole block on
+    the device against the oracle's CSR filter of four of its columns, with
+    the oracle's 10-step Lanczos bounds passed to both sides."""
+    import paper_2504_00998_amd as fe
+    wl = W.CFG4
+    om = O.Mesh.from_workload(wl)
+    Vq = W.workload_potential(wl, om.quad_points())
+    gm = fe.Mesh.from_workload(wl)
+    assert gm.n == om.n
+    gm.set_potential(torch.from_numpy(Vq).cuda(), wl.E, wl.z0)
+    Xh = wl.X(om.n)
+    X = torch.from_numpy(Xh).cuda()
+    print(f"case: cfg4 full size hx rows, n={om.n} N={wl.N}", flush=True)
+    rng = np.random.default_rng(41)
+    rows = np.unique(np.concatenate([rng.choice(om.n, 40, replace=False), np.arange(0, 4),
+                                     np.arange(om.n - 4, om.n), [96, 96 * 96 - 1, 96 * 96 * 95]]))
+    R = O.apply_rows(om, Vq, wl.E, wl.z0, rows, Xh)
+    Ys = gm.hx(X)[torch.from_numpy(rows).cuda()].cpu().numpy()
+    err = (np.linalg.norm(Ys - R, axis=0) / np.linalg.norm(R, axis=0)).max()
+    print(f"cfg4 hx: rel err on {rows.size} rows x {wl.N} cols = {err:.3e}", flush=True)
+    assert err < 1e-13
+    op = O.Operator(om, Vq, wl.E, wl.z0)
+    a0, b, _ = O.lanczos_bounds(op.apply, wl.lanczos_start(op.n), 10)
+    a = O.weyl_cut(a0, b, wl.N, op.n)
+    print(f"case: cfg4 full size filter m={wl.m}, bounds a0={a0:.6f} a={a:.6f} b={b:.6f}", flush=True)
+    Rf = op.filter(np.ascontiguousarray(Xh[:, CFG4_COLS]), wl.m, a, b, a0)
+    del op
+    Y = gm.cheb_filter(X, wl.m, a, b, a0)[:, CFG4_COLS].cpu().numpy()
+    errf = np.linalg.norm(Y - Rf, axis=0) / np.linalg.norm(Rf, axis=0)
+    print("cfg4 filter per-vector rel err", errf, flush=True)
+    assert errf.max() < 1e-12
+    del X
+    torch.cuda.empty_cache()

@@ -46,3 +46,19 @@ def test_subspace_iteration_mixed_precision_ritz_error(slab, prec):
     print(f"{prec}: max |Ritz - FP64 oracle| all {err_all:.3e} lowest half {err_low:.3e} Ha", flush=True)
     if prec == "f32":
         assert err_low < 1e-7
+
+
+def test_rayleigh_ritz_refuses_aliased_blocks(slab):
+    """fe_rayleigh_ritz writes X = Q W at the end: an X (or P) that shares
+    memory with Q would be overwritten while still read, so the library
+    refuses overlapping blocks."""
+    import paper_2504_00998_amd as fe
+    wl, op, gm, _, _ = slab
+    Q = torch.from_numpy(wl.X(op.n)).cuda()
+    gm.cholqr2(Q)
+    P = torch.empty_like(Q)
+    for X, Pp in ((Q, P), (P, P), (torch.empty_like(Q), Q)):
+        with pytest.raises(RuntimeError, match="overlap"):
+            gm.rayleigh_ritz(Q, X=X, P=Pp)
+    theta, _ = gm.rayleigh_ritz(Q, X=torch.empty_like(Q), P=P)
+    assert np.all(np.diff(theta) >= 0)

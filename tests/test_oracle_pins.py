@@ -519,6 +519,85 @@ def test_nonlocal_term_symmetric_and_reduces():
     np.testing.assert_allclose(col, raw, atol=1e-14)
 
 
+def _real_solid_harmonic(l, mm, d):
+    """r^l times the real spherical harmonic of degree l and order mm at the
+    displacements d (k, 3), from scipy's complex Y_l^m (polar angle theta,
+    azimuth phi): Y_l^0; sqrt(2) (-1)^m Re Y_l^m for m > 0; sqrt(2) (-1)^m
+    Im Y_l^|m| for m < 0.  An independent route to the angular factors (no
+    Cartesian polynomial is written out)."""
+    from scipy.special import sph_harm_y
+    r = np.sqrt((d ** 2).sum(axis=1))
+    theta = np.arccos(np.clip(d[:, 2] / np.where(r > 0, r, 1.0), -1.0, 1.0))
+    phi = np.arctan2(d[:, 1], d[:, 0])
+    Y = sph_harm_y(l, abs(mm), theta, phi)
+    if mm == 0:
+        re = Y.real
+    elif mm > 0:
+        re = np.sqrt(2.0) * (-1) ** mm * Y.real
+    else:
+        re = np.sqrt(2.0) * (-1) ** mm * Y.imag
+    return r ** l * re
+
+
+# projector beta -> (l, m) of the real harmonic: s; p_x, p_y, p_z; d_xy, d_yz,
+# d_zx, d_{x^2-y^2}, d_{3z^2-r^2} (the order the projector columns take)
+_BETA_LM = [(0, 0), (1, 1), (1, -1), (1, 0), (2, -2), (2, -1), (2, 1), (2, 2), (2, 0)]
+
+
+def test_projector_angular_factors_are_real_solid_harmonics():
+    """Pin of all nine projector shapes (Sec. 2.1, Eq. V_nloc; s, p and d
+    channels): column (s, beta) of C~ equals M^1/2 p with p = r^l Y_lm(x - R)
+    exp(-r^2 / 2 r_g^2) [r < r_cut], the real harmonic taken from scipy,
+    normalised to unit discrete M-norm -- up to the sign convention of the
+    harmonic, which the normalisation leaves free.  The sites sit at generic
+    points, one of them with a ball wrapping through the periodic x face, so
+    no two channels coincide on the node set and a permuted or mistyped
+    channel (yz for zx, z^2 - r^2 for 3z^2 - r^2) misses by O(1)."""
+    m = _mesh((6.0, 5.0, 7.0), (6, 5, 7), 3, (1, 1, 0))
+    cen = np.array([[2.37, 2.61, 3.43], [0.31, 4.12, 3.77]])
+    P = O.Projectors(m, cen, 2.0, 0.5)
+    Cm = P.to_scipy().toarray()
+    M = m.mass()
+    xyz = m.dof_coords()
+    for s in range(cen.shape[0]):
+        d = xyz - cen[s]
+        for a in range(2):
+            d[:, a] -= m.L[a] * np.round(d[:, a] / m.L[a])
+        r2 = (d ** 2).sum(axis=1)
+        inside = r2 < 4.0
+        rad = np.exp(-r2 / (2 * 0.5 ** 2))
+        for beta, (l, mm) in enumerate(_BETA_LM):
+            ref = np.where(inside, _real_solid_harmonic(l, mm, d) * rad, 0.0)
+            ref = ref / np.sqrt((M * ref ** 2).sum()) * np.sqrt(M)
+            col = Cm[:, 9 * s + beta]
+            sign = np.sign(col @ ref)
+            assert sign != 0
+            err = np.abs(col - sign * ref).max()
+            assert err < 1e-12, (s, beta, err)
+            # and it is far from every other channel's shape
+            for b2, (l2, m2) in enumerate(_BETA_LM):
+                if b2 == beta:
+                    continue
+                o = np.where(inside, _real_solid_harmonic(l2, m2, d) * rad, 0.0)
+                o = o / np.sqrt((M * o ** 2).sum()) * np.sqrt(M)
+                assert min(np.abs(col - o).max(), np.abs(col + o).max()) > 1e-2, (s, beta, b2)
+
+
+def test_projector_gram_is_diagonal_at_a_cubic_site():
+    """At a site on a mesh node whose neighbourhood has the full symmetry of
+    the cube (interior cell corner, cubic cells, GLL nodes symmetric in each
+    cell), the discrete Gram C~^T C~ = sum_I M_I p_a p_b of one site is the
+    identity: the nine real harmonics lie in different rows of the cube
+    group's representations (A1g; T1u; T2g; Eg), so every cross term sums to
+    zero over the symmetric node set, and the diagonal is 1 by the
+    normalisation.  A duplicated or mixed channel breaks the zeros."""
+    m = _mesh((8.0, 8.0, 8.0), (4, 4, 4), 4, (0, 0, 0))
+    cen = np.array([[4.0, 4.0, 4.0]])
+    Cm = O.Projectors(m, cen, 2.0, 0.5).to_scipy().toarray()
+    G = Cm.T @ Cm
+    np.testing.assert_allclose(G, np.eye(9), atol=1e-13)
+
+
 def test_separable_wells_equal_pointwise_sum():
     """The tensor-grid evaluation of the Gaussian wells equals the pointwise
     minimum-image sum (input recipe, both periodic and bounded axes)."""
