@@ -158,6 +158,22 @@ fe_status fe_set_nonlocal(fe_mesh *mesh, int32_t n_site, const double *centres_h
 fe_status fe_hx_apply(fe_mesh *mesh, const double *X, double *Y, int64_t N, int64_t ld, fe_dtype prec,
                       hipStream_t stream);
 
+/* Y = H~ X exactly as fe_hx_apply (same kernels, same results bit for bit),
+ * for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The only
+ * scratch of H~X, the nonlocal projections W = diag(D) C~^T X (9 * n_site * N
+ * doubles, needed when fe_set_nonlocal has set sites), lives in a static
+ * device array of 4,194,304 doubles (32 MiB) per device, instead of the
+ * mesh's buffer that fe_hx_apply grows with hipMalloc / hipFree (hipFree
+ * synchronises the device).  This call allocates and frees nothing.  Every
+ * call on one device shares that array: calls that overlap on a device (on
+ * concurrent streams or threads) race and must be serialised by the caller.
+ * Errors as for fe_hx_apply, plus FE_ENOMEM (nothing enqueued) when
+ * 9 * n_site * N exceeds 4,194,304, and FE_EDEVICE if the array's device
+ * address could not be resolved when the mesh was created. */
+fe_status fe_hx_apply_noalloc(fe_mesh *mesh, const double *X, double *Y, int64_t N, int64_t ld, fe_dtype prec,
+                              hipStream_t stream);
+
 /* Chebyshev filter of degree m on the unwanted interval [a, b]
  * (e = (b-a)/2, c = (b+a)/2), by the three-term recurrence
  *   Y_1 = alpha_0 (H~ - c) X,   Y_{k+1} = alpha_k (H~ - c) Y_k - beta_k Y_{k-1}.

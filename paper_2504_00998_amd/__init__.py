@@ -64,6 +64,7 @@ def lib() -> C.CDLL:
         "fe_set_potential": ([vp, vp, dbl, dbl, vp], C.c_int),
         "fe_set_nonlocal": ([vp, i32, vp, vp, dbl, dbl, vp], C.c_int),
         "fe_hx_apply": ([vp, vp, vp, i64, i64, C.c_int, vp], C.c_int),
+        "fe_hx_apply_noalloc": ([vp, vp, vp, i64, i64, C.c_int, vp], C.c_int),
         "fe_cheb_filter": ([vp, vp, vp, i64, i64, i32, dbl, dbl, dbl, C.c_int, vp, C.c_size_t, vp], C.c_int),
         "fe_cheb_filter_vjp_work_bytes": ([vp, i64, i32, i32, i32], C.c_size_t),
         "fe_cheb_filter_vjp": ([vp, vp, vp, i64, i64, i32, dbl, dbl, dbl, C.c_int, vp, vp, vp, i32, i32, vp,
@@ -221,6 +222,17 @@ class Mesh:
         if Y.shape[1] != N or Y.stride(0) != ld:
             raise ValueError("Y must have X's shape and leading dimension")
         _check(lib().fe_hx_apply(self._h, _ptr(X), _ptr(Y), N, ld, _PREC[prec], _stream(stream)))
+        return Y
+
+    def hx_noalloc(self, X, Y, prec="f64", stream=None):
+        """Y = H~ X through fe_hx_apply_noalloc, which allocates nothing (its
+        nonlocal scratch is a static device array): Y must be given."""
+        _check_block(X, self.n, "X")
+        N, ld = X.shape[1], X.stride(0)
+        _check_block(Y, self.n, "Y")
+        if Y.shape[1] != N or Y.stride(0) != ld:
+            raise ValueError("Y must have X's shape and leading dimension")
+        _check(lib().fe_hx_apply_noalloc(self._h, _ptr(X), _ptr(Y), N, ld, _PREC[prec], _stream(stream)))
         return Y
 
     def cheb_filter(self, X, m: int, a: float, b: float, a0: float = math.nan, prec="f64", Y=None, work=None,

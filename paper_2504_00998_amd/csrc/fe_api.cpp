@@ -113,12 +113,12 @@ void cheb_coefficients(int mdeg, double a, double b, double a0, std::vector<doub
 
 // One recurrence step Y = alpha (H~ - c) X - beta Ym1, nonlocal term included.
 fe_status filter_step(fe_mesh *m, const double *X, int64_t ldx, double *Y, int64_t ldy, const double *Ym1,
-                      int64_t ldm, double alpha, double beta, double shift, int64_t N, fe_dtype prec,
-                      hipStream_t s) {
+                      int64_t ldm, double alpha, double beta, double shift, int64_t N, fe_dtype prec, hipStream_t s,
+                      double *nlW) {
     StepArgs a{X, ldx, Y, ldy, Ym1, ldm, alpha, beta, shift, N};
     FE_HIP(launch_step(m, a, prec, s), "step kernel launch");
     // the nonlocal term after all colour passes: they write the base values
-    if (m->nl.n_site > 0) FE_HIP(launch_nonlocal(m, X, ldx, Y, ldy, N, alpha, s), "nonlocal kernel launch");
+    if (m->nl.n_site > 0) FE_HIP(launch_nonlocal(m, X, ldx, Y, ldy, N, alpha, s, nlW), "nonlocal kernel launch");
     return FE_OK;
 }
 
@@ -201,8 +201,13 @@ fe_status fe_mesh_create(const fe_mesh_desc *d, fe_mesh **out) {
     for (int a = 1; a < 3; ++a)
         if (std::fabs(d->L[a] / d->ncell[a] - h) > 1e-12 * h) return fail(FE_EINVAL, "cells must be cubes");
 
+    int dev = 0;
+    FE_HIP(hipGetDevice(&dev), "hipGetDevice");
+    // the device address of the allocation-free entry point's scratch, once per device
+    fe_status sst = static_scratch_init(dev);
+    if (sst != FE_OK) return sst;
     fe_mesh *m = new fe_mesh();
-    (void)hipGetDevice(&m->device);
+    m->device = dev;
     m->h = h;
     m->p = d->p;
     m->n1 = d->p + 1;
@@ -376,6 +381,31 @@ fe_status fe_hx_apply(fe_mesh *m, const double *X, double *Y, int64_t N, int64_t
     if (overlap(X, m->n, N, ld, Y, m->n, N, ld)) return fail(FE_EINVAL, "X and Y overlap");
     if (!m->potential_set) return fail(FE_ESTATE, "fe_set_potential has not been called");
     return filter_step(m, X, ld, Y, ld, nullptr, 0, 1.0, 0.0, 0.0, N, prec, s);
+}
+
+fe_status fe_hx_apply_noalloc(fe_mesh *m, const double *X, double *Y, int64_t N, int64_t ld, fe_dtype prec,
+                              hipStream_t s) {
+    if (!m) return fail(FE_EINVAL, "NULL mesh");
+    if (N == 0) return FE_OK;
+    if (N < 0) return fail(FE_EINVAL, "N must be >= 0");
+    fe_status st;
+    if ((st = check_prec(prec)) != FE_OK) return st;
+    if ((st = check_block(m, X, N, ld, "X")) != FE_OK) return st;
+    if ((st = check_block(m, Y, N, ld, "Y")) != FE_OK) return st;
+    if (overlap(X, m->n, N, ld, Y, m->n, N, ld)) return fail(FE_EINVAL, "X and Y overlap");
+    if (!m->potential_set) return fail(FE_ESTATE, "fe_set_potential has not been called");
+    double *W = nullptr;
+    if (m->nl.n_site > 0) {
+        // the projections of the nonlocal term go to the device's static
+        // scratch instead of the mesh's buffer grown on demand
+        if (nonlocal_work_doubles(m, N) > kStaticScratchDoubles)
+            return fail(FE_ENOMEM, "9 * n_site * N = " + std::to_string(nonlocal_work_doubles(m, N)) +
+                                       " doubles exceeds the static scratch of " +
+                                       std::to_string(kStaticScratchDoubles) + " doubles");
+        W = static_scratch(m->device);
+        if (!W) return fail(FE_EDEVICE, "static scratch not resolved on the mesh's device");
+    }
+    return filter_step(m, X, ld, Y, ld, nullptr, 0, 1.0, 0.0, 0.0, N, prec, s, W);
 }
 
 fe_status fe_cheb_filter(fe_mesh *m, const double *X, double *Y, int64_t N, int64_t ld, int32_t mdeg, double a,

@@ -131,7 +131,8 @@ hipError_t launch_potential_vjp(const fe_mesh *m, const double *g, double z0, do
 hipError_t launch_rowdot_accum(const fe_mesh *m, const double *U, int64_t ldu, const double *V, int64_t ldv,
                                int64_t N, double scale, double *g, hipStream_t s);
 fe_status filter_step(fe_mesh *m, const double *X, int64_t ldx, double *Y, int64_t ldy, const double *Ym1,
-                      int64_t ldm, double alpha, double beta, double shift, int64_t N, fe_dtype prec, hipStream_t s);
+                      int64_t ldm, double alpha, double beta, double shift, int64_t N, fe_dtype prec, hipStream_t s,
+                      double *nlW = nullptr);
 void cheb_coefficients(int mdeg, double a, double b, double a0, std::vector<double> &al, std::vector<double> &be,
                        double &c);
 fe_status validate_filter_args(fe_mesh *m, int64_t N, int32_t mdeg, double a, double b, double a0, fe_dtype prec);
@@ -151,8 +152,13 @@ fe_status filter_step_k(fe_mesh *m, const double *X, int64_t ldx, double *Y, int
                         int64_t ldm, double alpha, double beta, double shift, int64_t N, hipStream_t s);
 hipError_t launch_axpby(double *Y, int64_t ldy, const double *X, int64_t ldx, int64_t n, int64_t N, double a,
                         double b, hipStream_t s);
+// W: the projection buffer (9 n_site N doubles); null: the mesh's own, grown on demand
 hipError_t launch_nonlocal(fe_mesh *m, const double *X, int64_t ldx, double *Y, int64_t ldy, int64_t N,
-                           double alpha, hipStream_t s);
+                           double alpha, hipStream_t s, double *W = nullptr);
+// device scratch of the allocation-free entry point (fe_nonlocal.hip)
+constexpr size_t kStaticScratchDoubles = (size_t)4 << 20;
+fe_status static_scratch_init(int device);
+double *static_scratch(int device);
 size_t nonlocal_work_doubles(const fe_mesh *m, int64_t N);
 hipError_t launch_nonlocal_k(fe_mesh *m, const double *X, int64_t ldx, double *Y, int64_t ldy, int64_t N,
                              double alpha, hipStream_t s);

@@ -13,12 +13,53 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "fe_internal.h"
 
 namespace fe {
+
+// Device-resident scratch of the allocation-free H~X entry point
+// (fe_hx_apply_noalloc): the nonlocal projections W = D C~^T X of one call,
+// 9 n_site N doubles, at most kStaticScratchDoubles (32 MiB) per device.  Each
+// device that loads the library holds its own copy until the process ends;
+// every call on a device shares it, so calls that overlap on one device race.
+// Host code never uses the array's name as an address: the device address is
+// resolved once per device (static_scratch_init, from fe_mesh_create) and
+// kept in g_scratch_ptr.
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+fe_status static_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return fail(FE_EDEVICE, "device index out of range for the static scratch");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return FE_OK;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != device) e = hipSetDevice(device);
+    double *ptr = nullptr;
+    if (e == hipSuccess) e = hipGetSymbolAddress(reinterpret_cast<void **>(&ptr), HIP_SYMBOL(scratch));
+    if (cur >= 0 && cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return fail(FE_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[device] = ptr;
+    return FE_OK;
+}
+
+double *static_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
 
 namespace {
 
@@ -172,23 +213,26 @@ static hipError_t ensure_nl_work(fe_mesh *m, int64_t N) {
 }
 
 hipError_t launch_nonlocal(fe_mesh *m, const double *X, int64_t ldx, double *Y, int64_t ldy, int64_t N,
-                           double alpha, hipStream_t s) {
+                           double alpha, hipStream_t s, double *W) {
     if (m->nl.n_site == 0) return hipSuccess;
-    hipError_t e = ensure_nl_work(m, N);
-    if (e != hipSuccess) return e;
+    if (!W) {
+        hipError_t e = ensure_nl_work(m, N);
+        if (e != hipSuccess) return e;
+        W = m->nl.d_W;
+    }
+    hipError_t e;
     const int TB = 128;
     dim3 g1((unsigned)m->nl.n_site, (unsigned)((N + TB - 1) / TB));
     hipLaunchKernelGGL(nl_project_kernel, g1, dim3(TB), 0, s, X, ldx, N, (const int64_t *)m->nl.d_supp_ptr,
                        (const int32_t *)m->nl.d_supp_dof, (const double *)m->nl.d_vals, (const double *)m->nl.d_D,
-                       m->nl.d_W);
+                       W);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (m->nl.n_node == 0) return hipSuccess;
     dim3 g2((unsigned)m->nl.n_node, (unsigned)((N + TB - 1) / TB));
     hipLaunchKernelGGL(nl_expand_kernel, g2, dim3(TB), 0, s, Y, ldy, N, alpha, (const int32_t *)m->nl.d_node,
                        (const int64_t *)m->nl.d_inc_ptr, (const int64_t *)m->nl.d_inc_entry,
-                       (const int32_t *)m->nl.d_entry_site, (const double *)m->nl.d_vals,
-                       (const double *)m->nl.d_W);
+                       (const int32_t *)m->nl.d_entry_site, (const double *)m->nl.d_vals, (const double *)W);
     return hipGetLastError();
 }
 

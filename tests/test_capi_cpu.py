@@ -49,6 +49,7 @@ def test_mesh_create_rejects_bad_descriptors_before_device_use(kw, msg):
 def test_null_mesh_is_rejected_everywhere():
     L = fe.lib()
     assert L.fe_hx_apply(None, None, None, 1, 1, 0, None) == fe.FE_EINVAL
+    assert L.fe_hx_apply_noalloc(None, None, None, 1, 1, 0, None) == fe.FE_EINVAL
     assert L.fe_cheb_filter(None, None, None, 1, 1, 3, 0.0, 1.0, math.nan, 0, None, 0, None) == fe.FE_EINVAL
     assert L.fe_set_potential(None, None, 0.0, 0.0, None) == fe.FE_EINVAL
     assert L.fe_mesh_info(None, None, None, None) == fe.FE_EINVAL
