@@ -167,6 +167,8 @@ static void free_mesh(fe_mesh *m) {
     (void)hipFree(m->d_axis);
     (void)hipFree(m->d_zcoord);
     (void)hipFree(m->d_Af64);
+    (void)hipFree(m->d_Af64s);
+    (void)hipFree(m->d_zero);
     (void)hipFree(m->d_Af32);
     (void)hipFree(m->d_Abf16);
     (void)hipFree(m->d_v);
@@ -268,6 +270,26 @@ fe_status fe_mesh_create(const fe_mesh_desc *d, fe_mesh **out) {
     std::vector<float> f32;
     std::vector<uint16_t> bf;
     swizzle_fragments(m, f64, f32, bf);
+    // D^ (1/2 Kc) D^ with D^ the per-local-index M^-1/2 of a node inside the
+    // mesh: (h/2) w_i per cell, summed over the two cells at a cell face
+    // (i = 0 or p), the same sums as the assembled masses above.  It equals
+    // every free node's scale unless an axis is zero-Neumann (a boundary face
+    // node there has one cell's mass only).
+    const bool fold = m->bc[0] != FE_BC_NEUMANN && m->bc[1] != FE_BC_NEUMANN && m->bc[2] != FE_BC_NEUMANN;
+    std::vector<double> f64s;
+    if (fold) {
+        std::vector<double> dh(m->n1);
+        for (int i = 0; i <= m->p; ++i) {
+            const double mi = (i == 0 || i == m->p) ? 0.5 * h * m->w[m->p] + 0.5 * h * m->w[0] : 0.5 * h * m->w[i];
+            dh[i] = 1.0 / std::sqrt(mi);
+        }
+        std::vector<double> As((size_t)m->nc * m->nc);
+        auto dl = [&](int l) { return (dh[l % m->n1] * dh[(l / m->n1) % m->n1]) * dh[l / (m->n1 * m->n1)]; };
+        for (int l = 0; l < m->nc; ++l)
+            for (int q = 0; q < m->nc; ++q) As[(size_t)l * m->nc + q] = dl(l) * m->cellA[(size_t)l * m->nc + q] * dl(q);
+        swizzle_f64(m, As, f64s);
+    }
+    const double zeros[32] = {};
 
     auto up = [&](void **dst, const void *src, size_t bytes) -> bool {
         if (hipMalloc(dst, bytes) != hipSuccess) return false;
@@ -277,6 +299,8 @@ fe_status fe_mesh_create(const fe_mesh_desc *d, fe_mesh **out) {
               up((void **)&m->d_zcoord, m->axis_coord[2].data(), m->axis_coord[2].size() * sizeof(double)) &&
               up((void **)&m->d_wrel, wrel.data(), wrel.size() * sizeof(double)) &&
               up((void **)&m->d_Af64, f64.data(), f64.size() * sizeof(double)) &&
+              (!fold || up((void **)&m->d_Af64s, f64s.data(), f64s.size() * sizeof(double))) &&
+              up((void **)&m->d_zero, zeros, sizeof(zeros)) &&
               up((void **)&m->d_Af32, f32.data(), f32.size() * sizeof(float)) &&
               up((void **)&m->d_Abf16, bf.data(), bf.size() * sizeof(uint16_t)) &&
               hipMalloc((void **)&m->d_v, (size_t)m->n * sizeof(double)) == hipSuccess;
@@ -315,8 +339,8 @@ fe_status fe_mesh_destroy(fe_mesh *mesh) {
 
 fe_status fe_mesh_set_kernel(fe_mesh *m, int32_t variant) {
     if (!m) return fail(FE_EINVAL, "NULL mesh");
-    if (variant < 0 || variant > 9 || variant == 2 || variant == 5 || variant == 8)
-        return fail(FE_EINVAL, "kernel variant must be 0, 1, 3, 4, 6, 7 or 9 (2, 5 and 8 were removed)");
+    if (variant < 0 || variant > 10 || variant == 2 || variant == 5 || variant == 8)
+        return fail(FE_EINVAL, "kernel variant must be 0, 1, 3, 4, 6, 7, 9 or 10 (2, 5 and 8 were removed)");
     m->kernel_variant = variant;
     return FE_OK;
 }

@@ -75,6 +75,12 @@ struct fe_mesh {
     double *d_zcoord = nullptr;   // [nf_z] z coordinate of free z positions
     int maxf = 0;
     double *d_Af64 = nullptr;     // swizzled A fragments of 1/2 Kc (f64)
+    // with no Neumann axis every free node's M^-1/2 is the product of per-axis
+    // factors that depend only on its local index in any cell containing it,
+    // so D Kc D folds into one cell matrix: swizzled f64 fragments of
+    // D^ (1/2 Kc) D^ (null with a Neumann axis)
+    double *d_Af64s = nullptr;
+    double *d_zero = nullptr;     // 32 zero doubles (source of padded / absent rows)
     float *d_Af32 = nullptr;      // f32
     uint16_t *d_Abf16 = nullptr;  // bf16 bits
     double *d_v = nullptr;        // [n] diagonal potential term of H~

@@ -94,6 +94,7 @@ struct StepParams {
     int64_t nfx, nfy;
     AxisInfo zs;  // z axis in segments of zl cells (the pipelined kernel's z segments; zl = 1: cells)
     int zl;
+    const double *zero;  // >= 32 zero doubles (source of padded and absent rows)
 };
 
 template <int PREC> struct PrecTraits;
@@ -1725,6 +1726,344 @@ static hipError_t launch_pipe_p(StepParams prm, const fe_mesh *m, hipStream_t s)
     return hipSuccess;
 }
 
+// ------------------------------------------------------------------------
+// FP64 step kernel with direct-to-LDS prefetch (p <= 4; meshes without a
+// zero-Neumann axis, where M^-1/2 of a free node depends only on its local
+// index and folds into the cell matrix: A' = D^ (1/2 Kc) D^).
+//
+// Persistent workgroups walk the items (z segment of cells, 32 vectors) of
+// a colour as the pipelined kernel does, one wave per 16-row tile of A' with
+// the tile's fragments in registers.  The cell's X rows go from HBM straight
+// into LDS with 16-byte global-to-LDS loads (eight rows of 16 vectors, 128 B
+// each, per wave instruction), two positions ahead, into three LDS buffers;
+// they need no scaling, so no register holds them and nothing in flight is
+// carried from one position to the next in registers.  A position's other
+// inputs (the old value of each output, v) are loaded to registers at the
+// start of the same position and used after its product.  Rows off the cell,
+// on Dirichlet faces or beyond N read a buffer of zeros.  With z segments the
+// partial sums of a segment's inner z faces stay in an LDS hold, as in the
+// pipelined kernel; the X rows of those faces are read again (from L2, one
+// position after their first read).
+//
+// Per position t: the old values and v of t are requested, then the X rows of
+// t + 2 (into buffer (t + 2) % 3, free since the barrier that ended t - 1);
+// the product reads buffer t % 3; one wait for the memory counter down to the
+// four newest requests (the X rows of t + 2) covers both the old values of t
+// and the X rows of t + 1 (requested before them); then the epilogue, the
+// stores, and one barrier that makes every wave's X rows of t + 1 visible.
+template <int P> struct DmaShape {
+    static constexpr int NCP = ((P + 1) * (P + 1) * (P + 1) + 31) / 32 * 32, NT = NCP / 16, NKS = NCP / 4;
+    static constexpr int W = NT, G = 2, NB = 3, XS = NCP * 16;  // waves, 16-vector groups, buffers, doubles per group
+    static constexpr size_t xbytes = (size_t)NB * G * XS * sizeof(double);
+    static constexpr size_t hbytes = (size_t)2 * (P + 1) * (P + 1) * 16 * G * sizeof(double);
+};
+
+// s_waitcnt immediates: vector-memory counter <= n, the other counters free;
+// LDS counter 0, the other counters free
+__device__ __forceinline__ constexpr int vmcnt_imm(int n) { return (n & 0xF) | ((n >> 4) << 14) | (0x7 << 4) | (0xF << 8); }
+__device__ __forceinline__ constexpr int lgkmcnt0_imm() { return 0xF | (0x3 << 14) | (0x7 << 4); }
+
+// 16-byte LDS store written out as the instruction itself, so that the
+// compiler's wait analysis does not order it behind the global-to-LDS
+// requests in flight (it cannot tell that they write other buffers); the
+// caller drains the LDS counter before the barrier that publishes it.
+__device__ __forceinline__ void lds_store16(double *p, double a, double b) {
+    const uint32_t off = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) double *)p;
+    typedef double dv2 __attribute__((ext_vector_type(2)));
+    const dv2 v = {a, b};
+    asm volatile("ds_write_b128 %0, %1" : : "v"(off), "v"(v) : "memory");
+}
+
+// DoF of padded row r of a cell (-1 off the cell or on a Dirichlet face)
+template <int P> __device__ __forceinline__ int node_index(const StepParams &k, const ItemCell &c, int r) {
+    constexpr int N1 = P + 1, NC = N1 * N1 * N1;
+    const int l = min(r, NC - 1);
+    const int t0 = axis_free_index32(k.ax[0], P, c.cx * P + l % N1);
+    const int t1 = axis_free_index32(k.ax[1], P, c.cy * P + (l / N1) % N1);
+    const int t2 = axis_free_index32(k.ax[2], P, c.cz * P + l / (N1 * N1));
+    const bool ok = r < NC && t0 >= 0 && t1 >= 0 && t2 >= 0;
+    return ok ? t0 + (int)k.nfx * (t1 + (int)k.nfy * t2) : -1;
+}
+
+template <int P, bool ZS>
+__global__ __launch_bounds__(64 * DmaShape<P>::W) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void step_dma_kernel(StepParams k, int64_t nitems) {
+    typedef DmaShape<P> S;
+    constexpr int N1 = P + 1, NC = N1 * N1 * N1, NKS = S::NKS, G = S::G, XS = S::XS;
+    constexpr int HS = N1 * N1 * 16 * G;  // doubles per hold buffer
+    // three X buffers [G][NCP][16] as distinct arrays, each named at compile
+    // time by the position it serves, so that the compiler sees that a
+    // product's LDS reads and the X requests in flight touch different
+    // buffers; the hold [2][N1*N1][16G]
+    __shared__ __align__(16) double xb0[G * XS], xb1[G * XS], xb2[G * XS];
+    __shared__ __align__(16) double hold[ZS ? 2 * HS : 2];
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int ngroups = (k.nchunk + G - 1) / G;
+    const int stride = (int)gridDim.x;
+    if ((int64_t)blockIdx.x >= nitems) return;  // whole workgroup
+    const int zl = ZS ? k.zl : 1;
+    const int npos = (int)((nitems - 1 - blockIdx.x) / stride + 1) * zl;  // < 2^31, as items per launch
+    auto item_of = [&](int t) { return (int)blockIdx.x + (ZS ? t / zl : t) * stride; };
+    auto cell_of = [&](int t) { return ZS ? t % zl : 0; };
+    // the wave's row tile of A', resident for the launch
+    double ar[NKS];
+    {
+        const double *A = reinterpret_cast<const double *>(k.A) + (size_t)wave * NKS * 64 + lane;
+#pragma unroll
+        for (int s = 0; s < NKS; ++s) ar[s] = A[s * 64];
+    }
+    // X rows of position tp into buffer bufp: lane l of the wave's
+    // instruction (h, g) carries row 16 wave + 8 h + l / 8, vectors
+    // 16 g + 2 (l % 8) + {0, 1} of the item's group
+    auto prefetch = [&](int tp, double *__restrict__ bufp) {
+        const int it = item_of(tp);
+        const int grp = it % ngroups;
+        int seg;
+        const ItemCell cc = seg_cell(k, it / ngroups, cell_of(tp), seg);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int rr = 16 * wave + 8 * h + (lane >> 3);
+            const int I = node_index<P>(k, cc, rr);
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int64_t col = (int64_t)grp * G * 16 + 16 * g + 2 * (lane & 7);
+                const double *src = (I >= 0 && col < k.N) ? k.X + (int64_t)I * k.ldx + col : k.zero + 2 * (lane & 7);
+                __builtin_amdgcn_global_load_lds(src, bufp + g * XS + (16 * wave + 8 * h) * 16, 16, 0, 0);
+            }
+        }
+        asm volatile("" ::: "memory");
+    };
+    const int r = 16 * wave + pipe_row<0>(lane);  // the row this lane's accumulators hold
+    const int vq = pipe_vec<0>(lane);
+    const double *ob = k.Ym1 ? k.Ym1 : k.X;
+    const int64_t ol = k.Ym1 ? k.ldm : k.ldx;
+
+    // position t: product from xs, X rows of t + 2 into xn; false after the last
+    auto body = [&](int t, const double *__restrict__ xs, double *__restrict__ xn,
+                    double *__restrict__ hd) -> bool {
+        // this position's row: node, first-writer test, segment faces
+        const int it = item_of(t);
+        const int grp = it % ngroups;
+        const int c = cell_of(t);
+        int seg;
+        const ItemCell cc = seg_cell(k, it / ngroups, c, seg);
+        const int I = node_index<P>(k, cc, r);
+        const int l = min(r, NC - 1);
+        const int lz = l / (N1 * N1);
+        const bool f0 = axis_first_sel(k.ax[0], P, cc.cx, l % N1);
+        const bool f1 = axis_first_sel(k.ax[1], P, cc.cy, (l / N1) % N1);
+        bool f2, bot, top;
+        if constexpr (ZS) {
+            // along z only the segment's end faces meet other workgroups
+            const int iz = lz == 0 ? (c == 0 ? 0 : -1) : lz == P ? (c == k.zl - 1 ? P : -1) : -1;
+            f2 = axis_first_sel(k.zs, P, seg, iz);
+            bot = r < NC && lz == 0 && c > 0;
+            top = r < NC && lz == P && c < k.zl - 1;
+        } else {
+            f2 = axis_first_sel(k.ax[2], P, cc.cz, lz);
+            bot = top = false;
+        }
+        const bool fst = (r < NC) & f0 & f1 & f2;
+        const int64_t v0 = (int64_t)grp * G * 16 + vq;
+        // old values: Y where an earlier colour has written the node, else the
+        // previous iterate; rows that need none (off the cell or on a
+        // Dirichlet face, a later cell's bottom face, a first writer without
+        // a previous iterate) read the zero buffer.  All loads unconditional.
+        const int64_t Ic = max(I, 0);
+        const bool none = I < 0 || bot || (fst && !k.Ym1);
+        const double *orow = none ? k.zero : fst ? ob + Ic * ol : k.Y + Ic * k.ldy;
+        const double vraw = k.v[Ic];
+        double o[G][4];
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) o[g][q] = orow[none ? 0 : min(v0 + 16 * g + pipe_off(q), k.N - 1)];
+        asm volatile("" ::: "memory");  // these requests go out before the X rows of t + 2
+        // X rows two positions ahead (past the walk's end the last position's
+        // rows again, into the free buffer, which nobody reads afterwards)
+        prefetch(min(t + 2, npos - 1), xn);
+        double acc[G][4];
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[g][q] = 0.0;
+        {
+            double bc[G][4], bn[G][4];
+#pragma unroll
+            for (int g = 0; g < G; ++g) f64_pair_b(xs + g * XS, 0, lane, bc[g]);
+#pragma unroll
+            for (int s = 0; s < NKS; ++s) {
+                if (s + 1 < NKS)
+#pragma unroll
+                    for (int g = 0; g < G; ++g) f64_pair_b(xs + g * XS, s + 1, lane, bn[g]);
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        acc[g][q] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[s], bc[g][q], acc[g][q], 0, 0, 0);
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) bc[g][q] = bn[g][q];
+            }
+        }
+        // the old values and v of t, and the X rows of t + 1 (both requested
+        // before the four X requests of t + 2)
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm(4));
+        asm volatile("" ::: "memory");
+        // the loaded values are used only from here on (not inside the product)
+        double vr = vraw;
+        asm volatile("" : "+v"(vr));
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(o[g][q]));
+        // epilogue: first writer alpha (v - c) x - beta y_{k-1} (x raw, from
+        // the buffer), else the old value, or the hold for a later cell's
+        // bottom face
+        const double vI = (I >= 0 && fst) ? vr : 0.0;
+        const double sc = k.alpha * (vI - k.shift);
+        const bool useo = !fst || k.Ym1 != nullptr;
+        double out[G][4];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            double bo[4];
+            if (ZS && bot) {
+                const double *h = hd + ((t - 1) & 1) * HS + r * 16 * G + vq + 16 * g;
+                const double2 u = *reinterpret_cast<const double2 *>(h);
+                const double2 w = *reinterpret_cast<const double2 *>(h + 8);
+                bo[0] = u.x; bo[1] = u.y; bo[2] = w.x; bo[3] = w.y;
+            } else {
+                const double *xr = xs + g * XS + r * 16 + vq;
+                const double2 x01 = *reinterpret_cast<const double2 *>(xr);
+                const double2 x23 = *reinterpret_cast<const double2 *>(xr + 8);
+                const double xv[4] = {x01.x, x01.y, x23.x, x23.y};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const bool ok = I >= 0 && v0 + 16 * g + pipe_off(q) < k.N;
+                    const double x = ok ? xv[q] : 0.0;
+                    const double oo = (ok && useo) ? o[g][q] : 0.0;
+                    double base = sc * x;
+                    if (k.Ym1) base -= k.beta * oo;
+                    bo[q] = fst ? base : oo;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) out[g][q] = bo[q] + k.alpha * acc[g][q];
+        }
+        if (ZS && top) {
+            double *h = hd + (t & 1) * HS + (r - P * N1 * N1) * 16 * G + vq;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                lds_store16(h + 16 * g, out[g][0], out[g][1]);
+                lds_store16(h + 16 * g + 8, out[g][2], out[g][3]);
+            }
+        } else if (I >= 0) {
+            double *yrow = k.Y + (int64_t)I * k.ldy;
+            if (wide_ok(k, v0 - vq, 16 * G)) {
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    double *yp = yrow + v0 + 16 * g;
+                    *reinterpret_cast<double2 *>(yp) = double2{out[g][0], out[g][1]};
+                    *reinterpret_cast<double2 *>(yp + 8) = double2{out[g][2], out[g][3]};
+                }
+            } else {
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int64_t vec = v0 + 16 * g + pipe_off(q);
+                        if (vec < k.N) yrow[vec] = out[g][q];
+                    }
+            }
+        }
+        // every wave's LDS writes done, then the barrier; the X rows of t + 1
+        // were waited for above, those of t + 2 stay in flight
+        __builtin_amdgcn_s_waitcnt(lgkmcnt0_imm());
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        return t + 1 < npos;
+    };
+
+    prefetch(0, xb0);
+    prefetch(min(1, npos - 1), xb1);
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+    asm volatile("" ::: "memory");
+    __syncthreads();
+    // the walk, three positions per round so that each buffer is named
+    for (int t = 0;; t += 3) {
+        if (!body(t, xb0, xb2, hold)) break;
+        if (!body(t + 1, xb1, xb0, hold)) break;
+        if (!body(t + 2, xb2, xb1, hold)) break;
+    }
+}
+
+template <int P, bool ZS>
+static hipError_t launch_dma_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
+    typedef DmaShape<P> S;
+    constexpr int W = S::W, G = S::G;
+    const size_t smem = 0;  // static LDS only
+    static bool attr = false;
+    static int resident = 0;
+    if (!attr) {
+        hipError_t e;
+        int per_cu = 0, dev = 0, cus = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(&step_dma_kernel<P, ZS>), 64 * W, smem);
+        if (e != hipSuccess) return e;
+        e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        resident = std::max(1, per_cu) * std::max(1, cus);
+        attr = true;
+    }
+    prm.A = m->d_Af64s;
+    prm.zl = ZS ? zseg_length(m) : 1;
+    prm.zs = prm.ax[2];
+    prm.zs.ncell = prm.ax[2].ncell / prm.zl;
+    prm.zs.ncol = (prm.zs.bc == FE_BC_PERIODIC && (prm.zs.ncell & 1)) ? 3 : prm.zs.ncell >= 2 ? 2 : 1;
+    const int ngroups = (prm.nchunk + G - 1) / G;
+    for (int c2 = 0; c2 < prm.zs.ncol; ++c2)
+        for (int c1 = 0; c1 < m->ncol[1]; ++c1)
+            for (int c0 = 0; c0 < m->ncol[0]; ++c0) {
+                int col[3] = {c0, c1, c2};
+                int64_t cells = 1;
+                for (int a = 0; a < 3; ++a) {
+                    const AxisInfo &ax = a == 2 ? prm.zs : prm.ax[a];
+                    int cnt;
+                    if (col[a] == 2) cnt = 1;
+                    else {
+                        int limit = ax.ncol == 3 ? ax.ncell - 1 : ax.ncell;
+                        cnt = limit > col[a] ? (limit - col[a] + 1) / 2 : 0;
+                    }
+                    prm.col[a] = col[a];
+                    prm.cnt[a] = cnt;
+                    cells *= cnt;
+                }
+                if (cells == 0) continue;
+                const int64_t nitems = cells * ngroups;
+                const int64_t grid = std::min<int64_t>(nitems, resident);
+                hipLaunchKernelGGL((step_dma_kernel<P, ZS>), dim3((unsigned)grid), dim3(64 * W), smem, s, prm, nitems);
+                hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+            }
+    return hipSuccess;
+}
+
+// Whether the direct-to-LDS kernel applies: FP64 products, real mode, folded
+// cell matrix (no Neumann axis), and 16-byte loads at every row and column
+// pair (blocks 16-byte aligned, even leading dimensions and N).
+static bool dma_applies(const fe_mesh *m, const StepArgs &a, fe_dtype prec) {
+    if (prec != FE_F64 || a.S || !m->d_Af64s || m->p > 4 || (a.N & 1)) return false;
+    const uintptr_t ptrs = reinterpret_cast<uintptr_t>(a.X) | reinterpret_cast<uintptr_t>(a.Y) |
+                           reinterpret_cast<uintptr_t>(a.Ym1 ? a.Ym1 : a.X);
+    const int64_t lds = a.ldx | a.ldy | (a.Ym1 ? a.ldm : a.ldx);
+    return (ptrs & 15) == 0 && (lds & 1) == 0;
+}
+
 size_t assembled_scratch_doubles(const fe_mesh *m) {
     return m->p <= 5 ? (size_t)m->ncells * (size_t)padded_nc(m->p) : 0;
 }
@@ -1745,6 +2084,7 @@ hipError_t launch_step_assembled(const fe_mesh *m, const StepArgs &a, double *Zc
     prm.v = a.v ? a.v : m->d_v;
     prm.A = m->d_Af64;
     prm.S = nullptr;
+    prm.zero = m->d_zero;
     for (int d = 0; d < 3; ++d) {
         prm.ax[d].ncell = m->ncell[d];
         prm.ax[d].nfree = (int)m->nf[d];
@@ -1777,6 +2117,7 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
     prm.v = a.v ? a.v : m->d_v;
     prm.A = prec == FE_F64 ? (const void *)m->d_Af64 : prec == FE_F32 ? (const void *)m->d_Af32 : (const void *)m->d_Abf16;
     prm.S = a.S;
+    prm.zero = m->d_zero;
     for (int d = 0; d < 3; ++d) {
         prm.ax[d].ncell = m->ncell[d];
         prm.ax[d].nfree = (int)m->nf[d];
@@ -1809,6 +2150,16 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
         case 3: return launch_cells_p<3>(prm, m, s);
         case 4: return launch_cells_p<4>(prm, m, s);
         case 5: return launch_cells_p<5>(prm, m, s);
+        default: break;
+        }
+    }
+    // variant 10: the direct-to-LDS FP64 kernel (z segments), where it applies
+    if (m->kernel_variant == 10 && dma_applies(m, a, prec)) {
+        switch (m->p) {
+        case 1: return launch_dma_p<1, true>(prm, m, s);
+        case 2: return launch_dma_p<2, true>(prm, m, s);
+        case 3: return launch_dma_p<3, true>(prm, m, s);
+        case 4: return launch_dma_p<4, true>(prm, m, s);
         default: break;
         }
     }

@@ -1,0 +1,147 @@
+"""The FP64 step kernel with direct-to-LDS prefetch (kernel variant 10):
+parity with the oracle, reproducibility, the cases where it does not apply
+(it falls back to the one-cell kernel), and walks of several segments per
+workgroup.  It multiplies with the cell matrix pre-scaled by the per-local-
+index M^-1/2 (meshes without a zero-Neumann axis), so its rounding differs
+from the other kernels'; it is compared with the oracle and with them to
+rounding."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2504_00998_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _setup(wl):
+    import paper_2504_00998_amd as fe
+    om = O.Mesh.from_workload(wl)
+    Vq = W.workload_potential(wl, om.quad_points())
+    op = O.Operator(om, Vq, wl.E, wl.z0)
+    gm = fe.Mesh.from_workload(wl)
+    gm.set_potential(torch.from_numpy(Vq).cuda(), wl.E, wl.z0)
+    return op, gm
+
+
+def _relerr(Y, R):
+    return (np.linalg.norm(Y - R, axis=0) / np.maximum(np.linalg.norm(R, axis=0), 1e-300)).max()
+
+
+CASES = [
+    # (label, workload): Dirichlet / periodic z, segment colours, odd periodic
+    # axes, ragged vector groups (even N), p = 1..4
+    ("p4-D-z12-N40", W.small_slab((3, 3, 12), p=4, N=40)),
+    ("p4-odd-periodic-x-N18", W.small_slab((3, 2, 12), p=4, N=18)),
+    ("p4-periodic-z-3seg-N34", W.small_slab((2, 2, 18), p=4, N=34, bc=(W.PERIODIC,) * 3, E=0.0)),
+    ("p4-no-segments-z7-N32", W.small_slab((2, 3, 7), p=4, N=32)),
+    ("p3-periodic-z-N20", W.small_slab((3, 3, 9), p=3, N=20, bc=(W.PERIODIC,) * 3, E=0.0)),
+    ("p2-dirichlet-all-N64", W.small_slab((3, 4, 8), p=2, N=64, bc=(W.DIRICHLET,) * 3)),
+    ("p1-N2", W.small_slab((4, 3, 12), p=1, N=2)),
+    ("p4-DPP-N16", W.small_slab((3, 2, 8), p=4, N=16, bc=(W.DIRICHLET, W.PERIODIC, W.PERIODIC), E=0.0)),
+]
+
+
+@pytest.mark.parametrize("label,wl", CASES, ids=[c[0] for c in CASES])
+def test_dma_kernel_matches_oracle_and_is_reproducible(label, wl):
+    print("case: dma", label, wl.ncell, wl.p, wl.N, flush=True)
+    op, gm = _setup(wl)
+    Xh = wl.X(op.n)
+    X = torch.from_numpy(Xh).cuda()
+    gm.set_kernel(10)
+    try:
+        H = gm.hx(X)
+        assert torch.equal(gm.hx(X), H)
+        assert _relerr(H.cpu().numpy(), op.apply(Xh)) < 1e-13
+        a0, b, _ = O.lanczos_bounds(op.apply, wl.lanczos_start(op.n), 10)
+        a = O.weyl_cut(a0, b, wl.N, op.n)
+        for a0s, m in ((a0, wl.m), (math.nan, 6)):
+            Y = gm.cheb_filter(X, m, a, b, a0s)
+            assert torch.equal(gm.cheb_filter(X, m, a, b, a0s), Y)
+            assert _relerr(Y.cpu().numpy(), op.filter(Xh, m, a, b, a0s)) < 1e-12
+        # and the one-cell kernel to rounding (another summation order)
+        gm.set_kernel(1)
+        H1 = gm.hx(X)
+        rel = ((H - H1).norm(dim=0) / H1.norm(dim=0)).max().item()
+        assert rel < 1e-13, rel
+    finally:
+        gm.set_kernel(0)
+
+
+def test_dma_kernel_leading_dimension_and_padding_untouched():
+    """Blocks inside wider buffers (even leading dimension N + 6): columns
+    past N are neither read into the product nor written."""
+    wl = W.small_slab((3, 3, 12), p=4, N=22)
+    op, gm = _setup(wl)
+    Xh = wl.X(op.n)
+    Xb = torch.full((op.n, wl.N + 6), float("nan"), dtype=torch.float64, device="cuda")
+    Xb[:, :wl.N] = torch.from_numpy(Xh).cuda()
+    Yb = torch.full_like(Xb, float("nan"))
+    gm.set_kernel(10)
+    try:
+        a0, b, _ = O.lanczos_bounds(op.apply, wl.lanczos_start(op.n), 10)
+        a = O.weyl_cut(a0, b, wl.N, op.n)
+        gm.cheb_filter(Xb[:, :wl.N], wl.m, a, b, a0, Y=Yb[:, :wl.N])
+        assert _relerr(Yb[:, :wl.N].cpu().numpy(), op.filter(Xh, wl.m, a, b, a0)) < 1e-12
+        assert torch.isnan(Yb[:, wl.N:]).all()
+    finally:
+        gm.set_kernel(0)
+
+
+@pytest.mark.parametrize("why,wl,ld_extra", [
+    ("odd-N", W.small_slab((3, 3, 12), p=4, N=17), 0),
+    ("neumann-axis", W.small_slab((3, 2, 10), p=4, N=16, bc=(W.PERIODIC, W.DIRICHLET, W.NEUMANN)), 0),
+    ("odd-leading-dimension", W.small_slab((3, 3, 12), p=4, N=16), 1),
+    ("p5", W.small_slab((2, 2, 3), p=5, N=16), 0),
+])
+def test_dma_kernel_falls_back_where_it_does_not_apply(why, wl, ld_extra):
+    """Odd N (a 16-byte request would straddle the last column), a Neumann
+    axis (no folded cell matrix), an odd leading dimension (unaligned rows)
+    and p > 4: variant 10 runs the one-cell kernel, bit for bit."""
+    print("case: dma fallback", why, flush=True)
+    op, gm = _setup(wl)
+    Xb = torch.zeros((op.n, wl.N + ld_extra), dtype=torch.float64, device="cuda")
+    Xb[:, :wl.N] = torch.from_numpy(wl.X(op.n)).cuda()
+    X = Xb[:, :wl.N]
+    Yb = torch.zeros_like(Xb)
+    gm.set_kernel(1)
+    Y1 = gm.cheb_filter(X, 5, 2.0, 400.0, -0.5, Y=Yb[:, :wl.N]).clone()
+    gm.set_kernel(10)
+    try:
+        Y10 = gm.cheb_filter(X, 5, 2.0, 400.0, -0.5, Y=Yb[:, :wl.N])
+        assert torch.equal(Y10, Y1)
+    finally:
+        gm.set_kernel(0)
+
+
+@pytest.mark.parametrize("p,N", [(4, 64), (3, 96)])
+def test_dma_kernel_several_segments_per_workgroup(p, N):
+    """24 x 24 x 24 cells: a workgroup walks several segments per colour
+    pass, so the three LDS buffers rotate through position counts that are
+    and are not multiples of three, and the two-ahead requests cross from
+    one segment into the next.  Against the z-segment kernel (variant 9) and
+    the one-cell kernel to rounding; reproducible."""
+    import paper_2504_00998_amd as fe
+    wl = W.small_slab((24, 24, 24), p=p, N=N)
+    print("case: dma multi-item", p, N, flush=True)
+    gm = fe.Mesh.from_workload(wl)
+    Vq = W.workload_potential(wl, gm.quad_points())
+    gm.set_potential(torch.from_numpy(Vq).cuda(), wl.E, wl.z0)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(wl.seed(2))
+    X = torch.randn(gm.n, N, generator=g, dtype=torch.float64, device="cuda")
+    try:
+        gm.set_kernel(1)
+        Y1, F1 = gm.hx(X), gm.cheb_filter(X, 6, 2.0, 400.0, -0.5)
+        gm.set_kernel(10)
+        Y10, F10 = gm.hx(X), gm.cheb_filter(X, 6, 2.0, 400.0, -0.5)
+        assert torch.equal(gm.hx(X), Y10)
+        assert torch.equal(gm.cheb_filter(X, 6, 2.0, 400.0, -0.5), F10)
+        for A, B in ((Y10, Y1), (F10, F1)):
+            rel = ((A - B).norm(dim=0) / B.norm(dim=0)).max().item()
+            assert rel < 1e-13, rel
+    finally:
+        gm.set_kernel(0)
