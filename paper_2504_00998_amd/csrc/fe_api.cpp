@@ -169,6 +169,7 @@ static void free_mesh(fe_mesh *m) {
     (void)hipFree(m->d_Af64);
     (void)hipFree(m->d_Af64s);
     (void)hipFree(m->d_zero);
+    (void)hipFree(m->d_segtab);
     (void)hipFree(m->d_Af32);
     (void)hipFree(m->d_Abf16);
     (void)hipFree(m->d_v);
@@ -290,6 +291,9 @@ fe_status fe_mesh_create(const fe_mesh_desc *d, fe_mesh **out) {
         swizzle_f64(m, As, f64s);
     }
     const double zeros[32] = {};
+    std::vector<int32_t> segtab;
+    // the table kernel indexes DoFs in 32 bits
+    if (fold && (m->p == 3 || m->p == 4) && m->n < INT32_MAX) build_segment_table(m, segtab, m->seg_off, m->seg_zl);
 
     auto up = [&](void **dst, const void *src, size_t bytes) -> bool {
         if (hipMalloc(dst, bytes) != hipSuccess) return false;
@@ -301,6 +305,7 @@ fe_status fe_mesh_create(const fe_mesh_desc *d, fe_mesh **out) {
               up((void **)&m->d_Af64, f64.data(), f64.size() * sizeof(double)) &&
               (!fold || up((void **)&m->d_Af64s, f64s.data(), f64s.size() * sizeof(double))) &&
               up((void **)&m->d_zero, zeros, sizeof(zeros)) &&
+              (segtab.empty() || up((void **)&m->d_segtab, segtab.data(), segtab.size() * sizeof(int32_t))) &&
               up((void **)&m->d_Af32, f32.data(), f32.size() * sizeof(float)) &&
               up((void **)&m->d_Abf16, bf.data(), bf.size() * sizeof(uint16_t)) &&
               hipMalloc((void **)&m->d_v, (size_t)m->n * sizeof(double)) == hipSuccess;

@@ -81,6 +81,11 @@ struct fe_mesh {
     // D^ (1/2 Kc) D^ (null with a Neumann axis)
     double *d_Af64s = nullptr;
     double *d_zero = nullptr;     // 32 zero doubles (source of padded / absent rows)
+    // segment table of the FP64 table kernel (p = 3, 4 with the folded cell
+    // matrix): per colour pass, per z segment, first DoF and face masks
+    int32_t *d_segtab = nullptr;
+    std::vector<int64_t> seg_off;  // entries of colour pass c: [seg_off[c], seg_off[c+1])
+    int seg_zl = 1;
     float *d_Af32 = nullptr;      // f32
     uint16_t *d_Abf16 = nullptr;  // bf16 bits
     double *d_v = nullptr;        // [n] diagonal potential term of H~
@@ -170,6 +175,8 @@ hipError_t launch_nonlocal_k(fe_mesh *m, const double *X, int64_t ldx, double *Y
                              double alpha, hipStream_t s);
 fe_status nonlocal_set_phase(fe_mesh *m);
 void swizzle_f64(const fe_mesh *m, const std::vector<double> &A, std::vector<double> &f64);
+// segment table of the FP64 table kernel (fe_kernels.hip)
+void build_segment_table(const fe_mesh *m, std::vector<int32_t> &tab, std::vector<int64_t> &off, int &zl);
 void nonlocal_release(fe_mesh *m);
 
 }  // namespace fe

@@ -95,6 +95,7 @@ struct StepParams {
     AxisInfo zs;  // z axis in segments of zl cells (the pipelined kernel's z segments; zl = 1: cells)
     int zl;
     const double *zero;  // >= 32 zero doubles (source of padded and absent rows)
+    int nfz;
 };
 
 template <int PREC> struct PrecTraits;
@@ -1727,23 +1728,34 @@ static hipError_t launch_pipe_p(StepParams prm, const fe_mesh *m, hipStream_t s)
 }
 
 // ------------------------------------------------------------------------
-// FP64 step kernel with direct-to-LDS prefetch (p <= 4; meshes without a
-// zero-Neumann axis, where M^-1/2 of a free node depends only on its local
-// index and folds into the cell matrix: A' = D^ (1/2 Kc) D^).
+// FP64 step kernel with direct-to-LDS prefetch and a segment table (p = 3, 4;
+// meshes without a zero-Neumann axis, where M^-1/2 of a free node depends
+// only on its local index and folds into the cell matrix:
+// A' = D^ (1/2 Kc) D^).
 //
-// Persistent workgroups walk the items (z segment of cells, 32 vectors) of
-// a colour as the pipelined kernel does, one wave per 16-row tile of A' with
-// the tile's fragments in registers.  The cell's X rows go from HBM straight
-// into LDS with 16-byte global-to-LDS loads (eight rows of 16 vectors, 128 B
-// each, per wave instruction), two positions ahead, into three LDS buffers;
-// they need no scaling, so no register holds them and nothing in flight is
-// carried from one position to the next in registers.  A position's other
-// inputs (the old value of each output, v) are loaded to registers at the
-// start of the same position and used after its product.  Rows off the cell,
-// on Dirichlet faces or beyond N read a buffer of zeros.  With z segments the
-// partial sums of a segment's inner z faces stay in an LDS hold, as in the
-// pipelined kernel; the X rows of those faces are read again (from L2, one
-// position after their first read).
+// On gfx950 the FP64 4x4x4 MFMA and every other vector instruction share the
+// SIMD's vector ALU (an FP64 MFMA holds it as long as 16 wave-wide FMA
+// instructions would), and a wave issues about one instruction per four
+// cycles, so every instruction a wave spends per cell position besides its
+// products is taken from them.  This kernel keeps that count small:
+// - the X rows go from HBM straight into LDS with 16-byte global-to-LDS
+//   requests, two positions ahead, into three LDS buffers (no staging
+//   arithmetic; with the folded cell matrix they need no scaling);
+// - everything a position needs to know about its cell comes from one 8-byte
+//   entry per z segment of a colour, built on the host: the DoF of the
+//   segment's first node and masks of the cell faces that are shared with a
+//   cell of an earlier colour, lie on a Dirichlet face, or wrap on a periodic
+//   axis.  A row's DoF is then the cell's first DoF plus a per-lane constant
+//   (minus a per-lane wrap correction where the mask says so), and its
+//   first-writer and validity tests are its per-lane face bits against those
+//   masks: no per-row index arithmetic, no colour logic, no divisions.
+// Persistent workgroups walk the items (z segment of cells, 32 vectors; N a
+// multiple of 32, the launcher hands the rest to another kernel) of a colour
+// as the pipelined kernel does, one wave per 16-row tile of A' with the
+// tile's fragments in registers.  A position's old values and v are
+// loaded to registers at its start and used after its product; with z
+// segments the partial sums of a segment's inner z faces stay in an LDS hold
+// (the X rows of those faces are read again, from L2).
 //
 // Per position t: the old values and v of t are requested, then the X rows of
 // t + 2 (into buffer (t + 2) % 3, free since the barrier that ended t - 1);
@@ -1751,12 +1763,20 @@ static hipError_t launch_pipe_p(StepParams prm, const fe_mesh *m, hipStream_t s)
 // four newest requests (the X rows of t + 2) covers both the old values of t
 // and the X rows of t + 1 (requested before them); then the epilogue, the
 // stores, and one barrier that makes every wave's X rows of t + 1 visible.
-template <int P> struct DmaShape {
+template <int P> struct TabShape {
     static constexpr int NCP = ((P + 1) * (P + 1) * (P + 1) + 31) / 32 * 32, NT = NCP / 16, NKS = NCP / 4;
-    static constexpr int W = NT, G = 2, NB = 3, XS = NCP * 16;  // waves, 16-vector groups, buffers, doubles per group
-    static constexpr size_t xbytes = (size_t)NB * G * XS * sizeof(double);
-    static constexpr size_t hbytes = (size_t)2 * (P + 1) * (P + 1) * 16 * G * sizeof(double);
+    static constexpr int W = NT, G = 2, XS = NCP * 16;  // waves; 16-vector groups per item; doubles per group
 };
+
+// Segment-table entry: .x the DoF of local node 0 of the segment's first
+// cell (its free-index arithmetic extended below 0 on a Dirichlet face),
+// .y face masks (bit order lo x, hi x, lo y, hi y, lo z, hi z):
+//   bits 0-5   faces shared with a cell of an earlier colour (z: the
+//              segment's first cell's lo face, last cell's hi face)
+//   bits 6-11  faces on a Dirichlet boundary (z: as above)
+//   bits 12-17 faces that wrap on a periodic axis (hi faces only; z: the
+//              segment's last cell)
+enum : int { SEG_FM = 0, SEG_DM = 6, SEG_WM = 12 };
 
 // s_waitcnt immediates: vector-memory counter <= n, the other counters free;
 // LDS counter 0, the other counters free
@@ -1774,38 +1794,70 @@ __device__ __forceinline__ void lds_store16(double *p, double a, double b) {
     asm volatile("ds_write_b128 %0, %1" : : "v"(off), "v"(v) : "memory");
 }
 
-// DoF of padded row r of a cell (-1 off the cell or on a Dirichlet face)
-template <int P> __device__ __forceinline__ int node_index(const StepParams &k, const ItemCell &c, int r) {
-    constexpr int N1 = P + 1, NC = N1 * N1 * N1;
-    const int l = min(r, NC - 1);
-    const int t0 = axis_free_index32(k.ax[0], P, c.cx * P + l % N1);
-    const int t1 = axis_free_index32(k.ax[1], P, c.cy * P + (l / N1) % N1);
-    const int t2 = axis_free_index32(k.ax[2], P, c.cz * P + l / (N1 * N1));
-    const bool ok = r < NC && t0 >= 0 && t1 >= 0 && t2 >= 0;
-    return ok ? t0 + (int)k.nfx * (t1 + (int)k.nfy * t2) : -1;
+// a where c, else b, as two lane selects written out, so that the compiler
+// keeps a select of request addresses a select instead of splitting the
+// request under two execution masks (then it can no longer count the
+// requests in flight and waits for all of them); all lanes active
+__device__ __forceinline__ const double *select_ptr(bool c, const double *a, const double *b) {
+    const uint64_t m = __builtin_amdgcn_ballot_w64(c);
+    const uint64_t pa = reinterpret_cast<uint64_t>(a), pb = reinterpret_cast<uint64_t>(b);
+    uint32_t lo, hi;
+    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(lo) : "v"((uint32_t)pb), "v"((uint32_t)pa), "s"(m));
+    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(hi) : "v"((uint32_t)(pb >> 32)), "v"((uint32_t)(pa >> 32)), "s"(m));
+    return reinterpret_cast<const double *>(((uint64_t)hi << 32) | lo);
 }
 
+// Launch constants of one padded row r of the cell for one lane: element
+// offset of the row within a block relative to the cell's local node 0
+// (in-order DoF offset times the leading dimension, plus the lane's column),
+// DoF offset, and face bits (bit 6: a padding row past (p+1)^3).
+template <int P> struct TabRow {
+    int64_t e;
+    int off, faces;
+    __device__ __forceinline__ void init(const StepParams &k, int r, int col) {
+        constexpr int N1 = P + 1, NC = N1 * N1 * N1;
+        const int l = min(r, NC - 1);
+        const int i = l % N1, j = (l / N1) % N1, kk = l / (N1 * N1);
+        off = i + (int)k.nfx * (j + (int)k.nfy * kk);
+        e = (int64_t)off * k.ldx + col;
+        faces = r < NC ? ((i == 0 ? 1 : 0) | (i == P ? 2 : 0) | (j == 0 ? 4 : 0) | (j == P ? 8 : 0) |
+                          (kk == 0 ? 16 : 0) | (kk == P ? 32 : 0))
+                       : 64;
+    }
+    // DoF correction of a row on a wrapping hi face (wm: the position's wrap mask)
+    __device__ __forceinline__ int wrap(const StepParams &k, int wm) const {
+        const int w = faces & wm;
+        return ((w & 2) ? (int)k.nfx : 0) + ((w & 8) ? (int)(k.nfx * k.nfy) : 0) +
+               ((w & 32) ? (int)(k.nfx * k.nfy) * k.nfz : 0);
+    }
+};
+
 template <int P, bool ZS>
-__global__ __launch_bounds__(64 * DmaShape<P>::W) __attribute__((amdgpu_waves_per_eu(1, 2)))
-void step_dma_kernel(StepParams k, int64_t nitems) {
-    typedef DmaShape<P> S;
-    constexpr int N1 = P + 1, NC = N1 * N1 * N1, NKS = S::NKS, G = S::G, XS = S::XS;
+__global__ __launch_bounds__(64 * TabShape<P>::W) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nitems) {
+    typedef TabShape<P> S;
+    constexpr int N1 = P + 1, NKS = S::NKS, G = S::G, XS = S::XS;
     constexpr int HS = N1 * N1 * 16 * G;  // doubles per hold buffer
     // three X buffers [G][NCP][16] as distinct arrays, each named at compile
     // time by the position it serves, so that the compiler sees that a
     // product's LDS reads and the X requests in flight touch different
-    // buffers; the hold [2][N1*N1][16G]
+    // buffers; the hold [2][N1*N1][16G] followed by 32 zeros (the hold term
+    // of rows that take none; every hold read is based on the one array, so
+    // that the compiler sees it apart from the X requests in flight)
     __shared__ __align__(16) double xb0[G * XS], xb1[G * XS], xb2[G * XS];
-    __shared__ __align__(16) double hold[ZS ? 2 * HS : 2];
+    __shared__ __align__(16) double hold[2 * HS + 32];
 
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    if ((int64_t)blockIdx.x >= nitems) return;  // whole workgroup
+    if (tid < 32) hold[2 * HS + tid] = 0.0;
     const int ngroups = (k.nchunk + G - 1) / G;
     const int stride = (int)gridDim.x;
-    if ((int64_t)blockIdx.x >= nitems) return;  // whole workgroup
+    const int sdiv = stride / ngroups, smod = stride % ngroups;
     const int zl = ZS ? k.zl : 1;
     const int npos = (int)((nitems - 1 - blockIdx.x) / stride + 1) * zl;  // < 2^31, as items per launch
-    auto item_of = [&](int t) { return (int)blockIdx.x + (ZS ? t / zl : t) * stride; };
-    auto cell_of = [&](int t) { return ZS ? t % zl : 0; };
+    const int zstep = P * (int)(k.nfx * k.nfy);  // DoF step from a cell to the next along z
+    const int64_t ld = k.ldx;                    // one leading dimension for X, Y and the previous iterate
     // the wave's row tile of A', resident for the launch
     double ar[NKS];
     {
@@ -1813,76 +1865,115 @@ void step_dma_kernel(StepParams k, int64_t nitems) {
 #pragma unroll
         for (int s = 0; s < NKS; ++s) ar[s] = A[s * 64];
     }
-    // X rows of position tp into buffer bufp: lane l of the wave's
-    // instruction (h, g) carries row 16 wave + 8 h + l / 8, vectors
-    // 16 g + 2 (l % 8) + {0, 1} of the item's group
-    auto prefetch = [&](int tp, double *__restrict__ bufp) {
-        const int it = item_of(tp);
-        const int grp = it % ngroups;
-        int seg;
-        const ItemCell cc = seg_cell(k, it / ngroups, cell_of(tp), seg);
+    // the row this lane's accumulators hold (vectors vq + pipe_off(q) of each
+    // 16-vector group) and the two rows it requests X for (rows 16 wave +
+    // 8 h + l / 8, vectors 2 (l % 8) + {0, 1} of each group)
+    const int r = 16 * wave + pipe_row<0>(lane);
+    const int vq = pipe_vec<0>(lane);
+    TabRow<P> R, Q[2];
+    R.init(k, r, vq);
+    Q[0].init(k, 16 * wave + (lane >> 3), 2 * (lane & 7));
+    Q[1].init(k, 16 * wave + 8 + (lane >> 3), 2 * (lane & 7));
+    const bool lo_z = (R.faces & 16) != 0, hi_z = (R.faces & 32) != 0;
+    // LDS byte offsets of the lane's accumulator row: in an X buffer, in a
+    // hold buffer as a bottom-face row and as a top-face row
+    const int xo = r * 16 + vq;
+    const int ho_bot = r * 16 * G + vq, ho_top = (r - P * N1 * N1) * 16 * G + vq;
+    const double *ob = k.Ym1 ? k.Ym1 : k.X;
+    const double nbeta = k.Ym1 ? -k.beta : 0.0;
+
+    // a walk position: z segment s of the colour, vector group grp, cell c
+    // of the segment; e its segment's table entry
+    struct Pos {
+        int s, grp, c;
+        int2 e;
+    };
+    auto advance = [&](Pos p) {
+        if (++p.c == zl) {
+            p.c = 0;
+            p.s += sdiv;
+            p.grp += smod;
+            if (p.grp >= ngroups) {
+                p.grp -= ngroups;
+                ++p.s;
+            }
+            p.e = segtab[p.s];
+        }
+        return p;
+    };
+    // what a position needs (uniform): element offset of its cell's node 0
+    // and first vector, DoF of node 0, face masks with the z bits that apply
+    // at its place in the segment
+    struct Cell {
+        int64_t U;
+        int I0, fm, dm, wm;
+    };
+    auto cell = [&](const Pos &p) {
+        Cell q;
+        q.I0 = p.e.x + p.c * zstep;
+        q.U = (int64_t)q.I0 * ld + (int64_t)p.grp * G * 16;
+        const int zhi = p.c == zl - 1 ? 32 : 0, zm = 0xF | (p.c == 0 ? 16 : 0) | zhi;
+        q.fm = (p.e.y >> SEG_FM) & zm;
+        q.dm = (p.e.y >> SEG_DM) & zm;
+        q.wm = (p.e.y >> SEG_WM) & (0xF | zhi);
+        return q;
+    };
+    // X rows of a position into buffer bufp.  Padding rows take the row of
+    // the cell's last node (their columns of A' are zero), which exists when
+    // no face of the cell is on a Dirichlet boundary or wraps; otherwise they
+    // come from the zero buffer, as the rows on a Dirichlet face do.
+    auto prefetch = [&](const Cell &q, double *__restrict__ bufp) {
+        const int col = 2 * (lane & 7);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int rr = 16 * wave + 8 * h + (lane >> 3);
-            const int I = node_index<P>(k, cc, rr);
+            const double *src0 = k.X + (q.U + Q[h].e);
+            if (q.dm | q.wm)  // uniform: a cell on a Dirichlet face or a periodic wrap
+                src0 = select_ptr((Q[h].faces & (q.dm | 64)) == 0,
+                                  k.X + (q.U + Q[h].e - (int64_t)Q[h].wrap(k, q.wm) * ld), k.zero + col);
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int64_t col = (int64_t)grp * G * 16 + 16 * g + 2 * (lane & 7);
-                const double *src = (I >= 0 && col < k.N) ? k.X + (int64_t)I * k.ldx + col : k.zero + 2 * (lane & 7);
-                __builtin_amdgcn_global_load_lds(src, bufp + g * XS + (16 * wave + 8 * h) * 16, 16, 0, 0);
-            }
+            for (int g = 0; g < G; ++g)
+                __builtin_amdgcn_global_load_lds(src0 + 16 * g, bufp + g * XS + (16 * wave + 8 * h) * 16, 16, 0, 0);
         }
         asm volatile("" ::: "memory");
     };
-    const int r = 16 * wave + pipe_row<0>(lane);  // the row this lane's accumulators hold
-    const int vq = pipe_vec<0>(lane);
-    const double *ob = k.Ym1 ? k.Ym1 : k.X;
-    const int64_t ol = k.Ym1 ? k.ldm : k.ldx;
 
-    // position t: product from xs, X rows of t + 2 into xn; false after the last
-    auto body = [&](int t, const double *__restrict__ xs, double *__restrict__ xn,
-                    double *__restrict__ hd) -> bool {
-        // this position's row: node, first-writer test, segment faces
-        const int it = item_of(t);
-        const int grp = it % ngroups;
-        const int c = cell_of(t);
-        int seg;
-        const ItemCell cc = seg_cell(k, it / ngroups, c, seg);
-        const int I = node_index<P>(k, cc, r);
-        const int l = min(r, NC - 1);
-        const int lz = l / (N1 * N1);
-        const bool f0 = axis_first_sel(k.ax[0], P, cc.cx, l % N1);
-        const bool f1 = axis_first_sel(k.ax[1], P, cc.cy, (l / N1) % N1);
-        bool f2, bot, top;
-        if constexpr (ZS) {
-            // along z only the segment's end faces meet other workgroups
-            const int iz = lz == 0 ? (c == 0 ? 0 : -1) : lz == P ? (c == k.zl - 1 ? P : -1) : -1;
-            f2 = axis_first_sel(k.zs, P, seg, iz);
-            bot = r < NC && lz == 0 && c > 0;
-            top = r < NC && lz == P && c < k.zl - 1;
-        } else {
-            f2 = axis_first_sel(k.ax[2], P, cc.cz, lz);
-            bot = top = false;
+    // position t (cell cur): product from xs, X rows of t + 2 (n2, the
+    // position after n1) into xn; false after the last position
+    auto body = [&](int t, const Pos &cur, const Pos &n1, Pos &n2, const double *__restrict__ xs,
+                    double *__restrict__ xn, double *__restrict__ hd) -> bool {
+        const Cell e = cell(cur);
+        // the accumulator row: DoF, element offset, validity, first writer
+        int I = e.I0 + R.off;
+        int64_t E = e.U + R.e;
+        bool valid = R.faces < 64;
+        if (e.dm | e.wm) {  // uniform
+            const int w = R.wrap(k, e.wm);
+            I -= w;
+            E -= (int64_t)w * ld;
+            valid = (R.faces & (e.dm | 64)) == 0;
         }
-        const bool fst = (r < NC) & f0 & f1 & f2;
-        const int64_t v0 = (int64_t)grp * G * 16 + vq;
-        // old values: Y where an earlier colour has written the node, else the
-        // previous iterate; rows that need none (off the cell or on a
-        // Dirichlet face, a later cell's bottom face, a first writer without
-        // a previous iterate) read the zero buffer.  All loads unconditional.
-        const int64_t Ic = max(I, 0);
-        const bool none = I < 0 || bot || (fst && !k.Ym1);
-        const double *orow = none ? k.zero : fst ? ob + Ic * ol : k.Y + Ic * k.ldy;
-        const double vraw = k.v[Ic];
+        const bool bot = ZS && lo_z && cur.c > 0;
+        const bool top = ZS && hi_z && cur.c < zl - 1;
+        const bool fst = valid && (R.faces & e.fm) == 0 && !bot;
+        // old values: the previous iterate for a first writer, else Y (an
+        // earlier colour has written the node); none for rows off the cell,
+        // a later cell's bottom face (its hold carries them) or a first
+        // writer without a previous iterate
+        const bool none = !valid || bot || (fst && !k.Ym1);
+        const double *orow = none ? k.zero : (fst ? ob : k.Y) + E;
+        const double vraw = k.v[valid ? I : 0];
         double o[G][4];
 #pragma unroll
-        for (int g = 0; g < G; ++g)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) o[g][q] = orow[none ? 0 : min(v0 + 16 * g + pipe_off(q), k.N - 1)];
+        for (int g = 0; g < G; ++g) {
+            const double2 a = *reinterpret_cast<const double2 *>(orow + 16 * g);
+            const double2 b = *reinterpret_cast<const double2 *>(orow + 16 * g + 8);
+            o[g][0] = a.x; o[g][1] = a.y; o[g][2] = b.x; o[g][3] = b.y;
+        }
         asm volatile("" ::: "memory");  // these requests go out before the X rows of t + 2
         // X rows two positions ahead (past the walk's end the last position's
         // rows again, into the free buffer, which nobody reads afterwards)
-        prefetch(min(t + 2, npos - 1), xn);
+        n2 = t + 2 < npos ? advance(n1) : n1;
+        prefetch(cell(n2), xn);
         double acc[G][4];
 #pragma unroll
         for (int g = 0; g < G; ++g)
@@ -1919,63 +2010,39 @@ void step_dma_kernel(StepParams k, int64_t nitems) {
         for (int g = 0; g < G; ++g)
 #pragma unroll
             for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(o[g][q]));
-        // epilogue: first writer alpha (v - c) x - beta y_{k-1} (x raw, from
-        // the buffer), else the old value, or the hold for a later cell's
-        // bottom face
-        const double vI = (I >= 0 && fst) ? vr : 0.0;
-        const double sc = k.alpha * (vI - k.shift);
-        const bool useo = !fst || k.Ym1 != nullptr;
+        // epilogue, one form for every row:
+        //   out = alpha acc + (s x + (gamma o + h))
+        // first writer: s = alpha (v - c), gamma = -beta, h = 0 (x raw from
+        // the buffer); a later cell's bottom face: s = 0, o = 0, h = the
+        // hold; any other row: s = 0, gamma = 1, h = 0
+        const double sl = fst ? k.alpha * (vr - k.shift) : 0.0;
+        const double gl = fst ? nbeta : 1.0;
+        const double *hrow = hd + (bot ? ((t - 1) & 1) * HS + ho_bot : 2 * HS);
         double out[G][4];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            double bo[4];
-            if (ZS && bot) {
-                const double *h = hd + ((t - 1) & 1) * HS + r * 16 * G + vq + 16 * g;
-                const double2 u = *reinterpret_cast<const double2 *>(h);
-                const double2 w = *reinterpret_cast<const double2 *>(h + 8);
-                bo[0] = u.x; bo[1] = u.y; bo[2] = w.x; bo[3] = w.y;
-            } else {
-                const double *xr = xs + g * XS + r * 16 + vq;
-                const double2 x01 = *reinterpret_cast<const double2 *>(xr);
-                const double2 x23 = *reinterpret_cast<const double2 *>(xr + 8);
-                const double xv[4] = {x01.x, x01.y, x23.x, x23.y};
+            const double2 x01 = *reinterpret_cast<const double2 *>(xs + g * XS + xo);
+            const double2 x23 = *reinterpret_cast<const double2 *>(xs + g * XS + xo + 8);
+            const double2 h01 = *reinterpret_cast<const double2 *>(hrow + 16 * g);
+            const double2 h23 = *reinterpret_cast<const double2 *>(hrow + 16 * g + 8);
+            const double xv[4] = {x01.x, x01.y, x23.x, x23.y}, hv[4] = {h01.x, h01.y, h23.x, h23.y};
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const bool ok = I >= 0 && v0 + 16 * g + pipe_off(q) < k.N;
-                    const double x = ok ? xv[q] : 0.0;
-                    const double oo = (ok && useo) ? o[g][q] : 0.0;
-                    double base = sc * x;
-                    if (k.Ym1) base -= k.beta * oo;
-                    bo[q] = fst ? base : oo;
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) out[g][q] = bo[q] + k.alpha * acc[g][q];
+            for (int q = 0; q < 4; ++q)
+                out[g][q] = __builtin_fma(k.alpha, acc[g][q], __builtin_fma(sl, xv[q], __builtin_fma(gl, o[g][q], hv[q])));
         }
-        if (ZS && top) {
-            double *h = hd + (t & 1) * HS + (r - P * N1 * N1) * 16 * G + vq;
+        if (top) {
+            double *h = hd + (t & 1) * HS + ho_top;
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 lds_store16(h + 16 * g, out[g][0], out[g][1]);
                 lds_store16(h + 16 * g + 8, out[g][2], out[g][3]);
             }
-        } else if (I >= 0) {
-            double *yrow = k.Y + (int64_t)I * k.ldy;
-            if (wide_ok(k, v0 - vq, 16 * G)) {
+        } else if (valid) {
+            double *yrow = k.Y + E;
 #pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    double *yp = yrow + v0 + 16 * g;
-                    *reinterpret_cast<double2 *>(yp) = double2{out[g][0], out[g][1]};
-                    *reinterpret_cast<double2 *>(yp + 8) = double2{out[g][2], out[g][3]};
-                }
-            } else {
-#pragma unroll
-                for (int g = 0; g < G; ++g)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int64_t vec = v0 + 16 * g + pipe_off(q);
-                        if (vec < k.N) yrow[vec] = out[g][q];
-                    }
+            for (int g = 0; g < G; ++g) {
+                *reinterpret_cast<double2 *>(yrow + 16 * g) = double2{out[g][0], out[g][1]};
+                *reinterpret_cast<double2 *>(yrow + 16 * g + 8) = double2{out[g][2], out[g][3]};
             }
         }
         // every wave's LDS writes done, then the barrier; the X rows of t + 1
@@ -1987,31 +2054,38 @@ void step_dma_kernel(StepParams k, int64_t nitems) {
         return t + 1 < npos;
     };
 
-    prefetch(0, xb0);
-    prefetch(min(1, npos - 1), xb1);
+    Pos p0, p1, p2;
+    {
+        const int it = (int)blockIdx.x;
+        p0.s = it / ngroups;
+        p0.grp = it % ngroups;
+        p0.c = 0;
+        p0.e = segtab[p0.s];
+    }
+    p1 = npos > 1 ? advance(p0) : p0;
+    prefetch(cell(p0), xb0);
+    prefetch(cell(p1), xb1);
     __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
     asm volatile("" ::: "memory");
     __syncthreads();
     // the walk, three positions per round so that each buffer is named
     for (int t = 0;; t += 3) {
-        if (!body(t, xb0, xb2, hold)) break;
-        if (!body(t + 1, xb1, xb0, hold)) break;
-        if (!body(t + 2, xb2, xb1, hold)) break;
+        if (!body(t, p0, p1, p2, xb0, xb2, hold)) break;
+        if (!body(t + 1, p1, p2, p0, xb1, xb0, hold)) break;
+        if (!body(t + 2, p2, p0, p1, xb2, xb1, hold)) break;
     }
 }
 
 template <int P, bool ZS>
-static hipError_t launch_dma_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
-    typedef DmaShape<P> S;
+static hipError_t launch_tab_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
+    typedef TabShape<P> S;
     constexpr int W = S::W, G = S::G;
-    const size_t smem = 0;  // static LDS only
     static bool attr = false;
     static int resident = 0;
     if (!attr) {
-        hipError_t e;
         int per_cu = 0, dev = 0, cus = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(&step_dma_kernel<P, ZS>), 64 * W, smem);
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(&step_tab_kernel<P, ZS>), 64 * W, 0);
         if (e != hipSuccess) return e;
         e = hipGetDevice(&dev);
         if (e != hipSuccess) return e;
@@ -2021,47 +2095,105 @@ static hipError_t launch_dma_p(StepParams prm, const fe_mesh *m, hipStream_t s) 
         attr = true;
     }
     prm.A = m->d_Af64s;
-    prm.zl = ZS ? zseg_length(m) : 1;
-    prm.zs = prm.ax[2];
-    prm.zs.ncell = prm.ax[2].ncell / prm.zl;
-    prm.zs.ncol = (prm.zs.bc == FE_BC_PERIODIC && (prm.zs.ncell & 1)) ? 3 : prm.zs.ncell >= 2 ? 2 : 1;
+    prm.zl = m->seg_zl;
+    prm.nfz = (int)m->nf[2];
     const int ngroups = (prm.nchunk + G - 1) / G;
-    for (int c2 = 0; c2 < prm.zs.ncol; ++c2)
-        for (int c1 = 0; c1 < m->ncol[1]; ++c1)
-            for (int c0 = 0; c0 < m->ncol[0]; ++c0) {
-                int col[3] = {c0, c1, c2};
-                int64_t cells = 1;
-                for (int a = 0; a < 3; ++a) {
-                    const AxisInfo &ax = a == 2 ? prm.zs : prm.ax[a];
-                    int cnt;
-                    if (col[a] == 2) cnt = 1;
-                    else {
-                        int limit = ax.ncol == 3 ? ax.ncell - 1 : ax.ncell;
-                        cnt = limit > col[a] ? (limit - col[a] + 1) / 2 : 0;
-                    }
-                    prm.col[a] = col[a];
-                    prm.cnt[a] = cnt;
-                    cells *= cnt;
-                }
-                if (cells == 0) continue;
-                const int64_t nitems = cells * ngroups;
-                const int64_t grid = std::min<int64_t>(nitems, resident);
-                hipLaunchKernelGGL((step_dma_kernel<P, ZS>), dim3((unsigned)grid), dim3(64 * W), smem, s, prm, nitems);
-                hipError_t e = hipGetLastError();
-                if (e != hipSuccess) return e;
-            }
+    for (size_t col = 0; col + 1 < m->seg_off.size(); ++col) {
+        const int64_t segs = m->seg_off[col + 1] - m->seg_off[col];
+        if (segs == 0) continue;
+        const int2 *tab = reinterpret_cast<const int2 *>(m->d_segtab) + m->seg_off[col];
+        const int64_t nitems = segs * ngroups;
+        const int64_t grid = std::min<int64_t>(nitems, resident);
+        hipLaunchKernelGGL((step_tab_kernel<P, ZS>), dim3((unsigned)grid), dim3(64 * W), 0, s, prm, tab, nitems);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     return hipSuccess;
 }
 
-// Whether the direct-to-LDS kernel applies: FP64 products, real mode, folded
-// cell matrix (no Neumann axis), and 16-byte loads at every row and column
-// pair (blocks 16-byte aligned, even leading dimensions and N).
+// Segment table of the table kernel (host): for every colour pass, in launch
+// order, the z segments of that colour in the order the pipelined kernel
+// walks them, one entry each (see SEG_FM / SEG_DM / SEG_WM).  Empty when the
+// kernel does not apply to the mesh.
+void build_segment_table(const fe_mesh *m, std::vector<int32_t> &tab, std::vector<int64_t> &off, int &zl_out) {
+    tab.clear();
+    off.assign(1, 0);
+    const int P = m->p;
+    const int zl = zseg_length(m);
+    zl_out = zl;
+    AxisInfo ax[3];
+    for (int d = 0; d < 3; ++d) {
+        ax[d].ncell = m->ncell[d];
+        ax[d].nfree = (int)m->nf[d];
+        ax[d].bc = m->bc[d];
+        ax[d].ncol = m->ncol[d];
+    }
+    AxisInfo zs = ax[2];
+    zs.ncell = ax[2].ncell / zl;
+    zs.ncol = (zs.bc == FE_BC_PERIODIC && (zs.ncell & 1)) ? 3 : zs.ncell >= 2 ? 2 : 1;
+    auto colour_of = [](const AxisInfo &a, int c) { return (a.ncol == 3 && c == a.ncell - 1) ? 2 : (c & 1); };
+    // whether the neighbour across face lo (i = 0) or hi of cell c exists and has a lower colour
+    auto shared_earlier = [&](const AxisInfo &a, int c, bool hi) {
+        int nb = hi ? c + 1 : c - 1;
+        bool wrap = false;
+        if (nb < 0) { nb = a.ncell - 1; wrap = true; }
+        if (nb >= a.ncell) { nb = 0; wrap = true; }
+        const bool exists = !wrap || a.bc == FE_BC_PERIODIC;
+        return exists && colour_of(a, nb) < colour_of(a, c);
+    };
+    auto first_free = [&](const AxisInfo &a, int c) { return c * P - (a.bc == FE_BC_DIRICHLET ? 1 : 0); };
+    for (int c2 = 0; c2 < zs.ncol; ++c2)
+        for (int c1 = 0; c1 < ax[1].ncol; ++c1)
+            for (int c0 = 0; c0 < ax[0].ncol; ++c0) {
+                const int col[3] = {c0, c1, c2};
+                int cnt[3];
+                for (int a = 0; a < 3; ++a) {
+                    const AxisInfo &A = a == 2 ? zs : ax[a];
+                    if (col[a] == 2) cnt[a] = 1;
+                    else {
+                        const int limit = A.ncol == 3 ? A.ncell - 1 : A.ncell;
+                        cnt[a] = limit > col[a] ? (limit - col[a] + 1) / 2 : 0;
+                    }
+                }
+                for (int iz = 0; iz < cnt[2]; ++iz)
+                    for (int iy = 0; iy < cnt[1]; ++iy)
+                        for (int ix = 0; ix < cnt[0]; ++ix) {
+                            const int cx = col[0] == 2 ? ax[0].ncell - 1 : col[0] + 2 * ix;
+                            const int cy = col[1] == 2 ? ax[1].ncell - 1 : col[1] + 2 * iy;
+                            const int seg = col[2] == 2 ? zs.ncell - 1 : col[2] + 2 * iz;
+                            const int I0 = first_free(ax[0], cx) +
+                                           (int)m->nf[0] * (first_free(ax[1], cy) + (int)m->nf[1] * first_free(ax[2], seg * zl));
+                            int fm = 0, dm = 0, wm = 0;
+                            const int cc[2] = {cx, cy};
+                            for (int a = 0; a < 2; ++a) {
+                                fm |= (shared_earlier(ax[a], cc[a], false) ? 1 : 0) << (2 * a);
+                                fm |= (shared_earlier(ax[a], cc[a], true) ? 2 : 0) << (2 * a);
+                                if (ax[a].bc == FE_BC_DIRICHLET) {
+                                    dm |= (cc[a] == 0 ? 1 : 0) << (2 * a);
+                                    dm |= (cc[a] == ax[a].ncell - 1 ? 2 : 0) << (2 * a);
+                                }
+                                if (ax[a].bc == FE_BC_PERIODIC) wm |= (cc[a] == ax[a].ncell - 1 ? 2 : 0) << (2 * a);
+                            }
+                            fm |= (shared_earlier(zs, seg, false) ? 16 : 0) | (shared_earlier(zs, seg, true) ? 32 : 0);
+                            if (zs.bc == FE_BC_DIRICHLET) dm |= (seg == 0 ? 16 : 0) | (seg == zs.ncell - 1 ? 32 : 0);
+                            if (zs.bc == FE_BC_PERIODIC) wm |= seg == zs.ncell - 1 ? 32 : 0;
+                            tab.push_back(I0);
+                            tab.push_back((fm << SEG_FM) | (dm << SEG_DM) | (wm << SEG_WM));
+                        }
+                off.push_back((int64_t)tab.size() / 2);
+            }
+}
+
+// Whether the table kernel applies: FP64 products, real mode, folded cell
+// matrix and segment table (no Neumann axis, p = 3 or 4), one leading
+// dimension for X, Y and the previous iterate, and 16-byte requests at every
+// row and column pair (blocks 16-byte aligned, even leading dimension).
 static bool dma_applies(const fe_mesh *m, const StepArgs &a, fe_dtype prec) {
-    if (prec != FE_F64 || a.S || !m->d_Af64s || m->p > 4 || (a.N & 1)) return false;
+    if (prec != FE_F64 || a.S || !m->d_Af64s || !m->d_segtab || m->p < 3 || m->p > 4) return false;
     const uintptr_t ptrs = reinterpret_cast<uintptr_t>(a.X) | reinterpret_cast<uintptr_t>(a.Y) |
                            reinterpret_cast<uintptr_t>(a.Ym1 ? a.Ym1 : a.X);
-    const int64_t lds = a.ldx | a.ldy | (a.Ym1 ? a.ldm : a.ldx);
-    return (ptrs & 15) == 0 && (lds & 1) == 0;
+    const bool same_ld = a.ldy == a.ldx && (!a.Ym1 || a.ldm == a.ldx);
+    return (ptrs & 15) == 0 && (a.ldx & 1) == 0 && same_ld;
 }
 
 size_t assembled_scratch_doubles(const fe_mesh *m) {
@@ -2104,7 +2236,13 @@ hipError_t launch_step_assembled(const fe_mesh *m, const StepArgs &a, double *Zc
     }
 }
 
+static hipError_t launch_step_v(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipStream_t s, int variant);
+
 hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipStream_t s) {
+    return launch_step_v(m, a, prec, s, m->kernel_variant);
+}
+
+static hipError_t launch_step_v(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipStream_t s, int variant) {
     StepParams prm;
     prm.X = a.X; prm.ldx = a.ldx;
     prm.Y = a.Y; prm.ldy = a.ldy;
@@ -2143,7 +2281,7 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
         default: return hipErrorInvalidValue;
         }
     }
-    if (m->kernel_variant == 0 && prec == FE_F64 && prm.N == 1 && m->p <= 5) {
+    if (variant == 0 && prec == FE_F64 && prm.N == 1 && m->p <= 5) {
         switch (m->p) {
         case 1: return launch_cells_p<1>(prm, m, s);
         case 2: return launch_cells_p<2>(prm, m, s);
@@ -2153,23 +2291,29 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
         default: break;
         }
     }
-    // variant 10: the direct-to-LDS FP64 kernel (z segments), where it applies
-    if (m->kernel_variant == 10 && dma_applies(m, a, prec)) {
-        switch (m->p) {
-        case 1: return launch_dma_p<1, true>(prm, m, s);
-        case 2: return launch_dma_p<2, true>(prm, m, s);
-        case 3: return launch_dma_p<3, true>(prm, m, s);
-        case 4: return launch_dma_p<4, true>(prm, m, s);
-        default: break;
-        }
+    // variant 10: the FP64 table kernel with direct-to-LDS prefetch (z
+    // segments) on the whole 32-vector groups; the columns past the last
+    // whole group (fewer than 32) go to the z-segment pipelined kernel
+    if (variant == 10 && a.N >= 32 && dma_applies(m, a, prec)) {
+        const int64_t Nf = a.N / 32 * 32;
+        prm.N = Nf;
+        prm.nchunk = (int)(Nf / 16);
+        const hipError_t e = m->p == 3 ? launch_tab_p<3, true>(prm, m, s) : launch_tab_p<4, true>(prm, m, s);
+        if (e != hipSuccess || Nf == a.N) return e;
+        StepArgs rest = a;
+        rest.X += Nf;
+        rest.Y += Nf;
+        if (rest.Ym1) rest.Ym1 += Nf;
+        rest.N = a.N - Nf;
+        return launch_step_v(m, rest, prec, s, 9);
     }
     // the pipelined kernel walking z segments is the default at p = 4 for all
     // three product precisions, where it was measured fastest (FP64 5.7-6.0
     // against 5.9-6.1 for the one-cell pipelined kernel, FP32 4.24 against
     // 5.8, BF16 3.84 against 5.0 for the multi-chunk kernel, ms per H~X on
     // the 24x24x48-cell slab, 256 vectors)
-    const bool zseg = m->kernel_variant == 9 || (m->kernel_variant == 0 && m->p == 4);
-    if (m->kernel_variant == 7 && prec != FE_BF16) {
+    const bool zseg = variant == 9 || (variant == 0 && m->p == 4);
+    if (variant == 7 && prec != FE_BF16) {
 #define FE_PIPE(PP)                                                                       \
     case PP:                                                                              \
         return prec == FE_F64 ? launch_pipe_p<PP, 0, 2, false>(prm, m, s) : launch_pipe_p<PP, 1, 2, false>(prm, m, s);
@@ -2199,8 +2343,8 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
         }
 #undef FE_ZSEG
     }
-    if ((m->kernel_variant == 0 && prec == FE_F64) || m->kernel_variant == 6 ||
-        ((m->kernel_variant == 7 || m->kernel_variant == 9) && prec == FE_F64)) {
+    if ((variant == 0 && prec == FE_F64) || variant == 6 ||
+        ((variant == 7 || variant == 9) && prec == FE_F64)) {
         // 32 vectors per workgroup and one row tile per wave measured best
         // where the tiles fit one workgroup (p <= 5); above that two tiles
         // per wave keep the workgroup within 1024 threads
@@ -2225,9 +2369,9 @@ hipError_t launch_step(const fe_mesh *m, const StepArgs &a, fe_dtype prec, hipSt
     // variant 3/4: one cell x 2/4 chunks per workgroup; variant 0 picks the
     // multi-chunk kernel with the chunk count measured best for the precision
     // (bf16 with p >= 6 is fastest with one chunk per workgroup)
-    if ((m->kernel_variant == 0 && !(prec == FE_BF16 && m->p >= 6)) || m->kernel_variant == 3 ||
-        m->kernel_variant == 4 || m->kernel_variant == 7 || m->kernel_variant == 9) {
-        const int G = m->kernel_variant == 4 ? 4 : m->kernel_variant == 3 ? 2 : (prec == FE_BF16 ? 4 : 2);
+    if ((variant == 0 && !(prec == FE_BF16 && m->p >= 6)) || variant == 3 ||
+        variant == 4 || variant == 7 || variant == 9) {
+        const int G = variant == 4 ? 4 : variant == 3 ? 2 : (prec == FE_BF16 ? 4 : 2);
 #define FE_MC(PP)                                                                                   \
     case PP:                                                                                        \
         if (prec == FE_F64) return G == 4 ? launch_mc_p<PP, 0, 4>(prm, m, s) : launch_mc_p<PP, 0, 2>(prm, m, s); \

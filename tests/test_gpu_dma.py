@@ -1,10 +1,12 @@
-"""The FP64 step kernel with direct-to-LDS prefetch (kernel variant 10):
+"""The FP64 table kernel with direct-to-LDS prefetch (kernel variant 10):
 parity with the oracle, reproducibility, the cases where it does not apply
-(it falls back to the one-cell kernel), and walks of several segments per
-workgroup.  It multiplies with the cell matrix pre-scaled by the per-local-
-index M^-1/2 (meshes without a zero-Neumann axis), so its rounding differs
-from the other kernels'; it is compared with the oracle and with them to
-rounding."""
+(it falls back to the one-cell kernel), walks of several segments per
+workgroup, and the split of N into whole 32-vector groups (table kernel)
+and the rest (z-segment kernel).  It multiplies with the cell matrix
+pre-scaled by the per-local-index M^-1/2 (meshes without a zero-Neumann
+axis) and folds the epilogue into fused multiply-adds, so its rounding
+differs from the other kernels'; it is compared with the oracle and with
+them to rounding."""
 import math
 
 import numpy as np
@@ -32,16 +34,21 @@ def _relerr(Y, R):
 
 
 CASES = [
-    # (label, workload): Dirichlet / periodic z, segment colours, odd periodic
-    # axes, ragged vector groups (even N), p = 1..4
+    # (label, workload): Dirichlet / periodic axes (the table's Dirichlet and
+    # wrap masks), segment colours, odd periodic axes (three colours), no z
+    # segments, N with and without a rest past the last 32-vector group, and
+    # p = 1, 2 and N < 32 (the kernel does not apply: the one-cell kernel)
     ("p4-D-z12-N40", W.small_slab((3, 3, 12), p=4, N=40)),
-    ("p4-odd-periodic-x-N18", W.small_slab((3, 2, 12), p=4, N=18)),
+    ("p4-odd-periodic-x-N64", W.small_slab((3, 2, 12), p=4, N=64)),
     ("p4-periodic-z-3seg-N34", W.small_slab((2, 2, 18), p=4, N=34, bc=(W.PERIODIC,) * 3, E=0.0)),
+    ("p4-periodic-odd-all-N96", W.small_slab((3, 5, 9), p=4, N=96, bc=(W.PERIODIC,) * 3, E=0.0)),
     ("p4-no-segments-z7-N32", W.small_slab((2, 3, 7), p=4, N=32)),
-    ("p3-periodic-z-N20", W.small_slab((3, 3, 9), p=3, N=20, bc=(W.PERIODIC,) * 3, E=0.0)),
+    ("p4-DPP-N48", W.small_slab((3, 2, 8), p=4, N=48, bc=(W.DIRICHLET, W.PERIODIC, W.PERIODIC), E=0.0)),
+    ("p3-periodic-z-N52", W.small_slab((3, 3, 9), p=3, N=52, bc=(W.PERIODIC,) * 3, E=0.0)),
+    ("p3-dirichlet-all-N32", W.small_slab((3, 4, 8), p=3, N=32, bc=(W.DIRICHLET,) * 3)),
     ("p2-dirichlet-all-N64", W.small_slab((3, 4, 8), p=2, N=64, bc=(W.DIRICHLET,) * 3)),
     ("p1-N2", W.small_slab((4, 3, 12), p=1, N=2)),
-    ("p4-DPP-N16", W.small_slab((3, 2, 8), p=4, N=16, bc=(W.DIRICHLET, W.PERIODIC, W.PERIODIC), E=0.0)),
+    ("p4-N20", W.small_slab((3, 2, 8), p=4, N=20)),
 ]
 
 
@@ -72,9 +79,11 @@ def test_dma_kernel_matches_oracle_and_is_reproducible(label, wl):
 
 
 def test_dma_kernel_leading_dimension_and_padding_untouched():
-    """Blocks inside wider buffers (even leading dimension N + 6): columns
-    past N are neither read into the product nor written."""
-    wl = W.small_slab((3, 3, 12), p=4, N=22)
+    """Blocks inside wider buffers (even leading dimension N + 6, N = 40: one
+    whole group and a rest of 8): columns past N are neither read into the
+    product nor written.  The filter's work block has leading dimension N, so
+    the steps that mix the two run the one-cell kernel."""
+    wl = W.small_slab((3, 3, 12), p=4, N=40)
     op, gm = _setup(wl)
     Xh = wl.X(op.n)
     Xb = torch.full((op.n, wl.N + 6), float("nan"), dtype=torch.float64, device="cuda")
@@ -92,15 +101,15 @@ def test_dma_kernel_leading_dimension_and_padding_untouched():
 
 
 @pytest.mark.parametrize("why,wl,ld_extra", [
-    ("odd-N", W.small_slab((3, 3, 12), p=4, N=17), 0),
-    ("neumann-axis", W.small_slab((3, 2, 10), p=4, N=16, bc=(W.PERIODIC, W.DIRICHLET, W.NEUMANN)), 0),
-    ("odd-leading-dimension", W.small_slab((3, 3, 12), p=4, N=16), 1),
-    ("p5", W.small_slab((2, 2, 3), p=5, N=16), 0),
+    ("N-below-32", W.small_slab((3, 3, 12), p=4, N=17), 0),
+    ("neumann-axis", W.small_slab((3, 2, 10), p=4, N=32, bc=(W.PERIODIC, W.DIRICHLET, W.NEUMANN)), 0),
+    ("odd-leading-dimension", W.small_slab((3, 3, 12), p=4, N=32), 1),
+    ("p5", W.small_slab((2, 2, 3), p=5, N=32), 0),
 ])
 def test_dma_kernel_falls_back_where_it_does_not_apply(why, wl, ld_extra):
-    """Odd N (a 16-byte request would straddle the last column), a Neumann
-    axis (no folded cell matrix), an odd leading dimension (unaligned rows)
-    and p > 4: variant 10 runs the one-cell kernel, bit for bit."""
+    """Fewer than 32 vectors (no whole group), a Neumann axis (no folded
+    cell matrix), an odd leading dimension (unaligned rows) and p > 4:
+    variant 10 runs the one-cell kernel, bit for bit."""
     print("case: dma fallback", why, flush=True)
     op, gm = _setup(wl)
     Xb = torch.zeros((op.n, wl.N + ld_extra), dtype=torch.float64, device="cuda")
