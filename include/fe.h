@@ -98,20 +98,28 @@ fe_status fe_mesh_destroy(fe_mesh *mesh);
  * fragment read from L2 feeds 2 / 4 products (falls back to 1 when the block
  * would exceed the LDS); 6 = row-owner kernel (each thread loads
  * everything its outputs need in one round trip before the cell product;
- * the FP64 default for p != 4); 7 = persistent pipelined row-owner
- * kernel with the cell matrix in registers and the loads of the next two
- * items in flight during each cell product (FP64 and FP32, p <= 4; else 6;
- * BF16: 3); 9 = the pipelined kernel of 7 walking z segments of up to 6
- * cells (the largest length that divides the z cell count, at least two
- * segments on a periodic z axis), the faces shared inside a segment kept in
- * LDS instead of being read and written in HBM (FP64, FP32 and BF16
- * products, p <= 4, the default for all three at p = 4; else as 7).
+ * the FP64 default for p = 1, 2 and p >= 5); 7 = persistent pipelined
+ * row-owner kernel with the cell matrix in registers and the loads of the
+ * next two items in flight during each cell product (FP64 and FP32, p <= 4;
+ * else 6; BF16: 3); 9 = the pipelined kernel of 7 walking z segments of up
+ * to 6 cells (the largest length that divides the z cell count, at least
+ * two segments on a periodic z axis), the faces shared inside a segment
+ * kept in LDS instead of being read and written in HBM (FP64, FP32 and BF16
+ * products, p <= 4; the FP32 and BF16 default at p = 4; else as 7);
+ * 10 = the table kernel: the walk of 9 with the X rows copied from HBM
+ * straight into LDS two positions ahead, each position's cell read from a
+ * per-segment table of first DoF and face masks built at mesh creation, and
+ * the cell matrix pre-scaled by M^-1/2 (FP64 products, p = 3 and 4, no
+ * zero-Neumann axis, one leading dimension for X, Y and the previous
+ * iterate, 16-byte aligned blocks with an even leading dimension; applied
+ * to the whole 32-vector groups of N, the columns past the last whole group
+ * run variant 9; the FP64 default at p = 3 and 4; else as 0).
  * Variants 0, 1, 3, 4, 6 and 7 give bitwise-identical results (variant 0
- * wherever it is not variant 9); variant 9 sums each node's contributions in
- * another fixed order (equal to rounding, reproducible).  Variants 2
- * (register-resident), 5 (tiles of cells) and 8 (warp-specialised), slower
- * than the defaults everywhere, were removed: FE_EINVAL for them and for
- * values outside 0..9. */
+ * wherever it is not variant 9 or 10); variants 9 and 10 sum each node's
+ * contributions in other fixed orders (equal to rounding, reproducible).
+ * Variants 2 (register-resident), 5 (tiles of cells) and 8
+ * (warp-specialised), slower than the defaults everywhere, were removed:
+ * FE_EINVAL for them and for values outside 0..10. */
 fe_status fe_mesh_set_kernel(fe_mesh *mesh, int32_t variant);
 
 /* Sizes: free DoFs n, cells, and points per cell n_c = (p+1)^3.  Any output

@@ -1763,9 +1763,13 @@ static hipError_t launch_pipe_p(StepParams prm, const fe_mesh *m, hipStream_t s)
 // four newest requests (the X rows of t + 2) covers both the old values of t
 // and the X rows of t + 1 (requested before them); then the epilogue, the
 // stores, and one barrier that makes every wave's X rows of t + 1 visible.
-template <int P> struct TabShape {
+// Shape: TPW row tiles of A' per wave (tiles wave + W j), G 16-vector groups
+// per item; W waves; XS doubles per group of an X buffer; DMA requests per
+// position and wave (one per 8 rows and group).
+template <int P, int TPW, int NGRP> struct TabShape {
     static constexpr int NCP = ((P + 1) * (P + 1) * (P + 1) + 31) / 32 * 32, NT = NCP / 16, NKS = NCP / 4;
-    static constexpr int W = NT, G = 2, XS = NCP * 16;  // waves; 16-vector groups per item; doubles per group
+    static constexpr int W = NT / TPW, G = NGRP, XS = NCP * 16, NDMA = 2 * TPW * G;
+    static_assert(NT % TPW == 0, "row tiles split evenly over the waves");
 };
 
 // Segment-table entry: .x the DoF of local node 0 of the segment's first
@@ -1832,11 +1836,11 @@ template <int P> struct TabRow {
     }
 };
 
-template <int P, bool ZS>
-__global__ __launch_bounds__(64 * TabShape<P>::W) __attribute__((amdgpu_waves_per_eu(1, 2)))
+template <int P, int TPW, int NGRP>
+__global__ __launch_bounds__((64 * TabShape<P, TPW, NGRP>::W)) __attribute__((amdgpu_waves_per_eu(1, 2)))
 void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nitems) {
-    typedef TabShape<P> S;
-    constexpr int N1 = P + 1, NKS = S::NKS, G = S::G, XS = S::XS;
+    typedef TabShape<P, TPW, NGRP> S;
+    constexpr int N1 = P + 1, NKS = S::NKS, G = S::G, XS = S::XS, W = S::W, NDMA = S::NDMA;
     constexpr int HS = N1 * N1 * 16 * G;  // doubles per hold buffer
     // three X buffers [G][NCP][16] as distinct arrays, each named at compile
     // time by the position it serves, so that the compiler sees that a
@@ -1854,31 +1858,38 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nite
     const int ngroups = (k.nchunk + G - 1) / G;
     const int stride = (int)gridDim.x;
     const int sdiv = stride / ngroups, smod = stride % ngroups;
-    const int zl = ZS ? k.zl : 1;
+    const int zl = k.zl;
     const int npos = (int)((nitems - 1 - blockIdx.x) / stride + 1) * zl;  // < 2^31, as items per launch
     const int zstep = P * (int)(k.nfx * k.nfy);  // DoF step from a cell to the next along z
     const int64_t ld = k.ldx;                    // one leading dimension for X, Y and the previous iterate
-    // the wave's row tile of A', resident for the launch
-    double ar[NKS];
-    {
-        const double *A = reinterpret_cast<const double *>(k.A) + (size_t)wave * NKS * 64 + lane;
+    // the wave's row tiles of A' (tiles wave + W j), resident for the launch
+    double ar[TPW][NKS];
 #pragma unroll
-        for (int s = 0; s < NKS; ++s) ar[s] = A[s * 64];
+    for (int j = 0; j < TPW; ++j) {
+        const double *A = reinterpret_cast<const double *>(k.A) + (size_t)(wave + W * j) * NKS * 64 + lane;
+#pragma unroll
+        for (int s = 0; s < NKS; ++s) ar[j][s] = A[s * 64];
     }
-    // the row this lane's accumulators hold (vectors vq + pipe_off(q) of each
-    // 16-vector group) and the two rows it requests X for (rows 16 wave +
-    // 8 h + l / 8, vectors 2 (l % 8) + {0, 1} of each group)
-    const int r = 16 * wave + pipe_row<0>(lane);
+    // per tile: the row this lane's accumulators hold (vectors vq +
+    // pipe_off(q) of each 16-vector group) and the two rows it requests X
+    // for (rows 16 tile + 8 h + l / 8, vectors 2 (l % 8) + {0, 1} of each
+    // group)
     const int vq = pipe_vec<0>(lane);
-    TabRow<P> R, Q[2];
-    R.init(k, r, vq);
-    Q[0].init(k, 16 * wave + (lane >> 3), 2 * (lane & 7));
-    Q[1].init(k, 16 * wave + 8 + (lane >> 3), 2 * (lane & 7));
-    const bool lo_z = (R.faces & 16) != 0, hi_z = (R.faces & 32) != 0;
-    // LDS byte offsets of the lane's accumulator row: in an X buffer, in a
-    // hold buffer as a bottom-face row and as a top-face row
-    const int xo = r * 16 + vq;
-    const int ho_bot = r * 16 * G + vq, ho_top = (r - P * N1 * N1) * 16 * G + vq;
+    TabRow<P> R[TPW], Q[TPW][2];
+    bool lo_z[TPW], hi_z[TPW];
+    int xo[TPW], ho_bot[TPW], ho_top[TPW];  // offsets in an X buffer and a hold buffer
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) {
+        const int tile = wave + W * j, r = 16 * tile + pipe_row<0>(lane);
+        R[j].init(k, r, vq);
+        Q[j][0].init(k, 16 * tile + (lane >> 3), 2 * (lane & 7));
+        Q[j][1].init(k, 16 * tile + 8 + (lane >> 3), 2 * (lane & 7));
+        lo_z[j] = (R[j].faces & 16) != 0;
+        hi_z[j] = (R[j].faces & 32) != 0;
+        xo[j] = r * 16 + vq;
+        ho_bot[j] = r * 16 * G + vq;
+        ho_top[j] = (r - P * N1 * N1) * 16 * G + vq;
+    }
     const double *ob = k.Ym1 ? k.Ym1 : k.X;
     const double nbeta = k.Ym1 ? -k.beta : 0.0;
 
@@ -1925,15 +1936,19 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nite
     auto prefetch = [&](const Cell &q, double *__restrict__ bufp) {
         const int col = 2 * (lane & 7);
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const double *src0 = k.X + (q.U + Q[h].e);
-            if (q.dm | q.wm)  // uniform: a cell on a Dirichlet face or a periodic wrap
-                src0 = select_ptr((Q[h].faces & (q.dm | 64)) == 0,
-                                  k.X + (q.U + Q[h].e - (int64_t)Q[h].wrap(k, q.wm) * ld), k.zero + col);
+        for (int j = 0; j < TPW; ++j)
 #pragma unroll
-            for (int g = 0; g < G; ++g)
-                __builtin_amdgcn_global_load_lds(src0 + 16 * g, bufp + g * XS + (16 * wave + 8 * h) * 16, 16, 0, 0);
-        }
+            for (int h = 0; h < 2; ++h) {
+                const TabRow<P> &T = Q[j][h];
+                const double *src0 = k.X + (q.U + T.e);
+                if (q.dm | q.wm)  // uniform: a cell on a Dirichlet face or a periodic wrap
+                    src0 = select_ptr((T.faces & (q.dm | 64)) == 0, k.X + (q.U + T.e - (int64_t)T.wrap(k, q.wm) * ld),
+                                      k.zero + col);
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+                    __builtin_amdgcn_global_load_lds(src0 + 16 * g, bufp + g * XS + (16 * (wave + W * j) + 8 * h) * 16,
+                                                     16, 0, 0);
+            }
         asm volatile("" ::: "memory");
     };
 
@@ -1942,43 +1957,51 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nite
     auto body = [&](int t, const Pos &cur, const Pos &n1, Pos &n2, const double *__restrict__ xs,
                     double *__restrict__ xn, double *__restrict__ hd) -> bool {
         const Cell e = cell(cur);
-        // the accumulator row: DoF, element offset, validity, first writer
-        int I = e.I0 + R.off;
-        int64_t E = e.U + R.e;
-        bool valid = R.faces < 64;
-        if (e.dm | e.wm) {  // uniform
-            const int w = R.wrap(k, e.wm);
-            I -= w;
-            E -= (int64_t)w * ld;
-            valid = (R.faces & (e.dm | 64)) == 0;
-        }
-        const bool bot = ZS && lo_z && cur.c > 0;
-        const bool top = ZS && hi_z && cur.c < zl - 1;
-        const bool fst = valid && (R.faces & e.fm) == 0 && !bot;
-        // old values: the previous iterate for a first writer, else Y (an
-        // earlier colour has written the node); none for rows off the cell,
-        // a later cell's bottom face (its hold carries them) or a first
-        // writer without a previous iterate
-        const bool none = !valid || bot || (fst && !k.Ym1);
-        const double *orow = none ? k.zero : (fst ? ob : k.Y) + E;
-        const double vraw = k.v[valid ? I : 0];
-        double o[G][4];
+        const bool slow = (e.dm | e.wm) != 0;  // uniform
+        int64_t E[TPW];
+        bool valid[TPW], fst[TPW], bot[TPW], top[TPW];
+        double vraw[TPW], o[TPW][G][4];
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const double2 a = *reinterpret_cast<const double2 *>(orow + 16 * g);
-            const double2 b = *reinterpret_cast<const double2 *>(orow + 16 * g + 8);
-            o[g][0] = a.x; o[g][1] = a.y; o[g][2] = b.x; o[g][3] = b.y;
+        for (int j = 0; j < TPW; ++j) {
+            // the accumulator row: DoF, element offset, validity, first writer
+            int I = e.I0 + R[j].off;
+            E[j] = e.U + R[j].e;
+            valid[j] = R[j].faces < 64;
+            if (slow) {
+                const int w = R[j].wrap(k, e.wm);
+                I -= w;
+                E[j] -= (int64_t)w * ld;
+                valid[j] = (R[j].faces & (e.dm | 64)) == 0;
+            }
+            bot[j] = lo_z[j] && cur.c > 0;
+            top[j] = hi_z[j] && cur.c < zl - 1;
+            fst[j] = valid[j] && (R[j].faces & e.fm) == 0 && !bot[j];
+            // old values: the previous iterate for a first writer, else Y
+            // (an earlier colour has written the node); none for rows off the
+            // cell, a later cell's bottom face (its hold carries them) or a
+            // first writer without a previous iterate
+            const bool none = !valid[j] || bot[j] || (fst[j] && !k.Ym1);
+            const double *orow = none ? k.zero : (fst[j] ? ob : k.Y) + E[j];
+            vraw[j] = k.v[valid[j] ? I : 0];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const double2 a = *reinterpret_cast<const double2 *>(orow + 16 * g);
+                const double2 b = *reinterpret_cast<const double2 *>(orow + 16 * g + 8);
+                o[j][g][0] = a.x; o[j][g][1] = a.y; o[j][g][2] = b.x; o[j][g][3] = b.y;
+            }
         }
         asm volatile("" ::: "memory");  // these requests go out before the X rows of t + 2
         // X rows two positions ahead (past the walk's end the last position's
         // rows again, into the free buffer, which nobody reads afterwards)
         n2 = t + 2 < npos ? advance(n1) : n1;
         prefetch(cell(n2), xn);
-        double acc[G][4];
+        double acc[TPW][G][4];
 #pragma unroll
-        for (int g = 0; g < G; ++g)
+        for (int j = 0; j < TPW; ++j)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[g][q] = 0.0;
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[j][g][q] = 0.0;
         {
             double bc[G][4], bn[G][4];
 #pragma unroll
@@ -1989,10 +2012,12 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nite
 #pragma unroll
                     for (int g = 0; g < G; ++g) f64_pair_b(xs + g * XS, s + 1, lane, bn[g]);
 #pragma unroll
-                for (int g = 0; g < G; ++g)
+                for (int j = 0; j < TPW; ++j)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        acc[g][q] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[s], bc[g][q], acc[g][q], 0, 0, 0);
+                    for (int g = 0; g < G; ++g)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            acc[j][g][q] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[j][s], bc[g][q], acc[j][g][q], 0, 0, 0);
 #pragma unroll
                 for (int g = 0; g < G; ++g)
 #pragma unroll
@@ -2000,49 +2025,55 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nite
             }
         }
         // the old values and v of t, and the X rows of t + 1 (both requested
-        // before the four X requests of t + 2)
-        __builtin_amdgcn_s_waitcnt(vmcnt_imm(4));
+        // before the NDMA X requests of t + 2)
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm(NDMA));
         asm volatile("" ::: "memory");
         // the loaded values are used only from here on (not inside the product)
-        double vr = vraw;
-        asm volatile("" : "+v"(vr));
 #pragma unroll
-        for (int g = 0; g < G; ++g)
+        for (int j = 0; j < TPW; ++j) {
+            asm volatile("" : "+v"(vraw[j]));
 #pragma unroll
-            for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(o[g][q]));
-        // epilogue, one form for every row:
-        //   out = alpha acc + (s x + (gamma o + h))
-        // first writer: s = alpha (v - c), gamma = -beta, h = 0 (x raw from
-        // the buffer); a later cell's bottom face: s = 0, o = 0, h = the
-        // hold; any other row: s = 0, gamma = 1, h = 0
-        const double sl = fst ? k.alpha * (vr - k.shift) : 0.0;
-        const double gl = fst ? nbeta : 1.0;
-        const double *hrow = hd + (bot ? ((t - 1) & 1) * HS + ho_bot : 2 * HS);
-        double out[G][4];
+            for (int g = 0; g < G; ++g)
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const double2 x01 = *reinterpret_cast<const double2 *>(xs + g * XS + xo);
-            const double2 x23 = *reinterpret_cast<const double2 *>(xs + g * XS + xo + 8);
-            const double2 h01 = *reinterpret_cast<const double2 *>(hrow + 16 * g);
-            const double2 h23 = *reinterpret_cast<const double2 *>(hrow + 16 * g + 8);
-            const double xv[4] = {x01.x, x01.y, x23.x, x23.y}, hv[4] = {h01.x, h01.y, h23.x, h23.y};
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                out[g][q] = __builtin_fma(k.alpha, acc[g][q], __builtin_fma(sl, xv[q], __builtin_fma(gl, o[g][q], hv[q])));
+                for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(o[j][g][q]));
         }
-        if (top) {
-            double *h = hd + (t & 1) * HS + ho_top;
+#pragma unroll
+        for (int j = 0; j < TPW; ++j) {
+            // epilogue, one form for every row:
+            //   out = alpha acc + (s x + (gamma o + h))
+            // first writer: s = alpha (v - c), gamma = -beta, h = 0 (x raw
+            // from the buffer); a later cell's bottom face: s = 0, o = 0,
+            // h = the hold; any other row: s = 0, gamma = 1, h = 0
+            const double sl = fst[j] ? k.alpha * (vraw[j] - k.shift) : 0.0;
+            const double gl = fst[j] ? nbeta : 1.0;
+            const double *hrow = hd + (bot[j] ? ((t - 1) & 1) * HS + ho_bot[j] : 2 * HS);
+            double out[G][4];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                lds_store16(h + 16 * g, out[g][0], out[g][1]);
-                lds_store16(h + 16 * g + 8, out[g][2], out[g][3]);
+                const double2 x01 = *reinterpret_cast<const double2 *>(xs + g * XS + xo[j]);
+                const double2 x23 = *reinterpret_cast<const double2 *>(xs + g * XS + xo[j] + 8);
+                const double2 h01 = *reinterpret_cast<const double2 *>(hrow + 16 * g);
+                const double2 h23 = *reinterpret_cast<const double2 *>(hrow + 16 * g + 8);
+                const double xv[4] = {x01.x, x01.y, x23.x, x23.y}, hv[4] = {h01.x, h01.y, h23.x, h23.y};
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    out[g][q] = __builtin_fma(k.alpha, acc[j][g][q],
+                                              __builtin_fma(sl, xv[q], __builtin_fma(gl, o[j][g][q], hv[q])));
             }
-        } else if (valid) {
-            double *yrow = k.Y + E;
+            if (top[j]) {
+                double *h = hd + (t & 1) * HS + ho_top[j];
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                *reinterpret_cast<double2 *>(yrow + 16 * g) = double2{out[g][0], out[g][1]};
-                *reinterpret_cast<double2 *>(yrow + 16 * g + 8) = double2{out[g][2], out[g][3]};
+                for (int g = 0; g < G; ++g) {
+                    lds_store16(h + 16 * g, out[g][0], out[g][1]);
+                    lds_store16(h + 16 * g + 8, out[g][2], out[g][3]);
+                }
+            } else if (valid[j]) {
+                double *yrow = k.Y + E[j];
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    *reinterpret_cast<double2 *>(yrow + 16 * g) = double2{out[g][0], out[g][1]};
+                    *reinterpret_cast<double2 *>(yrow + 16 * g + 8) = double2{out[g][2], out[g][3]};
+                }
             }
         }
         // every wave's LDS writes done, then the barrier; the X rows of t + 1
@@ -2076,16 +2107,16 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nite
     }
 }
 
-template <int P, bool ZS>
+template <int P, int TPW, int G>
 static hipError_t launch_tab_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
-    typedef TabShape<P> S;
-    constexpr int W = S::W, G = S::G;
+    typedef TabShape<P, TPW, G> S;
+    constexpr int W = S::W;
     static bool attr = false;
     static int resident = 0;
     if (!attr) {
         int per_cu = 0, dev = 0, cus = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(&step_tab_kernel<P, ZS>), 64 * W, 0);
+            &per_cu, reinterpret_cast<const void *>(&step_tab_kernel<P, TPW, G>), 64 * W, 0);
         if (e != hipSuccess) return e;
         e = hipGetDevice(&dev);
         if (e != hipSuccess) return e;
@@ -2104,7 +2135,7 @@ static hipError_t launch_tab_p(StepParams prm, const fe_mesh *m, hipStream_t s) 
         const int2 *tab = reinterpret_cast<const int2 *>(m->d_segtab) + m->seg_off[col];
         const int64_t nitems = segs * ngroups;
         const int64_t grid = std::min<int64_t>(nitems, resident);
-        hipLaunchKernelGGL((step_tab_kernel<P, ZS>), dim3((unsigned)grid), dim3(64 * W), 0, s, prm, tab, nitems);
+        hipLaunchKernelGGL((step_tab_kernel<P, TPW, G>), dim3((unsigned)grid), dim3(64 * W), 0, s, prm, tab, nitems);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -2294,11 +2325,15 @@ static hipError_t launch_step_v(const fe_mesh *m, const StepArgs &a, fe_dtype pr
     // variant 10: the FP64 table kernel with direct-to-LDS prefetch (z
     // segments) on the whole 32-vector groups; the columns past the last
     // whole group (fewer than 32) go to the z-segment pipelined kernel
-    if (variant == 10 && a.N >= 32 && dma_applies(m, a, prec)) {
+    // (the default for FP64 at p = 3 and 4, where it was measured fastest:
+    // 1.62 / 4.73 ms per H~X against 2.02 / 5.75 for the z-segment kernel on
+    // the 24x24x48-cell slab, 256 vectors)
+    const bool tab = variant == 10 || (variant == 0 && prec == FE_F64 && (m->p == 3 || m->p == 4));
+    if (tab && a.N >= 32 && dma_applies(m, a, prec)) {
         const int64_t Nf = a.N / 32 * 32;
         prm.N = Nf;
         prm.nchunk = (int)(Nf / 16);
-        const hipError_t e = m->p == 3 ? launch_tab_p<3, true>(prm, m, s) : launch_tab_p<4, true>(prm, m, s);
+        const hipError_t e = m->p == 3 ? launch_tab_p<3, 1, 2>(prm, m, s) : launch_tab_p<4, 1, 2>(prm, m, s);
         if (e != hipSuccess || Nf == a.N) return e;
         StepArgs rest = a;
         rest.X += Nf;

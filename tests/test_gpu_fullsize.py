@@ -45,10 +45,11 @@ def test_fullsize_filter_f64_sampled_columns(cfg2):
 def test_fullsize_kernel_variants_bitwise(cfg2):
     """At the benchmark's size the one-cell FP64 variants give the same bits,
     including the persistent pipelined kernel (variant 7), whose workgroups
-    each walk about 108 items per pass.  The default, the z-segment kernel
-    (variant 9: segments of 6 cells, about 18 segments per workgroup and
-    pass), sums shared nodes in another fixed order: equal to them to
-    rounding, and to itself bit for bit."""
+    each walk about 108 items per pass.  The z-segment kernel (variant 9:
+    segments of 6 cells, about 18 segments per workgroup and pass) and the
+    default, the table kernel (variant 10: the same walk, the folded cell
+    matrix), sum shared nodes in other fixed orders: equal to them to
+    rounding, and to themselves bit for bit."""
     wl, op, gm, X, R, (a, b, a0) = cfg2
     gm.set_kernel(7)
     Y7 = gm.hx(X)
@@ -57,12 +58,15 @@ def test_fullsize_kernel_variants_bitwise(cfg2):
             print("case: fullsize variant", var, flush=True)
             gm.set_kernel(var)
             assert torch.equal(gm.hx(X), Y7), var
-        print("case: fullsize default (z segments)", flush=True)
-        gm.set_kernel(0)
-        Y0 = gm.hx(X)
+        for var in (9, 0):
+            print("case: fullsize variant", var, flush=True)
+            gm.set_kernel(var)
+            Y0 = gm.hx(X)
+            assert torch.equal(gm.hx(X), Y0)
+            rel = ((Y0 - Y7).norm(dim=0) / Y7.norm(dim=0)).max().item()
+            assert 0 < rel < 1e-13, rel
+        gm.set_kernel(10)
         assert torch.equal(gm.hx(X), Y0)
-        rel = ((Y0 - Y7).norm(dim=0) / Y7.norm(dim=0)).max().item()
-        assert 0 < rel < 1e-13, rel
     finally:
         gm.set_kernel(0)
 
@@ -107,7 +111,9 @@ def test_fullsize_bloch_sampled_rows_and_gamma():
     err = np.linalg.norm(Ys - R, axis=1) / np.linalg.norm(R, axis=1)
     print("per-row rel err max", err.max(), flush=True)
     assert err.max() < 1e-13
-    # Gamma: the degree-30 complex filter is the real one, bit for bit
+    # Gamma: the degree-30 complex filter is the real one, bit for bit (at
+    # k = 0 the complex block runs the real step kernel on its interleaved
+    # columns, here the table kernel on 256 columns against 128)
     gm.set_kpoint(0.0, 0.0)
     Yk = gm.cheb_filter_k(X, wl.m, 5.66, 315.0, 4.8)
     Yr = gm.cheb_filter(X.real.contiguous(), wl.m, 5.66, 315.0, 4.8)

@@ -121,31 +121,35 @@ def test_filter_degrees_and_leading_dimension(m):
 def test_kernel_variants_bitwise_equal(prec, p):
     """The multi-vector kernels and the one-cell-per-workgroup kernel perform
     the same operations in the same order.  The default at p = 4 is the
-    z-segment kernel (variant 9), which sums shared nodes in another order
-    (and in BF16 takes the products transposed): equal to rounding, and
-    bitwise equal to variant 9.  The removed variants are refused."""
+    table kernel (variant 10) for FP64 products and the z-segment kernel
+    (variant 9) for FP32 and BF16; both sum shared nodes in another order
+    (the table kernel also multiplies with the folded cell matrix, BF16 takes
+    the products transposed): equal to rounding, and bitwise equal to the
+    variant they run.  Where the table kernel does not apply (p = 2, 5,
+    FP32, BF16) variant 10 runs the one-cell kernel.  The removed variants
+    are refused."""
     wl = W.small_slab((3, 3, 4), p=p, N=40)
     op, gm, _ = _setup(wl)
     X = torch.from_numpy(wl.X(op.n)).cuda()
-    for gone in (2, 5, 8, 10, -1):
+    for gone in (2, 5, 8, 11, -1):
         with pytest.raises(RuntimeError, match="kernel variant"):
             gm.set_kernel(gone)
     gm.set_kernel(1)
     Y1 = gm.cheb_filter(X, 5, 2.0, 400.0, -0.5, prec=prec)
-    zseg_default = p == 4
+    tab = p == 4 and prec == "f64"
     # above p = 4 variant 9 runs what variant 7 runs (one-cell kernels)
-    for var in (0, 3, 4, 6, 7) + ((9,) if p > 4 else ()):
+    for var in (0, 3, 4, 6, 7, 10) + ((9,) if p > 4 else ()):
         gm.set_kernel(var)
         Y0 = gm.cheb_filter(X, 5, 2.0, 400.0, -0.5, prec=prec)
-        if var == 0 and zseg_default:
+        if (var == 0 and p == 4) or (var == 10 and tab):
             rel = ((Y0 - Y1).norm(dim=0) / Y1.norm(dim=0)).max().item()
-            assert rel < {"f64": 1e-13, "f32": 1e-6, "bf16": 1e-5}[prec], rel
+            assert 0 < rel < {"f64": 1e-13, "f32": 1e-6, "bf16": 1e-5}[prec], rel
         else:
             assert torch.equal(Y0, Y1), var
-    if zseg_default:
+    if p == 4:
         gm.set_kernel(0)
         Y0 = gm.cheb_filter(X, 5, 2.0, 400.0, -0.5, prec=prec)
-        gm.set_kernel(9)
+        gm.set_kernel(10 if tab else 9)
         assert torch.equal(gm.cheb_filter(X, 5, 2.0, 400.0, -0.5, prec=prec), Y0)
     gm.set_kernel(0)
 
