@@ -500,6 +500,44 @@ def poisson(mesh: Mesh, s: np.ndarray) -> np.ndarray:
     return sol[:-1]
 
 
+def cpd_constrained(mesh: Mesh, z_lo: float, z_hi: float) -> np.ndarray:
+    """Free nodes inside the conductor regions of the constrained-potential
+    setup (Sec. 2.2.2): Omega_0 = {z <= z_lo}, Omega_1 = {z >= z_hi}.
+    Returns 0 (not constrained), 1 (Omega_0) or 2 (Omega_1) per node."""
+    z = mesh.dof_coords()[:, 2]
+    return np.where(z <= z_lo, 1, np.where(z >= z_hi, 2, 0))
+
+
+def poisson_cpd(mesh: Mesh, s: np.ndarray, w: Optional[np.ndarray], z_lo: float, z_hi: float,
+                dV: float) -> np.ndarray:
+    """Sec. 2.2.2 electrostatics with constrained potential difference:
+    K phi = 4 pi M s at the nodes between the conductors, and phi prescribed
+    inside them, phi = -w on Omega_0 = {z <= z_lo} and phi = dV - w on
+    Omega_1 = {z >= z_hi}, where w = V_loc - V_sm at the nodes (None: 0), so
+    that the total potential phi + w is 0 and dV in the two conductors.
+    Rows of constrained nodes are replaced by the constraint, the rest is a
+    sparse direct solve of the remaining block (data moved to the right-hand
+    side)."""
+    import scipy.sparse.linalg as sla
+    n = mesh.n
+    K = stiffness(mesh).tocsr()
+    M = mesh.mass()
+    s = np.asarray(s, dtype=np.float64)
+    w = np.zeros(n) if w is None else np.asarray(w, dtype=np.float64)
+    reg = cpd_constrained(mesh, z_lo, z_hi)
+    C = reg > 0
+    F = ~C
+    if not C.any() or not F.any():
+        raise ValueError("the conductor regions must hold some nodes and leave some free")
+    g = np.where(reg == 2, dV, 0.0) - w
+    phi = np.empty(n)
+    phi[C] = g[C]
+    KF = K[F]
+    rhs = 4.0 * np.pi * M[F] * s[F] - KF[:, C] @ g[C]
+    phi[F] = sla.spsolve(KF[:, F].tocsc(), rhs)
+    return phi
+
+
 def stiffness(mesh: Mesh):
     """Global stiffness K (no 1/2, unscaled) as scipy CSR."""
     return CSR(lib().or_assemble(C.byref(mesh._m), 0, None, 0.0, 0.0)).to_scipy()

@@ -765,6 +765,75 @@ def test_poisson_residual_mean_and_neutralisation():
     np.testing.assert_allclose(O.poisson(m, s + 2.5), phi, atol=1e-9 * np.abs(phi).max())
 
 
+# --------------------------- constrained potential difference (Sec. 2.2.2)
+
+def test_cpd_uniform_charge_gives_the_exact_quadratic():
+    """Periodic x, y, conductors below z_lo and above z_hi on cell faces,
+    uniform charge s0, w = 0: the continuum solution between them is
+    phi = -2 pi s0 (z - z_lo)(z - z_hi) + dV (z - z_lo) / (z_hi - z_lo), a
+    quadratic that the p = 2 and p = 4 spaces hold and that GLL quadrature
+    of the uniform right-hand side integrates exactly, so the nodal values
+    are exact; phi is 0 and dV inside the conductors (no field there)."""
+    for p in (2, 4):
+        L = (2.0, 3.0, 10.0)
+        m = _mesh(L, (2, 3, 10), p, (1, 1, 2))
+        z = m.dof_coords()[:, 2]
+        z_lo, z_hi, s0, dV = 2.0, 7.0, 0.013, -0.4
+        phi = O.poisson_cpd(m, np.full(m.n, s0), None, z_lo, z_hi, dV)
+        exact = np.where(z <= z_lo, 0.0, np.where(z >= z_hi, dV,
+                         -2 * np.pi * s0 * (z - z_lo) * (z - z_hi) + dV * (z - z_lo) / (z_hi - z_lo)))
+        assert np.abs(phi - exact).max() < 1e-12, p
+        reg = O.cpd_constrained(m, z_lo, z_hi)
+        assert (phi[reg == 1] == 0.0).all() and (phi[reg == 2] == dV).all()
+
+
+def test_cpd_conductor_data_enter_as_the_total_potential():
+    """No charge, w = V_loc - V_sm varying in z and x inside the conductors:
+    the constraint holds phi + w at 0 and dV there, and between the
+    conductors phi is the linear interpolant of the two planes' values
+    (w constant over each boundary plane)."""
+    L = (3.0, 2.0, 9.0)
+    m = _mesh(L, (3, 2, 9), 3, (1, 1, 2))
+    xyz = m.dof_coords()
+    x, z = xyz[:, 0], xyz[:, 2]
+    z_lo, z_hi, dV = 3.0, 6.0, 0.25
+    # w constant on the planes z = z_lo and z = z_hi, varying elsewhere
+    w = 0.1 * np.cos(2 * np.pi * x / L[0]) * (z - z_lo) * (z - z_hi) + 0.05 + 0.02 * z
+    phi = O.poisson_cpd(m, np.zeros(m.n), w, z_lo, z_hi, dV)
+    reg = O.cpd_constrained(m, z_lo, z_hi)
+    assert np.abs((phi + w)[reg == 1]).max() < 1e-15
+    assert np.abs((phi + w)[reg == 2] - dV).max() < 1e-15
+    glo, ghi = -(0.05 + 0.02 * z_lo), dV - (0.05 + 0.02 * z_hi)
+    mid = reg == 0
+    lin = glo + (ghi - glo) * (z[mid] - z_lo) / (z_hi - z_lo)
+    assert np.abs(phi[mid] - lin).max() < 1e-12
+
+
+def test_cpd_solution_satisfies_the_free_rows_and_reduces_to_dirichlet():
+    """Random charge: K phi = 4 pi M s holds on every free row (rows of
+    constrained nodes are not equations).  With z_lo, z_hi at the z faces of
+    a zero-Neumann-z mesh the conductors hold only the face nodes, and with
+    dV = 0, w = 0 the solution equals the homogeneous Dirichlet solve on the
+    same cells (whose free nodes are the Neumann mesh's inner nodes, in the
+    same order)."""
+    rng = np.random.default_rng(12)
+    L = (2.0, 2.0, 6.0)
+    mN = _mesh(L, (2, 2, 6), 3, (1, 1, 2))
+    s = rng.standard_normal(mN.n)
+    z_lo, z_hi = 0.0, L[2]
+    phi = O.poisson_cpd(mN, s, None, z_lo, z_hi, 0.0)
+    reg = O.cpd_constrained(mN, z_lo, z_hi)
+    K, M = O.stiffness(mN), mN.mass()
+    r = (K @ phi - 4 * np.pi * M * s)[reg == 0]
+    assert np.linalg.norm(r) < 1e-10 * np.linalg.norm(4 * np.pi * M * s)
+    mD = _mesh(L, (2, 2, 6), 3, (1, 1, 0))
+    # the Dirichlet mesh's free nodes are the Neumann mesh's nodes strictly inside
+    inner = reg == 0
+    phiD = O.poisson(mD, s[inner])
+    np.testing.assert_allclose(phi[inner], phiD, rtol=0, atol=1e-11 * np.abs(phiD).max())
+    assert (phi[~inner] == 0.0).all()
+
+
 # ------------------------------------------- dipole and polarisability (Sec. 3.1)
 
 def test_dipole_of_polynomial_profile_is_exact():
