@@ -261,6 +261,20 @@ fe_status fe_density(fe_mesh *mesh, const double *X, int64_t N, int64_t ld, cons
 fe_status fe_planar_average(fe_mesh *mesh, const double *field, int32_t normalize, double *out,
                             hipStream_t stream);
 
+/* Planar average of the bare potential (Sec. 3.2): V_bare = phi~ + V_app
+ * with phi~ = phi + (V_loc - V_self) the total electrostatic potential, so
+ *   out[k] = (1 / A) sum over the free nodes of z plane k of
+ *            m_x m_y ((phi + w) + vapp),
+ * with w = V_loc - V_self at the nodes and vapp the applied potential at the
+ * nodes (the sawtooth of the constant-field setup; zero in the
+ * constrained-potential setup, where the bias sits in phi), A the plane
+ * area; the quadrature and fixed reduction order of fe_planar_average.
+ * phi: device, n doubles; w, vapp: device, n doubles or NULL (0); out:
+ * device, n_z doubles (ascending z).  Enqueued on stream.  FE_EINVAL for a
+ * NULL mesh, phi or out. */
+fe_status fe_bare_potential_planar(fe_mesh *mesh, const double *phi, const double *w, const double *vapp,
+                                   double *out, hipStream_t stream);
+
 /* Electronic dipole about z0 (Sec. 3.1, mu_z = int rho (z - z0) for the
  * electron density; the nuclear part is the caller's):
  *   *mu_host = sum_I M_I rho[I] (z_I - z0),
@@ -280,8 +294,8 @@ fe_status fe_dipole(fe_mesh *mesh, const double *rho, double z0, double *mu_host
  * mesh's: phi = 0 on Dirichlet faces; with no Dirichlet axis (periodic x-y
  * and zero-Neumann z, Sec. 2.2.1) the constant null space is projected out
  * and phi has zero mean (the charge's mean is removed, i.e. a neutral slab
- * is assumed).  Inhomogeneous Dirichlet data (Sec. 2.2.2) are added by the
- * caller as a lifting with zero Laplacian.  charge, phi: device, n doubles;
+ * is assumed).  The constrained-potential setup of Sec. 2.2.2 is
+ * fe_poisson_solve_cpd below.  charge, phi: device, n doubles;
  * work: device, >= fe_poisson_work_bytes(mesh) bytes.  Stops when
  * |r| / |b| <= tol or after maxit iterations (r, b: residual and right-hand
  * side of the scaled system in x = M^1/2 phi); *iters_host and *relres_host
@@ -298,6 +312,30 @@ size_t fe_poisson_work_bytes(const fe_mesh *mesh);
 fe_status fe_poisson_solve(fe_mesh *mesh, const double *charge, double *phi, double tol, int32_t maxit,
                            double *work, size_t work_bytes, int32_t *iters_host, double *relres_host,
                            hipStream_t stream);
+
+/* Electrostatics of the constrained-potential-difference setup (Sec. 2.2.2,
+ * its governing equations): K phi = 4 pi M s at the nodes between the two
+ * metal conductors, and phi prescribed inside them,
+ *   phi = -w       on Omega_0 = {z <= z_lo},
+ *   phi = dV - w   on Omega_1 = {z >= z_hi},
+ * where w = V_loc - V_sm at the nodes (NULL: 0), so that the total
+ * electrostatic potential phi + w is 0 in one conductor and dV in the other
+ * (no field inside them).  x and y keep the mesh's boundary conditions
+ * (periodic for the paper's slabs); the z faces lie inside the conductors.
+ * The same device CG as fe_poisson_solve runs on the free nodes: the
+ * constrained values start at their data, enter the right-hand side through
+ * one product, and carry a zero preconditioner entry, so search directions
+ * never touch them; on return phi holds the data there exactly.  The
+ * relative residual is measured against the reduced right-hand side
+ * (2 pi M^1/2 s - H0 M^1/2 g on the free nodes).  charge, w, phi: device,
+ * n doubles (phi may not alias charge or w); work, tol, maxit, iters_host,
+ * relres_host, stream as for fe_poisson_solve.  FE_EINVAL for NULL mesh,
+ * charge, phi or work, non-finite z_lo / z_hi / dV, z_lo >= z_hi, a
+ * periodic z axis, or when no node (or every node) lies in a conductor;
+ * FE_ENOMEM if work is too small; FE_EDEVICE for a failed launch. */
+fe_status fe_poisson_solve_cpd(fe_mesh *mesh, const double *charge, const double *w, double z_lo, double z_hi,
+                               double dV, double *phi, double tol, int32_t maxit, double *work, size_t work_bytes,
+                               int32_t *iters_host, double *relres_host, hipStream_t stream);
 
 /* ---------------------------------------------------------------- Bloch-k
  * Bloch form of the Hamiltonian over the periodic x-y directions (Sec. 2.1,

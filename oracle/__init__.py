@@ -474,6 +474,19 @@ def planar_integral(mesh: Mesh, field: np.ndarray, normalize: bool = False) -> n
     return out
 
 
+def bare_potential_planar(mesh: Mesh, phi: np.ndarray, w: Optional[np.ndarray] = None,
+                          vapp: Optional[np.ndarray] = None) -> np.ndarray:
+    """Sec. 3.2 planar average of the bare potential V_bare = phi~ + V_app,
+    phi~ = phi + (V_loc - V_self): the planar average of the nodal sum
+    phi + w + vapp (w = V_loc - V_self and vapp at the nodes, None: 0)."""
+    v = np.asarray(phi, dtype=np.float64).copy()
+    if w is not None:
+        v = v + np.asarray(w, dtype=np.float64)
+    if vapp is not None:
+        v = v + np.asarray(vapp, dtype=np.float64)
+    return planar_integral(mesh, v, normalize=True)
+
+
 def dipole(mesh: Mesh, rho: np.ndarray, z0: float) -> float:
     """Sec. 3.1 electronic dipole about z0, int rho (z - z0), by the GLL
     quadrature of the nodal density."""

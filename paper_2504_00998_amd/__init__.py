@@ -77,6 +77,9 @@ def lib() -> C.CDLL:
         "fe_dipole": ([vp, vp, dbl, C.POINTER(dbl), vp], C.c_int),
         "fe_poisson_work_bytes": ([vp], C.c_size_t),
         "fe_poisson_solve": ([vp, vp, vp, dbl, i32, vp, C.c_size_t, C.POINTER(i32), C.POINTER(dbl), vp], C.c_int),
+        "fe_bare_potential_planar": ([vp, vp, vp, vp, vp, vp], C.c_int),
+        "fe_poisson_solve_cpd": ([vp, vp, vp, dbl, dbl, dbl, vp, dbl, i32, vp, C.c_size_t, C.POINTER(i32),
+                                  C.POINTER(dbl), vp], C.c_int),
         "fe_set_kpoint": ([vp, dbl, dbl], C.c_int),
         "fe_get_kpoint": ([vp, vp], C.c_int),
         "fe_hx_apply_k": ([vp, vp, vp, i64, i64, vp], C.c_int),
@@ -375,6 +378,22 @@ class Mesh:
         _check(lib().fe_planar_average(self._h, _ptr(field), int(bool(normalize)), _ptr(out), _stream(stream)))
         return out
 
+    def bare_potential_planar(self, phi, w=None, vapp=None, out=None, stream=None):
+        """Planar average of V_bare = (phi + w) + vapp per free z position,
+        ascending z (fe_bare_potential_planar); w = V_loc - V_self and vapp at
+        the nodes, None for 0."""
+        import torch
+        _check_vec(phi, self.n, "phi")
+        for t, nm in ((w, "w"), (vapp, "vapp")):
+            if t is not None:
+                _check_vec(t, self.n, nm)
+        if out is None:
+            out = torch.empty(self.nf[2], dtype=torch.float64, device=phi.device)
+        _check_vec(out, int(self.nf[2]), "out")
+        _check(lib().fe_bare_potential_planar(self._h, _ptr(phi), _ptr(w) if w is not None else None,
+                                              _ptr(vapp) if vapp is not None else None, _ptr(out), _stream(stream)))
+        return out
+
     def dipole(self, rho, z0: float, stream=None) -> float:
         """Electronic dipole sum_I M_I rho_I (z_I - z0) (fe_dipole)."""
         import torch
@@ -400,6 +419,29 @@ class Mesh:
         it, rel = C.c_int32(), C.c_double()
         _check(lib().fe_poisson_solve(self._h, _ptr(charge), _ptr(phi), float(tol), int(maxit), _ptr(work),
                                       _work_bytes(work), C.byref(it), C.byref(rel), _stream(stream)))
+        return phi, it.value, rel.value
+
+    def poisson_cpd(self, charge, z_lo: float, z_hi: float, dV: float, w=None, tol: float = 1e-12,
+                    maxit: int = 100000, phi=None, work=None, stream=None):
+        """Electrostatic potential of the constrained-potential-difference
+        setup (fe_poisson_solve_cpd): phi + w = 0 for z <= z_lo and dV for
+        z >= z_hi (w = V_loc - V_sm at the nodes, None: 0), K phi = 4 pi M s
+        between.  Returns (phi, iterations, final relative residual)."""
+        import torch
+        if charge.dtype != torch.float64 or not charge.is_cuda or not charge.is_contiguous() or charge.numel() != self.n:
+            raise ValueError("charge must be a contiguous float64 device tensor of n values")
+        if w is not None:
+            _check_vec(w, self.n, "w")
+        if phi is None:
+            phi = torch.empty(self.n, dtype=torch.float64, device=charge.device)
+        _check_vec(phi, self.n, "phi")
+        need = int(lib().fe_poisson_work_bytes(self._h))
+        if work is None:
+            work = torch.empty((need + 7) // 8, dtype=torch.float64, device=charge.device)
+        it, rel = C.c_int32(), C.c_double()
+        _check(lib().fe_poisson_solve_cpd(self._h, _ptr(charge), _ptr(w) if w is not None else None, float(z_lo),
+                                          float(z_hi), float(dV), _ptr(phi), float(tol), int(maxit), _ptr(work),
+                                          _work_bytes(work), C.byref(it), C.byref(rel), _stream(stream)))
         return phi, it.value, rel.value
 
     def lanczos_bounds(self, v0, k: int = 10, stream=None):

@@ -67,6 +67,31 @@ __global__ __launch_bounds__(256) void planar_kernel(const double *F, int nfx, i
     if (threadIdx.x == 0) out[k] = red[0] * scale;
 }
 
+// planar average of V_bare = (phi + w) + vapp (w, vapp may be null: 0),
+// one workgroup per free z plane k, the order of planar_kernel
+__global__ __launch_bounds__(256) void planar_bare_kernel(const double *phi, const double *w, const double *vapp,
+                                                          int nfx, int nfy, const double *mass, int maxf,
+                                                          double scale, double *out) {
+    __shared__ double red[256];
+    const int k = blockIdx.x;
+    const int64_t plane = (int64_t)nfx * nfy, off = (int64_t)k * plane;
+    double s = 0.0;
+    for (int64_t e = threadIdx.x; e < plane; e += 256) {
+        const int tx = (int)(e % nfx), ty = (int)(e / nfx);
+        double v = phi[off + e];
+        if (w) v += w[off + e];
+        if (vapp) v += vapp[off + e];
+        s += (mass[tx] * mass[maxf + ty]) * v;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int wd = 128; wd >= 1; wd >>= 1) {
+        if ((int)threadIdx.x < wd) red[threadIdx.x] += red[threadIdx.x + wd];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = red[0] * scale;
+}
+
 // mu = sum_k m_z(k) (z_k - z0) P[k] over the free z positions, one workgroup,
 // fixed order
 __global__ __launch_bounds__(256) void zmoment_kernel(const double *P, int nz, const double *massz, const double *zc,
@@ -128,6 +153,19 @@ fe_status fe_planar_average(fe_mesh *m, const double *field, int32_t normalize, 
     }
     hipLaunchKernelGGL(planar_kernel, dim3((unsigned)m->nf[2]), dim3(256), 0, st, field, (int)m->nf[0], (int)m->nf[1],
                        m->d_axis + 6 * m->maxf, m->maxf, scale, out);
+    FE_HIPD(hipGetLastError(), "planar kernel");
+    return FE_OK;
+}
+
+fe_status fe_bare_potential_planar(fe_mesh *m, const double *phi, const double *w, const double *vapp, double *out,
+                                   hipStream_t st) {
+    if (!m || !phi || !out) return fail(FE_EINVAL, "NULL argument");
+    FE_HIPD(hipSetDevice(m->device), "hipSetDevice");
+    double ax = 0.0, ay = 0.0;
+    for (double v : m->axis_mass[0]) ax += v;
+    for (double v : m->axis_mass[1]) ay += v;
+    hipLaunchKernelGGL(planar_bare_kernel, dim3((unsigned)m->nf[2]), dim3(256), 0, st, phi, w, vapp, (int)m->nf[0],
+                       (int)m->nf[1], m->d_axis + 6 * m->maxf, m->maxf, 1.0 / (ax * ay), out);
     FE_HIPD(hipGetLastError(), "planar kernel");
     return FE_OK;
 }

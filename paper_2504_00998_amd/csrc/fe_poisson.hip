@@ -17,6 +17,16 @@
 // results, and the CG scalars computed from them, stay in device memory; the
 // host reads the convergence state once per batch of iterations, and
 // iterations queued after convergence leave the iterate untouched.
+//
+// The constrained-potential-difference setup (Sec. 2.2.2) prescribes phi in
+// the two conductor regions, Omega_0 = {z <= z_lo} and Omega_1 = {z >= z_hi}:
+// phi = -w there, plus dV in Omega_1 (w = V_loc - V_sm at the nodes), so the
+// total potential phi + w is 0 and dV inside the conductors.  The same CG runs
+// on the free block: the constrained entries of x start at M^1/2 g, the
+// initial residual b - H0 x0 is taken on the free nodes only, and the Jacobi
+// preconditioner is zero on constrained nodes, which keeps every search
+// direction and the residual zero there; the constrained phi are written as
+// the data themselves at the end.
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 
@@ -138,7 +148,8 @@ __global__ __launch_bounds__(kRedThreads) void cg_update_kernel(double *x, doubl
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRedThreads) {
         x[i] += al * p[i];
-        const double ri = r[i] - al * q[i];
+        // a zero preconditioner entry marks a constrained node: no equation there
+        const double ri = pinv[i] != 0.0 ? r[i] - al * q[i] : 0.0;
         r[i] = ri;
         const double zi = pinv[i] * ri;
         v[0] += ri * ri;
@@ -184,6 +195,37 @@ __global__ void cg_direction_kernel(double *p, const double *r, const double *pi
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     p[i] = (pinv[i] * r[i] - sc[S_EZ] * e[i]) + sc[S_BETA] * p[i];
+}
+
+// Region of a node for the constrained setup: 0 free, 1 Omega_0, 2 Omega_1.
+__device__ __forceinline__ int cpd_region(double z, double z_lo, double z_hi) {
+    return z <= z_lo ? 1 : (z >= z_hi ? 2 : 0);
+}
+
+// x = M^1/2 g on constrained nodes (g = -w, plus dV in Omega_1), 0 elsewhere
+__global__ void cpd_start_kernel(double *x, const double *msqrt, const double *w, const double *zcoord, int nfx,
+                                 int nfy, int64_t n, double z_lo, double z_hi, double dV) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int reg = cpd_region(zcoord[i / ((int64_t)nfx * nfy)], z_lo, z_hi);
+    const double g = (reg == 2 ? dV : 0.0) - (w ? w[i] : 0.0);
+    x[i] = reg ? msqrt[i] * g : 0.0;
+}
+
+// r = b - q on free nodes, 0 on constrained ones
+__global__ void cpd_residual_kernel(double *r, const double *q, const double *pinv, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    r[i] = pinv[i] != 0.0 ? r[i] - q[i] : 0.0;
+}
+
+// phi = g on constrained nodes (the data, exactly)
+__global__ void cpd_fix_kernel(double *phi, const double *w, const double *zcoord, int nfx, int nfy, int64_t n,
+                               double z_lo, double z_hi, double dV) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int reg = cpd_region(zcoord[i / ((int64_t)nfx * nfy)], z_lo, z_hi);
+    if (reg) phi[i] = (reg == 2 ? dV : 0.0) - (w ? w[i] : 0.0);
 }
 
 #define FE_HIPP(call, what)                                                                          \
@@ -256,16 +298,23 @@ hipError_t launch_xpby(double *p, const double *z, double beta, int64_t n, hipSt
 
 using namespace fe;
 
-extern "C" {
-
-size_t fe_poisson_work_bytes(const fe_mesh *m) {
+extern "C" size_t fe_poisson_work_bytes(const fe_mesh *m) {
     if (!m) return 0;
     return ((size_t)8 * (size_t)m->n + 4 * (size_t)kRedBlocks + 16 + assembled_scratch_doubles(m)) * sizeof(double);
 }
 
-fe_status fe_poisson_solve(fe_mesh *m, const double *charge, double *phi, double tol, int32_t maxit,
-                           double *work, size_t work_bytes, int32_t *iters_host, double *relres_host,
-                           hipStream_t st) {
+namespace fe {
+
+// The conductor regions of the constrained setup (null: the mesh's own
+// boundary conditions only).
+struct CpdSpec {
+    const double *w;
+    double z_lo, z_hi, dV;
+};
+
+fe_status poisson_solve(fe_mesh *m, const double *charge, double *phi, double tol, int32_t maxit, double *work,
+                        size_t work_bytes, int32_t *iters_host, double *relres_host, hipStream_t st,
+                        const CpdSpec *cpd) {
     if (!m || !charge || !phi || !work) return fail(FE_EINVAL, "NULL argument");
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(FE_EINVAL, "tol must be positive");
     if (maxit < 1) return fail(FE_EINVAL, "maxit must be >= 1");
@@ -275,7 +324,8 @@ fe_status fe_poisson_solve(fe_mesh *m, const double *charge, double *phi, double
     const int64_t n = m->n;
     const int ni = (int)n;
     double *x = work, *r = x + n, *z = r + n, *p = z + n, *q = p + n, *e = q + n, *pinv = e + n, *zero = pinv + n;
-    const bool singular = m->bc[0] != FE_BC_DIRICHLET && m->bc[1] != FE_BC_DIRICHLET && m->bc[2] != FE_BC_DIRICHLET;
+    const bool singular =
+        !cpd && m->bc[0] != FE_BC_DIRICHLET && m->bc[1] != FE_BC_DIRICHLET && m->bc[2] != FE_BC_DIRICHLET;
 
     void *hv = nullptr;
     fe_status stt = blas_handle(m, st, &hv);
@@ -284,15 +334,42 @@ fe_status fe_poisson_solve(fe_mesh *m, const double *charge, double *phi, double
 
     std::vector<double> pinv_h;
     jacobi_inverse(m, pinv_h);
+    if (cpd) {
+        // no equation on constrained nodes: a zero preconditioner entry marks them
+        int64_t nc = 0;
+        const int64_t plane = m->nf[0] * m->nf[1];
+        for (int64_t tz = 0; tz < m->nf[2]; ++tz) {
+            const double zz = m->axis_coord[2][(size_t)tz];
+            if (zz > cpd->z_lo && zz < cpd->z_hi) continue;
+            std::fill(pinv_h.begin() + tz * plane, pinv_h.begin() + (tz + 1) * plane, 0.0);
+            nc += plane;
+        }
+        if (nc == 0) return fail(FE_EINVAL, "no node lies in a conductor region (z <= z_lo or z >= z_hi)");
+        if (nc == n) return fail(FE_EINVAL, "every node lies in a conductor region: nothing to solve");
+    }
     FE_HIPP(hipMemcpyAsync(pinv, pinv_h.data(), n * sizeof(double), hipMemcpyHostToDevice, st), "copy pinv");
     FE_HIPP(launch_fill(zero, n, 0.0, st), "fill");
-    FE_HIPP(launch_fill(x, n, 0.0, st), "fill");
     // e = M^1/2 1 / |M^1/2 1| (the null vector when no axis is Dirichlet)
     FE_HIPP(launch_mass_sqrt(m, e, st), "mass sqrt");
+    if (cpd) {
+        hipLaunchKernelGGL(cpd_start_kernel, dim3(blocks(n)), dim3(256), 0, st, x, e, cpd->w, m->d_zcoord,
+                           (int)m->nf[0], (int)m->nf[1], n, cpd->z_lo, cpd->z_hi, cpd->dV);
+        FE_HIPP(hipGetLastError(), "cpd start");
+    } else {
+        FE_HIPP(launch_fill(x, n, 0.0, st), "fill");
+    }
     // r = b = 2 pi M^1/2 s
     FE_HIPP(launch_vmul(r, e, charge, n, st), "rhs");
     const double twopi = 2.0 * M_PI;
     FE_BLASP(rocblas_dscal(h, ni, &twopi, r, 1), "dscal");
+    if (cpd) {
+        // r = b - H0 x0 on the free nodes (the prescribed values moved to the right-hand side)
+        double *Zc = zero + n + 4 * kRedBlocks + 16;
+        StepArgs a{x, 1, q, 1, nullptr, 0, 1.0, 0.0, 0.0, 1, zero};
+        FE_HIPP(launch_step_assembled(m, a, Zc, st), "product");
+        hipLaunchKernelGGL(cpd_residual_kernel, dim3(blocks(n)), dim3(256), 0, st, r, q, pinv, n);
+        FE_HIPP(hipGetLastError(), "cpd residual");
+    }
     double enrm = 0.0;
     FE_BLASP(rocblas_dnrm2(h, ni, e, 1, &enrm), "dnrm2");
     const double ie = 1.0 / enrm;
@@ -391,9 +468,38 @@ fe_status fe_poisson_solve(fe_mesh *m, const double *charge, double *phi, double
     hipLaunchKernelGGL(dscale_kernel, dim3(blocks(n)), dim3(256), 0, st, m->d_axis, m->maxf, (int)m->nf[0],
                        (int)m->nf[1], n, x, phi);
     FE_HIPP(hipGetLastError(), "scale");
+    if (cpd) {
+        hipLaunchKernelGGL(cpd_fix_kernel, dim3(blocks(n)), dim3(256), 0, st, phi, cpd->w, m->d_zcoord,
+                           (int)m->nf[0], (int)m->nf[1], n, cpd->z_lo, cpd->z_hi, cpd->dV);
+        FE_HIPP(hipGetLastError(), "cpd data");
+    }
     if (iters_host) *iters_host = it;
     if (relres_host) *relres_host = rel;
     return FE_OK;
+}
+
+}  // namespace fe
+
+extern "C" {
+
+fe_status fe_poisson_solve(fe_mesh *m, const double *charge, double *phi, double tol, int32_t maxit,
+                           double *work, size_t work_bytes, int32_t *iters_host, double *relres_host,
+                           hipStream_t st) {
+    return fe::poisson_solve(m, charge, phi, tol, maxit, work, work_bytes, iters_host, relres_host, st, nullptr);
+}
+
+fe_status fe_poisson_solve_cpd(fe_mesh *m, const double *charge, const double *w, double z_lo, double z_hi,
+                               double dV, double *phi, double tol, int32_t maxit, double *work, size_t work_bytes,
+                               int32_t *iters_host, double *relres_host, hipStream_t st) {
+    if (!m) return fail(FE_EINVAL, "NULL argument");
+    if (!std::isfinite(z_lo) || !std::isfinite(z_hi) || !std::isfinite(dV) || !(z_lo < z_hi))
+        return fail(FE_EINVAL, "z_lo < z_hi and dV must be finite");
+    if (m->bc[2] == FE_BC_PERIODIC) return fail(FE_EINVAL, "the z axis of a CPD mesh cannot be periodic");
+    if (phi && ((charge && fe::overlap(phi, m->n, 1, 1, charge, m->n, 1, 1)) ||
+                (w && fe::overlap(phi, m->n, 1, 1, w, m->n, 1, 1))))
+        return fail(FE_EINVAL, "phi overlaps charge or w");
+    const fe::CpdSpec cpd{w, z_lo, z_hi, dV};
+    return fe::poisson_solve(m, charge, phi, tol, maxit, work, work_bytes, iters_host, relres_host, st, &cpd);
 }
 
 }  // extern "C"

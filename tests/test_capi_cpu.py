@@ -82,6 +82,7 @@ def test_density_entry_points_reject_null_without_a_device():
     L = fe.lib()
     assert L.fe_density(None, None, 4, 4, None, None, None) == fe.FE_EINVAL
     assert L.fe_planar_average(None, None, 0, None, None) == fe.FE_EINVAL
+    assert L.fe_bare_potential_planar(None, None, None, None, None, None) == fe.FE_EINVAL
 
 
 def test_poisson_entry_points_reject_null_without_a_device():
@@ -89,6 +90,8 @@ def test_poisson_entry_points_reject_null_without_a_device():
     L = fe.lib()
     assert L.fe_poisson_work_bytes(None) == 0
     assert L.fe_poisson_solve(None, None, None, 1e-8, 10, None, 0, None, None, None) == fe.FE_EINVAL
+    assert L.fe_poisson_solve_cpd(None, None, None, 1.0, 2.0, 0.1, None, 1e-8, 10, None, 0, None, None,
+                                  None) == fe.FE_EINVAL
 
 
 def test_bloch_entry_points_reject_null_without_a_device():

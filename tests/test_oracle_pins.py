@@ -834,6 +834,26 @@ def test_cpd_solution_satisfies_the_free_rows_and_reduces_to_dirichlet():
     assert (phi[~inner] == 0.0).all()
 
 
+def test_bare_potential_planar_average_of_plane_constant_fields():
+    """Fields constant over each x-y plane average to their z profile at
+    every free z position; the sawtooth of the constant-field setup comes
+    back as -E (z - z0) exactly; the three terms add."""
+    L = (3.0, 2.0, 6.0)
+    m = _mesh(L, (3, 2, 6), 3, (1, 1, 2))
+    z = m.dof_coords()[:, 2]
+    zc, _ = O.axis_positions(m, 2)
+    E, z0 = 0.02, 2.5
+    phi, w, vapp = np.cos(z), 0.1 * z ** 2, -E * (z - z0)
+    np.testing.assert_allclose(O.bare_potential_planar(m, np.zeros(m.n), None, vapp), -E * (zc - z0),
+                               rtol=0, atol=1e-15)
+    np.testing.assert_allclose(O.bare_potential_planar(m, phi, w, vapp),
+                               np.cos(zc) + 0.1 * zc ** 2 - E * (zc - z0), rtol=0, atol=1e-14)
+    # a field varying in x averages over the plane: cos(2 pi x / L_x) has mean 0
+    x = m.dof_coords()[:, 0]
+    np.testing.assert_allclose(O.bare_potential_planar(m, np.cos(2 * np.pi * x / L[0]) + phi), np.cos(zc),
+                               rtol=0, atol=1e-5)
+
+
 # ------------------------------------------- dipole and polarisability (Sec. 3.1)
 
 def test_dipole_of_polynomial_profile_is_exact():
