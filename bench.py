@@ -36,14 +36,45 @@ PEAK = {"f64": (78.6, "mfma"), "f32": (157.3, "mfma"), "bf16": (2500.0, "mfma")}
 MEASURED_PEAK = {"f64": 74.2, "f32": 155.0}
 # HBM bytes per colour launch of the default step kernel on the p=4 slab
 # (N=256), from FETCH_SIZE/WRITE_SIZE counters scaled by a plain copy of known
-# size; valid for this kernel build only
-COUNTED_TRAFFIC = {("slab-p4-24x24x48", 256, "f64"): (1.779e9, "step_pipe_kernel<4,0,2,true>"),
-                   ("slab-p4-24x24x48", 256, "f32"): (1.779e9, "step_pipe_kernel<4,1,2,true>"),
-                   ("slab-p4-24x24x48", 256, "bf16"): (1.779e9, "step_pipe_kernel<4,2,2,true>")}
+# size, averaged over the launches of a degree-30 filter (the first step reads
+# no previous iterate: FP64 1.784e9 B, FP32/BF16 1.779e9 B; the 29 others
+# 2.269e9 / 2.235e9 B); valid for these kernel builds only (None: not counted)
+COUNTED_TRAFFIC = {("slab-p4-24x24x48", 256, "f64"): (2.253e9, "step_tab_kernel<4,1,2>"),
+                   ("slab-p4-24x24x48", 256, "f32"): (2.220e9, "step_pipe_kernel<4,1,2,true>"),
+                   ("slab-p4-24x24x48", 256, "bf16"): (2.220e9, "step_pipe_kernel<4,2,2,true>")}
+# MI355X ceilings of the filter rate (GDoF.vec/s) of the large workloads:
+# the dense-MFMA roofline of one H~X (2 n_c^2 flop per cell and vector; FP64
+# 78.6, FP32 157.3 TFLOP/s) expressed per DoF and vector
+CEILING = {("slab-p6-16x16x32", "f64"): 71.8, ("slab-p5-40x40x80-nonlocal", "f32"): 210.0}
+GOLDEN_RITZ = os.path.join(ROOT, "tests", "golden", "cfg3_ritz_oracle.txt")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def host_description():
+    """CPU model, thread count and memory of this host (the oracle's machine)."""
+    import subprocess
+    model, mem_gib = None, None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if model is None and os.path.exists("/proc/cpuinfo"):
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    try:
+        out = subprocess.run(["free", "-g"], capture_output=True, text=True, timeout=10).stdout
+        mem_gib = int(out.splitlines()[1].split()[1])
+    except (OSError, subprocess.SubprocessError, IndexError, ValueError):
+        pass
+    return {"lscpu_model": model, "nproc": os.cpu_count(), "free_g_total": mem_gib}
 
 
 def cpu_baseline(wl, a, b, a0, ncols: int = 4):
@@ -61,7 +92,7 @@ def cpu_baseline(wl, a, b, a0, ncols: int = 4):
     t = time.perf_counter()
     op.filter(X, wl.m, a, b, a0)
     dt = time.perf_counter() - t
-    return {
+    rec = {
         "value": wl.m * om.n * ncols / dt / 1e9,
         "unit": UNIT,
         "cores": O.num_threads(),
@@ -69,46 +100,152 @@ def cpu_baseline(wl, a, b, a0, ncols: int = 4):
         "sample": f"degree-{wl.m} filter on {ncols} of {wl.N} columns of the full mesh "
                   f"(CSR SpMM, nnz {op.A.nnz}); assembly excluded; {dt:.1f} s",
     }
+    rec.update(host_description())
+    return rec
+
+
+def golden_ritz():
+    """Bounds (a0, b, a) and per-iteration Ritz values of the oracle's
+    5-iteration subspace iteration on the cfg-3 block (written by
+    tests/golden/make_cfg3_ritz.py from the CPU oracle alone)."""
+    import numpy as np
+    bounds, hist = None, {}
+    for line in open(GOLDEN_RITZ):
+        if line.startswith("#") or not line.strip():
+            continue
+        t = line.split()
+        if t[0] == "bounds":
+            bounds = tuple(float(x) for x in t[1:4])
+        else:
+            hist.setdefault(int(t[0]), []).append((int(t[1]), float(t[2])))
+    return bounds, [np.array([v for _, v in sorted(hist[k])]) for k in sorted(hist)]
 
 
 def mixed_precision_report(gm, wl, X, Y, work, a, b, a0, steps, ms_f64, launches, flops_per_launch, variant):
-    """FP32 / BF16 cell products on the same workload: filter throughput,
+    """FP32 / BF16 cell products: filter throughput on the benchmark block,
     speedup over FP64, the step kernel's launch time against the MFMA peak of
     the precision (and its counted HBM rate where the counters of the kernel
-    are known), and the Ritz values after 5 subspace iterations (filter in the
-    given precision; CholQR2 and Rayleigh-Ritz in FP64) against the same
-    iteration with FP64 cell products."""
+    are known).  Accuracy on the cfg-3 block (same mesh and potential, cfg-3
+    seeds): the Ritz values after 5 subspace iterations (filter in the given
+    precision; CholQR2 and Rayleigh-Ritz in FP64), every iteration from the
+    oracle's Lanczos bounds and updating its own cut, against the oracle's
+    own 5 iterations (tests/golden/cfg3_ritz_oracle.txt); FP64 on the device
+    is reported the same way.  The bar is max |Ritz error| <= 1e-7 Ha over
+    all N values; the lowest N/2 are reported beside it.  Also the
+    per-vector relative error of one filter pass against the device's FP64
+    filter of the same block."""
     import numpy as np
     import torch
     from paper_2504_00998_amd import solver
+    from paper_2504_00998_amd import workloads as W
 
     stream = torch.cuda.current_stream()
     n, N, m = gm.n, wl.N, wl.m
-    hist64, _ = solver.subspace_iteration(gm, X, m, 5, a, b, a0, prec="f64", work=work)
-    out = {"ritz_iterations": 5, "ritz_reference": "same subspace iteration with FP64 cell products"}
-    for prec in ("f32", "bf16"):
-        gm.cheb_filter(X, m, a, b, a0, prec=prec, Y=Y, work=work)
-        torch.cuda.synchronize()
+    (ga0, gb, ga), ref = golden_ritz()
+    wl3 = W.CFG3
+    X3 = torch.from_numpy(wl3.X(n)).to(X.device)
+    out = {"ritz_iterations": len(ref), "ritz_reference": "CPU oracle, 5-iteration subspace iteration on the cfg-3 "
+           "block (tests/golden/cfg3_ritz_oracle.txt)", "ritz_bar_Ha": 1e-7,
+           "y_reference": "device FP64 filter of the cfg-3 block, one pass"}
+    Y64 = gm.cheb_filter(X3, m, ga, gb, ga0, prec="f64")
+    for prec in ("f64", "f32", "bf16"):
+        rec = {}
+        if prec != "f64":
+            gm.cheb_filter(X, m, a, b, a0, prec=prec, Y=Y, work=work)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                gm.cheb_filter(X, m, a, b, a0, prec=prec, Y=Y, work=work)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            launch_ms = ms / launches
+            tf = flops_per_launch / (launch_ms * 1e-3) / 1e12
+            traffic = COUNTED_TRAFFIC.get((wl.name, N, prec)) if variant == 0 else None
+            rec = {"value": round(m * n * N / (ms * 1e-3) / 1e9, 4), "ms_per_filter": round(ms, 4),
+                   "speedup_vs_f64": round(ms_f64 / ms, 3),
+                   "avg_launch_ms": round(launch_ms, 5), "achieved_TFLOPs": round(tf, 3),
+                   "frac_of_mfma_peak": round(tf / PEAK[prec][0], 4),
+                   "hbm_GBps": round(traffic[0] / (launch_ms * 1e-3) / 1e9, 1) if traffic and traffic[0] else None,
+                   "kernel": traffic[1] if traffic else None}
+            Yp = gm.cheb_filter(X3, m, ga, gb, ga0, prec=prec, Y=Y, work=work)
+            rec["y_rel_err_max"] = float(((Yp - Y64).norm(dim=0) / Y64.norm(dim=0)).max().item())
+        hist, _ = solver.subspace_iteration(gm, X3, m, len(ref), ga, gb, ga0, prec=prec, work=work)
+        d = np.abs(hist[-1] - ref[-1])
+        rec.update({"ritz_err_max_Ha": float(d.max()), "ritz_err_lowest_half_Ha": float(d[: N // 2].max()),
+                    "ritz_err_max_all_iterations_Ha": float(max(np.abs(h - r).max() for h, r in zip(hist, ref))),
+                    "ritz_ok_1e-7": bool(d.max() <= 1e-7)})
+        if prec == "bf16" and not rec["ritz_ok_1e-7"]:
+            rec["note"] = ("BF16 cell products fail the 1e-7 Ha Ritz bar: their rate does not count toward the "
+                           "metric")
+        out[prec] = rec
+    del X3, Y64
+    torch.cuda.empty_cache()
+    return out
+
+
+def large_workloads(dev, steps):
+    """The p = 6 slab (FP64 filter) and the p = 5 slab with nonlocal
+    projectors (FP32 cell products) at full size, against their MFMA
+    ceilings; X drawn on the device."""
+    import numpy as np
+    import torch
+
+    import paper_2504_00998_amd as fe
+    from paper_2504_00998_amd import workloads as W
+
+    stream = torch.cuda.current_stream()
+    out = {}
+    for wl, prec in ((W.CFG4, "f64"), (W.CFG5, "f32")):
+        t0 = time.time()
+        gm = fe.Mesh.from_workload(wl)
+        n, N, m = gm.n, wl.N, wl.m
+        gm.set_potential(torch.from_numpy(W.workload_potential(wl, gm.quad_points())).to(dev), wl.E, wl.z0)
+        if wl.nonlocal_sites:
+            gm.set_nonlocal(wl.centres(), wl.nonlocal_coupling(), wl.r_cut, wl.r_g)
+        v0 = torch.from_numpy(wl.lanczos_start(n)).to(dev)
+        a0, b = gm.lanczos_bounds(v0, 10)
+        a = a0 + (b - a0) * (N / n) ** (2.0 / 3.0)
+        X = wl.X_device(n, N)
+        Y = torch.empty_like(X)
+        work = torch.empty(n * N, dtype=torch.float64, device=dev)
+        setup_s = time.time() - t0
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(2):
+            gm.hx(X, Y=Y, prec=prec)
+        torch.cuda.synchronize()
+        reps = 3
         e0.record(stream)
-        for _ in range(steps):
+        for _ in range(reps):
+            gm.hx(X, Y=Y, prec=prec)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_hx = e0.elapsed_time(e1) / reps
+        nf = 1 if wl.m * ms_hx > 2000 else min(steps, 3)  # the p = 5 filter takes seconds
+        e0.record(stream)
+        for _ in range(nf):
             gm.cheb_filter(X, m, a, b, a0, prec=prec, Y=Y, work=work)
         e1.record(stream)
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / steps
-        hist, _ = solver.subspace_iteration(gm, X, m, 5, a, b, a0, prec=prec, work=work)
-        d = np.abs(hist[-1] - hist64[-1])
-        launch_ms = ms / launches
-        tf = flops_per_launch / (launch_ms * 1e-3) / 1e12
-        traffic = COUNTED_TRAFFIC.get((wl.name, N, prec)) if variant == 0 else None
-        out[prec] = {"value": round(m * n * N / (ms * 1e-3) / 1e9, 4), "ms_per_filter": round(ms, 4),
-                     "speedup_vs_f64": round(ms_f64 / ms, 3),
-                     "avg_launch_ms": round(launch_ms, 5), "achieved_TFLOPs": round(tf, 3),
-                     "frac_of_mfma_peak": round(tf / PEAK[prec][0], 4),
-                     "hbm_GBps": round(traffic[0] / (launch_ms * 1e-3) / 1e9, 1) if traffic and traffic[0] else None,
-                     "kernel": traffic[1] if traffic else None,
-                     "ritz_err_max_Ha": float(d.max()), "ritz_err_lowest_half_Ha": float(d[: N // 2].max()),
-                     "ritz_ok_1e-7": bool(d[: N // 2].max() <= 1e-7)}
+        ms_f = e0.elapsed_time(e1) / nf
+        if not torch.isfinite(Y).all():
+            raise RuntimeError(f"non-finite filter output on {wl.name}")
+        nc = (wl.p + 1) ** 3
+        flops_hx = 2.0 * nc * nc * wl.n_cells * N
+        value = m * n * N / (ms_f * 1e-3) / 1e9
+        ceil = CEILING[(wl.name, prec)]
+        out[wl.name] = {"prec": prec, "n_dof": n, "N": N, "m": m, "p": wl.p, "cells": list(wl.ncell),
+                        "nonlocal_sites": int(wl.centres().shape[0]) if wl.nonlocal_sites else 0,
+                        "value": round(value, 4), "unit": UNIT, "ceiling": ceil, "frac_of_ceiling": round(value / ceil, 4),
+                        "ms_per_filter": round(ms_f, 3), "filters_timed": nf, "ms_per_hx": round(ms_hx, 4),
+                        "hx_TFLOPs": round(flops_hx / (ms_hx * 1e-3) / 1e12, 3),
+                        "hx_frac_of_mfma_peak": round(flops_hx / (ms_hx * 1e-3) / 1e12 / PEAK[prec][0], 4),
+                        "setup_s": round(setup_s, 1)}
+        log(f"[bench] {wl.name} {prec}: {value:.2f} GDoF.vec/s ({value / ceil:.3f} of {ceil}), "
+            f"H~X {ms_hx:.3f} ms")
+        del X, Y, work, gm
+        torch.cuda.empty_cache()
     return out
 
 
@@ -120,8 +257,9 @@ def main():
     ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
     ap.add_argument("--cfg", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-cols", type=int, default=24)
+    ap.add_argument("--cpu-cols", type=int, default=64)
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32/BF16 report")
+    ap.add_argument("--no-large", action="store_true", help="skip the p = 6 and p = 5 full-size workloads")
     ap.add_argument("--variant", type=int, default=0,
                     help="step-kernel variant (fe_mesh_set_kernel; 0 = the fastest measured)")
     args = ap.parse_args()
@@ -320,6 +458,8 @@ def main():
         t_pot_ms = t_pot
         rec["mixed_precision"] = mixed_precision_report(gm, wl, X, Y, work, a, b, a0, args.steps, ms - t_pot_ms,
                                                         launches, flops_per_launch, args.variant)
+    if not args.no_large and args.cfg == 2:
+        rec["large_workloads"] = large_workloads(dev, args.steps)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(wl, a, b, a0, args.cpu_cols)
     print(json.dumps(rec), flush=True)

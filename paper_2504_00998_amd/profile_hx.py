@@ -8,7 +8,9 @@ kernels, e.g. (from any directory)::
 
 Before the H~X launches it copies one (n x N) FP64 block with PyTorch, so the
 same trace holds a plain copy kernel of known size (n*N*8 bytes read and
-written) against which HBM byte counters can be calibrated.
+written) against which HBM byte counters can be calibrated.  With --filter M
+it then runs a degree-M filter per precision as well, whose steps after the
+first read the previous iterate (the launches the filter rate is made of).
 """
 from __future__ import annotations
 
@@ -26,6 +28,7 @@ def main():
     ap.add_argument("--cfg", type=int, default=2)
     ap.add_argument("--precs", default="f64,f32,bf16")
     ap.add_argument("--variant", type=int, default=0, help="step-kernel variant (fe_mesh_set_kernel)")
+    ap.add_argument("--filter", type=int, default=0, help="also run a filter of this degree per precision")
     args = ap.parse_args()
 
     import torch
@@ -49,6 +52,11 @@ def main():
         gm.hx(X, Y, prec=prec)
         torch.cuda.synchronize()
         print(f"hx {prec} done ({wl.name}, n={n}, N={N}, variant {args.variant})", flush=True)
+        if args.filter > 0:
+            # bounds of the slab workloads' spectra (the values only scale the recurrence)
+            gm.cheb_filter(X, args.filter, 5.6, 314.0, 4.8, prec=prec, Y=Y)
+            torch.cuda.synchronize()
+            print(f"filter {prec} degree {args.filter} done", flush=True)
 
 
 if __name__ == "__main__":
