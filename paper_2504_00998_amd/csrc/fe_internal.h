@@ -85,7 +85,7 @@ struct fe_mesh {
     // matrix): per colour pass, per z segment, first DoF and face masks
     int32_t *d_segtab = nullptr;
     std::vector<int64_t> seg_off;  // entries of colour pass c: [seg_off[c], seg_off[c+1])
-    int seg_zl = 1;
+    int seg_zl = 1, seg_bx = 1;    // cells of a brick along z and along x
     float *d_Af32 = nullptr;      // f32
     uint16_t *d_Abf16 = nullptr;  // bf16 bits
     double *d_v = nullptr;        // [n] diagonal potential term of H~
@@ -176,7 +176,7 @@ hipError_t launch_nonlocal_k(fe_mesh *m, const double *X, int64_t ldx, double *Y
 fe_status nonlocal_set_phase(fe_mesh *m);
 void swizzle_f64(const fe_mesh *m, const std::vector<double> &A, std::vector<double> &f64);
 // segment table of the FP64 table kernel (fe_kernels.hip)
-void build_segment_table(const fe_mesh *m, std::vector<int32_t> &tab, std::vector<int64_t> &off, int &zl);
+void build_segment_table(const fe_mesh *m, std::vector<int32_t> &tab, std::vector<int64_t> &off, int &zl, int &bx);
 void nonlocal_release(fe_mesh *m);
 
 }  // namespace fe

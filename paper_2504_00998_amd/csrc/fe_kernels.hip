@@ -1782,6 +1782,12 @@ template <int P, int TPW, int NGRP> struct TabShape {
 //              segment's last cell)
 enum : int { SEG_FM = 0, SEG_DM = 6, SEG_WM = 12 };
 
+// Buffer descriptors of the table kernel's X requests: byte range (offsets
+// at or past it read zeros) and the fourth descriptor word of a raw buffer
+// on this architecture family.
+constexpr uint32_t kTabRange = 0x7FFFFFFFu;
+constexpr int kBufferWord3 = 0x00020000;
+
 // s_waitcnt immediates: vector-memory counter <= n, the other counters free;
 // LDS counter 0, the other counters free
 __device__ __forceinline__ constexpr int vmcnt_imm(int n) { return (n & 0xF) | ((n >> 4) << 14) | (0x7 << 4) | (0xF << 8); }
@@ -1811,6 +1817,14 @@ __device__ __forceinline__ const double *select_ptr(bool c, const double *a, con
     return reinterpret_cast<const double *>(((uint64_t)hi << 32) | lo);
 }
 
+// a where c, else b, as one lane select written out (see select_ptr)
+__device__ __forceinline__ uint32_t select_u32(bool c, uint32_t a, uint32_t b) {
+    const uint64_t m = __builtin_amdgcn_ballot_w64(c);
+    uint32_t r;
+    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(b), "v"(a), "s"(m));
+    return r;
+}
+
 // Launch constants of one padded row r of the cell for one lane: element
 // offset of the row within a block relative to the cell's local node 0
 // (in-order DoF offset times the leading dimension, plus the lane's column),
@@ -1818,12 +1832,14 @@ __device__ __forceinline__ const double *select_ptr(bool c, const double *a, con
 template <int P> struct TabRow {
     int64_t e;
     int off, faces;
+    uint32_t eb;  // e in bytes (the request offset of a cell without Dirichlet or wrapping faces)
     __device__ __forceinline__ void init(const StepParams &k, int r, int col) {
         constexpr int N1 = P + 1, NC = N1 * N1 * N1;
         const int l = min(r, NC - 1);
         const int i = l % N1, j = (l / N1) % N1, kk = l / (N1 * N1);
         off = i + (int)k.nfx * (j + (int)k.nfy * kk);
         e = (int64_t)off * k.ldx + col;
+        eb = (uint32_t)(e * 8);
         faces = r < NC ? ((i == 0 ? 1 : 0) | (i == P ? 2 : 0) | (j == 0 ? 4 : 0) | (j == P ? 8 : 0) |
                           (kk == 0 ? 16 : 0) | (kk == P ? 32 : 0))
                        : 64;
@@ -1836,30 +1852,35 @@ template <int P> struct TabRow {
     }
 };
 
-template <int P, int TPW, int NGRP>
+template <int P, int TPW, int NGRP, int BX>
 __global__ __launch_bounds__((64 * TabShape<P, TPW, NGRP>::W)) __attribute__((amdgpu_waves_per_eu(1, 2)))
 void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nitems) {
     typedef TabShape<P, TPW, NGRP> S;
     constexpr int N1 = P + 1, NKS = S::NKS, G = S::G, XS = S::XS, W = S::W, NDMA = S::NDMA;
-    constexpr int HS = N1 * N1 * 16 * G;  // doubles per hold buffer
+    // LDS holds (doubles per buffer, each two-deep): the x face between
+    // consecutive cells of a brick row, and the top faces of a whole brick
+    // row ((BX p + 1) x (p + 1) nodes, each node once)
+    constexpr int XHS = BX > 1 ? N1 * N1 * 16 * G : 0, ZW = BX * P + 1, ZHS = ZW * N1 * 16 * G;
+    constexpr int ZH0 = 2 * XHS, ZERO0 = ZH0 + 2 * ZHS;
     // three X buffers [G][NCP][16] as distinct arrays, each named at compile
     // time by the position it serves, so that the compiler sees that a
     // product's LDS reads and the X requests in flight touch different
-    // buffers; the hold [2][N1*N1][16G] followed by 32 zeros (the hold term
-    // of rows that take none; every hold read is based on the one array, so
-    // that the compiler sees it apart from the X requests in flight)
+    // buffers; the holds followed by 32 zeros (the hold term of rows that
+    // take none) in one array, so that every hold read is based on it and the
+    // compiler sees it apart from the X requests in flight
     __shared__ __align__(16) double xb0[G * XS], xb1[G * XS], xb2[G * XS];
-    __shared__ __align__(16) double hold[2 * HS + 32];
+    __shared__ __align__(16) double hold[ZERO0 + 32];
+    static_assert(sizeof(double) * (3 * G * XS + ZERO0 + 32) <= 160 * 1024, "LDS of one workgroup");
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     if ((int64_t)blockIdx.x >= nitems) return;  // whole workgroup
-    if (tid < 32) hold[2 * HS + tid] = 0.0;
+    if (tid < 32) hold[ZERO0 + tid] = 0.0;
     const int ngroups = (k.nchunk + G - 1) / G;
     const int stride = (int)gridDim.x;
     const int sdiv = stride / ngroups, smod = stride % ngroups;
     const int zl = k.zl;
-    const int npos = (int)((nitems - 1 - blockIdx.x) / stride + 1) * zl;  // < 2^31, as items per launch
+    const int npos = (int)((nitems - 1 - blockIdx.x) / stride + 1) * zl * BX;  // < 2^31, as items per launch
     const int zstep = P * (int)(k.nfx * k.nfy);  // DoF step from a cell to the next along z
     const int64_t ld = k.ldx;                    // one leading dimension for X, Y and the previous iterate
     // the wave's row tiles of A' (tiles wave + W j), resident for the launch
@@ -1876,79 +1897,110 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nite
     // group)
     const int vq = pipe_vec<0>(lane);
     TabRow<P> R[TPW], Q[TPW][2];
-    bool lo_z[TPW], hi_z[TPW];
-    int xo[TPW], ho_bot[TPW], ho_top[TPW];  // offsets in an X buffer and a hold buffer
+    int xo[TPW], xh[TPW], zh[TPW];  // offsets in an X buffer, an x-face hold, the top-face hold of a brick row
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
         const int tile = wave + W * j, r = 16 * tile + pipe_row<0>(lane);
         R[j].init(k, r, vq);
         Q[j][0].init(k, 16 * tile + (lane >> 3), 2 * (lane & 7));
         Q[j][1].init(k, 16 * tile + 8 + (lane >> 3), 2 * (lane & 7));
-        lo_z[j] = (R[j].faces & 16) != 0;
-        hi_z[j] = (R[j].faces & 32) != 0;
+        const int l = min(r, N1 * N1 * N1 - 1), i = l % N1, jy = (l / N1) % N1, kk = l / (N1 * N1);
         xo[j] = r * 16 + vq;
-        ho_bot[j] = r * 16 * G + vq;
-        ho_top[j] = (r - P * N1 * N1) * 16 * G + vq;
+        xh[j] = (jy + N1 * kk) * 16 * G + vq;
+        zh[j] = ZH0 + (i + ZW * jy) * 16 * G + vq;
     }
     const double *ob = k.Ym1 ? k.Ym1 : k.X;
     const double nbeta = k.Ym1 ? -k.beta : 0.0;
 
-    // a walk position: z segment s of the colour, vector group grp, cell c
-    // of the segment; e its segment's table entry
+    // a walk position: brick s of the colour, vector group grp, cell (bx, c)
+    // of the brick (bx along x, fastest; c along z); e its table entry
     struct Pos {
-        int s, grp, c;
+        int s, grp, c, bx;
         int2 e;
     };
     auto advance = [&](Pos p) {
-        if (++p.c == zl) {
-            p.c = 0;
-            p.s += sdiv;
-            p.grp += smod;
-            if (p.grp >= ngroups) {
-                p.grp -= ngroups;
-                ++p.s;
+        if (++p.bx == BX) {
+            p.bx = 0;
+            if (++p.c == zl) {
+                p.c = 0;
+                p.s += sdiv;
+                p.grp += smod;
+                if (p.grp >= ngroups) {
+                    p.grp -= ngroups;
+                    ++p.s;
+                }
+                p.e = segtab[p.s];
             }
-            p.e = segtab[p.s];
         }
         return p;
     };
     // what a position needs (uniform): element offset of its cell's node 0
-    // and first vector, DoF of node 0, face masks with the z bits that apply
-    // at its place in the segment
+    // and first vector, DoF of node 0, face masks with the x and z bits that
+    // apply at its place in the brick
     struct Cell {
         int64_t U;
         int I0, fm, dm, wm;
     };
     auto cell = [&](const Pos &p) {
         Cell q;
-        q.I0 = p.e.x + p.c * zstep;
+        q.I0 = p.e.x + p.bx * P + p.c * zstep;
         q.U = (int64_t)q.I0 * ld + (int64_t)p.grp * G * 16;
-        const int zhi = p.c == zl - 1 ? 32 : 0, zm = 0xF | (p.c == 0 ? 16 : 0) | zhi;
-        q.fm = (p.e.y >> SEG_FM) & zm;
-        q.dm = (p.e.y >> SEG_DM) & zm;
-        q.wm = (p.e.y >> SEG_WM) & (0xF | zhi);
+        const int hi = (p.bx == BX - 1 ? 2 : 0) | (p.c == zl - 1 ? 32 : 0);
+        const int m = 0xC | hi | (p.bx == 0 ? 1 : 0) | (p.c == 0 ? 16 : 0);
+        q.fm = (p.e.y >> SEG_FM) & m;
+        q.dm = (p.e.y >> SEG_DM) & m;
+        q.wm = (p.e.y >> SEG_WM) & (8 | hi);
         return q;
     };
-    // X rows of a position into buffer bufp.  Padding rows take the row of
-    // the cell's last node (their columns of A' are zero), which exists when
-    // no face of the cell is on a Dirichlet boundary or wraps; otherwise they
-    // come from the zero buffer, as the rows on a Dirichlet face do.
+    // X rows of a position into buffer bufp, as buffer requests (a global
+    // request that writes LDS would make the compiler drain the LDS counter
+    // at every wait of the product loop): the buffer starts at the cell's
+    // first row, less the largest wrap correction of the position, so that
+    // every row's byte offset is a non-negative 32-bit value, a launch
+    // constant for cells without Dirichlet or wrapping faces.  Padding rows
+    // take the row of the cell's last node (their columns of A' are zero),
+    // which exists when no face of the cell is on a Dirichlet boundary or
+    // wraps; otherwise they, and the rows on a Dirichlet face, take an offset
+    // past the buffer's range, which reads zeros.
     auto prefetch = [&](const Cell &q, double *__restrict__ bufp) {
-        const int col = 2 * (lane & 7);
+        int64_t wt = 0;  // uniform: the wrap corrections that apply to the position
+        if (q.wm)
+            wt = ((q.wm & 2) ? k.nfx : 0) + ((q.wm & 8) ? k.nfx * k.nfy : 0) +
+                 ((q.wm & 32) ? k.nfx * k.nfy * (int64_t)k.nfz : 0);
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc((void *)(k.X + (q.U - wt * ld)), (short)0, kTabRange, kBufferWord3);
+        uint32_t vo[TPW][2];
 #pragma unroll
         for (int j = 0; j < TPW; ++j)
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const TabRow<P> &T = Q[j][h];
-                const double *src0 = k.X + (q.U + T.e);
-                if (q.dm | q.wm)  // uniform: a cell on a Dirichlet face or a periodic wrap
-                    src0 = select_ptr((T.faces & (q.dm | 64)) == 0, k.X + (q.U + T.e - (int64_t)T.wrap(k, q.wm) * ld),
-                                      k.zero + col);
+            for (int h = 0; h < 2; ++h) vo[j][h] = Q[j][h].eb;
+        if (q.dm | q.wm) {  // uniform: a cell on a Dirichlet face or a periodic wrap
 #pragma unroll
-                for (int g = 0; g < G; ++g)
-                    __builtin_amdgcn_global_load_lds(src0 + 16 * g, bufp + g * XS + (16 * (wave + W * j) + 8 * h) * 16,
-                                                     16, 0, 0);
-            }
+            for (int j = 0; j < TPW; ++j)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const TabRow<P> &T = Q[j][h];
+                    vo[j][h] = select_u32((T.faces & (q.dm | 64)) == 0,
+                                          (uint32_t)((T.e + (wt - T.wrap(k, q.wm)) * ld) * 8), kTabRange + 1u);
+                }
+        }
+        // one join before the requests, so that both paths issue them in the
+        // same block (the compiler counts the requests in flight only there)
+#pragma unroll
+        for (int j = 0; j < TPW; ++j) asm volatile("" : "+v"(vo[j][0]), "+v"(vo[j][1]));
+#pragma unroll
+        for (int j = 0; j < TPW; ++j)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    // (the offset goes through a scalar local: an array element
+                    // as the argument leaves the kernel without its host stub)
+                    const uint32_t voff = vo[j][h];
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                        rs, (__attribute__((address_space(3))) void *)(bufp + g * XS + (16 * (wave + W * j) + 8 * h) * 16),
+                        16u, voff, 128u * (unsigned)g, 0, 0);
+                }
         asm volatile("" ::: "memory");
     };
 
@@ -1959,7 +2011,7 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nite
         const Cell e = cell(cur);
         const bool slow = (e.dm | e.wm) != 0;  // uniform
         int64_t E[TPW];
-        bool valid[TPW], fst[TPW], bot[TPW], top[TPW];
+        bool valid[TPW], fst[TPW], left[TPW], right[TPW], bot[TPW], top[TPW];
         double vraw[TPW], o[TPW][G][4];
 #pragma unroll
         for (int j = 0; j < TPW; ++j) {
@@ -1973,14 +2025,19 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nite
                 E[j] -= (int64_t)w * ld;
                 valid[j] = (R[j].faces & (e.dm | 64)) == 0;
             }
-            bot[j] = lo_z[j] && cur.c > 0;
-            top[j] = hi_z[j] && cur.c < zl - 1;
-            fst[j] = valid[j] && (R[j].faces & e.fm) == 0 && !bot[j];
+            // faces shared with the brick's previous / next cell along x
+            // (held in the x-face hold) and along z (the top-face hold)
+            left[j] = BX > 1 && (R[j].faces & 1) != 0 && cur.bx > 0;
+            right[j] = BX > 1 && (R[j].faces & 2) != 0 && cur.bx < BX - 1;
+            bot[j] = (R[j].faces & 16) != 0 && cur.c > 0;
+            top[j] = (R[j].faces & 32) != 0 && cur.c < zl - 1;
+            const bool held = left[j] || bot[j];
+            fst[j] = valid[j] && (R[j].faces & e.fm) == 0 && !held;
             // old values: the previous iterate for a first writer, else Y
             // (an earlier colour has written the node); none for rows off the
-            // cell, a later cell's bottom face (its hold carries them) or a
-            // first writer without a previous iterate
-            const bool none = !valid[j] || bot[j] || (fst[j] && !k.Ym1);
+            // cell, rows whose partial sum a hold carries, or a first writer
+            // without a previous iterate
+            const bool none = !valid[j] || held || (fst[j] && !k.Ym1);
             const double *orow = none ? k.zero : (fst[j] ? ob : k.Y) + E[j];
             vraw[j] = k.v[valid[j] ? I : 0];
 #pragma unroll
@@ -2037,16 +2094,20 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nite
 #pragma unroll
                 for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(o[j][g][q]));
         }
+        const int zcol = cur.bx * P * 16 * G;  // this cell's x offset in the top-face hold
 #pragma unroll
         for (int j = 0; j < TPW; ++j) {
             // epilogue, one form for every row:
             //   out = alpha acc + (s x + (gamma o + h))
             // first writer: s = alpha (v - c), gamma = -beta, h = 0 (x raw
-            // from the buffer); a later cell's bottom face: s = 0, o = 0,
-            // h = the hold; any other row: s = 0, gamma = 1, h = 0
+            // from the buffer); a row whose partial sum a hold carries (from
+            // the previous cell along x, else along z): s = 0, o = 0, h = the
+            // hold; any other row: s = 0, gamma = 1, h = 0
             const double sl = fst[j] ? k.alpha * (vraw[j] - k.shift) : 0.0;
             const double gl = fst[j] ? nbeta : 1.0;
-            const double *hrow = hd + (bot[j] ? ((t - 1) & 1) * HS + ho_bot[j] : 2 * HS);
+            const int hoff = left[j] ? ((t - 1) & 1) * XHS + xh[j]
+                                     : bot[j] ? ((cur.c - 1) & 1) * ZHS + zh[j] + zcol : ZERO0;
+            const double *hrow = hd + hoff;
             double out[G][4];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
@@ -2060,8 +2121,10 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nite
                     out[g][q] = __builtin_fma(k.alpha, acc[j][g][q],
                                               __builtin_fma(sl, xv[q], __builtin_fma(gl, o[j][g][q], hv[q])));
             }
-            if (top[j]) {
-                double *h = hd + (t & 1) * HS + ho_top[j];
+            // the partial sum goes on to the next cell along x, else along z,
+            // else to Y
+            if (right[j] || top[j]) {
+                double *h = hd + (right[j] ? (t & 1) * XHS + xh[j] : (cur.c & 1) * ZHS + zh[j] + zcol);
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
                     lds_store16(h + 16 * g, out[g][0], out[g][1]);
@@ -2091,6 +2154,7 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nite
         p0.s = it / ngroups;
         p0.grp = it % ngroups;
         p0.c = 0;
+        p0.bx = 0;
         p0.e = segtab[p0.s];
     }
     p1 = npos > 1 ? advance(p0) : p0;
@@ -2107,7 +2171,7 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nite
     }
 }
 
-template <int P, int TPW, int G>
+template <int P, int TPW, int G, int BX>
 static hipError_t launch_tab_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
     typedef TabShape<P, TPW, G> S;
     constexpr int W = S::W;
@@ -2116,7 +2180,7 @@ static hipError_t launch_tab_p(StepParams prm, const fe_mesh *m, hipStream_t s) 
     if (!attr) {
         int per_cu = 0, dev = 0, cus = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(&step_tab_kernel<P, TPW, G>), 64 * W, 0);
+            &per_cu, reinterpret_cast<const void *>(&step_tab_kernel<P, TPW, G, BX>), 64 * W, 0);
         if (e != hipSuccess) return e;
         e = hipGetDevice(&dev);
         if (e != hipSuccess) return e;
@@ -2135,23 +2199,47 @@ static hipError_t launch_tab_p(StepParams prm, const fe_mesh *m, hipStream_t s) 
         const int2 *tab = reinterpret_cast<const int2 *>(m->d_segtab) + m->seg_off[col];
         const int64_t nitems = segs * ngroups;
         const int64_t grid = std::min<int64_t>(nitems, resident);
-        hipLaunchKernelGGL((step_tab_kernel<P, TPW, G>), dim3((unsigned)grid), dim3(64 * W), 0, s, prm, tab, nitems);
+        hipLaunchKernelGGL((step_tab_kernel<P, TPW, G, BX>), dim3((unsigned)grid), dim3(64 * W), 0, s, prm, tab,
+                           nitems);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
+template <int P>
+static hipError_t launch_tab(StepParams prm, const fe_mesh *m, hipStream_t s) {
+    switch (m->seg_bx) {
+    case 3: return launch_tab_p<P, 1, 2, 3>(prm, m, s);
+    case 2: return launch_tab_p<P, 1, 2, 2>(prm, m, s);
+    default: return launch_tab_p<P, 1, 2, 1>(prm, m, s);
+    }
+}
+
+// Cells per brick along x for the table kernel: the largest length up to 3
+// that divides the x cell count and leaves a periodic axis at least two
+// bricks; 1 when there is none above 1.
+static int xbrick_length(const fe_mesh *m) {
+    const int nx = m->ncell[0];
+    for (int L = 3; L >= 2; --L)
+        if (nx % L == 0 && (m->bc[0] != FE_BC_PERIODIC || nx / L >= 2)) return L;
+    return 1;
+}
+
 // Segment table of the table kernel (host): for every colour pass, in launch
-// order, the z segments of that colour in the order the pipelined kernel
-// walks them, one entry each (see SEG_FM / SEG_DM / SEG_WM).  Empty when the
-// kernel does not apply to the mesh.
-void build_segment_table(const fe_mesh *m, std::vector<int32_t> &tab, std::vector<int64_t> &off, int &zl_out) {
+// order, the bricks of that colour (BX cells along x by zl cells along z, at
+// one y), in the order the kernel walks them, one entry each (see SEG_FM /
+// SEG_DM / SEG_WM; the x and z bits describe the brick's outer faces).
+// Bricks are coloured along x and z as cells are.  Empty when the kernel
+// does not apply to the mesh.
+void build_segment_table(const fe_mesh *m, std::vector<int32_t> &tab, std::vector<int64_t> &off, int &zl_out,
+                         int &bx_out) {
     tab.clear();
     off.assign(1, 0);
     const int P = m->p;
-    const int zl = zseg_length(m);
+    const int zl = zseg_length(m), bxl = xbrick_length(m);
     zl_out = zl;
+    bx_out = bxl;
     AxisInfo ax[3];
     for (int d = 0; d < 3; ++d) {
         ax[d].ncell = m->ncell[d];
@@ -2159,11 +2247,15 @@ void build_segment_table(const fe_mesh *m, std::vector<int32_t> &tab, std::vecto
         ax[d].bc = m->bc[d];
         ax[d].ncol = m->ncol[d];
     }
-    AxisInfo zs = ax[2];
-    zs.ncell = ax[2].ncell / zl;
-    zs.ncol = (zs.bc == FE_BC_PERIODIC && (zs.ncell & 1)) ? 3 : zs.ncell >= 2 ? 2 : 1;
+    // the brick axes: x in runs of bxl cells, z in runs of zl cells
+    AxisInfo bk[3] = {ax[0], ax[1], ax[2]};
+    const int len[3] = {bxl, 1, zl};
+    for (int a = 0; a < 3; a += 2) {
+        bk[a].ncell = ax[a].ncell / len[a];
+        bk[a].ncol = (bk[a].bc == FE_BC_PERIODIC && (bk[a].ncell & 1)) ? 3 : bk[a].ncell >= 2 ? 2 : 1;
+    }
     auto colour_of = [](const AxisInfo &a, int c) { return (a.ncol == 3 && c == a.ncell - 1) ? 2 : (c & 1); };
-    // whether the neighbour across face lo (i = 0) or hi of cell c exists and has a lower colour
+    // whether the neighbour across face lo or hi of brick (cell) c exists and has a lower colour
     auto shared_earlier = [&](const AxisInfo &a, int c, bool hi) {
         int nb = hi ? c + 1 : c - 1;
         bool wrap = false;
@@ -2173,13 +2265,13 @@ void build_segment_table(const fe_mesh *m, std::vector<int32_t> &tab, std::vecto
         return exists && colour_of(a, nb) < colour_of(a, c);
     };
     auto first_free = [&](const AxisInfo &a, int c) { return c * P - (a.bc == FE_BC_DIRICHLET ? 1 : 0); };
-    for (int c2 = 0; c2 < zs.ncol; ++c2)
-        for (int c1 = 0; c1 < ax[1].ncol; ++c1)
-            for (int c0 = 0; c0 < ax[0].ncol; ++c0) {
+    for (int c2 = 0; c2 < bk[2].ncol; ++c2)
+        for (int c1 = 0; c1 < bk[1].ncol; ++c1)
+            for (int c0 = 0; c0 < bk[0].ncol; ++c0) {
                 const int col[3] = {c0, c1, c2};
                 int cnt[3];
                 for (int a = 0; a < 3; ++a) {
-                    const AxisInfo &A = a == 2 ? zs : ax[a];
+                    const AxisInfo &A = bk[a];
                     if (col[a] == 2) cnt[a] = 1;
                     else {
                         const int limit = A.ncol == 3 ? A.ncell - 1 : A.ncell;
@@ -2189,25 +2281,23 @@ void build_segment_table(const fe_mesh *m, std::vector<int32_t> &tab, std::vecto
                 for (int iz = 0; iz < cnt[2]; ++iz)
                     for (int iy = 0; iy < cnt[1]; ++iy)
                         for (int ix = 0; ix < cnt[0]; ++ix) {
-                            const int cx = col[0] == 2 ? ax[0].ncell - 1 : col[0] + 2 * ix;
-                            const int cy = col[1] == 2 ? ax[1].ncell - 1 : col[1] + 2 * iy;
-                            const int seg = col[2] == 2 ? zs.ncell - 1 : col[2] + 2 * iz;
-                            const int I0 = first_free(ax[0], cx) +
-                                           (int)m->nf[0] * (first_free(ax[1], cy) + (int)m->nf[1] * first_free(ax[2], seg * zl));
+                            const int ic[3] = {iz, iy, ix};
+                            int b[3];  // brick index along each axis
+                            for (int a = 0; a < 3; ++a)
+                                b[a] = col[a] == 2 ? bk[a].ncell - 1 : col[a] + 2 * ic[2 - a];
+                            const int I0 = first_free(ax[0], b[0] * bxl) +
+                                           (int)m->nf[0] * (first_free(ax[1], b[1]) +
+                                                            (int)m->nf[1] * first_free(ax[2], b[2] * zl));
                             int fm = 0, dm = 0, wm = 0;
-                            const int cc[2] = {cx, cy};
-                            for (int a = 0; a < 2; ++a) {
-                                fm |= (shared_earlier(ax[a], cc[a], false) ? 1 : 0) << (2 * a);
-                                fm |= (shared_earlier(ax[a], cc[a], true) ? 2 : 0) << (2 * a);
-                                if (ax[a].bc == FE_BC_DIRICHLET) {
-                                    dm |= (cc[a] == 0 ? 1 : 0) << (2 * a);
-                                    dm |= (cc[a] == ax[a].ncell - 1 ? 2 : 0) << (2 * a);
+                            for (int a = 0; a < 3; ++a) {
+                                fm |= (shared_earlier(bk[a], b[a], false) ? 1 : 0) << (2 * a);
+                                fm |= (shared_earlier(bk[a], b[a], true) ? 2 : 0) << (2 * a);
+                                if (bk[a].bc == FE_BC_DIRICHLET) {
+                                    dm |= (b[a] == 0 ? 1 : 0) << (2 * a);
+                                    dm |= (b[a] == bk[a].ncell - 1 ? 2 : 0) << (2 * a);
                                 }
-                                if (ax[a].bc == FE_BC_PERIODIC) wm |= (cc[a] == ax[a].ncell - 1 ? 2 : 0) << (2 * a);
+                                if (bk[a].bc == FE_BC_PERIODIC) wm |= (b[a] == bk[a].ncell - 1 ? 2 : 0) << (2 * a);
                             }
-                            fm |= (shared_earlier(zs, seg, false) ? 16 : 0) | (shared_earlier(zs, seg, true) ? 32 : 0);
-                            if (zs.bc == FE_BC_DIRICHLET) dm |= (seg == 0 ? 16 : 0) | (seg == zs.ncell - 1 ? 32 : 0);
-                            if (zs.bc == FE_BC_PERIODIC) wm |= seg == zs.ncell - 1 ? 32 : 0;
                             tab.push_back(I0);
                             tab.push_back((fm << SEG_FM) | (dm << SEG_DM) | (wm << SEG_WM));
                         }
@@ -2217,14 +2307,23 @@ void build_segment_table(const fe_mesh *m, std::vector<int32_t> &tab, std::vecto
 
 // Whether the table kernel applies: FP64 products, real mode, folded cell
 // matrix and segment table (no Neumann axis, p = 3 or 4), one leading
-// dimension for X, Y and the previous iterate, and 16-byte requests at every
-// row and column pair (blocks 16-byte aligned, even leading dimension).
+// dimension for X, Y and the previous iterate, 16-byte requests at every row
+// and column pair (blocks 16-byte aligned, even leading dimension), and X
+// request offsets within the 31-bit range of its buffer requests.
 static bool dma_applies(const fe_mesh *m, const StepArgs &a, fe_dtype prec) {
     if (prec != FE_F64 || a.S || !m->d_Af64s || !m->d_segtab || m->p < 3 || m->p > 4) return false;
     const uintptr_t ptrs = reinterpret_cast<uintptr_t>(a.X) | reinterpret_cast<uintptr_t>(a.Y) |
                            reinterpret_cast<uintptr_t>(a.Ym1 ? a.Ym1 : a.X);
     const bool same_ld = a.ldy == a.ldx && (!a.Ym1 || a.ldm == a.ldx);
-    return (ptrs & 15) == 0 && (a.ldx & 1) == 0 && same_ld;
+    // every X request's byte offset from its position's buffer start (the
+    // largest in-cell offset plus the largest wrap correction) below 2^31
+    const int64_t P = m->p;
+    const int64_t offmax = P * (1 + m->nf[0] * (1 + m->nf[1]));
+    const int64_t wrapmax = (m->bc[0] == FE_BC_PERIODIC ? m->nf[0] : 0) +
+                            (m->bc[1] == FE_BC_PERIODIC ? m->nf[0] * m->nf[1] : 0) +
+                            (m->bc[2] == FE_BC_PERIODIC ? m->n : 0);
+    const bool in_range = ((offmax + wrapmax + 1) * a.ldx + 64) * 8 < (int64_t)kTabRange;
+    return (ptrs & 15) == 0 && (a.ldx & 1) == 0 && same_ld && in_range;
 }
 
 size_t assembled_scratch_doubles(const fe_mesh *m) {
@@ -2333,7 +2432,7 @@ static hipError_t launch_step_v(const fe_mesh *m, const StepArgs &a, fe_dtype pr
         const int64_t Nf = a.N / 32 * 32;
         prm.N = Nf;
         prm.nchunk = (int)(Nf / 16);
-        const hipError_t e = m->p == 3 ? launch_tab_p<3, 1, 2>(prm, m, s) : launch_tab_p<4, 1, 2>(prm, m, s);
+        const hipError_t e = m->p == 3 ? launch_tab<3>(prm, m, s) : launch_tab<4>(prm, m, s);
         if (e != hipSuccess || Nf == a.N) return e;
         StepArgs rest = a;
         rest.X += Nf;

@@ -46,6 +46,14 @@ CASES = [
     ("p4-DPP-N48", W.small_slab((3, 2, 8), p=4, N=48, bc=(W.DIRICHLET, W.PERIODIC, W.PERIODIC), E=0.0)),
     ("p3-periodic-z-N52", W.small_slab((3, 3, 9), p=3, N=52, bc=(W.PERIODIC,) * 3, E=0.0)),
     ("p3-dirichlet-all-N32", W.small_slab((3, 4, 8), p=3, N=32, bc=(W.DIRICHLET,) * 3)),
+    # x bricks (3 or 2 cells per brick, inner x faces in LDS): periodic x
+    # with two bricks, three bricks (three colours), Dirichlet x with one and
+    # two bricks
+    ("p4-bricks3-periodic-x6-N64", W.small_slab((6, 2, 12), p=4, N=64)),
+    ("p4-bricks3-3colour-x9-N32", W.small_slab((9, 2, 6), p=4, N=32, bc=(W.PERIODIC,) * 3, E=0.0)),
+    ("p4-bricks2-periodic-x4-N48", W.small_slab((4, 3, 8), p=4, N=48)),
+    ("p4-bricks2-dirichlet-x2-N32", W.small_slab((2, 3, 8), p=4, N=32, bc=(W.DIRICHLET, W.PERIODIC, W.DIRICHLET))),
+    ("p3-bricks3-dirichlet-x6-N40", W.small_slab((6, 2, 6), p=3, N=40, bc=(W.DIRICHLET, W.PERIODIC, W.DIRICHLET))),
     ("p2-dirichlet-all-N64", W.small_slab((3, 4, 8), p=2, N=64, bc=(W.DIRICHLET,) * 3)),
     ("p1-N2", W.small_slab((4, 3, 12), p=1, N=2)),
     ("p4-N20", W.small_slab((3, 2, 8), p=4, N=20)),
