@@ -2481,7 +2481,9 @@ static hipError_t launch_step_v(const fe_mesh *m, const StepArgs &a, fe_dtype pr
         ((variant == 7 || variant == 9) && prec == FE_F64)) {
         // 32 vectors per workgroup and one row tile per wave measured best
         // where the tiles fit one workgroup (p <= 5); above that two tiles
-        // per wave keep the workgroup within 1024 threads
+        // per wave keep the workgroup within 1024 threads (p = 6: 32 vectors
+        // per workgroup, 158 VGPRs for three waves per SIMD, 5.78 ms per H~X
+        // on the 16x16x32-cell slab against 6.32 for 16 vectors)
         // BK / BKL: fragment batch (k-steps) for FP64 / for FP32 and BF16
 #define FE_ROW(PP, G, TPW, OCC, BK, BKL)                                                     \
     case PP:                                                                                 \
@@ -2494,7 +2496,7 @@ static hipError_t launch_step_v(const fe_mesh *m, const StepArgs &a, fe_dtype pr
             FE_ROW(3, 2, 1, 5, 4, 4)
             FE_ROW(4, 2, 1, 5, 4, 4)
             FE_ROW(5, 2, 1, 5, 4, 4)
-            FE_ROW(6, 1, 2, 5, 2, 2)
+            FE_ROW(6, 2, 2, 3, 2, 2)
             FE_ROW(7, 1, 2, 5, 2, 2)
         default: break;
         }
