@@ -168,6 +168,7 @@ static void free_mesh(fe_mesh *m) {
     (void)hipFree(m->d_zcoord);
     (void)hipFree(m->d_Af64);
     (void)hipFree(m->d_Af64s);
+    (void)hipFree(m->d_Af32s);
     (void)hipFree(m->d_zero);
     (void)hipFree(m->d_segtab);
     (void)hipFree(m->d_Af32);
@@ -278,6 +279,7 @@ fe_status fe_mesh_create(const fe_mesh_desc *d, fe_mesh **out) {
     // node there has one cell's mass only).
     const bool fold = m->bc[0] != FE_BC_NEUMANN && m->bc[1] != FE_BC_NEUMANN && m->bc[2] != FE_BC_NEUMANN;
     std::vector<double> f64s;
+    std::vector<float> f32s;
     if (fold) {
         std::vector<double> dh(m->n1);
         for (int i = 0; i <= m->p; ++i) {
@@ -289,6 +291,7 @@ fe_status fe_mesh_create(const fe_mesh_desc *d, fe_mesh **out) {
         for (int l = 0; l < m->nc; ++l)
             for (int q = 0; q < m->nc; ++q) As[(size_t)l * m->nc + q] = dl(l) * m->cellA[(size_t)l * m->nc + q] * dl(q);
         swizzle_f64(m, As, f64s);
+        f32s.assign(f64s.begin(), f64s.end());
     }
     const double zeros[32] = {};
     std::vector<int32_t> segtab;
@@ -304,6 +307,7 @@ fe_status fe_mesh_create(const fe_mesh_desc *d, fe_mesh **out) {
               up((void **)&m->d_wrel, wrel.data(), wrel.size() * sizeof(double)) &&
               up((void **)&m->d_Af64, f64.data(), f64.size() * sizeof(double)) &&
               (!fold || up((void **)&m->d_Af64s, f64s.data(), f64s.size() * sizeof(double))) &&
+              (!fold || up((void **)&m->d_Af32s, f32s.data(), f32s.size() * sizeof(float))) &&
               up((void **)&m->d_zero, zeros, sizeof(zeros)) &&
               (segtab.empty() || up((void **)&m->d_segtab, segtab.data(), segtab.size() * sizeof(int32_t))) &&
               up((void **)&m->d_Af32, f32.data(), f32.size() * sizeof(float)) &&

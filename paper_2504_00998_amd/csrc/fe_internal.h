@@ -78,10 +78,11 @@ struct fe_mesh {
     // with no Neumann axis every free node's M^-1/2 is the product of per-axis
     // factors that depend only on its local index in any cell containing it,
     // so D Kc D folds into one cell matrix: swizzled f64 fragments of
-    // D^ (1/2 Kc) D^ (null with a Neumann axis)
+    // D^ (1/2 Kc) D^ (null with a Neumann axis), and the same rounded to f32
     double *d_Af64s = nullptr;
+    float *d_Af32s = nullptr;
     double *d_zero = nullptr;     // 32 zero doubles (source of padded / absent rows)
-    // segment table of the FP64 table kernel (p = 3, 4 with the folded cell
+    // segment table of the table kernel (p = 3, 4 with the folded cell
     // matrix): per colour pass, per z segment, first DoF and face masks
     int32_t *d_segtab = nullptr;
     std::vector<int64_t> seg_off;  // entries of colour pass c: [seg_off[c], seg_off[c+1])
@@ -175,7 +176,7 @@ hipError_t launch_nonlocal_k(fe_mesh *m, const double *X, int64_t ldx, double *Y
                              double alpha, hipStream_t s);
 fe_status nonlocal_set_phase(fe_mesh *m);
 void swizzle_f64(const fe_mesh *m, const std::vector<double> &A, std::vector<double> &f64);
-// segment table of the FP64 table kernel (fe_kernels.hip)
+// segment table of the table kernel (fe_kernels.hip)
 void build_segment_table(const fe_mesh *m, std::vector<int32_t> &tab, std::vector<int64_t> &off, int &zl, int &bx);
 void nonlocal_release(fe_mesh *m);
 

@@ -1728,10 +1728,13 @@ static hipError_t launch_pipe_p(StepParams prm, const fe_mesh *m, hipStream_t s)
 }
 
 // ------------------------------------------------------------------------
-// FP64 step kernel with direct-to-LDS prefetch and a segment table (p = 3, 4;
+// Step kernel with direct-to-LDS prefetch and a segment table (p = 3, 4;
 // meshes without a zero-Neumann axis, where M^-1/2 of a free node depends
 // only on its local index and folds into the cell matrix:
-// A' = D^ (1/2 Kc) D^).
+// A' = D^ (1/2 Kc) D^), with FP64 cell products (PREC 0) or FP32 ones
+// (PREC 1: A' rounded to FP32, each X element rounded to FP32 as the
+// product reads it from the FP64 buffer, FP32 accumulation; everything
+// else, the buffers and the epilogue, in FP64 as for PREC 0).
 //
 // On gfx950 the FP64 4x4x4 MFMA and every other vector instruction share the
 // SIMD's vector ALU (an FP64 MFMA holds it as long as 16 wave-wide FMA
@@ -1852,9 +1855,11 @@ template <int P> struct TabRow {
     }
 };
 
-template <int P, int TPW, int NGRP, int BX>
+template <int P, int PREC, int TPW, int NGRP, int BX>
 __global__ __launch_bounds__((64 * TabShape<P, TPW, NGRP>::W)) __attribute__((amdgpu_waves_per_eu(1, 2)))
 void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nitems) {
+    static_assert(PREC == 0 || PREC == 1, "FP64 or FP32 cell products");
+    typedef typename FragOf<PREC>::T AT;
     typedef TabShape<P, TPW, NGRP> S;
     constexpr int N1 = P + 1, NKS = S::NKS, G = S::G, XS = S::XS, W = S::W, NDMA = S::NDMA;
     // LDS holds (doubles per buffer, each two-deep): the x face between
@@ -1884,10 +1889,10 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nite
     const int zstep = P * (int)(k.nfx * k.nfy);  // DoF step from a cell to the next along z
     const int64_t ld = k.ldx;                    // one leading dimension for X, Y and the previous iterate
     // the wave's row tiles of A' (tiles wave + W j), resident for the launch
-    double ar[TPW][NKS];
+    AT ar[TPW][NKS];
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
-        const double *A = reinterpret_cast<const double *>(k.A) + (size_t)(wave + W * j) * NKS * 64 + lane;
+        const AT *A = reinterpret_cast<const AT *>(k.A) + (size_t)(wave + W * j) * NKS * 64 + lane;
 #pragma unroll
         for (int s = 0; s < NKS; ++s) ar[j][s] = A[s * 64];
     }
@@ -1895,12 +1900,12 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nite
     // pipe_off(q) of each 16-vector group) and the two rows it requests X
     // for (rows 16 tile + 8 h + l / 8, vectors 2 (l % 8) + {0, 1} of each
     // group)
-    const int vq = pipe_vec<0>(lane);
+    const int vq = pipe_vec<PREC>(lane);
     TabRow<P> R[TPW], Q[TPW][2];
     int xo[TPW], xh[TPW], zh[TPW];  // offsets in an X buffer, an x-face hold, the top-face hold of a brick row
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
-        const int tile = wave + W * j, r = 16 * tile + pipe_row<0>(lane);
+        const int tile = wave + W * j, r = 16 * tile + pipe_row<PREC>(lane);
         R[j].init(k, r, vq);
         Q[j][0].init(k, 16 * tile + (lane >> 3), 2 * (lane & 7));
         Q[j][1].init(k, 16 * tile + 8 + (lane >> 3), 2 * (lane & 7));
@@ -2053,13 +2058,13 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nite
         n2 = t + 2 < npos ? advance(n1) : n1;
         prefetch(cell(n2), xn);
         double acc[TPW][G][4];
+        if constexpr (PREC == 0) {
 #pragma unroll
-        for (int j = 0; j < TPW; ++j)
+            for (int j = 0; j < TPW; ++j)
 #pragma unroll
-            for (int g = 0; g < G; ++g)
+                for (int g = 0; g < G; ++g)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc[j][g][q] = 0.0;
-        {
+                    for (int q = 0; q < 4; ++q) acc[j][g][q] = 0.0;
             double bc[G][4], bn[G][4];
 #pragma unroll
             for (int g = 0; g < G; ++g) f64_pair_b(xs + g * XS, 0, lane, bc[g]);
@@ -2080,6 +2085,39 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nite
 #pragma unroll
                     for (int q = 0; q < 4; ++q) bc[g][q] = bn[g][q];
             }
+        } else {
+            // transposed 16x16x4 products: the X slice (row 4s + l / 16,
+            // vector pipe_perm(l % 16), rounded from the buffer's f64 to f32)
+            // first, the fragment second; lane l's accumulator q then holds
+            // row pipe_row(l), vector vq + pipe_off(q)
+            const int bo = (lane >> 4) * 16 + pipe_perm(lane & 15);
+            f4 c4[TPW][G];
+            float bc[G], bn[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) bc[g] = (float)xs[g * XS + bo];
+#pragma unroll
+            for (int j = 0; j < TPW; ++j)
+#pragma unroll
+                for (int g = 0; g < G; ++g) c4[j][g] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < NKS; ++s) {
+                if (s + 1 < NKS)
+#pragma unroll
+                    for (int g = 0; g < G; ++g) bn[g] = (float)xs[g * XS + 64 * (s + 1) + bo];
+#pragma unroll
+                for (int j = 0; j < TPW; ++j)
+#pragma unroll
+                    for (int g = 0; g < G; ++g)
+                        c4[j][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(bc[g], ar[j][s], c4[j][g], 0, 0, 0);
+#pragma unroll
+                for (int g = 0; g < G; ++g) bc[g] = bn[g];
+            }
+#pragma unroll
+            for (int j = 0; j < TPW; ++j)
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[j][g][q] = (double)c4[j][g][q];
         }
         // the old values and v of t, and the X rows of t + 1 (both requested
         // before the NDMA X requests of t + 2)
@@ -2171,7 +2209,7 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nite
     }
 }
 
-template <int P, int TPW, int G, int BX>
+template <int P, int PREC, int TPW, int G, int BX>
 static hipError_t launch_tab_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
     typedef TabShape<P, TPW, G> S;
     constexpr int W = S::W;
@@ -2180,7 +2218,7 @@ static hipError_t launch_tab_p(StepParams prm, const fe_mesh *m, hipStream_t s) 
     if (!attr) {
         int per_cu = 0, dev = 0, cus = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(&step_tab_kernel<P, TPW, G, BX>), 64 * W, 0);
+            &per_cu, reinterpret_cast<const void *>(&step_tab_kernel<P, PREC, TPW, G, BX>), 64 * W, 0);
         if (e != hipSuccess) return e;
         e = hipGetDevice(&dev);
         if (e != hipSuccess) return e;
@@ -2189,7 +2227,7 @@ static hipError_t launch_tab_p(StepParams prm, const fe_mesh *m, hipStream_t s) 
         resident = std::max(1, per_cu) * std::max(1, cus);
         attr = true;
     }
-    prm.A = m->d_Af64s;
+    prm.A = PREC == 0 ? (const void *)m->d_Af64s : (const void *)m->d_Af32s;
     prm.zl = m->seg_zl;
     prm.nfz = (int)m->nf[2];
     const int ngroups = (prm.nchunk + G - 1) / G;
@@ -2199,7 +2237,7 @@ static hipError_t launch_tab_p(StepParams prm, const fe_mesh *m, hipStream_t s) 
         const int2 *tab = reinterpret_cast<const int2 *>(m->d_segtab) + m->seg_off[col];
         const int64_t nitems = segs * ngroups;
         const int64_t grid = std::min<int64_t>(nitems, resident);
-        hipLaunchKernelGGL((step_tab_kernel<P, TPW, G, BX>), dim3((unsigned)grid), dim3(64 * W), 0, s, prm, tab,
+        hipLaunchKernelGGL((step_tab_kernel<P, PREC, TPW, G, BX>), dim3((unsigned)grid), dim3(64 * W), 0, s, prm, tab,
                            nitems);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -2207,12 +2245,12 @@ static hipError_t launch_tab_p(StepParams prm, const fe_mesh *m, hipStream_t s) 
     return hipSuccess;
 }
 
-template <int P>
+template <int P, int PREC>
 static hipError_t launch_tab(StepParams prm, const fe_mesh *m, hipStream_t s) {
     switch (m->seg_bx) {
-    case 3: return launch_tab_p<P, 1, 2, 3>(prm, m, s);
-    case 2: return launch_tab_p<P, 1, 2, 2>(prm, m, s);
-    default: return launch_tab_p<P, 1, 2, 1>(prm, m, s);
+    case 3: return launch_tab_p<P, PREC, 1, 2, 3>(prm, m, s);
+    case 2: return launch_tab_p<P, PREC, 1, 2, 2>(prm, m, s);
+    default: return launch_tab_p<P, PREC, 1, 2, 1>(prm, m, s);
     }
 }
 
@@ -2305,13 +2343,14 @@ void build_segment_table(const fe_mesh *m, std::vector<int32_t> &tab, std::vecto
             }
 }
 
-// Whether the table kernel applies: FP64 products, real mode, folded cell
-// matrix and segment table (no Neumann axis, p = 3 or 4), one leading
+// Whether the table kernel applies: FP64 or FP32 products, real mode, folded
+// cell matrix and segment table (no Neumann axis, p = 3 or 4), one leading
 // dimension for X, Y and the previous iterate, 16-byte requests at every row
 // and column pair (blocks 16-byte aligned, even leading dimension), and X
 // request offsets within the 31-bit range of its buffer requests.
 static bool dma_applies(const fe_mesh *m, const StepArgs &a, fe_dtype prec) {
-    if (prec != FE_F64 || a.S || !m->d_Af64s || !m->d_segtab || m->p < 3 || m->p > 4) return false;
+    if (a.S || !m->d_segtab || m->p < 3 || m->p > 4) return false;
+    if (!(prec == FE_F64 ? m->d_Af64s != nullptr : prec == FE_F32 && m->d_Af32s != nullptr)) return false;
     const uintptr_t ptrs = reinterpret_cast<uintptr_t>(a.X) | reinterpret_cast<uintptr_t>(a.Y) |
                            reinterpret_cast<uintptr_t>(a.Ym1 ? a.Ym1 : a.X);
     const bool same_ld = a.ldy == a.ldx && (!a.Ym1 || a.ldm == a.ldx);
@@ -2421,18 +2460,20 @@ static hipError_t launch_step_v(const fe_mesh *m, const StepArgs &a, fe_dtype pr
         default: break;
         }
     }
-    // variant 10: the FP64 table kernel with direct-to-LDS prefetch (z
-    // segments) on the whole 32-vector groups; the columns past the last
-    // whole group (fewer than 32) go to the z-segment pipelined kernel
-    // (the default for FP64 at p = 3 and 4, where it was measured fastest:
-    // 1.62 / 4.73 ms per H~X against 2.02 / 5.75 for the z-segment kernel on
-    // the 24x24x48-cell slab, 256 vectors)
-    const bool tab = variant == 10 || (variant == 0 && prec == FE_F64 && (m->p == 3 || m->p == 4));
+    // variant 10: the table kernel with direct-to-LDS prefetch (bricks) on
+    // the whole 32-vector groups, FP64 or FP32 cell products; the columns
+    // past the last whole group (fewer than 32) go to the z-segment
+    // pipelined kernel (the default at p = 3 and 4 for both, where it was
+    // measured fastest on the 24x24x48-cell slab, 256 vectors: FP64 4.48
+    // against 5.75, FP32 3.26 against 4.17 ms per H~X for the z-segment
+    // kernel)
+    const bool tab = variant == 10 || (variant == 0 && (prec == FE_F64 || prec == FE_F32) && (m->p == 3 || m->p == 4));
     if (tab && a.N >= 32 && dma_applies(m, a, prec)) {
         const int64_t Nf = a.N / 32 * 32;
         prm.N = Nf;
         prm.nchunk = (int)(Nf / 16);
-        const hipError_t e = m->p == 3 ? launch_tab<3>(prm, m, s) : launch_tab<4>(prm, m, s);
+        const hipError_t e = prec == FE_F64 ? (m->p == 3 ? launch_tab<3, 0>(prm, m, s) : launch_tab<4, 0>(prm, m, s))
+                                            : (m->p == 3 ? launch_tab<3, 1>(prm, m, s) : launch_tab<4, 1>(prm, m, s));
         if (e != hipSuccess || Nf == a.N) return e;
         StepArgs rest = a;
         rest.X += Nf;

@@ -1,4 +1,4 @@
-"""The FP64 table kernel with direct-to-LDS prefetch (kernel variant 10):
+"""The table kernel with direct-to-LDS prefetch (kernel variant 10):
 parity with the oracle, reproducibility, the cases where it does not apply
 (it falls back to the one-cell kernel), walks of several segments per
 workgroup, and the split of N into whole 32-vector groups (table kernel)
@@ -160,5 +160,36 @@ def test_dma_kernel_several_segments_per_workgroup(p, N):
         for A, B in ((Y10, Y1), (F10, F1)):
             rel = ((A - B).norm(dim=0) / B.norm(dim=0)).max().item()
             assert rel < 1e-13, rel
+    finally:
+        gm.set_kernel(0)
+
+
+@pytest.mark.parametrize("label,wl", CASES[:13], ids=[c[0] for c in CASES[:13]])
+def test_dma_kernel_f32_products(label, wl):
+    """FP32 cell products (the folded matrix rounded to FP32, X rounded to
+    FP32 as it leaves LDS, FP32 accumulation; the epilogue in FP64) on every
+    mesh form the table applies to: H~X and the filter against the FP64
+    oracle within the FP32 bound of the other FP32 kernels, the z-segment
+    kernel's FP32 products to the same order, and reproducible."""
+    print("case: dma f32", label, wl.ncell, wl.p, wl.N, flush=True)
+    op, gm = _setup(wl)
+    Xh = wl.X(op.n)
+    X = torch.from_numpy(Xh).cuda()
+    gm.set_kernel(10)
+    try:
+        H = gm.hx(X, prec="f32")
+        assert torch.equal(gm.hx(X, prec="f32"), H)
+        eh = _relerr(H.cpu().numpy(), op.apply(Xh))
+        a0, b, _ = O.lanczos_bounds(op.apply, wl.lanczos_start(op.n), 10)
+        a = O.weyl_cut(a0, b, wl.N, op.n)
+        Y = gm.cheb_filter(X, wl.m, a, b, a0, prec="f32")
+        assert torch.equal(gm.cheb_filter(X, wl.m, a, b, a0, prec="f32"), Y)
+        ef = _relerr(Y.cpu().numpy(), op.filter(Xh, wl.m, a, b, a0))
+        gm.set_kernel(9)
+        H9 = gm.hx(X, prec="f32")
+        e9 = _relerr(H9.cpu().numpy(), op.apply(Xh))
+        print(f"f32 rel err: table {eh:.2e} (z-segment {e9:.2e}), filter {ef:.2e}", flush=True)
+        assert 0 < eh < 1e-6 and ef < 5e-6
+        assert ((H - H9).norm(dim=0) / H9.norm(dim=0)).max().item() < 1e-6
     finally:
         gm.set_kernel(0)

@@ -121,13 +121,13 @@ def test_filter_degrees_and_leading_dimension(m):
 def test_kernel_variants_bitwise_equal(prec, p):
     """The multi-vector kernels and the one-cell-per-workgroup kernel perform
     the same operations in the same order.  The default at p = 4 is the
-    table kernel (variant 10) for FP64 products and the z-segment kernel
-    (variant 9) for FP32 and BF16; both sum shared nodes in another order
-    (the table kernel also multiplies with the folded cell matrix, BF16 takes
-    the products transposed): equal to rounding, and bitwise equal to the
-    variant they run.  Where the table kernel does not apply (p = 2, 5,
-    FP32, BF16) variant 10 runs the one-cell kernel.  The removed variants
-    are refused."""
+    table kernel (variant 10) for FP64 and FP32 products and the z-segment
+    kernel (variant 9) for BF16; both sum shared nodes in another order (the
+    table kernel also multiplies with the folded cell matrix, BF16 takes the
+    products transposed): equal to rounding, and bitwise equal to the variant
+    they run.  Where the table kernel does not apply (p = 2, 5, BF16)
+    variant 10 runs the one-cell kernel.  The removed variants are
+    refused."""
     wl = W.small_slab((3, 3, 4), p=p, N=40)
     op, gm, _ = _setup(wl)
     X = torch.from_numpy(wl.X(op.n)).cuda()
@@ -136,7 +136,7 @@ def test_kernel_variants_bitwise_equal(prec, p):
             gm.set_kernel(gone)
     gm.set_kernel(1)
     Y1 = gm.cheb_filter(X, 5, 2.0, 400.0, -0.5, prec=prec)
-    tab = p == 4 and prec == "f64"
+    tab = p == 4 and prec in ("f64", "f32")
     # above p = 4 variant 9 runs what variant 7 runs (one-cell kernels)
     for var in (0, 3, 4, 6, 7, 10) + ((9,) if p > 4 else ()):
         gm.set_kernel(var)
