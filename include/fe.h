@@ -109,11 +109,12 @@ fe_status fe_mesh_destroy(fe_mesh *mesh);
  * 10 = the table kernel: the walk of 9 with the X rows copied from HBM
  * straight into LDS two positions ahead, each position's cell read from a
  * per-segment table of first DoF and face masks built at mesh creation, and
- * the cell matrix pre-scaled by M^-1/2 (FP64 and FP32 products, p = 3 and
- * 4, no zero-Neumann axis, one leading dimension for X, Y and the previous
- * iterate, 16-byte aligned blocks with an even leading dimension; applied
- * to the whole 32-vector groups of N, the columns past the last whole group
- * run variant 9; the FP64 and FP32 default at p = 3 and 4; else as 0).
+ * the cell matrix pre-scaled by M^-1/2 (FP64 products at p = 3 and 4, FP32
+ * products at p = 3, 4 and 5; no zero-Neumann axis, one leading dimension
+ * for X, Y and the previous iterate, 16-byte aligned blocks with an even
+ * leading dimension; applied to the whole 32-vector groups of N, the
+ * columns past the last whole group run variant 9; the default wherever it
+ * applies; else as 0).
  * Variants 0, 1, 3, 4, 6 and 7 give bitwise-identical results (variant 0
  * wherever it is not variant 9 or 10); variants 9 and 10 sum each node's
  * contributions in other fixed orders (equal to rounding, reproducible).

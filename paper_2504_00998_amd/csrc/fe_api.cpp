@@ -296,7 +296,8 @@ fe_status fe_mesh_create(const fe_mesh_desc *d, fe_mesh **out) {
     const double zeros[32] = {};
     std::vector<int32_t> segtab;
     // the table kernel indexes DoFs in 32 bits
-    if (fold && (m->p == 3 || m->p == 4) && m->n < INT32_MAX) build_segment_table(m, segtab, m->seg_off, m->seg_zl, m->seg_bx);
+    if (fold && m->p >= 3 && m->p <= 5 && m->n < INT32_MAX)
+        build_segment_table(m, segtab, m->seg_off, m->seg_zl, m->seg_bx);
 
     auto up = [&](void **dst, const void *src, size_t bytes) -> bool {
         if (hipMalloc(dst, bytes) != hipSuccess) return false;

@@ -82,7 +82,7 @@ struct fe_mesh {
     double *d_Af64s = nullptr;
     float *d_Af32s = nullptr;
     double *d_zero = nullptr;     // 32 zero doubles (source of padded / absent rows)
-    // segment table of the table kernel (p = 3, 4 with the folded cell
+    // segment table of the table kernel (p = 3, 4, 5 with the folded cell
     // matrix): per colour pass, per z segment, first DoF and face masks
     int32_t *d_segtab = nullptr;
     std::vector<int64_t> seg_off;  // entries of colour pass c: [seg_off[c], seg_off[c+1])

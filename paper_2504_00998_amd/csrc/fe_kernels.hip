@@ -2245,12 +2245,21 @@ static hipError_t launch_tab_p(StepParams prm, const fe_mesh *m, hipStream_t s) 
     return hipSuccess;
 }
 
+// Shapes of the table kernel: p = 3, 4 one 16-row tile of A' per wave
+// (8 waves) and 32 vectors per item; p = 5 (FP32 products only: 224 padded
+// rows) two tiles per wave (7 waves, 56 fragment registers each) and 16
+// vectors per item, so that three X buffers of 224 rows fit the LDS.
+template <int P> struct TabCfg {
+    static constexpr int TPW = P == 5 ? 2 : 1, G = P == 5 ? 1 : 2;
+};
+
 template <int P, int PREC>
 static hipError_t launch_tab(StepParams prm, const fe_mesh *m, hipStream_t s) {
+    constexpr int TPW = TabCfg<P>::TPW, G = TabCfg<P>::G;
     switch (m->seg_bx) {
-    case 3: return launch_tab_p<P, PREC, 1, 2, 3>(prm, m, s);
-    case 2: return launch_tab_p<P, PREC, 1, 2, 2>(prm, m, s);
-    default: return launch_tab_p<P, PREC, 1, 2, 1>(prm, m, s);
+    case 3: return launch_tab_p<P, PREC, TPW, G, 3>(prm, m, s);
+    case 2: return launch_tab_p<P, PREC, TPW, G, 2>(prm, m, s);
+    default: return launch_tab_p<P, PREC, TPW, G, 1>(prm, m, s);
     }
 }
 
@@ -2343,13 +2352,14 @@ void build_segment_table(const fe_mesh *m, std::vector<int32_t> &tab, std::vecto
             }
 }
 
-// Whether the table kernel applies: FP64 or FP32 products, real mode, folded
-// cell matrix and segment table (no Neumann axis, p = 3 or 4), one leading
+// Whether the table kernel applies: FP64 (p = 3, 4) or FP32 (p = 3, 4, 5)
+// products, real mode, folded cell matrix and segment table (no Neumann
+// axis), one leading
 // dimension for X, Y and the previous iterate, 16-byte requests at every row
 // and column pair (blocks 16-byte aligned, even leading dimension), and X
 // request offsets within the 31-bit range of its buffer requests.
 static bool dma_applies(const fe_mesh *m, const StepArgs &a, fe_dtype prec) {
-    if (a.S || !m->d_segtab || m->p < 3 || m->p > 4) return false;
+    if (a.S || !m->d_segtab || m->p < 3 || m->p > 5 || (m->p == 5 && prec != FE_F32)) return false;
     if (!(prec == FE_F64 ? m->d_Af64s != nullptr : prec == FE_F32 && m->d_Af32s != nullptr)) return false;
     const uintptr_t ptrs = reinterpret_cast<uintptr_t>(a.X) | reinterpret_cast<uintptr_t>(a.Y) |
                            reinterpret_cast<uintptr_t>(a.Ym1 ? a.Ym1 : a.X);
@@ -2461,19 +2471,20 @@ static hipError_t launch_step_v(const fe_mesh *m, const StepArgs &a, fe_dtype pr
         }
     }
     // variant 10: the table kernel with direct-to-LDS prefetch (bricks) on
-    // the whole 32-vector groups, FP64 or FP32 cell products; the columns
-    // past the last whole group (fewer than 32) go to the z-segment
-    // pipelined kernel (the default at p = 3 and 4 for both, where it was
-    // measured fastest on the 24x24x48-cell slab, 256 vectors: FP64 4.48
-    // against 5.75, FP32 3.26 against 4.17 ms per H~X for the z-segment
-    // kernel)
-    const bool tab = variant == 10 || (variant == 0 && (prec == FE_F64 || prec == FE_F32) && (m->p == 3 || m->p == 4));
+    // the whole 32-vector groups, FP64 (p = 3, 4) or FP32 (p = 3, 4, 5) cell
+    // products; the columns past the last whole group (fewer than 32) go to
+    // the z-segment pipelined kernel (the default wherever it applies, where
+    // it was measured fastest: FP64 4.48 against 5.75, FP32 3.26 against
+    // 4.17 ms per H~X for the z-segment kernel on the 24x24x48-cell p = 4
+    // slab, 256 vectors)
+    const bool tab = variant == 10 || (variant == 0 && (prec == FE_F64 || prec == FE_F32));
     if (tab && a.N >= 32 && dma_applies(m, a, prec)) {
         const int64_t Nf = a.N / 32 * 32;
         prm.N = Nf;
         prm.nchunk = (int)(Nf / 16);
-        const hipError_t e = prec == FE_F64 ? (m->p == 3 ? launch_tab<3, 0>(prm, m, s) : launch_tab<4, 0>(prm, m, s))
-                                            : (m->p == 3 ? launch_tab<3, 1>(prm, m, s) : launch_tab<4, 1>(prm, m, s));
+        hipError_t e = hipErrorInvalidValue;
+        if (prec == FE_F64) e = m->p == 3 ? launch_tab<3, 0>(prm, m, s) : launch_tab<4, 0>(prm, m, s);
+        else e = m->p == 3 ? launch_tab<3, 1>(prm, m, s) : m->p == 4 ? launch_tab<4, 1>(prm, m, s) : launch_tab<5, 1>(prm, m, s);
         if (e != hipSuccess || Nf == a.N) return e;
         StepArgs rest = a;
         rest.X += Nf;

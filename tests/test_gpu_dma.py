@@ -164,13 +164,26 @@ def test_dma_kernel_several_segments_per_workgroup(p, N):
         gm.set_kernel(0)
 
 
-@pytest.mark.parametrize("label,wl", CASES[:13], ids=[c[0] for c in CASES[:13]])
+# p = 5 (FP32 products only): two row tiles per wave, 16 vectors per item;
+# three colours along x and one-cell bricks, bricks of 2 and 3 cells, all
+# axes periodic with a rest of 8 columns
+P5_CASES = [
+    ("p5-3colour-x3-N48", W.small_slab((3, 2, 6), p=5, N=48)),
+    ("p5-bricks2-periodic-x4-N32", W.small_slab((4, 2, 4), p=5, N=32)),
+    ("p5-bricks3-dirichlet-x3-N64", W.small_slab((3, 2, 5), p=5, N=64, bc=(W.DIRICHLET, W.PERIODIC, W.DIRICHLET))),
+    ("p5-periodic-all-N40", W.small_slab((2, 3, 4), p=5, N=40, bc=(W.PERIODIC,) * 3, E=0.0)),
+]
+F32_CASES = CASES[:13] + P5_CASES
+
+
+@pytest.mark.parametrize("label,wl", F32_CASES, ids=[c[0] for c in F32_CASES])
 def test_dma_kernel_f32_products(label, wl):
     """FP32 cell products (the folded matrix rounded to FP32, X rounded to
     FP32 as it leaves LDS, FP32 accumulation; the epilogue in FP64) on every
-    mesh form the table applies to: H~X and the filter against the FP64
-    oracle within the FP32 bound of the other FP32 kernels, the z-segment
-    kernel's FP32 products to the same order, and reproducible."""
+    mesh form the table applies to (and p = 5): H~X and the filter against
+    the FP64 oracle within the FP32 bound of the other FP32 kernels, the
+    FP32 products of variant 9 (the z-segment kernel; at p = 5 the one-cell
+    pipelined kernel) to the same order, and reproducible."""
     print("case: dma f32", label, wl.ncell, wl.p, wl.N, flush=True)
     op, gm = _setup(wl)
     Xh = wl.X(op.n)

@@ -122,12 +122,12 @@ def test_kernel_variants_bitwise_equal(prec, p):
     """The multi-vector kernels and the one-cell-per-workgroup kernel perform
     the same operations in the same order.  The default at p = 4 is the
     table kernel (variant 10) for FP64 and FP32 products and the z-segment
-    kernel (variant 9) for BF16; both sum shared nodes in another order (the
-    table kernel also multiplies with the folded cell matrix, BF16 takes the
-    products transposed): equal to rounding, and bitwise equal to the variant
-    they run.  Where the table kernel does not apply (p = 2, 5, BF16)
-    variant 10 runs the one-cell kernel.  The removed variants are
-    refused."""
+    kernel (variant 9) for BF16, and at p = 5 the table kernel for FP32; both
+    sum shared nodes in another order (the table kernel also multiplies with
+    the folded cell matrix, BF16 takes the products transposed): equal to
+    rounding, and bitwise equal to the variant they run.  Where the table
+    kernel does not apply (p = 2; p = 5 in FP64 and BF16; BF16) variant 10
+    runs the one-cell kernel.  The removed variants are refused."""
     wl = W.small_slab((3, 3, 4), p=p, N=40)
     op, gm, _ = _setup(wl)
     X = torch.from_numpy(wl.X(op.n)).cuda()
@@ -136,17 +136,19 @@ def test_kernel_variants_bitwise_equal(prec, p):
             gm.set_kernel(gone)
     gm.set_kernel(1)
     Y1 = gm.cheb_filter(X, 5, 2.0, 400.0, -0.5, prec=prec)
-    tab = p == 4 and prec in ("f64", "f32")
+    tab = (p == 4 and prec in ("f64", "f32")) or (p == 5 and prec == "f32")
     # above p = 4 variant 9 runs what variant 7 runs (one-cell kernels)
     for var in (0, 3, 4, 6, 7, 10) + ((9,) if p > 4 else ()):
         gm.set_kernel(var)
         Y0 = gm.cheb_filter(X, 5, 2.0, 400.0, -0.5, prec=prec)
-        if (var == 0 and p == 4) or (var == 10 and tab):
+        if (var == 0 and (p == 4 or tab)) or (var == 10 and tab):
+            # two FP32 product orders, each within about 1e-6 of the exact
+            # degree-5 filter (5e-7 at p = 4, up to 1.1e-6 apart at p = 5)
             rel = ((Y0 - Y1).norm(dim=0) / Y1.norm(dim=0)).max().item()
-            assert 0 < rel < {"f64": 1e-13, "f32": 1e-6, "bf16": 1e-5}[prec], rel
+            assert 0 < rel < {"f64": 1e-13, "f32": 3e-6, "bf16": 1e-5}[prec], rel
         else:
             assert torch.equal(Y0, Y1), var
-    if p == 4:
+    if p == 4 or tab:
         gm.set_kernel(0)
         Y0 = gm.cheb_filter(X, 5, 2.0, 400.0, -0.5, prec=prec)
         gm.set_kernel(10 if tab else 9)
