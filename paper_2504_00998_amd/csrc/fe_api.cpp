@@ -169,8 +169,10 @@ static void free_mesh(fe_mesh *m) {
     (void)hipFree(m->d_Af64);
     (void)hipFree(m->d_Af64s);
     (void)hipFree(m->d_Af32s);
+    (void)hipFree(m->d_tabperm);
     (void)hipFree(m->d_zero);
     (void)hipFree(m->d_segtab);
+    (void)hipFree(m->d_segtab1);
     (void)hipFree(m->d_Af32);
     (void)hipFree(m->d_Abf16);
     (void)hipFree(m->d_v);
@@ -278,6 +280,11 @@ fe_status fe_mesh_create(const fe_mesh_desc *d, fe_mesh **out) {
     // every free node's scale unless an axis is zero-Neumann (a boundary face
     // node there has one cell's mass only).
     const bool fold = m->bc[0] != FE_BC_NEUMANN && m->bc[1] != FE_BC_NEUMANN && m->bc[2] != FE_BC_NEUMANN;
+    // the table kernel (p = 3, 4, 5 with the folded matrix; it indexes DoFs
+    // in 32 bits) takes the rows of the folded matrix in its own order
+    const bool table = fold && m->p >= 3 && m->p <= 5 && m->n < INT32_MAX;
+    std::vector<int32_t> perm;
+    if (table) build_table_row_perm(m->p, table_tiles_per_wave(m->p), perm);
     std::vector<double> f64s;
     std::vector<float> f32s;
     if (fold) {
@@ -290,14 +297,35 @@ fe_status fe_mesh_create(const fe_mesh_desc *d, fe_mesh **out) {
         auto dl = [&](int l) { return (dh[l % m->n1] * dh[(l / m->n1) % m->n1]) * dh[l / (m->n1 * m->n1)]; };
         for (int l = 0; l < m->nc; ++l)
             for (int q = 0; q < m->nc; ++q) As[(size_t)l * m->nc + q] = dl(l) * m->cellA[(size_t)l * m->nc + q] * dl(q);
-        swizzle_f64(m, As, f64s);
+        if (table) {
+            // row r of the swizzled matrix: node perm[r] (padding rows zero;
+            // swizzle_f64 takes nc x nc and pads rows past nc with zeros)
+            std::vector<double> Ap((size_t)m->nc * m->nc, 0.0);
+            for (int r = 0; r < m->nc; ++r)
+                if (perm[r] >= 0) std::copy_n(&As[(size_t)perm[r] * m->nc], m->nc, &Ap[(size_t)r * m->nc]);
+            swizzle_f64(m, Ap, f64s);
+            // rows past nc that hold nodes
+            const int nks4 = m->ncp / 4;
+            for (int r = m->nc; r < m->ncp; ++r)
+                if (perm[r] >= 0)
+                    for (int sk = 0; sk < nks4; ++sk)
+                        for (int c4 = 0; c4 < 4; ++c4) {
+                            const int c = 4 * sk + c4;
+                            const int t = r / 16, lane = r % 16 + 16 * c4;
+                            f64s[((size_t)t * nks4 + sk) * 64 + lane] = c < m->nc ? As[(size_t)perm[r] * m->nc + c] : 0.0;
+                        }
+        } else {
+            swizzle_f64(m, As, f64s);
+        }
         f32s.assign(f64s.begin(), f64s.end());
     }
     const double zeros[32] = {};
-    std::vector<int32_t> segtab;
-    // the table kernel indexes DoFs in 32 bits
-    if (fold && m->p >= 3 && m->p <= 5 && m->n < INT32_MAX)
-        build_segment_table(m, segtab, m->seg_off, m->seg_zl, m->seg_bx);
+    std::vector<int32_t> segtab, segtab1;
+    if (table) {
+        build_segment_table(m, 2, segtab, m->seg_off, m->seg_zl, m->seg_bx, m->seg_by);
+        int zl1 = 1, bx1 = 1, by1 = 1;
+        if (m->seg_by > 1) build_segment_table(m, 1, segtab1, m->seg_off1, zl1, bx1, by1);
+    }
 
     auto up = [&](void **dst, const void *src, size_t bytes) -> bool {
         if (hipMalloc(dst, bytes) != hipSuccess) return false;
@@ -311,6 +339,8 @@ fe_status fe_mesh_create(const fe_mesh_desc *d, fe_mesh **out) {
               (!fold || up((void **)&m->d_Af32s, f32s.data(), f32s.size() * sizeof(float))) &&
               up((void **)&m->d_zero, zeros, sizeof(zeros)) &&
               (segtab.empty() || up((void **)&m->d_segtab, segtab.data(), segtab.size() * sizeof(int32_t))) &&
+              (segtab1.empty() || up((void **)&m->d_segtab1, segtab1.data(), segtab1.size() * sizeof(int32_t))) &&
+              (perm.empty() || up((void **)&m->d_tabperm, perm.data(), perm.size() * sizeof(int32_t))) &&
               up((void **)&m->d_Af32, f32.data(), f32.size() * sizeof(float)) &&
               up((void **)&m->d_Abf16, bf.data(), bf.size() * sizeof(uint16_t)) &&
               hipMalloc((void **)&m->d_v, (size_t)m->n * sizeof(double)) == hipSuccess;

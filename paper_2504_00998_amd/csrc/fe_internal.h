@@ -78,15 +78,21 @@ struct fe_mesh {
     // with no Neumann axis every free node's M^-1/2 is the product of per-axis
     // factors that depend only on its local index in any cell containing it,
     // so D Kc D folds into one cell matrix: swizzled f64 fragments of
-    // D^ (1/2 Kc) D^ (null with a Neumann axis), and the same rounded to f32
+    // D^ (1/2 Kc) D^ (null with a Neumann axis), and the same rounded to f32;
+    // where the table kernel applies (p = 3, 4, 5) their rows are in the
+    // order of d_tabperm (row r: local node d_tabperm[r], -1 a zero row)
     double *d_Af64s = nullptr;
     float *d_Af32s = nullptr;
+    int32_t *d_tabperm = nullptr;
     double *d_zero = nullptr;     // 32 zero doubles (source of padded / absent rows)
     // segment table of the table kernel (p = 3, 4, 5 with the folded cell
     // matrix): per colour pass, per z segment, first DoF and face masks
     int32_t *d_segtab = nullptr;
     std::vector<int64_t> seg_off;  // entries of colour pass c: [seg_off[c], seg_off[c+1])
-    int seg_zl = 1, seg_bx = 1;    // cells of a brick along z and along x
+    // the same for bricks one cell deep in y, where seg_by > 1 (else null)
+    int32_t *d_segtab1 = nullptr;
+    std::vector<int64_t> seg_off1;
+    int seg_zl = 1, seg_bx = 1, seg_by = 1;  // cells of a brick along z, x and y
     float *d_Af32 = nullptr;      // f32
     uint16_t *d_Abf16 = nullptr;  // bf16 bits
     double *d_v = nullptr;        // [n] diagonal potential term of H~
@@ -176,8 +182,12 @@ hipError_t launch_nonlocal_k(fe_mesh *m, const double *X, int64_t ldx, double *Y
                              double alpha, hipStream_t s);
 fe_status nonlocal_set_phase(fe_mesh *m);
 void swizzle_f64(const fe_mesh *m, const std::vector<double> &A, std::vector<double> &f64);
-// segment table of the table kernel (fe_kernels.hip)
-void build_segment_table(const fe_mesh *m, std::vector<int32_t> &tab, std::vector<int64_t> &off, int &zl, int &bx);
+// segment table, output-row order and row tiles per wave of the table
+// kernel (fe_kernels.hip)
+void build_segment_table(const fe_mesh *m, int by_most, std::vector<int32_t> &tab, std::vector<int64_t> &off,
+                         int &zl, int &bx, int &by);
+void build_table_row_perm(int p, int tiles_per_wave, std::vector<int32_t> &perm);
+int table_tiles_per_wave(int p);
 void nonlocal_release(fe_mesh *m);
 
 }  // namespace fe

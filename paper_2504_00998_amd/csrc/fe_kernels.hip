@@ -1855,18 +1855,29 @@ template <int P> struct TabRow {
     }
 };
 
-template <int P, int PREC, int TPW, int NGRP, int BX>
+// Shapes of the table kernel: p = 3, 4 one 16-row tile of A' per wave
+// (8 waves) and 32 vectors per item; p = 5 (FP32 products only: 224 padded
+// rows) two tiles per wave (7 waves, 56 fragment registers each) and 16
+// vectors per item, so that three X buffers of 224 rows fit the LDS.
+template <int P> struct TabCfg {
+    static constexpr int TPW = P == 5 ? 2 : 1, G = P == 5 ? 1 : 2;
+};
+
+template <int P, int PREC, int TPW, int NGRP, int BX, int BY>
 __global__ __launch_bounds__((64 * TabShape<P, TPW, NGRP>::W)) __attribute__((amdgpu_waves_per_eu(1, 2)))
-void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nitems) {
+void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, const int *__restrict__ rowperm, int64_t nitems) {
     static_assert(PREC == 0 || PREC == 1, "FP64 or FP32 cell products");
     typedef typename FragOf<PREC>::T AT;
     typedef TabShape<P, TPW, NGRP> S;
     constexpr int N1 = P + 1, NKS = S::NKS, G = S::G, XS = S::XS, W = S::W, NDMA = S::NDMA;
-    // LDS holds (doubles per buffer, each two-deep): the x face between
-    // consecutive cells of a brick row, and the top faces of a whole brick
-    // row ((BX p + 1) x (p + 1) nodes, each node once)
-    constexpr int XHS = BX > 1 ? N1 * N1 * 16 * G : 0, ZW = BX * P + 1, ZHS = ZW * N1 * 16 * G;
-    constexpr int ZH0 = 2 * XHS, ZERO0 = ZH0 + 2 * ZHS;
+    // LDS holds (doubles), each node once: the x face between consecutive
+    // cells of a brick row (N1 x N1 nodes), the back faces of a brick row
+    // ((BX p + 1) x N1 nodes: x by z), the top faces of a brick layer
+    // ((BX p + 1) x (BY p + 1) nodes: x by y); each slot is read and written
+    // at one position by two rows of the same wave (see build_table_row_perm)
+    constexpr int ZW = BX * P + 1, V = 16 * G;
+    constexpr int XHS = BX > 1 ? N1 * N1 * V : 0, YHS = BY > 1 ? ZW * N1 * V : 0, ZHS = ZW * (BY * P + 1) * V;
+    constexpr int YH0 = XHS, ZH0 = YH0 + YHS, ZERO0 = ZH0 + ZHS;
     // three X buffers [G][NCP][16] as distinct arrays, each named at compile
     // time by the position it serves, so that the compiler sees that a
     // product's LDS reads and the X requests in flight touch different
@@ -1885,9 +1896,9 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nite
     const int stride = (int)gridDim.x;
     const int sdiv = stride / ngroups, smod = stride % ngroups;
     const int zl = k.zl;
-    const int npos = (int)((nitems - 1 - blockIdx.x) / stride + 1) * zl * BX;  // < 2^31, as items per launch
-    const int zstep = P * (int)(k.nfx * k.nfy);  // DoF step from a cell to the next along z
-    const int64_t ld = k.ldx;                    // one leading dimension for X, Y and the previous iterate
+    const int npos = (int)((nitems - 1 - blockIdx.x) / stride + 1) * zl * BX * BY;  // < 2^31, as items per launch
+    const int ystep = P * (int)k.nfx, zstep = P * (int)(k.nfx * k.nfy);  // DoF steps to the next cell along y, z
+    const int64_t ld = k.ldx;  // one leading dimension for X, Y and the previous iterate
     // the wave's row tiles of A' (tiles wave + W j), resident for the launch
     AT ar[TPW][NKS];
 #pragma unroll
@@ -1896,65 +1907,71 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nite
 #pragma unroll
         for (int s = 0; s < NKS; ++s) ar[j][s] = A[s * 64];
     }
-    // per tile: the row this lane's accumulators hold (vectors vq +
-    // pipe_off(q) of each 16-vector group) and the two rows it requests X
-    // for (rows 16 tile + 8 h + l / 8, vectors 2 (l % 8) + {0, 1} of each
-    // group)
+    // per tile: the node whose output row this lane's accumulators hold
+    // (row pipe_row of the tile, vectors vq + pipe_off(q) of each 16-vector
+    // group; the rows of A' are the cell's nodes in the order rowperm gives)
+    // and the two rows it requests X for (rows 16 tile + 8 h + l / 8, in
+    // node order, vectors 2 (l % 8) + {0, 1} of each group)
     const int vq = pipe_vec<PREC>(lane);
     TabRow<P> R[TPW], Q[TPW][2];
-    int xo[TPW], xh[TPW], zh[TPW];  // offsets in an X buffer, an x-face hold, the top-face hold of a brick row
+    int xo[TPW], xh[TPW], yh[TPW], zh[TPW];  // offsets in an X buffer and in the three holds
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
-        const int tile = wave + W * j, r = 16 * tile + pipe_row<PREC>(lane);
-        R[j].init(k, r, vq);
+        const int tile = wave + W * j, node = rowperm[16 * tile + pipe_row<PREC>(lane)];
+        R[j].init(k, node < 0 ? N1 * N1 * N1 : node, vq);
         Q[j][0].init(k, 16 * tile + (lane >> 3), 2 * (lane & 7));
         Q[j][1].init(k, 16 * tile + 8 + (lane >> 3), 2 * (lane & 7));
-        const int l = min(r, N1 * N1 * N1 - 1), i = l % N1, jy = (l / N1) % N1, kk = l / (N1 * N1);
-        xo[j] = r * 16 + vq;
-        xh[j] = (jy + N1 * kk) * 16 * G + vq;
-        zh[j] = ZH0 + (i + ZW * jy) * 16 * G + vq;
+        const int l = node < 0 ? 0 : node, i = l % N1, jy = (l / N1) % N1, kk = l / (N1 * N1);
+        xo[j] = l * 16 + vq;
+        xh[j] = (jy + N1 * kk) * V + vq;
+        yh[j] = YH0 + (i + ZW * kk) * V + vq;
+        zh[j] = ZH0 + (i + ZW * jy) * V + vq;
     }
     const double *ob = k.Ym1 ? k.Ym1 : k.X;
     const double nbeta = k.Ym1 ? -k.beta : 0.0;
 
-    // a walk position: brick s of the colour, vector group grp, cell (bx, c)
-    // of the brick (bx along x, fastest; c along z); e its table entry
+    // a walk position: brick s of the colour, vector group grp, cell
+    // (bx, by, c) of the brick (bx along x, fastest; by along y; c along z);
+    // e its table entry
     struct Pos {
-        int s, grp, c, bx;
+        int s, grp, c, bx, by;
         int2 e;
     };
     auto advance = [&](Pos p) {
         if (++p.bx == BX) {
             p.bx = 0;
-            if (++p.c == zl) {
-                p.c = 0;
-                p.s += sdiv;
-                p.grp += smod;
-                if (p.grp >= ngroups) {
-                    p.grp -= ngroups;
-                    ++p.s;
+            if (++p.by == BY) {
+                p.by = 0;
+                if (++p.c == zl) {
+                    p.c = 0;
+                    p.s += sdiv;
+                    p.grp += smod;
+                    if (p.grp >= ngroups) {
+                        p.grp -= ngroups;
+                        ++p.s;
+                    }
+                    p.e = segtab[p.s];
                 }
-                p.e = segtab[p.s];
             }
         }
         return p;
     };
     // what a position needs (uniform): element offset of its cell's node 0
-    // and first vector, DoF of node 0, face masks with the x and z bits that
-    // apply at its place in the brick
+    // and first vector, DoF of node 0, face masks with the bits that apply
+    // at its place in the brick
     struct Cell {
         int64_t U;
         int I0, fm, dm, wm;
     };
     auto cell = [&](const Pos &p) {
         Cell q;
-        q.I0 = p.e.x + p.bx * P + p.c * zstep;
+        q.I0 = p.e.x + p.bx * P + p.by * ystep + p.c * zstep;
         q.U = (int64_t)q.I0 * ld + (int64_t)p.grp * G * 16;
-        const int hi = (p.bx == BX - 1 ? 2 : 0) | (p.c == zl - 1 ? 32 : 0);
-        const int m = 0xC | hi | (p.bx == 0 ? 1 : 0) | (p.c == 0 ? 16 : 0);
+        const int hi = (p.bx == BX - 1 ? 2 : 0) | (p.by == BY - 1 ? 8 : 0) | (p.c == zl - 1 ? 32 : 0);
+        const int m = hi | (p.bx == 0 ? 1 : 0) | (p.by == 0 ? 4 : 0) | (p.c == 0 ? 16 : 0);
         q.fm = (p.e.y >> SEG_FM) & m;
         q.dm = (p.e.y >> SEG_DM) & m;
-        q.wm = (p.e.y >> SEG_WM) & (8 | hi);
+        q.wm = (p.e.y >> SEG_WM) & hi;
         return q;
     };
     // X rows of a position into buffer bufp, as buffer requests (a global
@@ -2016,7 +2033,7 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nite
         const Cell e = cell(cur);
         const bool slow = (e.dm | e.wm) != 0;  // uniform
         int64_t E[TPW];
-        bool valid[TPW], fst[TPW], left[TPW], right[TPW], bot[TPW], top[TPW];
+        bool valid[TPW], fst[TPW], left[TPW], right[TPW], front[TPW], back[TPW], bot[TPW], top[TPW];
         double vraw[TPW], o[TPW][G][4];
 #pragma unroll
         for (int j = 0; j < TPW; ++j) {
@@ -2031,12 +2048,15 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nite
                 valid[j] = (R[j].faces & (e.dm | 64)) == 0;
             }
             // faces shared with the brick's previous / next cell along x
-            // (held in the x-face hold) and along z (the top-face hold)
+            // (the x-face hold), along y (the back-face hold) and along z
+            // (the top-face hold)
             left[j] = BX > 1 && (R[j].faces & 1) != 0 && cur.bx > 0;
             right[j] = BX > 1 && (R[j].faces & 2) != 0 && cur.bx < BX - 1;
+            front[j] = BY > 1 && (R[j].faces & 4) != 0 && cur.by > 0;
+            back[j] = BY > 1 && (R[j].faces & 8) != 0 && cur.by < BY - 1;
             bot[j] = (R[j].faces & 16) != 0 && cur.c > 0;
             top[j] = (R[j].faces & 32) != 0 && cur.c < zl - 1;
-            const bool held = left[j] || bot[j];
+            const bool held = left[j] || front[j] || bot[j];
             fst[j] = valid[j] && (R[j].faces & e.fm) == 0 && !held;
             // old values: the previous iterate for a first writer, else Y
             // (an earlier colour has written the node); none for rows off the
@@ -2132,21 +2152,23 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nite
 #pragma unroll
                 for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(o[j][g][q]));
         }
-        const int zcol = cur.bx * P * 16 * G;  // this cell's x offset in the top-face hold
+        // this cell's offsets in the back-face hold (x) and the top-face hold (x, y)
+        const int yoff = cur.bx * P * V, zoff = yoff + cur.by * P * ZW * V;
+        // epilogue, one form for every row:
+        //   out = alpha acc + (s x + (gamma o + h))
+        // first writer: s = alpha (v - c), gamma = -beta, h = 0 (x raw from
+        // the buffer); a row whose partial sum a hold carries (from the
+        // previous cell along x, else along y, else along z): s = 0, o = 0,
+        // h = the hold; any other row: s = 0, gamma = 1, h = 0.  Every hold
+        // read of the wave comes before its hold writes (a slot read at this
+        // position is written at it only by a row of the same wave).
+        double out[TPW][G][4];
 #pragma unroll
         for (int j = 0; j < TPW; ++j) {
-            // epilogue, one form for every row:
-            //   out = alpha acc + (s x + (gamma o + h))
-            // first writer: s = alpha (v - c), gamma = -beta, h = 0 (x raw
-            // from the buffer); a row whose partial sum a hold carries (from
-            // the previous cell along x, else along z): s = 0, o = 0, h = the
-            // hold; any other row: s = 0, gamma = 1, h = 0
             const double sl = fst[j] ? k.alpha * (vraw[j] - k.shift) : 0.0;
             const double gl = fst[j] ? nbeta : 1.0;
-            const int hoff = left[j] ? ((t - 1) & 1) * XHS + xh[j]
-                                     : bot[j] ? ((cur.c - 1) & 1) * ZHS + zh[j] + zcol : ZERO0;
+            const int hoff = left[j] ? xh[j] : front[j] ? yh[j] + yoff : bot[j] ? zh[j] + zoff : ZERO0;
             const double *hrow = hd + hoff;
-            double out[G][4];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 const double2 x01 = *reinterpret_cast<const double2 *>(xs + g * XS + xo[j]);
@@ -2156,24 +2178,28 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nite
                 const double xv[4] = {x01.x, x01.y, x23.x, x23.y}, hv[4] = {h01.x, h01.y, h23.x, h23.y};
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    out[g][q] = __builtin_fma(k.alpha, acc[j][g][q],
-                                              __builtin_fma(sl, xv[q], __builtin_fma(gl, o[j][g][q], hv[q])));
+                    out[j][g][q] = __builtin_fma(k.alpha, acc[j][g][q],
+                                                 __builtin_fma(sl, xv[q], __builtin_fma(gl, o[j][g][q], hv[q])));
             }
-            // the partial sum goes on to the next cell along x, else along z,
-            // else to Y
-            if (right[j] || top[j]) {
-                double *h = hd + (right[j] ? (t & 1) * XHS + xh[j] : (cur.c & 1) * ZHS + zh[j] + zcol);
+        }
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int j = 0; j < TPW; ++j) {
+            // the partial sum goes on to the next cell along x, else along y,
+            // else along z, else to Y
+            if (right[j] || back[j] || top[j]) {
+                double *h = hd + (right[j] ? xh[j] : back[j] ? yh[j] + yoff : zh[j] + zoff);
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
-                    lds_store16(h + 16 * g, out[g][0], out[g][1]);
-                    lds_store16(h + 16 * g + 8, out[g][2], out[g][3]);
+                    lds_store16(h + 16 * g, out[j][g][0], out[j][g][1]);
+                    lds_store16(h + 16 * g + 8, out[j][g][2], out[j][g][3]);
                 }
             } else if (valid[j]) {
                 double *yrow = k.Y + E[j];
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
-                    *reinterpret_cast<double2 *>(yrow + 16 * g) = double2{out[g][0], out[g][1]};
-                    *reinterpret_cast<double2 *>(yrow + 16 * g + 8) = double2{out[g][2], out[g][3]};
+                    *reinterpret_cast<double2 *>(yrow + 16 * g) = double2{out[j][g][0], out[j][g][1]};
+                    *reinterpret_cast<double2 *>(yrow + 16 * g + 8) = double2{out[j][g][2], out[j][g][3]};
                 }
             }
         }
@@ -2193,6 +2219,7 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nite
         p0.grp = it % ngroups;
         p0.c = 0;
         p0.bx = 0;
+        p0.by = 0;
         p0.e = segtab[p0.s];
     }
     p1 = npos > 1 ? advance(p0) : p0;
@@ -2209,7 +2236,7 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, int64_t nite
     }
 }
 
-template <int P, int PREC, int TPW, int G, int BX>
+template <int P, int PREC, int TPW, int G, int BX, int BY>
 static hipError_t launch_tab_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
     typedef TabShape<P, TPW, G> S;
     constexpr int W = S::W;
@@ -2218,7 +2245,7 @@ static hipError_t launch_tab_p(StepParams prm, const fe_mesh *m, hipStream_t s) 
     if (!attr) {
         int per_cu = 0, dev = 0, cus = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(&step_tab_kernel<P, PREC, TPW, G, BX>), 64 * W, 0);
+            &per_cu, reinterpret_cast<const void *>(&step_tab_kernel<P, PREC, TPW, G, BX, BY>), 64 * W, 0);
         if (e != hipSuccess) return e;
         e = hipGetDevice(&dev);
         if (e != hipSuccess) return e;
@@ -2231,62 +2258,111 @@ static hipError_t launch_tab_p(StepParams prm, const fe_mesh *m, hipStream_t s) 
     prm.zl = m->seg_zl;
     prm.nfz = (int)m->nf[2];
     const int ngroups = (prm.nchunk + G - 1) / G;
-    for (size_t col = 0; col + 1 < m->seg_off.size(); ++col) {
-        const int64_t segs = m->seg_off[col + 1] - m->seg_off[col];
+    // the table of this brick shape (y bricks: the first table)
+    const std::vector<int64_t> &off = BY > 1 || m->seg_by == 1 ? m->seg_off : m->seg_off1;
+    const int32_t *tab0 = BY > 1 || m->seg_by == 1 ? m->d_segtab : m->d_segtab1;
+    for (size_t col = 0; col + 1 < off.size(); ++col) {
+        const int64_t segs = off[col + 1] - off[col];
         if (segs == 0) continue;
-        const int2 *tab = reinterpret_cast<const int2 *>(m->d_segtab) + m->seg_off[col];
+        const int2 *tab = reinterpret_cast<const int2 *>(tab0) + off[col];
         const int64_t nitems = segs * ngroups;
         const int64_t grid = std::min<int64_t>(nitems, resident);
-        hipLaunchKernelGGL((step_tab_kernel<P, PREC, TPW, G, BX>), dim3((unsigned)grid), dim3(64 * W), 0, s, prm, tab,
-                           nitems);
+        hipLaunchKernelGGL((step_tab_kernel<P, PREC, TPW, G, BX, BY>), dim3((unsigned)grid), dim3(64 * W), 0, s, prm,
+                           tab, m->d_tabperm, nitems);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-// Shapes of the table kernel: p = 3, 4 one 16-row tile of A' per wave
-// (8 waves) and 32 vectors per item; p = 5 (FP32 products only: 224 padded
-// rows) two tiles per wave (7 waves, 56 fragment registers each) and 16
-// vectors per item, so that three X buffers of 224 rows fit the LDS.
-template <int P> struct TabCfg {
-    static constexpr int TPW = P == 5 ? 2 : 1, G = P == 5 ? 1 : 2;
-};
-
-template <int P, int PREC>
-static hipError_t launch_tab(StepParams prm, const fe_mesh *m, hipStream_t s) {
+template <int P, int PREC, int BY>
+static hipError_t launch_tab_y(StepParams prm, const fe_mesh *m, hipStream_t s) {
     constexpr int TPW = TabCfg<P>::TPW, G = TabCfg<P>::G;
     switch (m->seg_bx) {
-    case 3: return launch_tab_p<P, PREC, TPW, G, 3>(prm, m, s);
-    case 2: return launch_tab_p<P, PREC, TPW, G, 2>(prm, m, s);
-    default: return launch_tab_p<P, PREC, TPW, G, 1>(prm, m, s);
+    case 3: return launch_tab_p<P, PREC, TPW, G, 3, BY>(prm, m, s);
+    case 2: return launch_tab_p<P, PREC, TPW, G, 2, BY>(prm, m, s);
+    default: return launch_tab_p<P, PREC, TPW, G, 1, BY>(prm, m, s);
     }
 }
 
-// Cells per brick along x for the table kernel: the largest length up to 3
-// that divides the x cell count and leaves a periodic axis at least two
-// bricks; 1 when there is none above 1.
-static int xbrick_length(const fe_mesh *m) {
-    const int nx = m->ncell[0];
-    for (int L = 3; L >= 2; --L)
-        if (nx % L == 0 && (m->bc[0] != FE_BC_PERIODIC || nx / L >= 2)) return L;
+// FP64 products walk the bricks with y extent (2 cells where the mesh
+// allows): fewer bytes, and faster where the products dominate; FP32
+// products, HBM-bound, were measured faster on bricks one cell deep in y
+// (the second table), where a brick's cells are closer together in memory.
+template <int P, int PREC>
+static hipError_t launch_tab(StepParams prm, const fe_mesh *m, hipStream_t s) {
+    return PREC == 0 && m->seg_by == 2 ? launch_tab_y<P, PREC, 2>(prm, m, s) : launch_tab_y<P, PREC, 1>(prm, m, s);
+}
+
+// Cells per brick along an axis of the table kernel (x: up to 3, y: up to
+// 2): the largest length that divides the axis' cell count and leaves a
+// periodic axis at least two bricks; 1 when there is none above 1.
+static int brick_length(const fe_mesh *m, int axis, int most) {
+    const int n = m->ncell[axis];
+    for (int L = most; L >= 2; --L)
+        if (n % L == 0 && (m->bc[axis] != FE_BC_PERIODIC || n / L >= 2)) return L;
     return 1;
 }
 
+// Output-row order of the table kernel's cell matrix (host): rowperm[r] is
+// the local node whose output row r of A' holds (-1: a padding row), so that
+// the rows a wave owns (its tiles wave + W j, 16 rows each) hold whole
+// classes of nodes linked by the holds: the two nodes of a cell at i = 0 and
+// i = p with the same (j, k) read and write the same x-face hold slot at one
+// position, those at j = 0, p with the same (i, k) the same back-face slot,
+// those at k = 0, p with the same (i, j) the same top-face slot.  The
+// classes (8 corners; 4 nodes of an edge; 2 of a face; 1 inside) are placed
+// largest first into the first wave with room (their sizes divide a wave's
+// rows, so they always fit).
+void build_table_row_perm(int p, int tiles_per_wave, std::vector<int32_t> &perm) {
+    const int n1 = p + 1, nc = n1 * n1 * n1, ncp = padded_nc(p), nt = ncp / 16, nw = nt / tiles_per_wave;
+    std::vector<int> cls(nc);
+    for (int l = 0; l < nc; ++l) {
+        // the class representative: each coordinate at p folded onto 0
+        int i = l % n1, j = (l / n1) % n1, kk = l / (n1 * n1);
+        i = i == p ? 0 : i;
+        j = j == p ? 0 : j;
+        kk = kk == p ? 0 : kk;
+        cls[l] = i + n1 * (j + n1 * kk);
+    }
+    std::vector<std::vector<int>> classes(nc);
+    for (int l = 0; l < nc; ++l) classes[cls[l]].push_back(l);
+    std::vector<int> order;
+    for (int c = 0; c < nc; ++c)
+        if (!classes[c].empty()) order.push_back(c);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return classes[a].size() > classes[b].size(); });
+    std::vector<std::vector<int>> waves(nw);
+    const size_t cap = 16 * (size_t)tiles_per_wave;
+    for (int c : order) {
+        size_t w = 0;
+        while (waves[w].size() + classes[c].size() > cap) ++w;  // the sizes are powers of 2 dividing cap
+        waves[w].insert(waves[w].end(), classes[c].begin(), classes[c].end());
+    }
+    perm.assign(ncp, -1);
+    for (int w = 0; w < nw; ++w)
+        for (size_t q = 0; q < waves[w].size(); ++q) {
+            const int tile = w + nw * (int)(q / 16);
+            perm[16 * tile + q % 16] = waves[w][q];
+        }
+}
+
+int table_tiles_per_wave(int p) { return p == 5 ? TabCfg<5>::TPW : TabCfg<4>::TPW; }
+
 // Segment table of the table kernel (host): for every colour pass, in launch
-// order, the bricks of that colour (BX cells along x by zl cells along z, at
-// one y), in the order the kernel walks them, one entry each (see SEG_FM /
-// SEG_DM / SEG_WM; the x and z bits describe the brick's outer faces).
-// Bricks are coloured along x and z as cells are.  Empty when the kernel
-// does not apply to the mesh.
-void build_segment_table(const fe_mesh *m, std::vector<int32_t> &tab, std::vector<int64_t> &off, int &zl_out,
-                         int &bx_out) {
+// order, the bricks of that colour (BX cells along x by BY along y by zl
+// along z), in the order the kernel walks them, one entry each (see SEG_FM /
+// SEG_DM / SEG_WM; the bits describe the brick's outer faces).  Bricks are
+// coloured along each axis as cells are.
+void build_segment_table(const fe_mesh *m, int by_most, std::vector<int32_t> &tab, std::vector<int64_t> &off,
+                         int &zl_out, int &bx_out, int &by_out) {
     tab.clear();
     off.assign(1, 0);
     const int P = m->p;
-    const int zl = zseg_length(m), bxl = xbrick_length(m);
+    const int zl = zseg_length(m), bxl = brick_length(m, 0, 3), byl = brick_length(m, 1, by_most);
     zl_out = zl;
     bx_out = bxl;
+    by_out = byl;
     AxisInfo ax[3];
     for (int d = 0; d < 3; ++d) {
         ax[d].ncell = m->ncell[d];
@@ -2294,10 +2370,10 @@ void build_segment_table(const fe_mesh *m, std::vector<int32_t> &tab, std::vecto
         ax[d].bc = m->bc[d];
         ax[d].ncol = m->ncol[d];
     }
-    // the brick axes: x in runs of bxl cells, z in runs of zl cells
+    // the brick axes: x in runs of bxl cells, y of byl, z of zl
     AxisInfo bk[3] = {ax[0], ax[1], ax[2]};
-    const int len[3] = {bxl, 1, zl};
-    for (int a = 0; a < 3; a += 2) {
+    const int len[3] = {bxl, byl, zl};
+    for (int a = 0; a < 3; ++a) {
         bk[a].ncell = ax[a].ncell / len[a];
         bk[a].ncol = (bk[a].bc == FE_BC_PERIODIC && (bk[a].ncell & 1)) ? 3 : bk[a].ncell >= 2 ? 2 : 1;
     }
@@ -2333,7 +2409,7 @@ void build_segment_table(const fe_mesh *m, std::vector<int32_t> &tab, std::vecto
                             for (int a = 0; a < 3; ++a)
                                 b[a] = col[a] == 2 ? bk[a].ncell - 1 : col[a] + 2 * ic[2 - a];
                             const int I0 = first_free(ax[0], b[0] * bxl) +
-                                           (int)m->nf[0] * (first_free(ax[1], b[1]) +
+                                           (int)m->nf[0] * (first_free(ax[1], b[1] * byl) +
                                                             (int)m->nf[1] * first_free(ax[2], b[2] * zl));
                             int fm = 0, dm = 0, wm = 0;
                             for (int a = 0; a < 3; ++a) {

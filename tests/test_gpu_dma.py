@@ -54,6 +54,14 @@ CASES = [
     ("p4-bricks2-periodic-x4-N48", W.small_slab((4, 3, 8), p=4, N=48)),
     ("p4-bricks2-dirichlet-x2-N32", W.small_slab((2, 3, 8), p=4, N=32, bc=(W.DIRICHLET, W.PERIODIC, W.DIRICHLET))),
     ("p3-bricks3-dirichlet-x6-N40", W.small_slab((6, 2, 6), p=3, N=40, bc=(W.DIRICHLET, W.PERIODIC, W.DIRICHLET))),
+    # y bricks (2 cells along y, inner y faces in LDS): periodic y with two
+    # bricks, x and y bricks together, three y bricks (three colours),
+    # Dirichlet y with one brick
+    ("p4-ybricks-periodic-y4-N32", W.small_slab((3, 4, 6), p=4, N=32)),
+    ("p4-xybricks-6x4-N64", W.small_slab((6, 4, 6), p=4, N=64)),
+    ("p4-ybricks-3colour-y6-N48", W.small_slab((4, 6, 4), p=4, N=48, bc=(W.PERIODIC,) * 3, E=0.0)),
+    ("p4-ybricks-dirichlet-y2-N40", W.small_slab((3, 2, 6), p=4, N=40, bc=(W.DIRICHLET,) * 3)),
+    ("p3-xybricks-6x4-N32", W.small_slab((6, 4, 6), p=3, N=32)),
     ("p2-dirichlet-all-N64", W.small_slab((3, 4, 8), p=2, N=64, bc=(W.DIRICHLET,) * 3)),
     ("p1-N2", W.small_slab((4, 3, 12), p=1, N=2)),
     ("p4-N20", W.small_slab((3, 2, 8), p=4, N=20)),
@@ -172,8 +180,11 @@ P5_CASES = [
     ("p5-bricks2-periodic-x4-N32", W.small_slab((4, 2, 4), p=5, N=32)),
     ("p5-bricks3-dirichlet-x3-N64", W.small_slab((3, 2, 5), p=5, N=64, bc=(W.DIRICHLET, W.PERIODIC, W.DIRICHLET))),
     ("p5-periodic-all-N40", W.small_slab((2, 3, 4), p=5, N=40, bc=(W.PERIODIC,) * 3, E=0.0)),
+    ("p5-xybricks-4x4-N32", W.small_slab((4, 4, 4), p=5, N=32)),
+    ("p5-ybricks-3colour-y6-N48", W.small_slab((2, 6, 3), p=5, N=48, bc=(W.DIRICHLET, W.PERIODIC, W.DIRICHLET))),
 ]
-F32_CASES = CASES[:13] + P5_CASES
+TAB_CASES = [c for c in CASES if c[1].p in (3, 4) and c[1].N >= 32]
+F32_CASES = TAB_CASES + P5_CASES
 
 
 @pytest.mark.parametrize("label,wl", F32_CASES, ids=[c[0] for c in F32_CASES])
