@@ -1855,16 +1855,19 @@ template <int P> struct TabRow {
     }
 };
 
-// Shapes of the table kernel: p = 3, 4 one 16-row tile of A' per wave
-// (8 waves) and 32 vectors per item; p = 5 (FP32 products only: 224 padded
-// rows) two tiles per wave (7 waves, 56 fragment registers each) and 16
-// vectors per item, so that three X buffers of 224 rows fit the LDS.
+// Shapes of the table kernel: one 16-row tile of A' per wave; p = 3, 4: 4 / 8
+// waves and 32 vectors per item; p = 5 (FP32 products only: 224 padded
+// rows): 14 waves (up to 4 per SIMD, within 128 registers: 56 fragment
+// registers each) and 16 vectors per item, so that three X buffers of 224
+// rows fit the LDS (7 waves of two tiles each, 2 per SIMD, were 7 % slower)
 template <int P> struct TabCfg {
-    static constexpr int TPW = P == 5 ? 2 : 1, G = P == 5 ? 1 : 2;
+    static constexpr int TPW = 1, G = P == 5 ? 1 : 2;
 };
 
+// (at most 2 waves per SIMD, or as many as the workgroup puts on one)
 template <int P, int PREC, int TPW, int NGRP, int BX, int BY>
-__global__ __launch_bounds__((64 * TabShape<P, TPW, NGRP>::W)) __attribute__((amdgpu_waves_per_eu(1, 2)))
+__global__ __launch_bounds__((64 * TabShape<P, TPW, NGRP>::W))
+__attribute__((amdgpu_waves_per_eu(1, TabShape<P, TPW, NGRP>::W > 8 ? (TabShape<P, TPW, NGRP>::W + 3) / 4 : 2)))
 void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, const int *__restrict__ rowperm, int64_t nitems) {
     static_assert(PREC == 0 || PREC == 1, "FP64 or FP32 cell products");
     typedef typename FragOf<PREC>::T AT;

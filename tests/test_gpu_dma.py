@@ -172,7 +172,7 @@ def test_dma_kernel_several_segments_per_workgroup(p, N):
         gm.set_kernel(0)
 
 
-# p = 5 (FP32 products only): two row tiles per wave, 16 vectors per item;
+# p = 5 (FP32 products only): 14 waves, 16 vectors per item;
 # three colours along x and one-cell bricks, bricks of 2 and 3 cells, all
 # axes periodic with a rest of 8 columns
 P5_CASES = [
