@@ -454,7 +454,9 @@ def main():
                         "avg_launch_ms": round(lk_ms, 5), "flops_per_launch": fl_k,
                         "achieved_TFLOPs": round(fl_k / (lk_ms * 1e-3) / 1e12, 3),
                         "frac_of_fp64_peak": round(fl_k / (lk_ms * 1e-3) / 1e12 / PEAK["f64"][0], 4),
-                        "kernel": f"step_row_kernel<{wl.p},0,...,CPX> (complex H~^k, one colour pass)"}
+                        "kernel": (f"step_tab_kernel<{wl.p},0,...,CPX> (complex H~^k, the table kernel with the k.G "
+                                   "product, one colour pass)" if wl.p in (3, 4) else
+                                   f"step_row_kernel<{wl.p},0,...,CPX> (complex H~^k, one colour pass)")}
     if not args.no_mixed and args.prec == "f64":
         t_pot_ms = t_pot
         rec["mixed_precision"] = mixed_precision_report(gm, wl, X, Y, work, a, b, a0, args.steps, ms - t_pot_ms,

@@ -118,6 +118,10 @@ fe_status fe_mesh_destroy(fe_mesh *mesh);
  * Variants 0, 1, 3, 4, 6 and 7 give bitwise-identical results (variant 0
  * wherever it is not variant 9 or 10); variants 9 and 10 sum each node's
  * contributions in other fixed orders (equal to rounding, reproducible).
+ * In the Bloch mode (the _k entry points at k != 0) variants 0 and 10 run
+ * the table kernel with the k.G product at p = 3, 4 on the whole groups of
+ * 16 complex vectors, the row-owner kernel elsewhere; the other variants
+ * run the row-owner kernel.
  * Variants 2 (register-resident), 5 (tiles of cells) and 8
  * (warp-specialised), slower than the defaults everywhere, were removed:
  * FE_EINVAL for them and for values outside 0..10. */

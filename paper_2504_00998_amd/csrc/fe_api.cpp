@@ -162,6 +162,35 @@ static void swizzle_fragments(const fe_mesh *m, std::vector<double> &f64, std::v
                 }
 }
 
+// Swizzled FP64 fragments of D^ A D^ for a cell matrix A (nc x nc), with D^
+// the per-local-index M^-1/2 of a node inside the mesh: (h/2) w_i per cell,
+// summed over the two cells at a cell face (i = 0 or p), the same sums as the
+// assembled masses.  It equals every free node's scale unless an axis is
+// zero-Neumann (a boundary face node there has one cell's mass only).  With
+// perm (the table kernel's output-row order), row r of the fragments holds
+// node perm[r] (-1: zeros).
+void fold_swizzle(const fe_mesh *m, const std::vector<double> &A, const std::vector<int32_t> *perm,
+                  std::vector<double> &f64) {
+    const int nc = m->nc, n1 = m->n1, p = m->p;
+    std::vector<double> dh(n1);
+    for (int i = 0; i <= p; ++i) {
+        const double mi = (i == 0 || i == p) ? 0.5 * m->h * m->w[p] + 0.5 * m->h * m->w[0] : 0.5 * m->h * m->w[i];
+        dh[i] = 1.0 / std::sqrt(mi);
+    }
+    auto dl = [&](int l) { return (dh[l % n1] * dh[(l / n1) % n1]) * dh[l / (n1 * n1)]; };
+    const int nks4 = m->ncp / 4;
+    f64.assign((size_t)(m->ncp / 16) * nks4 * 64, 0.0);
+    // fragment layout of swizzle_f64: frag[t][s][lane] = row 16t + lane % 16, column 4s + lane / 16
+    for (int r = 0; r < m->ncp; ++r) {
+        const int l = perm ? (*perm)[r] : (r < nc ? r : -1);
+        if (l < 0) continue;
+        for (int c = 0; c < nc; ++c) {
+            const int t = r / 16, sk = c / 4, lane = r % 16 + 16 * (c % 4);
+            f64[((size_t)t * nks4 + sk) * 64 + lane] = dl(l) * A[(size_t)l * nc + c] * dl(c);
+        }
+    }
+}
+
 static void free_mesh(fe_mesh *m) {
     if (!m) return;
     (void)hipFree(m->d_axis);
@@ -178,6 +207,7 @@ static void free_mesh(fe_mesh *m) {
     (void)hipFree(m->d_v);
     (void)hipFree(m->d_wrel);
     (void)hipFree(m->d_Sf64);
+    (void)hipFree(m->d_Sf64s);
     (void)hipFree(m->d_scratch);
     nonlocal_release(m);
     if (m->blas) rocblas_destroy_handle(static_cast<rocblas_handle>(m->blas));
@@ -285,38 +315,11 @@ fe_status fe_mesh_create(const fe_mesh_desc *d, fe_mesh **out) {
     const bool table = fold && m->p >= 3 && m->p <= 5 && m->n < INT32_MAX;
     std::vector<int32_t> perm;
     if (table) build_table_row_perm(m->p, table_tiles_per_wave(m->p), perm);
+    m->tab_perm = perm;
     std::vector<double> f64s;
     std::vector<float> f32s;
     if (fold) {
-        std::vector<double> dh(m->n1);
-        for (int i = 0; i <= m->p; ++i) {
-            const double mi = (i == 0 || i == m->p) ? 0.5 * h * m->w[m->p] + 0.5 * h * m->w[0] : 0.5 * h * m->w[i];
-            dh[i] = 1.0 / std::sqrt(mi);
-        }
-        std::vector<double> As((size_t)m->nc * m->nc);
-        auto dl = [&](int l) { return (dh[l % m->n1] * dh[(l / m->n1) % m->n1]) * dh[l / (m->n1 * m->n1)]; };
-        for (int l = 0; l < m->nc; ++l)
-            for (int q = 0; q < m->nc; ++q) As[(size_t)l * m->nc + q] = dl(l) * m->cellA[(size_t)l * m->nc + q] * dl(q);
-        if (table) {
-            // row r of the swizzled matrix: node perm[r] (padding rows zero;
-            // swizzle_f64 takes nc x nc and pads rows past nc with zeros)
-            std::vector<double> Ap((size_t)m->nc * m->nc, 0.0);
-            for (int r = 0; r < m->nc; ++r)
-                if (perm[r] >= 0) std::copy_n(&As[(size_t)perm[r] * m->nc], m->nc, &Ap[(size_t)r * m->nc]);
-            swizzle_f64(m, Ap, f64s);
-            // rows past nc that hold nodes
-            const int nks4 = m->ncp / 4;
-            for (int r = m->nc; r < m->ncp; ++r)
-                if (perm[r] >= 0)
-                    for (int sk = 0; sk < nks4; ++sk)
-                        for (int c4 = 0; c4 < 4; ++c4) {
-                            const int c = 4 * sk + c4;
-                            const int t = r / 16, lane = r % 16 + 16 * c4;
-                            f64s[((size_t)t * nks4 + sk) * 64 + lane] = c < m->nc ? As[(size_t)perm[r] * m->nc + c] : 0.0;
-                        }
-        } else {
-            swizzle_f64(m, As, f64s);
-        }
+        fold_swizzle(m, m->cellA, table ? &perm : nullptr, f64s);
         f32s.assign(f64s.begin(), f64s.end());
     }
     const double zeros[32] = {};
@@ -518,15 +521,25 @@ fe_status fe_set_kpoint(fe_mesh *m, double kx, double ky) {
     FE_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
     const double old[2] = {m->kvec[0], m->kvec[1]};
     if (kx != 0.0 || ky != 0.0) {
-        std::vector<double> S, f;
+        std::vector<double> S, f, fs;
         cell_matrix_bloch(m->p, m->rule, m->h, kx, ky, S);
         swizzle_f64(m, S, f);
+        // the table kernel's copy (FP64 at p = 3, 4): folded, rows in its order
+        const bool table = m->d_Af64s && !m->tab_perm.empty() && m->p <= 4;
+        if (table) fold_swizzle(m, S, &m->tab_perm, fs);
         if (!m->d_Sf64 && hipMalloc(&m->d_Sf64, f.size() * sizeof(double)) != hipSuccess) {
             (void)hipGetLastError();
             m->d_Sf64 = nullptr;
             return fail(FE_ENOMEM, "device allocation failed in fe_set_kpoint");
         }
+        if (table && !m->d_Sf64s && hipMalloc(&m->d_Sf64s, fs.size() * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            m->d_Sf64s = nullptr;
+            return fail(FE_ENOMEM, "device allocation failed in fe_set_kpoint");
+        }
         FE_HIP(hipMemcpy(m->d_Sf64, f.data(), f.size() * sizeof(double), hipMemcpyHostToDevice), "hipMemcpy");
+        if (table)
+            FE_HIP(hipMemcpy(m->d_Sf64s, fs.data(), fs.size() * sizeof(double), hipMemcpyHostToDevice), "hipMemcpy");
     }
     m->kvec[0] = kx;
     m->kvec[1] = ky;

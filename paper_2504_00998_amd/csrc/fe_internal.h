@@ -84,6 +84,7 @@ struct fe_mesh {
     double *d_Af64s = nullptr;
     float *d_Af32s = nullptr;
     int32_t *d_tabperm = nullptr;
+    std::vector<int32_t> tab_perm;  // its host copy
     double *d_zero = nullptr;     // 32 zero doubles (source of padded / absent rows)
     // segment table of the table kernel (p = 3, 4, 5 with the folded cell
     // matrix): per colour pass, per z segment, first DoF and face masks
@@ -99,6 +100,7 @@ struct fe_mesh {
     double *d_wrel = nullptr;     // [3][p+1]: (h/2) w_i per axis (for v and Vbar)
     double kvec[2] = {0.0, 0.0};  // Bloch wave vector (k_x, k_y) of the complex entry points
     double *d_Sf64 = nullptr;     // swizzled FP64 fragments of k.G_c (null while k = 0)
+    double *d_Sf64s = nullptr;    // the same folded as d_Af64s, for the table kernel (p = 3, 4)
     bool potential_set = false;
     int kernel_variant = 0;  // 0: fastest available, 1: generic colour-pass kernel
     double E = 0.0, z0 = 0.0;
@@ -182,6 +184,8 @@ hipError_t launch_nonlocal_k(fe_mesh *m, const double *X, int64_t ldx, double *Y
                              double alpha, hipStream_t s);
 fe_status nonlocal_set_phase(fe_mesh *m);
 void swizzle_f64(const fe_mesh *m, const std::vector<double> &A, std::vector<double> &f64);
+void fold_swizzle(const fe_mesh *m, const std::vector<double> &A, const std::vector<int32_t> *perm,
+                  std::vector<double> &f64);
 // segment table, output-row order and row tiles per wave of the table
 // kernel (fe_kernels.hip)
 void build_segment_table(const fe_mesh *m, int by_most, std::vector<int32_t> &tab, std::vector<int64_t> &off,

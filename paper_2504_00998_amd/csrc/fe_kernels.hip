@@ -1865,11 +1865,18 @@ template <int P> struct TabCfg {
 };
 
 // (at most 2 waves per SIMD, or as many as the workgroup puts on one)
-template <int P, int PREC, int TPW, int NGRP, int BX, int BY>
+// CPX (FP64 only): the Bloch-k mode, columns complex vectors stored as
+// interleaved (re, im) pairs; the operator gains -i D^ (k.G_c) D^ (folded
+// fragments in k.S, rows in the same order as k.A).  As -i S (x_r + i x_i) =
+// S x_i - i S x_r, each k-step adds S times the lane's im column to its re
+// accumulator and S times the negated re column (the product's B-operand
+// negation) to its im accumulator.
+template <int P, int PREC, int TPW, int NGRP, int BX, int BY, bool CPX = false>
 __global__ __launch_bounds__((64 * TabShape<P, TPW, NGRP>::W))
 __attribute__((amdgpu_waves_per_eu(1, TabShape<P, TPW, NGRP>::W > 8 ? (TabShape<P, TPW, NGRP>::W + 3) / 4 : 2)))
 void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, const int *__restrict__ rowperm, int64_t nitems) {
     static_assert(PREC == 0 || PREC == 1, "FP64 or FP32 cell products");
+    static_assert(!CPX || PREC == 0, "the Bloch mode is FP64 only");
     typedef typename FragOf<PREC>::T AT;
     typedef TabShape<P, TPW, NGRP> S;
     constexpr int N1 = P + 1, NKS = S::NKS, G = S::G, XS = S::XS, W = S::W, NDMA = S::NDMA;
@@ -1902,13 +1909,19 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, const int *_
     const int npos = (int)((nitems - 1 - blockIdx.x) / stride + 1) * zl * BX * BY;  // < 2^31, as items per launch
     const int ystep = P * (int)k.nfx, zstep = P * (int)(k.nfx * k.nfy);  // DoF steps to the next cell along y, z
     const int64_t ld = k.ldx;  // one leading dimension for X, Y and the previous iterate
-    // the wave's row tiles of A' (tiles wave + W j), resident for the launch
-    AT ar[TPW][NKS];
+    // the wave's row tiles of A' (tiles wave + W j), and in the Bloch mode
+    // of S', resident for the launch
+    AT ar[TPW][NKS], sr[CPX ? TPW : 1][CPX ? NKS : 1];
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
         const AT *A = reinterpret_cast<const AT *>(k.A) + (size_t)(wave + W * j) * NKS * 64 + lane;
 #pragma unroll
         for (int s = 0; s < NKS; ++s) ar[j][s] = A[s * 64];
+        if constexpr (CPX) {
+            const double *Sf = k.S + (size_t)(wave + W * j) * NKS * 64 + lane;
+#pragma unroll
+            for (int s = 0; s < NKS; ++s) sr[j][s] = Sf[s * 64];
+        }
     }
     // per tile: the node whose output row this lane's accumulators hold
     // (row pipe_row of the tile, vectors vq + pipe_off(q) of each 16-vector
@@ -2103,6 +2116,19 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, const int *_
 #pragma unroll
                         for (int q = 0; q < 4; ++q)
                             acc[j][g][q] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[j][s], bc[g][q], acc[j][g][q], 0, 0, 0);
+                if constexpr (CPX) {
+                    // columns q = 0, 2 are re, q = 1, 3 the im of the same
+                    // complex vectors; the last argument 2 negates B
+#pragma unroll
+                    for (int j = 0; j < TPW; ++j)
+#pragma unroll
+                        for (int g = 0; g < G; ++g) {
+                            acc[j][g][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(sr[j][s], bc[g][1], acc[j][g][0], 0, 0, 0);
+                            acc[j][g][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(sr[j][s], bc[g][0], acc[j][g][1], 0, 0, 2);
+                            acc[j][g][2] = __builtin_amdgcn_mfma_f64_4x4x4f64(sr[j][s], bc[g][3], acc[j][g][2], 0, 0, 0);
+                            acc[j][g][3] = __builtin_amdgcn_mfma_f64_4x4x4f64(sr[j][s], bc[g][2], acc[j][g][3], 0, 0, 2);
+                        }
+                }
 #pragma unroll
                 for (int g = 0; g < G; ++g)
 #pragma unroll
@@ -2239,7 +2265,7 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, const int *_
     }
 }
 
-template <int P, int PREC, int TPW, int G, int BX, int BY>
+template <int P, int PREC, int TPW, int G, int BX, int BY, bool CPX>
 static hipError_t launch_tab_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
     typedef TabShape<P, TPW, G> S;
     constexpr int W = S::W;
@@ -2248,7 +2274,7 @@ static hipError_t launch_tab_p(StepParams prm, const fe_mesh *m, hipStream_t s) 
     if (!attr) {
         int per_cu = 0, dev = 0, cus = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(&step_tab_kernel<P, PREC, TPW, G, BX, BY>), 64 * W, 0);
+            &per_cu, reinterpret_cast<const void *>(&step_tab_kernel<P, PREC, TPW, G, BX, BY, CPX>), 64 * W, 0);
         if (e != hipSuccess) return e;
         e = hipGetDevice(&dev);
         if (e != hipSuccess) return e;
@@ -2258,6 +2284,7 @@ static hipError_t launch_tab_p(StepParams prm, const fe_mesh *m, hipStream_t s) 
         attr = true;
     }
     prm.A = PREC == 0 ? (const void *)m->d_Af64s : (const void *)m->d_Af32s;
+    prm.S = CPX ? m->d_Sf64s : nullptr;
     prm.zl = m->seg_zl;
     prm.nfz = (int)m->nf[2];
     const int ngroups = (prm.nchunk + G - 1) / G;
@@ -2270,7 +2297,7 @@ static hipError_t launch_tab_p(StepParams prm, const fe_mesh *m, hipStream_t s) 
         const int2 *tab = reinterpret_cast<const int2 *>(tab0) + off[col];
         const int64_t nitems = segs * ngroups;
         const int64_t grid = std::min<int64_t>(nitems, resident);
-        hipLaunchKernelGGL((step_tab_kernel<P, PREC, TPW, G, BX, BY>), dim3((unsigned)grid), dim3(64 * W), 0, s, prm,
+        hipLaunchKernelGGL((step_tab_kernel<P, PREC, TPW, G, BX, BY, CPX>), dim3((unsigned)grid), dim3(64 * W), 0, s, prm,
                            tab, m->d_tabperm, nitems);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -2278,13 +2305,13 @@ static hipError_t launch_tab_p(StepParams prm, const fe_mesh *m, hipStream_t s) 
     return hipSuccess;
 }
 
-template <int P, int PREC, int BY>
+template <int P, int PREC, int BY, bool CPX>
 static hipError_t launch_tab_y(StepParams prm, const fe_mesh *m, hipStream_t s) {
     constexpr int TPW = TabCfg<P>::TPW, G = TabCfg<P>::G;
     switch (m->seg_bx) {
-    case 3: return launch_tab_p<P, PREC, TPW, G, 3, BY>(prm, m, s);
-    case 2: return launch_tab_p<P, PREC, TPW, G, 2, BY>(prm, m, s);
-    default: return launch_tab_p<P, PREC, TPW, G, 1, BY>(prm, m, s);
+    case 3: return launch_tab_p<P, PREC, TPW, G, 3, BY, CPX>(prm, m, s);
+    case 2: return launch_tab_p<P, PREC, TPW, G, 2, BY, CPX>(prm, m, s);
+    default: return launch_tab_p<P, PREC, TPW, G, 1, BY, CPX>(prm, m, s);
     }
 }
 
@@ -2292,9 +2319,10 @@ static hipError_t launch_tab_y(StepParams prm, const fe_mesh *m, hipStream_t s) 
 // allows): fewer bytes, and faster where the products dominate; FP32
 // products, HBM-bound, were measured faster on bricks one cell deep in y
 // (the second table), where a brick's cells are closer together in memory.
-template <int P, int PREC>
+template <int P, int PREC, bool CPX = false>
 static hipError_t launch_tab(StepParams prm, const fe_mesh *m, hipStream_t s) {
-    return PREC == 0 && m->seg_by == 2 ? launch_tab_y<P, PREC, 2>(prm, m, s) : launch_tab_y<P, PREC, 1>(prm, m, s);
+    return PREC == 0 && m->seg_by == 2 ? launch_tab_y<P, PREC, 2, CPX>(prm, m, s)
+                                       : launch_tab_y<P, PREC, 1, CPX>(prm, m, s);
 }
 
 // Cells per brick along an axis of the table kernel (x: up to 3, y: up to
@@ -2438,7 +2466,9 @@ void build_segment_table(const fe_mesh *m, int by_most, std::vector<int32_t> &ta
 // and column pair (blocks 16-byte aligned, even leading dimension), and X
 // request offsets within the 31-bit range of its buffer requests.
 static bool dma_applies(const fe_mesh *m, const StepArgs &a, fe_dtype prec) {
-    if (a.S || !m->d_segtab || m->p < 3 || m->p > 5 || (m->p == 5 && prec != FE_F32)) return false;
+    if (!m->d_segtab || m->p < 3 || m->p > 5 || (m->p == 5 && prec != FE_F32)) return false;
+    // the Bloch mode: FP64 at p = 3, 4, with the folded k.G fragments
+    if (a.S && (prec != FE_F64 || m->p > 4 || !m->d_Sf64s)) return false;
     if (!(prec == FE_F64 ? m->d_Af64s != nullptr : prec == FE_F32 && m->d_Af32s != nullptr)) return false;
     const uintptr_t ptrs = reinterpret_cast<uintptr_t>(a.X) | reinterpret_cast<uintptr_t>(a.Y) |
                            reinterpret_cast<uintptr_t>(a.Ym1 ? a.Ym1 : a.X);
@@ -2525,9 +2555,25 @@ static hipError_t launch_step_v(const fe_mesh *m, const StepArgs &a, fe_dtype pr
     prm.zs = prm.ax[2];
     prm.zl = 1;
     if (a.S) {
-        // Bloch mode: FP64 row-owner kernel in the configurations of the real
-        // mode, with one wave less per SIMD for the second fragment stream
         if (prec != FE_F64) return hipErrorInvalidValue;
+        // Bloch mode: the table kernel with the k.G product (p = 3, 4) on the
+        // whole 32-column groups (16 complex vectors), the rest in the
+        // row-owner kernel
+        if ((variant == 0 || variant == 10) && a.N >= 32 && dma_applies(m, a, prec)) {
+            const int64_t Nf = a.N / 32 * 32;
+            prm.N = Nf;
+            prm.nchunk = (int)(Nf / 16);
+            const hipError_t e = m->p == 3 ? launch_tab<3, 0, true>(prm, m, s) : launch_tab<4, 0, true>(prm, m, s);
+            if (e != hipSuccess || Nf == a.N) return e;
+            StepArgs rest = a;
+            rest.X += Nf;
+            rest.Y += Nf;
+            if (rest.Ym1) rest.Ym1 += Nf;
+            rest.N = a.N - Nf;
+            return launch_step_v(m, rest, prec, s, 6);
+        }
+        // the FP64 row-owner kernel in the configurations of the real mode,
+        // with one wave less per SIMD for the second fragment stream
         switch (m->p) {
         case 1: return launch_row_p<1, 0, 2, 1, 4, 4, true>(prm, m, s);
         case 2: return launch_row_p<2, 0, 2, 1, 4, 4, true>(prm, m, s);

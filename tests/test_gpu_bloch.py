@@ -53,6 +53,13 @@ CASES = [
     ("p6-kx-N8", W.small_slab((2, 2, 2), p=6, N=8), (1.1, 0.0), False),
     ("p7-kxy-N5", W.small_slab((2, 2, 2), p=7, N=5), (0.4, 0.7), False),
     ("p4-odd-periodic-N1-nl", W.small_slab((5, 5, 6), p=4, N=1, cfg=5), (0.3, 0.6), True),
+    # the table kernel with the k.G product (p = 3, 4, at least 16 complex
+    # vectors): x and y bricks, three colours in y with a rest of 4 complex
+    # vectors in the row-owner kernel, every axis periodic, nonlocal sites
+    ("p4-table-kxy-N32", W.small_slab((6, 4, 6), p=4, N=32), (0.37, 0.21), False),
+    ("p4-table-ky-N20-rest", W.small_slab((4, 3, 6), p=4, N=20), (0.0, 0.5), False),
+    ("p4-table-allper-N16", W.small_slab((3, 4, 4), p=4, N=16, bc=(W.PERIODIC,) * 3, E=0.0), (0.3, -0.6), False),
+    ("p3-table-kxy-N16-nl", W.small_slab((6, 6, 5), p=3, N=16, cfg=5), (0.21, -0.45), True),
 ]
 
 
@@ -68,7 +75,10 @@ def test_hx_k_matches_oracle(label, wl, k, nl):
     assert _relerr(Y, R) < 1e-13
 
 
-@pytest.mark.parametrize("label,wl,k,nl", [CASES[0], CASES[1], CASES[3]], ids=[CASES[i][0] for i in (0, 1, 3)])
+FILTER_CASES = [CASES[i] for i in (0, 1, 3, 9, 10)]
+
+
+@pytest.mark.parametrize("label,wl,k,nl", FILTER_CASES, ids=[c[0] for c in FILTER_CASES])
 @pytest.mark.parametrize("scaled", [True, False])
 def test_filter_k_matches_oracle(label, wl, k, nl, scaled):
     _print_case(test="filter_k", label=label, k=k, scaled=scaled)
