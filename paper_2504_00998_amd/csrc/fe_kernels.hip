@@ -1728,8 +1728,9 @@ static hipError_t launch_pipe_p(StepParams prm, const fe_mesh *m, hipStream_t s)
 }
 
 // ------------------------------------------------------------------------
-// Step kernel with direct-to-LDS prefetch and a segment table (p = 3, 4;
-// meshes without a zero-Neumann axis, where M^-1/2 of a free node depends
+// Step kernel with direct-to-LDS prefetch and a brick table (p = 3, 4, and
+// p = 5 with FP32 products; meshes without a zero-Neumann axis, where M^-1/2
+// of a free node depends
 // only on its local index and folds into the cell matrix:
 // A' = D^ (1/2 Kc) D^), with FP64 cell products (PREC 0) or FP32 ones
 // (PREC 1: A' rounded to FP32, each X element rounded to FP32 as the
@@ -1745,20 +1746,21 @@ static hipError_t launch_pipe_p(StepParams prm, const fe_mesh *m, hipStream_t s)
 //   requests, two positions ahead, into three LDS buffers (no staging
 //   arithmetic; with the folded cell matrix they need no scaling);
 // - everything a position needs to know about its cell comes from one 8-byte
-//   entry per z segment of a colour, built on the host: the DoF of the
-//   segment's first node and masks of the cell faces that are shared with a
+//   entry per brick of a colour, built on the host: the DoF of the brick's
+//   first node and masks of the cell faces that are shared with a
 //   cell of an earlier colour, lie on a Dirichlet face, or wrap on a periodic
 //   axis.  A row's DoF is then the cell's first DoF plus a per-lane constant
 //   (minus a per-lane wrap correction where the mask says so), and its
 //   first-writer and validity tests are its per-lane face bits against those
 //   masks: no per-row index arithmetic, no colour logic, no divisions.
-// Persistent workgroups walk the items (z segment of cells, 32 vectors; N a
-// multiple of 32, the launcher hands the rest to another kernel) of a colour
-// as the pipelined kernel does, one wave per 16-row tile of A' with the
+// Persistent workgroups walk the items (brick of BX x BY x zl cells, 32
+// vectors (16 at p = 5); the launcher hands the columns past the last whole
+// group to another kernel) of a colour with stride gridDim.x, cell by cell
+// (x fastest, then y, then z), one wave per 16-row tile of A' with the
 // tile's fragments in registers.  A position's old values and v are
-// loaded to registers at its start and used after its product; with z
-// segments the partial sums of a segment's inner z faces stay in an LDS hold
-// (the X rows of those faces are read again, from L2).
+// loaded to registers at its start and used after its product; the partial
+// sums of a brick's inner faces pass from cell to cell through LDS holds
+// (the X rows of those faces are read again, mostly from the caches).
 //
 // Per position t: the old values and v of t are requested, then the X rows of
 // t + 2 (into buffer (t + 2) % 3, free since the barrier that ended t - 1);
@@ -1775,14 +1777,14 @@ template <int P, int TPW, int NGRP> struct TabShape {
     static_assert(NT % TPW == 0, "row tiles split evenly over the waves");
 };
 
-// Segment-table entry: .x the DoF of local node 0 of the segment's first
-// cell (its free-index arithmetic extended below 0 on a Dirichlet face),
-// .y face masks (bit order lo x, hi x, lo y, hi y, lo z, hi z):
-//   bits 0-5   faces shared with a cell of an earlier colour (z: the
-//              segment's first cell's lo face, last cell's hi face)
-//   bits 6-11  faces on a Dirichlet boundary (z: as above)
-//   bits 12-17 faces that wrap on a periodic axis (hi faces only; z: the
-//              segment's last cell)
+// Brick-table entry: .x the DoF of local node 0 of the brick's first cell
+// (its free-index arithmetic extended below 0 on a Dirichlet face), .y face
+// masks of the brick (bit order lo x, hi x, lo y, hi y, lo z, hi z):
+//   bits 0-5   faces shared with a brick of an earlier colour
+//   bits 6-11  faces on a Dirichlet boundary
+//   bits 12-17 faces that wrap on a periodic axis (hi faces only)
+// A cell of the brick takes a lo bit only in the brick's first cell along
+// that axis and a hi bit only in its last.
 enum : int { SEG_FM = 0, SEG_DM = 6, SEG_WM = 12 };
 
 // Buffer descriptors of the table kernel's X requests: byte range (offsets
