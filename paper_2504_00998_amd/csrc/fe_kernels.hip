@@ -2265,6 +2265,9 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, const int *_
         if (!body(t + 1, p1, p2, p0, xb1, xb0, hold)) break;
         if (!body(t + 2, p2, p0, p1, xb2, xb1, hold)) break;
     }
+    // the requests of the last positions (rows past the walk's end, into free
+    // buffers) land before the workgroup's LDS is released
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
 }
 
 template <int P, int PREC, int TPW, int G, int BX, int BY, bool CPX>
@@ -2323,8 +2326,9 @@ static hipError_t launch_tab_y(StepParams prm, const fe_mesh *m, hipStream_t s) 
 // (the second table), where a brick's cells are closer together in memory.
 template <int P, int PREC, bool CPX = false>
 static hipError_t launch_tab(StepParams prm, const fe_mesh *m, hipStream_t s) {
-    return PREC == 0 && m->seg_by == 2 ? launch_tab_y<P, PREC, 2, CPX>(prm, m, s)
-                                       : launch_tab_y<P, PREC, 1, CPX>(prm, m, s);
+    if constexpr (PREC == 0)
+        if (m->seg_by == 2) return launch_tab_y<P, PREC, 2, CPX>(prm, m, s);
+    return launch_tab_y<P, PREC, 1, CPX>(prm, m, s);
 }
 
 // Cells per brick along an axis of the table kernel (x: up to 3, y: up to
