@@ -1858,12 +1858,16 @@ template <int P> struct TabRow {
 };
 
 // Shapes of the table kernel: one 16-row tile of A' per wave; p = 3, 4: 4 / 8
-// waves and 32 vectors per item; p = 5 (FP32 products only: 224 padded
-// rows): 14 waves (up to 4 per SIMD, within 128 registers: 56 fragment
+// tiles and 32 vectors per item; with FP32 products at p = 4 two waves per
+// tile, one 16-vector group each (16 waves, up to 4 per SIMD within 128
+// registers: 3-5 % faster than one wave per tile; no faster at p = 3; with
+// FP64 products the same split spills at 128 registers and was 4.7 %
+// slower); p = 5 (FP32
+// products only: 224 padded rows): 14 waves (up to 4 per SIMD; 56 fragment
 // registers each) and 16 vectors per item, so that three X buffers of 224
 // rows fit the LDS (7 waves of two tiles each, 2 per SIMD, were 7 % slower)
-template <int P> struct TabCfg {
-    static constexpr int TPW = 1, G = P == 5 ? 1 : 2;
+template <int P, int PREC = 0> struct TabCfg {
+    static constexpr int TPW = 1, G = P == 5 ? 1 : 2, GS = (PREC == 1 && P == 4) ? 2 : 1;
 };
 
 // (at most 2 waves per SIMD, or as many as the workgroup puts on one)
@@ -1873,21 +1877,25 @@ template <int P> struct TabCfg {
 // S x_i - i S x_r, each k-step adds S times the lane's im column to its re
 // accumulator and S times the negated re column (the product's B-operand
 // negation) to its im accumulator.
-template <int P, int PREC, int TPW, int NGRP, int BX, int BY, bool CPX = false>
-__global__ __launch_bounds__((64 * TabShape<P, TPW, NGRP>::W))
-__attribute__((amdgpu_waves_per_eu(1, TabShape<P, TPW, NGRP>::W > 8 ? (TabShape<P, TPW, NGRP>::W + 3) / 4 : 2)))
+// GS waves per row tile, each taking NGRP / GS of the item's 16-vector groups
+// (GS = 2: twice the waves, each with half the accumulators and requests).
+template <int P, int PREC, int TPW, int NGRP, int BX, int BY, bool CPX = false, int GS = 1>
+__global__ __launch_bounds__((64 * GS * TabShape<P, TPW, NGRP>::W))
+__attribute__((amdgpu_waves_per_eu(1, GS * TabShape<P, TPW, NGRP>::W > 8 ? (GS * TabShape<P, TPW, NGRP>::W + 3) / 4 : 2)))
 void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, const int *__restrict__ rowperm, int64_t nitems) {
     static_assert(PREC == 0 || PREC == 1, "FP64 or FP32 cell products");
     static_assert(!CPX || PREC == 0, "the Bloch mode is FP64 only");
     typedef typename FragOf<PREC>::T AT;
     typedef TabShape<P, TPW, NGRP> S;
-    constexpr int N1 = P + 1, NKS = S::NKS, G = S::G, XS = S::XS, W = S::W, NDMA = S::NDMA;
+    static_assert(NGRP % GS == 0, "groups split evenly over a tile's waves");
+    // GI groups per item, G per wave
+    constexpr int N1 = P + 1, NKS = S::NKS, GI = S::G, G = GI / GS, XS = S::XS, W = S::W, NDMA = 2 * TPW * G;
     // LDS holds (doubles), each node once: the x face between consecutive
     // cells of a brick row (N1 x N1 nodes), the back faces of a brick row
     // ((BX p + 1) x N1 nodes: x by z), the top faces of a brick layer
     // ((BX p + 1) x (BY p + 1) nodes: x by y); each slot is read and written
     // at one position by two rows of the same wave (see build_table_row_perm)
-    constexpr int ZW = BX * P + 1, V = 16 * G;
+    constexpr int ZW = BX * P + 1, V = 16 * GI;
     constexpr int XHS = BX > 1 ? N1 * N1 * V : 0, YHS = BY > 1 ? ZW * N1 * V : 0, ZHS = ZW * (BY * P + 1) * V;
     constexpr int YH0 = XHS, ZH0 = YH0 + YHS, ZERO0 = ZH0 + ZHS;
     // three X buffers [G][NCP][16] as distinct arrays, each named at compile
@@ -1896,15 +1904,17 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, const int *_
     // buffers; the holds followed by 32 zeros (the hold term of rows that
     // take none) in one array, so that every hold read is based on it and the
     // compiler sees it apart from the X requests in flight
-    __shared__ __align__(16) double xb0[G * XS], xb1[G * XS], xb2[G * XS];
+    __shared__ __align__(16) double xb0[GI * XS], xb1[GI * XS], xb2[GI * XS];
     __shared__ __align__(16) double hold[ZERO0 + 32];
-    static_assert(sizeof(double) * (3 * G * XS + ZERO0 + 32) <= 160 * 1024, "LDS of one workgroup");
+    static_assert(sizeof(double) * (3 * GI * XS + ZERO0 + 32) <= 160 * 1024, "LDS of one workgroup");
 
     const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    // the wave's row tile(s), and g0 the item's group of its first group
+    const int wall = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wave = GS == 1 ? wall : wall % W, g0 = GS == 1 ? 0 : (wall / W) * G;
     if ((int64_t)blockIdx.x >= nitems) return;  // whole workgroup
     if (tid < 32) hold[ZERO0 + tid] = 0.0;
-    const int ngroups = (k.nchunk + G - 1) / G;
+    const int ngroups = (k.nchunk + GI - 1) / GI;
     const int stride = (int)gridDim.x;
     const int sdiv = stride / ngroups, smod = stride % ngroups;
     const int zl = k.zl;
@@ -1984,7 +1994,7 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, const int *_
     auto cell = [&](const Pos &p) {
         Cell q;
         q.I0 = p.e.x + p.bx * P + p.by * ystep + p.c * zstep;
-        q.U = (int64_t)q.I0 * ld + (int64_t)p.grp * G * 16;
+        q.U = (int64_t)q.I0 * ld + (int64_t)p.grp * GI * 16 + g0 * 16;
         const int hi = (p.bx == BX - 1 ? 2 : 0) | (p.by == BY - 1 ? 8 : 0) | (p.c == zl - 1 ? 32 : 0);
         const int m = hi | (p.bx == 0 ? 1 : 0) | (p.by == 0 ? 4 : 0) | (p.c == 0 ? 16 : 0);
         q.fm = (p.e.y >> SEG_FM) & m;
@@ -2038,7 +2048,7 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, const int *_
                     // as the argument leaves the kernel without its host stub)
                     const uint32_t voff = vo[j][h];
                     __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                        rs, (__attribute__((address_space(3))) void *)(bufp + g * XS + (16 * (wave + W * j) + 8 * h) * 16),
+                        rs, (__attribute__((address_space(3))) void *)(bufp + (g0 + g) * XS + (16 * (wave + W * j) + 8 * h) * 16),
                         16u, voff, 128u * (unsigned)g, 0, 0);
                 }
         asm volatile("" ::: "memory");
@@ -2105,12 +2115,12 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, const int *_
                     for (int q = 0; q < 4; ++q) acc[j][g][q] = 0.0;
             double bc[G][4], bn[G][4];
 #pragma unroll
-            for (int g = 0; g < G; ++g) f64_pair_b(xs + g * XS, 0, lane, bc[g]);
+            for (int g = 0; g < G; ++g) f64_pair_b(xs + (g0 + g) * XS, 0, lane, bc[g]);
 #pragma unroll
             for (int s = 0; s < NKS; ++s) {
                 if (s + 1 < NKS)
 #pragma unroll
-                    for (int g = 0; g < G; ++g) f64_pair_b(xs + g * XS, s + 1, lane, bn[g]);
+                    for (int g = 0; g < G; ++g) f64_pair_b(xs + (g0 + g) * XS, s + 1, lane, bn[g]);
 #pragma unroll
                 for (int j = 0; j < TPW; ++j)
 #pragma unroll
@@ -2145,7 +2155,7 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, const int *_
             f4 c4[TPW][G];
             float bc[G], bn[G];
 #pragma unroll
-            for (int g = 0; g < G; ++g) bc[g] = (float)xs[g * XS + bo];
+            for (int g = 0; g < G; ++g) bc[g] = (float)xs[(g0 + g) * XS + bo];
 #pragma unroll
             for (int j = 0; j < TPW; ++j)
 #pragma unroll
@@ -2154,7 +2164,7 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, const int *_
             for (int s = 0; s < NKS; ++s) {
                 if (s + 1 < NKS)
 #pragma unroll
-                    for (int g = 0; g < G; ++g) bn[g] = (float)xs[g * XS + 64 * (s + 1) + bo];
+                    for (int g = 0; g < G; ++g) bn[g] = (float)xs[(g0 + g) * XS + 64 * (s + 1) + bo];
 #pragma unroll
                 for (int j = 0; j < TPW; ++j)
 #pragma unroll
@@ -2202,10 +2212,10 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, const int *_
             const double *hrow = hd + hoff;
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                const double2 x01 = *reinterpret_cast<const double2 *>(xs + g * XS + xo[j]);
-                const double2 x23 = *reinterpret_cast<const double2 *>(xs + g * XS + xo[j] + 8);
-                const double2 h01 = *reinterpret_cast<const double2 *>(hrow + 16 * g);
-                const double2 h23 = *reinterpret_cast<const double2 *>(hrow + 16 * g + 8);
+                const double2 x01 = *reinterpret_cast<const double2 *>(xs + (g0 + g) * XS + xo[j]);
+                const double2 x23 = *reinterpret_cast<const double2 *>(xs + (g0 + g) * XS + xo[j] + 8);
+                const double2 h01 = *reinterpret_cast<const double2 *>(hrow + 16 * (g0 + g));
+                const double2 h23 = *reinterpret_cast<const double2 *>(hrow + 16 * (g0 + g) + 8);
                 const double xv[4] = {x01.x, x01.y, x23.x, x23.y}, hv[4] = {h01.x, h01.y, h23.x, h23.y};
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
@@ -2222,8 +2232,8 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, const int *_
                 double *h = hd + (right[j] ? xh[j] : back[j] ? yh[j] + yoff : zh[j] + zoff);
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
-                    lds_store16(h + 16 * g, out[j][g][0], out[j][g][1]);
-                    lds_store16(h + 16 * g + 8, out[j][g][2], out[j][g][3]);
+                    lds_store16(h + 16 * (g0 + g), out[j][g][0], out[j][g][1]);
+                    lds_store16(h + 16 * (g0 + g) + 8, out[j][g][2], out[j][g][3]);
                 }
             } else if (valid[j]) {
                 double *yrow = k.Y + E[j];
@@ -2270,16 +2280,16 @@ void step_tab_kernel(StepParams k, const int2 *__restrict__ segtab, const int *_
     __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
 }
 
-template <int P, int PREC, int TPW, int G, int BX, int BY, bool CPX>
+template <int P, int PREC, int TPW, int G, int BX, int BY, bool CPX, int GS>
 static hipError_t launch_tab_p(StepParams prm, const fe_mesh *m, hipStream_t s) {
     typedef TabShape<P, TPW, G> S;
-    constexpr int W = S::W;
+    constexpr int W = GS * S::W;
     static bool attr = false;
     static int resident = 0;
     if (!attr) {
         int per_cu = 0, dev = 0, cus = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(&step_tab_kernel<P, PREC, TPW, G, BX, BY, CPX>), 64 * W, 0);
+            &per_cu, reinterpret_cast<const void *>(&step_tab_kernel<P, PREC, TPW, G, BX, BY, CPX, GS>), 64 * W, 0);
         if (e != hipSuccess) return e;
         e = hipGetDevice(&dev);
         if (e != hipSuccess) return e;
@@ -2302,7 +2312,7 @@ static hipError_t launch_tab_p(StepParams prm, const fe_mesh *m, hipStream_t s) 
         const int2 *tab = reinterpret_cast<const int2 *>(tab0) + off[col];
         const int64_t nitems = segs * ngroups;
         const int64_t grid = std::min<int64_t>(nitems, resident);
-        hipLaunchKernelGGL((step_tab_kernel<P, PREC, TPW, G, BX, BY, CPX>), dim3((unsigned)grid), dim3(64 * W), 0, s, prm,
+        hipLaunchKernelGGL((step_tab_kernel<P, PREC, TPW, G, BX, BY, CPX, GS>), dim3((unsigned)grid), dim3(64 * W), 0, s, prm,
                            tab, m->d_tabperm, nitems);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -2312,11 +2322,11 @@ static hipError_t launch_tab_p(StepParams prm, const fe_mesh *m, hipStream_t s) 
 
 template <int P, int PREC, int BY, bool CPX>
 static hipError_t launch_tab_y(StepParams prm, const fe_mesh *m, hipStream_t s) {
-    constexpr int TPW = TabCfg<P>::TPW, G = TabCfg<P>::G;
+    typedef TabCfg<P, PREC> C;
     switch (m->seg_bx) {
-    case 3: return launch_tab_p<P, PREC, TPW, G, 3, BY, CPX>(prm, m, s);
-    case 2: return launch_tab_p<P, PREC, TPW, G, 2, BY, CPX>(prm, m, s);
-    default: return launch_tab_p<P, PREC, TPW, G, 1, BY, CPX>(prm, m, s);
+    case 3: return launch_tab_p<P, PREC, C::TPW, C::G, 3, BY, CPX, C::GS>(prm, m, s);
+    case 2: return launch_tab_p<P, PREC, C::TPW, C::G, 2, BY, CPX, C::GS>(prm, m, s);
+    default: return launch_tab_p<P, PREC, C::TPW, C::G, 1, BY, CPX, C::GS>(prm, m, s);
     }
 }
 
