@@ -37,11 +37,11 @@ MEASURED_PEAK = {"f64": 74.2, "f32": 155.0}
 # HBM bytes per colour launch of the default step kernel on the p=4 slab
 # (N=256), from FETCH_SIZE/WRITE_SIZE counters scaled by a plain copy of known
 # size, averaged over the launches of a degree-30 filter (the first step reads
-# no previous iterate: FP64 1.467e9 B, FP32 1.590e9 B, BF16 1.779e9 B; the 29
-# others 1.950e9 / 2.069e9 / 2.235e9 B); valid for these kernel builds only
+# no previous iterate: FP64 1.467e9 B, FP32 1.588e9 B, BF16 1.779e9 B; the 29
+# others 1.950e9 / 2.065e9 / 2.235e9 B); valid for these kernel builds only
 # (None: not counted)
 COUNTED_TRAFFIC = {("slab-p4-24x24x48", 256, "f64"): (1.934e9, "step_tab_kernel<4,0,1,2,3,2>"),
-                   ("slab-p4-24x24x48", 256, "f32"): (2.053e9, "step_tab_kernel<4,1,1,2,3,1>"),
+                   ("slab-p4-24x24x48", 256, "f32"): (2.049e9, "step_tab_kernel<4,1,1,2,3,1,false,2>"),
                    ("slab-p4-24x24x48", 256, "bf16"): (2.220e9, "step_pipe_kernel<4,2,2,true>")}
 # MI355X ceilings of the filter rate (GDoF.vec/s) of the large workloads:
 # the dense-MFMA roofline of one H~X (2 n_c^2 flop per cell and vector; FP64
