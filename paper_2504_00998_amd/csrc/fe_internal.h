@@ -44,6 +44,13 @@ struct NonlocalData {
     double *d_W = nullptr;           // projections C~^T X, grown on demand
     size_t W_cap = 0;                // doubles
     std::vector<double> disp;        // [nnz][2] in-plane x_I - R_s of each entry (minimum image)
+    // chunks of at most kNlChunk support entries of one site, grouped by
+    // site colour (sites of one colour have disjoint supports): colour c holds
+    // chunks chunk_col_ptr[c] .. chunk_col_ptr[c + 1], chunk q being entries
+    // d_chunk_e0[q] .. min(d_chunk_e0[q] + kNlChunk, end of site d_chunk_site[q])
+    int32_t *d_chunk_site = nullptr;
+    int64_t *d_chunk_e0 = nullptr;
+    std::vector<int64_t> chunk_col_ptr;
     double *d_phase = nullptr;       // [nnz][2] cos, sin of k.(x_I - R_s) (Bloch mode)
 };
 

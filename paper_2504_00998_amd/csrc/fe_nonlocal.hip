@@ -7,8 +7,10 @@
 // cutoff ball |x - R_s| < r_cut (minimum image on periodic axes), normalised
 // to sum_I M_I p(x_I)^2 = 1, and S_beta the real solid harmonics 1; x, y, z;
 // xy, yz, zx, x^2 - y^2, 3z^2 - r^2 (s, p, d channels).  The host builds the
-// per-site supports and a node -> (site, entry) incidence list so that the
-// application  Y += alpha C~ D C~^T X  is a deterministic gather on the device.
+// per-site supports, a colouring of the sites (sites that share a node differ
+// in colour) and, for the Bloch mode, a node -> (site, entry) incidence list,
+// so that the application  Y += alpha C~ D C~^T X  runs on the device without
+// atomics and gives the same bits on every run.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,6 +22,11 @@
 #include "fe_internal.h"
 
 namespace fe {
+
+// support entries per workgroup of the expansion kernel
+constexpr int64_t kNlChunk = 64;
+// rows loaded ahead of their products in the projection and expansion loops
+constexpr int kNlBatch = 8;
 
 // Device-resident scratch of the allocation-free H~X entry point
 // (fe_hx_apply_noalloc): the nonlocal projections W = D C~^T X of one call,
@@ -88,6 +95,8 @@ void free_nl(NonlocalData &nl) {
     (void)hipFree(nl.d_entry_site);
     (void)hipFree(nl.d_W);
     (void)hipFree(nl.d_phase);
+    (void)hipFree(nl.d_chunk_site);
+    (void)hipFree(nl.d_chunk_e0);
     nl = NonlocalData();
 }
 
@@ -95,42 +104,154 @@ void free_nl(NonlocalData &nl) {
 
 void nonlocal_release(fe_mesh *m) { free_nl(m->nl); }
 
+// the value a double register holds in lane l (l uniform)
+__device__ __forceinline__ double lane_double(double v, int l) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // W[(s*9+beta)][j] = D_{s,beta} sum_{e in supp(s)} C~[e][beta] X[dof(e)][j]
-__global__ void nl_project_kernel(const double *X, int64_t ldx, int64_t N, const int64_t *supp_ptr,
-                                  const int32_t *supp_dof, const double *vals, const double *D, double *W) {
+// One workgroup per site and 64 columns; its kNlWaves waves take contiguous
+// parts of the support, and the partial sums meet in LDS in wave
+// order, so the result does not depend on timing.
+constexpr int kNlWaves = 8;
+__global__ void __launch_bounds__(64 * kNlWaves)
+    nl_project_kernel(const double *__restrict__ X, int64_t ldx, int64_t N, const int64_t *__restrict__ supp_ptr,
+                      const int32_t *__restrict__ supp_dof, const double *__restrict__ vals,
+                      const double *__restrict__ D, double *__restrict__ W) {
+    __shared__ double part[kNlWaves][9][64];
     const int s = blockIdx.x;
-    const int64_t j = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
-    if (j >= N) return;
+    // the wave index is uniform over the wave: the entry loop runs on scalar
+    // registers
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t j = (int64_t)blockIdx.y * 64 + lane;
+    const int64_t s0 = supp_ptr[s], len = supp_ptr[s + 1] - s0;
+    const int64_t e0 = s0 + len * wv / kNlWaves, e1 = s0 + len * (wv + 1) / kNlWaves;
+    // every lane takes part in the loads that are broadcast; a lane past the
+    // last column reads column N - 1 and its sums are dropped
+    const int64_t jl = j < N ? j : N - 1;
     double acc[9];
 #pragma unroll
     for (int b = 0; b < 9; ++b) acc[b] = 0.0;
-    for (int64_t e = supp_ptr[s]; e < supp_ptr[s + 1]; ++e) {
-        double x = X[(int64_t)supp_dof[e] * ldx + j];
+    int64_t e = e0;
+    if (e + kNlBatch <= e1) {
+        // batches of kNlBatch rows: the batch's row indices come through one
+        // scalar load, made while the previous batch is in flight; its 9
+        // kNlBatch matrix entries through two vector loads spread over the
+        // lanes (issued with the rows of X) and broadcast with readlane
+        static_assert(kNlBatch == 8, "72 matrix entries in two loads of 64 and 8");
+        int d[kNlBatch];
+#pragma unroll
+        for (int t = 0; t < kNlBatch; ++t) d[t] = supp_dof[e + t];
+        for (; e + kNlBatch <= e1; e += kNlBatch) {
+            const double va = vals[e * 9 + lane], vb = vals[e * 9 + 64 + (lane & 7)];
+            double x[kNlBatch];
+#pragma unroll
+            for (int t = 0; t < kNlBatch; ++t) x[t] = X[(int64_t)d[t] * ldx + jl];
+            // indices of the next full batch (this one's again after the last)
+            const int64_t en = e + 2 * kNlBatch <= e1 ? e + kNlBatch : e;
+#pragma unroll
+            for (int t = 0; t < kNlBatch; ++t) d[t] = supp_dof[en + t];
+            // keep all loads of the batch ahead of its products
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int t = 0; t < kNlBatch; ++t) {
+#pragma unroll
+                for (int b = 0; b < 9; ++b) {
+                    const int q = t * 9 + b;
+                    acc[b] += (q < 64 ? lane_double(va, q) : lane_double(vb, q - 64)) * x[t];
+                }
+            }
+        }
+    }
+    for (; e < e1; ++e) {
+        const double x = X[(int64_t)supp_dof[e] * ldx + jl];
         const double *v = vals + e * 9;
 #pragma unroll
         for (int b = 0; b < 9; ++b) acc[b] += v[b] * x;
     }
 #pragma unroll
-    for (int b = 0; b < 9; ++b) W[((int64_t)s * 9 + b) * N + j] = D[s * 9 + b] * acc[b];
+    for (int b = 0; b < 9; ++b) part[wv][b][lane] = acc[b];
+    __syncthreads();
+    for (int q = threadIdx.x; q < 9 * 64; q += 64 * kNlWaves) {
+        const int b = q >> 6, c = q & 63;
+        const int64_t jc = (int64_t)blockIdx.y * 64 + c;
+        if (jc >= N) continue;
+        double t = part[0][b][c];
+#pragma unroll
+        for (int w = 1; w < kNlWaves; ++w) t += part[w][b][c];
+        W[((int64_t)s * 9 + b) * N + jc] = D[s * 9 + b] * t;
+    }
 }
 
-// Y[node][j] += alpha sum_{e incident to node} sum_beta C~[e][beta] W[(site(e)*9+beta)][j]
-__global__ void nl_expand_kernel(double *Y, int64_t ldy, int64_t N, double alpha, const int32_t *node,
-                                 const int64_t *inc_ptr, const int64_t *inc_entry, const int32_t *entry_site,
-                                 const double *vals, const double *W) {
-    const int64_t u = blockIdx.x;
+// Y[dof(e)][j] += alpha sum_beta C~[e][beta] W[(site(e)*9+beta)][j], entry
+// by entry, over chunks of the supports of the sites of one colour (disjoint
+// supports, so no two workgroups of a launch touch one row of Y), the site's
+// nine W values held in registers.  A node in the supports of sites of
+// several colours takes their terms colour by colour.
+__global__ void nl_expand_chunk_kernel(double *__restrict__ Y, int64_t ldy, int64_t N, double alpha,
+                                       const int32_t *__restrict__ chunk_site, const int64_t *__restrict__ chunk_e0,
+                                       const int64_t *__restrict__ supp_ptr, const int32_t *__restrict__ supp_dof,
+                                       const double *__restrict__ vals, const double *__restrict__ W) {
+    const int s = chunk_site[blockIdx.x];
+    const int lane = threadIdx.x & 63;
     const int64_t j = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
-    if (j >= N) return;
-    double acc = 0.0;
-    for (int64_t q = inc_ptr[u]; q < inc_ptr[u + 1]; ++q) {
-        int64_t e = inc_entry[q];
-        int s = entry_site[e];
-        const double *v = vals + e * 9;
-        const double *w = W + (int64_t)s * 9 * N + j;
+    // a wave whose 64 columns all exist takes the batched path below, which
+    // broadcasts loads across the lanes; a wave at the ragged end of the
+    // columns goes entry by entry
+    const int64_t wave_end = (int64_t)blockIdx.y * blockDim.x + (threadIdx.x & ~63) + 64;
+    const bool full = wave_end <= N;
+    if (!full && j >= N) return;
+    double w[9];
 #pragma unroll
-        for (int b = 0; b < 9; ++b) acc += v[b] * w[(int64_t)b * N];
+    for (int b = 0; b < 9; ++b) w[b] = W[((int64_t)s * 9 + b) * N + j];
+    const int64_t e0 = chunk_e0[blockIdx.x];
+    const int64_t e1 = min(e0 + (int64_t)kNlChunk, supp_ptr[s + 1]);
+    int64_t e = e0;
+    if (full && e + kNlBatch <= e1) {
+        // batches of kNlBatch entries (distinct rows of Y): the row indices
+        // through one scalar load, made while the previous batch is in
+        // flight; the 9 kNlBatch matrix entries through two vector loads
+        // spread over the lanes and broadcast with readlane; all loads of a
+        // batch ahead of its stores
+        int d[kNlBatch];
+#pragma unroll
+        for (int t = 0; t < kNlBatch; ++t) d[t] = supp_dof[e + t];
+        for (; e + kNlBatch <= e1; e += kNlBatch) {
+            const double va = vals[e * 9 + lane], vb = vals[e * 9 + 64 + (lane & 7)];
+            double y[kNlBatch];
+            double *yp[kNlBatch];
+#pragma unroll
+            for (int t = 0; t < kNlBatch; ++t) {
+                yp[t] = Y + (int64_t)d[t] * ldy + j;
+                y[t] = *yp[t];
+            }
+            const int64_t en = e + 2 * kNlBatch <= e1 ? e + kNlBatch : e;
+#pragma unroll
+            for (int t = 0; t < kNlBatch; ++t) d[t] = supp_dof[en + t];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int t = 0; t < kNlBatch; ++t) {
+                double acc = 0.0;
+#pragma unroll
+                for (int b = 0; b < 9; ++b) {
+                    const int q = t * 9 + b;
+                    acc += (q < 64 ? lane_double(va, q) : lane_double(vb, q - 64)) * w[b];
+                }
+                *yp[t] = y[t] + alpha * acc;
+            }
+        }
     }
-    Y[(int64_t)node[u] * ldy + j] += alpha * acc;
+    for (; e < e1; ++e) {
+        const double *v = vals + e * 9;
+        double acc = 0.0;
+#pragma unroll
+        for (int b = 0; b < 9; ++b) acc += v[b] * w[b];
+        double *y = Y + (int64_t)supp_dof[e] * ldy + j;
+        *y += alpha * acc;
+    }
 }
 
 // Bloch mode (paper Sec. 2.3 with k-point sampling): with u = exp(-i k.r) psi
@@ -222,18 +343,27 @@ hipError_t launch_nonlocal(fe_mesh *m, const double *X, int64_t ldx, double *Y, 
     }
     hipError_t e;
     const int TB = 128;
-    dim3 g1((unsigned)m->nl.n_site, (unsigned)((N + TB - 1) / TB));
-    hipLaunchKernelGGL(nl_project_kernel, g1, dim3(TB), 0, s, X, ldx, N, (const int64_t *)m->nl.d_supp_ptr,
+    dim3 g1((unsigned)m->nl.n_site, (unsigned)((N + 63) / 64));
+    hipLaunchKernelGGL(nl_project_kernel, g1, dim3(64 * kNlWaves), 0, s, X, ldx, N, (const int64_t *)m->nl.d_supp_ptr,
                        (const int32_t *)m->nl.d_supp_dof, (const double *)m->nl.d_vals, (const double *)m->nl.d_D,
                        W);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (m->nl.n_node == 0) return hipSuccess;
-    dim3 g2((unsigned)m->nl.n_node, (unsigned)((N + TB - 1) / TB));
-    hipLaunchKernelGGL(nl_expand_kernel, g2, dim3(TB), 0, s, Y, ldy, N, alpha, (const int32_t *)m->nl.d_node,
-                       (const int64_t *)m->nl.d_inc_ptr, (const int64_t *)m->nl.d_inc_entry,
-                       (const int32_t *)m->nl.d_entry_site, (const double *)m->nl.d_vals, (const double *)W);
-    return hipGetLastError();
+    // one launch per site colour, one workgroup per support chunk and column block
+    const std::vector<int64_t> &cp = m->nl.chunk_col_ptr;
+    for (size_t c = 0; c + 1 < cp.size(); ++c) {
+        const int64_t nq = cp[c + 1] - cp[c];
+        if (nq == 0) continue;
+        dim3 g2((unsigned)nq, (unsigned)((N + TB - 1) / TB));
+        hipLaunchKernelGGL(nl_expand_chunk_kernel, g2, dim3(TB), 0, s, Y, ldy, N, alpha,
+                           (const int32_t *)m->nl.d_chunk_site + cp[c], (const int64_t *)m->nl.d_chunk_e0 + cp[c],
+                           (const int64_t *)m->nl.d_supp_ptr, (const int32_t *)m->nl.d_supp_dof,
+                           (const double *)m->nl.d_vals, (const double *)W);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // complex blocks: N complex columns, ldx / ldy in doubles
@@ -369,6 +499,44 @@ fe_status fe_set_nonlocal(fe_mesh *m, int32_t n_site, const double *centres, con
         inc_entry.push_back(inc[i].second);
     }
     inc_ptr.push_back((int64_t)inc_entry.size());
+    // site colours: sites that share a node get different colours (greedy,
+    // in site order), so that the sites of one colour can add to Y at once
+    std::vector<std::vector<int>> nbr(n_site);
+    for (size_t u = 0; u + 1 < inc_ptr.size(); ++u)
+        for (int64_t a = inc_ptr[u]; a < inc_ptr[u + 1]; ++a)
+            for (int64_t b = a + 1; b < inc_ptr[u + 1]; ++b) {
+                const int sa = entry_site[inc_entry[a]], sb = entry_site[inc_entry[b]];
+                if (sa != sb) {
+                    nbr[sa].push_back(sb);
+                    nbr[sb].push_back(sa);
+                }
+            }
+    for (auto &v : nbr) {
+        std::sort(v.begin(), v.end());
+        v.erase(std::unique(v.begin(), v.end()), v.end());
+    }
+    std::vector<int> colour(n_site, -1);
+    int ncol = 0;
+    for (int s = 0; s < n_site; ++s) {
+        std::vector<char> used(ncol + 1, 0);
+        for (int t : nbr[s])
+            if (colour[t] >= 0) used[colour[t]] = 1;
+        int c = 0;
+        while (used[c]) ++c;
+        colour[s] = c;
+        ncol = std::max(ncol, c + 1);
+    }
+    std::vector<int32_t> chunk_site;
+    std::vector<int64_t> chunk_e0, chunk_col_ptr(1, 0);
+    for (int c = 0; c < ncol; ++c) {
+        for (int s = 0; s < n_site; ++s)
+            if (colour[s] == c)
+                for (int64_t e = supp_ptr[s]; e < supp_ptr[s + 1]; e += kNlChunk) {
+                    chunk_site.push_back(s);
+                    chunk_e0.push_back(e);
+                }
+        chunk_col_ptr.push_back((int64_t)chunk_site.size());
+    }
 
     NonlocalData &nl = m->nl;
     auto up = [&](void **dst, const void *src, size_t bytes) -> bool {
@@ -383,7 +551,9 @@ fe_status fe_set_nonlocal(fe_mesh *m, int32_t n_site, const double *centres, con
               up((void **)&nl.d_node, node.data(), node.size() * sizeof(int32_t)) &&
               up((void **)&nl.d_inc_ptr, inc_ptr.data(), inc_ptr.size() * sizeof(int64_t)) &&
               up((void **)&nl.d_inc_entry, inc_entry.data(), inc_entry.size() * sizeof(int64_t)) &&
-              up((void **)&nl.d_entry_site, entry_site.data(), entry_site.size() * sizeof(int32_t));
+              up((void **)&nl.d_entry_site, entry_site.data(), entry_site.size() * sizeof(int32_t)) &&
+              up((void **)&nl.d_chunk_site, chunk_site.data(), chunk_site.size() * sizeof(int32_t)) &&
+              up((void **)&nl.d_chunk_e0, chunk_e0.data(), chunk_e0.size() * sizeof(int64_t));
     if (!ok) {
         (void)hipGetLastError();
         free_nl(nl);
@@ -393,6 +563,7 @@ fe_status fe_set_nonlocal(fe_mesh *m, int32_t n_site, const double *centres, con
     nl.nnz = (int64_t)supp_dof.size();
     nl.n_node = (int64_t)node.size();
     nl.disp.swap(disp);
+    nl.chunk_col_ptr.swap(chunk_col_ptr);
     const fe_status ps = nonlocal_set_phase(m);
     if (ps != FE_OK) free_nl(nl);
     return ps;

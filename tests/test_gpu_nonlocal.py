@@ -42,6 +42,19 @@ def test_hx_with_nonlocal(nl_case):
     assert _err(Y, op.apply(X)) < 1e-13
 
 
+def test_hx_with_nonlocal_wide_block(nl_case):
+    """150 columns: the projection and expansion kernels take their batched
+    path on the full waves of 64 columns and the entry-by-entry path on the
+    ragged last wave; two sites of this slab share nodes, so the expansion
+    runs colour by colour.  Two calls give the same bits."""
+    wl, op, gm = nl_case
+    X = wl.X(op.n, cols=range(150))
+    Xd = torch.from_numpy(X).cuda()
+    Y = gm.hx(Xd).cpu().numpy()
+    assert _err(Y, op.apply(X)) < 1e-13
+    assert np.array_equal(gm.hx(Xd).cpu().numpy(), Y)
+
+
 def test_filter_with_nonlocal(nl_case):
     wl, op, gm = nl_case
     X = wl.X(op.n)
