@@ -122,11 +122,14 @@ __global__ void __launch_bounds__(64 * kNlWaves)
                       const int32_t *__restrict__ supp_dof, const double *__restrict__ vals,
                       const double *__restrict__ D, double *__restrict__ W) {
     __shared__ double part[kNlWaves][9][64];
-    const int s = blockIdx.x;
+    // workgroups of one site are consecutive (its matrix rows stay in cache)
+    const int64_t ncb = (N + 63) / 64;
+    const int s = (int)(blockIdx.x / ncb);
+    const int64_t cb = blockIdx.x % ncb;
     // the wave index is uniform over the wave: the entry loop runs on scalar
     // registers
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t j = (int64_t)blockIdx.y * 64 + lane;
+    const int64_t j = cb * 64 + lane;
     const int64_t s0 = supp_ptr[s], len = supp_ptr[s + 1] - s0;
     const int64_t e0 = s0 + len * wv / kNlWaves, e1 = s0 + len * (wv + 1) / kNlWaves;
     // every lane takes part in the loads that are broadcast; a lane past the
@@ -177,7 +180,7 @@ __global__ void __launch_bounds__(64 * kNlWaves)
     __syncthreads();
     for (int q = threadIdx.x; q < 9 * 64; q += 64 * kNlWaves) {
         const int b = q >> 6, c = q & 63;
-        const int64_t jc = (int64_t)blockIdx.y * 64 + c;
+        const int64_t jc = cb * 64 + c;
         if (jc >= N) continue;
         double t = part[0][b][c];
 #pragma unroll
@@ -195,19 +198,22 @@ __global__ void nl_expand_chunk_kernel(double *__restrict__ Y, int64_t ldy, int6
                                        const int32_t *__restrict__ chunk_site, const int64_t *__restrict__ chunk_e0,
                                        const int64_t *__restrict__ supp_ptr, const int32_t *__restrict__ supp_dof,
                                        const double *__restrict__ vals, const double *__restrict__ W) {
-    const int s = chunk_site[blockIdx.x];
+    // workgroups of one chunk are consecutive (its matrix rows stay in cache)
+    const int64_t ncb = (N + blockDim.x - 1) / blockDim.x;
+    const int64_t q = blockIdx.x / ncb, cb = blockIdx.x % ncb;
+    const int s = chunk_site[q];
     const int lane = threadIdx.x & 63;
-    const int64_t j = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+    const int64_t j = cb * blockDim.x + threadIdx.x;
     // a wave whose 64 columns all exist takes the batched path below, which
     // broadcasts loads across the lanes; a wave at the ragged end of the
     // columns goes entry by entry
-    const int64_t wave_end = (int64_t)blockIdx.y * blockDim.x + (threadIdx.x & ~63) + 64;
+    const int64_t wave_end = cb * blockDim.x + (threadIdx.x & ~63) + 64;
     const bool full = wave_end <= N;
     if (!full && j >= N) return;
     double w[9];
 #pragma unroll
     for (int b = 0; b < 9; ++b) w[b] = W[((int64_t)s * 9 + b) * N + j];
-    const int64_t e0 = chunk_e0[blockIdx.x];
+    const int64_t e0 = chunk_e0[q];
     const int64_t e1 = min(e0 + (int64_t)kNlChunk, supp_ptr[s + 1]);
     int64_t e = e0;
     if (full && e + kNlBatch <= e1) {
@@ -343,7 +349,9 @@ hipError_t launch_nonlocal(fe_mesh *m, const double *X, int64_t ldx, double *Y, 
     }
     hipError_t e;
     const int TB = 128;
-    dim3 g1((unsigned)m->nl.n_site, (unsigned)((N + 63) / 64));
+    const int64_t nb1 = (int64_t)m->nl.n_site * ((N + 63) / 64);
+    if (nb1 > INT32_MAX) return hipErrorInvalidConfiguration;
+    dim3 g1((unsigned)nb1);
     hipLaunchKernelGGL(nl_project_kernel, g1, dim3(64 * kNlWaves), 0, s, X, ldx, N, (const int64_t *)m->nl.d_supp_ptr,
                        (const int32_t *)m->nl.d_supp_dof, (const double *)m->nl.d_vals, (const double *)m->nl.d_D,
                        W);
@@ -355,7 +363,9 @@ hipError_t launch_nonlocal(fe_mesh *m, const double *X, int64_t ldx, double *Y, 
     for (size_t c = 0; c + 1 < cp.size(); ++c) {
         const int64_t nq = cp[c + 1] - cp[c];
         if (nq == 0) continue;
-        dim3 g2((unsigned)nq, (unsigned)((N + TB - 1) / TB));
+        const int64_t nb2 = nq * ((N + TB - 1) / TB);
+        if (nb2 > INT32_MAX) return hipErrorInvalidConfiguration;
+        dim3 g2((unsigned)nb2);
         hipLaunchKernelGGL(nl_expand_chunk_kernel, g2, dim3(TB), 0, s, Y, ldy, N, alpha,
                            (const int32_t *)m->nl.d_chunk_site + cp[c], (const int64_t *)m->nl.d_chunk_e0 + cp[c],
                            (const int64_t *)m->nl.d_supp_ptr, (const int32_t *)m->nl.d_supp_dof,

@@ -11,6 +11,8 @@ same trace holds a plain copy kernel of known size (n*N*8 bytes read and
 written) against which HBM byte counters can be calibrated.  With --filter M
 it then runs a degree-M filter per precision as well, whose steps after the
 first read the previous iterate (the launches the filter rate is made of).
+With --nonlocal the workload's projector sites are set, so that each H~X
+also runs the projection and expansion kernels.
 """
 from __future__ import annotations
 
@@ -29,6 +31,7 @@ def main():
     ap.add_argument("--precs", default="f64,f32,bf16")
     ap.add_argument("--variant", type=int, default=0, help="step-kernel variant (fe_mesh_set_kernel)")
     ap.add_argument("--filter", type=int, default=0, help="also run a filter of this degree per precision")
+    ap.add_argument("--nonlocal", dest="with_nonlocal", action="store_true", help="set the workload's nonlocal sites (cfg5)")
     args = ap.parse_args()
 
     import torch
@@ -42,6 +45,8 @@ def main():
     n, N = gm.n, wl.N
     Vq = torch.from_numpy(W.workload_potential(wl, gm.quad_points())).cuda()
     gm.set_potential(Vq, wl.E, wl.z0)
+    if args.with_nonlocal and wl.nonlocal_sites:
+        gm.set_nonlocal(wl.centres(), wl.nonlocal_coupling(), wl.r_cut, wl.r_g)
     X = torch.randn(n, N, dtype=torch.float64, device="cuda")
     Y = torch.empty_like(X)
     torch.cuda.synchronize()
