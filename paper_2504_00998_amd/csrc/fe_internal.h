@@ -37,10 +37,6 @@ struct NonlocalData {
     int32_t *d_supp_dof = nullptr;   // [nnz] DoF of each support entry
     double *d_vals = nullptr;        // [nnz][9] C~ values per projector
     double *d_D = nullptr;           // [n_site][9] couplings
-    int32_t *d_node = nullptr;       // [n_node] DoFs with incident entries (ascending)
-    int64_t *d_inc_ptr = nullptr;    // [n_node + 1]
-    int64_t *d_inc_entry = nullptr;  // [nnz] incident entries, per node
-    int32_t *d_entry_site = nullptr; // [nnz] site of each entry
     double *d_W = nullptr;           // projections C~^T X, grown on demand
     size_t W_cap = 0;                // doubles
     std::vector<double> disp;        // [nnz][2] in-plane x_I - R_s of each entry (minimum image)

@@ -7,10 +7,10 @@
 // cutoff ball |x - R_s| < r_cut (minimum image on periodic axes), normalised
 // to sum_I M_I p(x_I)^2 = 1, and S_beta the real solid harmonics 1; x, y, z;
 // xy, yz, zx, x^2 - y^2, 3z^2 - r^2 (s, p, d channels).  The host builds the
-// per-site supports, a colouring of the sites (sites that share a node differ
-// in colour) and, for the Bloch mode, a node -> (site, entry) incidence list,
-// so that the application  Y += alpha C~ D C~^T X  runs on the device without
-// atomics and gives the same bits on every run.
+// per-site supports and a colouring of the sites (sites that share a node
+// differ in colour, found from the node -> site incidence), so that the
+// application  Y += alpha C~ D C~^T X  runs on the device without atomics and
+// gives the same bits on every run.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -89,10 +89,6 @@ void free_nl(NonlocalData &nl) {
     (void)hipFree(nl.d_supp_dof);
     (void)hipFree(nl.d_vals);
     (void)hipFree(nl.d_D);
-    (void)hipFree(nl.d_node);
-    (void)hipFree(nl.d_inc_ptr);
-    (void)hipFree(nl.d_inc_entry);
-    (void)hipFree(nl.d_entry_site);
     (void)hipFree(nl.d_W);
     (void)hipFree(nl.d_phase);
     (void)hipFree(nl.d_chunk_site);
@@ -265,18 +261,62 @@ __global__ void nl_expand_chunk_kernel(double *__restrict__ Y, int64_t ldy, int6
 // minimum-image displacement (the cutoff ball never wraps onto itself, so one
 // image per entry), and H~^k gains C^k diag(D) C^k^H.  Complex columns are
 // interleaved (re, im); ph[e] = (cos k.d_e, sin k.d_e).
-// W[(s*9+beta)][j] = D_{s,beta} sum_e exp(+i k.d_e) C~[e][beta] X[dof(e)][j]
-__global__ void nl_project_k_kernel(const double *X, int64_t ldx, int64_t N, const int64_t *supp_ptr,
-                                    const int32_t *supp_dof, const double *vals, const double *ph, const double *D,
-                                    double *W) {
-    const int s = blockIdx.x;
-    const int64_t j = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
-    if (j >= N) return;
+// W[(s*9+beta)][j] = D_{s,beta} sum_e exp(+i k.d_e) C~[e][beta] X[dof(e)][j],
+// the projection kernel's layout and batching with complex columns: one lane
+// per complex column (16 B), each batch's 16 phase values through one more
+// vector load broadcast with readlane.
+__global__ void __launch_bounds__(64 * kNlWaves)
+    nl_project_k_kernel(const double *__restrict__ X, int64_t ldx, int64_t N, const int64_t *__restrict__ supp_ptr,
+                        const int32_t *__restrict__ supp_dof, const double *__restrict__ vals,
+                        const double *__restrict__ ph, const double *__restrict__ D, double *__restrict__ W) {
+    __shared__ double part[kNlWaves][9][64][2];
+    const int64_t ncb = (N + 63) / 64;
+    const int s = (int)(blockIdx.x / ncb);
+    const int64_t cb = blockIdx.x % ncb;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t j = cb * 64 + lane;
+    const int64_t jl = j < N ? j : N - 1;
+    const int64_t s0 = supp_ptr[s], len = supp_ptr[s + 1] - s0;
+    const int64_t e0 = s0 + len * wv / kNlWaves, e1 = s0 + len * (wv + 1) / kNlWaves;
     double ar[9], ai[9];
 #pragma unroll
     for (int b = 0; b < 9; ++b) ar[b] = ai[b] = 0.0;
-    for (int64_t e = supp_ptr[s]; e < supp_ptr[s + 1]; ++e) {
-        const double *x = X + (int64_t)supp_dof[e] * ldx + 2 * j;
+    int64_t e = e0;
+    if (e + kNlBatch <= e1) {
+        static_assert(kNlBatch == 8, "72 matrix entries in two loads of 64 and 8, 16 phases in one");
+        int d[kNlBatch];
+#pragma unroll
+        for (int t = 0; t < kNlBatch; ++t) d[t] = supp_dof[e + t];
+        for (; e + kNlBatch <= e1; e += kNlBatch) {
+            const double va = vals[e * 9 + lane], vb = vals[e * 9 + 64 + (lane & 7)];
+            const double vp = ph[2 * e + (lane & 15)];
+            double xr[kNlBatch], xi[kNlBatch];  // complex blocks are only 8-byte aligned
+#pragma unroll
+            for (int t = 0; t < kNlBatch; ++t) {
+                const double *xp = X + (int64_t)d[t] * ldx + 2 * jl;
+                xr[t] = xp[0];
+                xi[t] = xp[1];
+            }
+            const int64_t en = e + 2 * kNlBatch <= e1 ? e + kNlBatch : e;
+#pragma unroll
+            for (int t = 0; t < kNlBatch; ++t) d[t] = supp_dof[en + t];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int t = 0; t < kNlBatch; ++t) {
+                const double c = lane_double(vp, 2 * t), sn = lane_double(vp, 2 * t + 1);
+                const double tr = c * xr[t] - sn * xi[t], ti = sn * xr[t] + c * xi[t];
+#pragma unroll
+                for (int b = 0; b < 9; ++b) {
+                    const int q = t * 9 + b;
+                    const double v = q < 64 ? lane_double(va, q) : lane_double(vb, q - 64);
+                    ar[b] += v * tr;
+                    ai[b] += v * ti;
+                }
+            }
+        }
+    }
+    for (; e < e1; ++e) {
+        const double *x = X + (int64_t)supp_dof[e] * ldx + 2 * jl;
         const double c = ph[2 * e], sn = ph[2 * e + 1];
         const double tr = c * x[0] - sn * x[1], ti = sn * x[0] + c * x[1];
         const double *v = vals + e * 9;
@@ -288,38 +328,99 @@ __global__ void nl_project_k_kernel(const double *X, int64_t ldx, int64_t N, con
     }
 #pragma unroll
     for (int b = 0; b < 9; ++b) {
-        double *w = W + ((int64_t)s * 9 + b) * 2 * N + 2 * j;
-        w[0] = D[s * 9 + b] * ar[b];
-        w[1] = D[s * 9 + b] * ai[b];
+        part[wv][b][lane][0] = ar[b];
+        part[wv][b][lane][1] = ai[b];
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < 9 * 64; q += 64 * kNlWaves) {
+        const int b = q >> 6, c = q & 63;
+        const int64_t jc = cb * 64 + c;
+        if (jc >= N) continue;
+        double tr = part[0][b][c][0], ti = part[0][b][c][1];
+#pragma unroll
+        for (int w = 1; w < kNlWaves; ++w) {
+            tr += part[w][b][c][0];
+            ti += part[w][b][c][1];
+        }
+        double *o = W + ((int64_t)s * 9 + b) * 2 * N + 2 * jc;
+        o[0] = D[s * 9 + b] * tr;
+        o[1] = D[s * 9 + b] * ti;
     }
 }
 
-// Y[node][j] += alpha sum_e exp(-i k.d_e) sum_beta C~[e][beta] W[(site(e)*9+beta)][j]
-__global__ void nl_expand_k_kernel(double *Y, int64_t ldy, int64_t N, double alpha, const int32_t *node,
-                                   const int64_t *inc_ptr, const int64_t *inc_entry, const int32_t *entry_site,
-                                   const double *vals, const double *ph, const double *W) {
-    const int64_t u = blockIdx.x;
-    const int64_t j = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
-    if (j >= N) return;
-    double yr = 0.0, yi = 0.0;
-    for (int64_t q = inc_ptr[u]; q < inc_ptr[u + 1]; ++q) {
-        const int64_t e = inc_entry[q];
-        const int s = entry_site[e];
+// Y[dof(e)][j] += alpha exp(-i k.d_e) sum_beta C~[e][beta] W[(site(e)*9+beta)][j],
+// the expansion kernel's chunks, colours and batching with complex columns.
+__global__ void nl_expand_k_kernel(double *__restrict__ Y, int64_t ldy, int64_t N, double alpha,
+                                   const int32_t *__restrict__ chunk_site, const int64_t *__restrict__ chunk_e0,
+                                   const int64_t *__restrict__ supp_ptr, const int32_t *__restrict__ supp_dof,
+                                   const double *__restrict__ vals, const double *__restrict__ ph,
+                                   const double *__restrict__ W) {
+    const int64_t ncb = (N + blockDim.x - 1) / blockDim.x;
+    const int64_t q = blockIdx.x / ncb, cb = blockIdx.x % ncb;
+    const int s = chunk_site[q];
+    const int lane = threadIdx.x & 63;
+    const int64_t j = cb * blockDim.x + threadIdx.x;
+    const int64_t wave_end = cb * blockDim.x + (threadIdx.x & ~63) + 64;
+    const bool full = wave_end <= N;
+    if (!full && j >= N) return;
+    double wr[9], wi[9];
+#pragma unroll
+    for (int b = 0; b < 9; ++b) {
+        const double *w = W + ((int64_t)s * 9 + b) * 2 * N + 2 * j;
+        wr[b] = w[0];
+        wi[b] = w[1];
+    }
+    const int64_t e0 = chunk_e0[q];
+    const int64_t e1 = min(e0 + (int64_t)kNlChunk, supp_ptr[s + 1]);
+    int64_t e = e0;
+    if (full && e + kNlBatch <= e1) {
+        int d[kNlBatch];
+#pragma unroll
+        for (int t = 0; t < kNlBatch; ++t) d[t] = supp_dof[e + t];
+        for (; e + kNlBatch <= e1; e += kNlBatch) {
+            const double va = vals[e * 9 + lane], vb = vals[e * 9 + 64 + (lane & 7)];
+            const double vp = ph[2 * e + (lane & 15)];
+            double yr[kNlBatch], yi[kNlBatch];
+            double *yp[kNlBatch];
+#pragma unroll
+            for (int t = 0; t < kNlBatch; ++t) {
+                yp[t] = Y + (int64_t)d[t] * ldy + 2 * j;
+                yr[t] = yp[t][0];
+                yi[t] = yp[t][1];
+            }
+            const int64_t en = e + 2 * kNlBatch <= e1 ? e + kNlBatch : e;
+#pragma unroll
+            for (int t = 0; t < kNlBatch; ++t) d[t] = supp_dof[en + t];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int t = 0; t < kNlBatch; ++t) {
+                double tr = 0.0, ti = 0.0;
+#pragma unroll
+                for (int b = 0; b < 9; ++b) {
+                    const int qq = t * 9 + b;
+                    const double v = qq < 64 ? lane_double(va, qq) : lane_double(vb, qq - 64);
+                    tr += v * wr[b];
+                    ti += v * wi[b];
+                }
+                const double c = lane_double(vp, 2 * t), sn = lane_double(vp, 2 * t + 1);
+                yp[t][0] = yr[t] + alpha * (c * tr + sn * ti);
+                yp[t][1] = yi[t] + alpha * (c * ti - sn * tr);
+            }
+        }
+    }
+    for (; e < e1; ++e) {
         const double *v = vals + e * 9;
-        const double *w = W + (int64_t)s * 9 * 2 * N + 2 * j;
         double tr = 0.0, ti = 0.0;
 #pragma unroll
         for (int b = 0; b < 9; ++b) {
-            tr += v[b] * w[(int64_t)b * 2 * N];
-            ti += v[b] * w[(int64_t)b * 2 * N + 1];
+            tr += v[b] * wr[b];
+            ti += v[b] * wi[b];
         }
         const double c = ph[2 * e], sn = ph[2 * e + 1];
-        yr += c * tr + sn * ti;
-        yi += c * ti - sn * tr;
+        double *y = Y + (int64_t)supp_dof[e] * ldy + 2 * j;
+        y[0] += alpha * (c * tr + sn * ti);
+        y[1] += alpha * (c * ti - sn * tr);
     }
-    double *y = Y + (int64_t)node[u] * ldy + 2 * j;
-    y[0] += alpha * yr;
-    y[1] += alpha * yi;
 }
 
 size_t nonlocal_work_doubles(const fe_mesh *m, int64_t N) { return (size_t)m->nl.n_site * 9 * (size_t)N; }
@@ -384,19 +485,28 @@ hipError_t launch_nonlocal_k(fe_mesh *m, const double *X, int64_t ldx, double *Y
     hipError_t e = ensure_nl_work(m, 2 * N);
     if (e != hipSuccess) return e;
     const int TB = 128;
-    dim3 g1((unsigned)m->nl.n_site, (unsigned)((N + TB - 1) / TB));
-    hipLaunchKernelGGL(nl_project_k_kernel, g1, dim3(TB), 0, s, X, ldx, N, (const int64_t *)m->nl.d_supp_ptr,
-                       (const int32_t *)m->nl.d_supp_dof, (const double *)m->nl.d_vals,
-                       (const double *)m->nl.d_phase, (const double *)m->nl.d_D, m->nl.d_W);
+    const int64_t nb1 = (int64_t)m->nl.n_site * ((N + 63) / 64);
+    if (nb1 > INT32_MAX) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(nl_project_k_kernel, dim3((unsigned)nb1), dim3(64 * kNlWaves), 0, s, X, ldx, N,
+                       (const int64_t *)m->nl.d_supp_ptr, (const int32_t *)m->nl.d_supp_dof,
+                       (const double *)m->nl.d_vals, (const double *)m->nl.d_phase, (const double *)m->nl.d_D,
+                       m->nl.d_W);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (m->nl.n_node == 0) return hipSuccess;
-    dim3 g2((unsigned)m->nl.n_node, (unsigned)((N + TB - 1) / TB));
-    hipLaunchKernelGGL(nl_expand_k_kernel, g2, dim3(TB), 0, s, Y, ldy, N, alpha, (const int32_t *)m->nl.d_node,
-                       (const int64_t *)m->nl.d_inc_ptr, (const int64_t *)m->nl.d_inc_entry,
-                       (const int32_t *)m->nl.d_entry_site, (const double *)m->nl.d_vals,
-                       (const double *)m->nl.d_phase, (const double *)m->nl.d_W);
-    return hipGetLastError();
+    const std::vector<int64_t> &cp = m->nl.chunk_col_ptr;
+    for (size_t c = 0; c + 1 < cp.size(); ++c) {
+        const int64_t nq = cp[c + 1] - cp[c];
+        if (nq == 0) continue;
+        const int64_t nb2 = nq * ((N + TB - 1) / TB);
+        if (nb2 > INT32_MAX) return hipErrorInvalidConfiguration;
+        hipLaunchKernelGGL(nl_expand_k_kernel, dim3((unsigned)nb2), dim3(TB), 0, s, Y, ldy, N, alpha,
+                           (const int32_t *)m->nl.d_chunk_site + cp[c], (const int64_t *)m->nl.d_chunk_e0 + cp[c],
+                           (const int64_t *)m->nl.d_supp_ptr, (const int32_t *)m->nl.d_supp_dof,
+                           (const double *)m->nl.d_vals, (const double *)m->nl.d_phase, (const double *)m->nl.d_W);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // (cos, sin) of k.d for every support entry, for the mesh's current k
@@ -558,10 +668,6 @@ fe_status fe_set_nonlocal(fe_mesh *m, int32_t n_site, const double *centres, con
               up((void **)&nl.d_supp_dof, supp_dof.data(), supp_dof.size() * sizeof(int32_t)) &&
               up((void **)&nl.d_vals, vals.data(), vals.size() * sizeof(double)) &&
               up((void **)&nl.d_D, D, (size_t)n_site * 9 * sizeof(double)) &&
-              up((void **)&nl.d_node, node.data(), node.size() * sizeof(int32_t)) &&
-              up((void **)&nl.d_inc_ptr, inc_ptr.data(), inc_ptr.size() * sizeof(int64_t)) &&
-              up((void **)&nl.d_inc_entry, inc_entry.data(), inc_entry.size() * sizeof(int64_t)) &&
-              up((void **)&nl.d_entry_site, entry_site.data(), entry_site.size() * sizeof(int32_t)) &&
               up((void **)&nl.d_chunk_site, chunk_site.data(), chunk_site.size() * sizeof(int32_t)) &&
               up((void **)&nl.d_chunk_e0, chunk_e0.data(), chunk_e0.size() * sizeof(int64_t));
     if (!ok) {

@@ -60,6 +60,9 @@ CASES = [
     ("p4-table-ky-N20-rest", W.small_slab((4, 3, 6), p=4, N=20), (0.0, 0.5), False),
     ("p4-table-allper-N16", W.small_slab((3, 4, 4), p=4, N=16, bc=(W.PERIODIC,) * 3, E=0.0), (0.3, -0.6), False),
     ("p3-table-kxy-N16-nl", W.small_slab((6, 6, 5), p=3, N=16, cfg=5), (0.21, -0.45), True),
+    # 80 complex vectors: the projector kernels' batched path on full waves of
+    # 64 columns and their entry-by-entry path on the ragged rest
+    ("p3-kxy-N80-nl", W.small_slab((5, 5, 6), p=3, N=80, cfg=5), (-0.33, 0.52), True),
 ]
 
 
