@@ -234,6 +234,19 @@ def large_workloads(dev, steps):
             raise RuntimeError(f"non-finite filter output on {wl.name}")
         nc = (wl.p + 1) ** 3
         flops_hx = 2.0 * nc * nc * wl.n_cells * N
+        extra = {}
+        if prec != "f64":
+            # the same H~X with FP64 cell products (the row-owner kernel at p = 5)
+            gm.hx(X, Y=Y, prec="f64")
+            torch.cuda.synchronize()
+            e0.record(stream)
+            gm.hx(X, Y=Y, prec="f64")
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms64 = e0.elapsed_time(e1)
+            extra = {"ms_per_hx_f64": round(ms64, 3),
+                     "hx_f64_TFLOPs": round(flops_hx / (ms64 * 1e-3) / 1e12, 3),
+                     "hx_f64_frac_of_mfma_peak": round(flops_hx / (ms64 * 1e-3) / 1e12 / PEAK["f64"][0], 4)}
         value = m * n * N / (ms_f * 1e-3) / 1e9
         ceil = CEILING[(wl.name, prec)]
         out[wl.name] = {"prec": prec, "n_dof": n, "N": N, "m": m, "p": wl.p, "cells": list(wl.ncell),
@@ -242,7 +255,7 @@ def large_workloads(dev, steps):
                         "ms_per_filter": round(ms_f, 3), "filters_timed": nf, "ms_per_hx": round(ms_hx, 4),
                         "hx_TFLOPs": round(flops_hx / (ms_hx * 1e-3) / 1e12, 3),
                         "hx_frac_of_mfma_peak": round(flops_hx / (ms_hx * 1e-3) / 1e12 / PEAK[prec][0], 4),
-                        "setup_s": round(setup_s, 1)}
+                        "setup_s": round(setup_s, 1), **extra}
         log(f"[bench] {wl.name} {prec}: {value:.2f} GDoF.vec/s ({value / ceil:.3f} of {ceil}), "
             f"H~X {ms_hx:.3f} ms")
         del X, Y, work, gm
