@@ -97,3 +97,28 @@ def test_nonlocal_clear_and_errors(nl_case):
     assert _err(Y, op_local.apply(X)) < 1e-13
     with pytest.raises(fe.FEError):
         gm2.set_nonlocal(wl.centres(), wl.nonlocal_coupling(), 3.0, wl.r_g)  # ball wraps on a 5-bohr period
+
+
+@pytest.mark.parametrize("r_cut", [0.35, 0.9])
+def test_hx_nonlocal_small_supports(r_cut):
+    """Supports shorter than one batch of eight rows (r_cut = 0.35 bohr,
+    including a site at the centre of the widest gap between GLL nodes with
+    no node inside its ball) and supports of about a hundred rows over two
+    expansion chunks (0.9 bohr), overlapping sites in several colours, 70
+    columns: H~X against the oracle."""
+    import paper_2504_00998_amd as fe
+    wl = W.small_slab((5, 5, 6), p=3, N=70, cfg=5)
+    print("case: small supports r_cut =", r_cut, flush=True)
+    rng = np.random.default_rng(31)
+    cen = np.concatenate([[[2.5, 2.5, 3.5]], rng.uniform((0.0, 0.0, 1.0), (5.0, 5.0, 5.0), size=(11, 3))])
+    D = rng.uniform(-1.0, 1.0, size=(cen.shape[0], 9))
+    om = O.Mesh.from_workload(wl)
+    Vq = W.workload_potential(wl, om.quad_points())
+    P = O.Projectors(om, cen, r_cut, 0.3)
+    op = O.Operator(om, Vq, wl.E, wl.z0, P, D.reshape(-1))
+    gm = fe.Mesh.from_workload(wl)
+    gm.set_potential(torch.from_numpy(Vq).cuda(), wl.E, wl.z0)
+    gm.set_nonlocal(cen, D, r_cut, 0.3)
+    X = wl.X(op.n)
+    Y = gm.hx(torch.from_numpy(X).cuda()).cpu().numpy()
+    assert _err(Y, op.apply(X)) < 1e-13
