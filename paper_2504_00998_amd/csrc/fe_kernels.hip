@@ -2675,8 +2675,11 @@ static hipError_t launch_step_v(const fe_mesh *m, const StepArgs &a, fe_dtype pr
         // 32 vectors per workgroup and one row tile per wave measured best
         // where the tiles fit one workgroup (p <= 5); above that two tiles
         // per wave keep the workgroup within 1024 threads (p = 6: 32 vectors
-        // per workgroup, 158 VGPRs for three waves per SIMD, 5.78 ms per H~X
-        // on the 16x16x32-cell slab against 6.32 for 16 vectors)
+        // per workgroup, three waves per SIMD, 5.78 ms per H~X on the
+        // 16x16x32-cell slab against 6.32 for 16 vectors; fragment batches of
+        // 4 k-steps, 168 VGPRs with 4 spilled, 5.42 ms against 5.75 for 2
+        // with 158 and none on one box; at p = 7, 4 k-steps were slower:
+        // 5.28 against 4.82 ms on a 12x12x24-cell slab)
         // BK / BKL: fragment batch (k-steps) for FP64 / for FP32 and BF16
 #define FE_ROW(PP, G, TPW, OCC, BK, BKL)                                                     \
     case PP:                                                                                 \
@@ -2689,7 +2692,7 @@ static hipError_t launch_step_v(const fe_mesh *m, const StepArgs &a, fe_dtype pr
             FE_ROW(3, 2, 1, 5, 4, 4)
             FE_ROW(4, 2, 1, 5, 4, 4)
             FE_ROW(5, 2, 1, 5, 4, 4)
-            FE_ROW(6, 2, 2, 3, 2, 2)
+            FE_ROW(6, 2, 2, 3, 4, 2)
             FE_ROW(7, 1, 2, 5, 2, 2)
         default: break;
         }
