@@ -417,7 +417,7 @@ def main():
     rho_bytes = 8.0 * n * N + 8.0 * N + 8.0 * n
     rec["density"] = {"ms": round(ms_rho, 4), "bytes": rho_bytes, "GB/s": round(rho_bytes / (ms_rho * 1e-3) / 1e9, 1),
                       "frac_of_hbm_peak": round(rho_bytes / (ms_rho * 1e-3) / 8e12, 4),
-                      "kernel": "density_kernel (2 sum_n f_n X[I,n]^2 / M_I, 16 lanes per DoF)"}
+                      "kernel": "density_kernel (2 sum_n f_n X[I,n]^2 / M_I, 16 lanes per DoF, 16-byte column pairs)"}
     # electrostatics on the same space (Sec. 2.2): the constant-field boundary
     # conditions (periodic x, y, zero-Neumann z) on a mesh of the workload's
     # size, charge = the filtered block's density (zero at the wavefunction

@@ -21,7 +21,11 @@ namespace fe {
 namespace {
 
 // 16 lanes per DoF: lane j sums f_n X[I,n]^2 over n = j, j+16, ..., then the
-// 16 partial sums are combined in a fixed butterfly order.
+// 16 partial sums are combined in a fixed butterfly order.  V2 (N even, X, f
+// 16-byte aligned, ld even): lane j takes the column pairs 2j + 32i, 2j + 1 +
+// 32i with one 16-byte load each, even and odd columns summed apart and then
+// added.
+template <bool V2>
 __global__ void density_kernel(const double *X, int64_t ld, int64_t N, const double *f, int64_t n, int nfx, int nfy,
                                const double *invM, int maxf, double *rho) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -30,9 +34,20 @@ __global__ void density_kernel(const double *X, int64_t ld, int64_t N, const dou
     double s = 0.0;
     if (I < n) {
         const double *row = X + I * ld;
-        for (int64_t c = j; c < N; c += 16) {
-            const double x = row[c];
-            s += f[c] * (x * x);
+        if constexpr (V2) {
+            double s1 = 0.0;
+            for (int64_t c = 2 * j; c < N; c += 32) {
+                const double2 x = *reinterpret_cast<const double2 *>(row + c);
+                const double2 w = *reinterpret_cast<const double2 *>(f + c);
+                s += w.x * (x.x * x.x);
+                s1 += w.y * (x.y * x.y);
+            }
+            s += s1;
+        } else {
+            for (int64_t c = j; c < N; c += 16) {
+                const double x = row[c];
+                s += f[c] * (x * x);
+            }
         }
     }
 #pragma unroll
@@ -134,8 +149,14 @@ fe_status fe_density(fe_mesh *m, const double *X, int64_t N, int64_t ld, const d
         return FE_OK;
     }
     const int64_t threads = m->n * 16;
-    hipLaunchKernelGGL(density_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, X, ld, N, f, m->n,
-                       (int)m->nf[0], (int)m->nf[1], m->d_axis + 3 * m->maxf, m->maxf, rho);
+    const bool v2 = N % 2 == 0 && ld % 2 == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0 &&
+                    (reinterpret_cast<uintptr_t>(f) & 15) == 0;
+    if (v2)
+        hipLaunchKernelGGL(density_kernel<true>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, X, ld, N, f,
+                           m->n, (int)m->nf[0], (int)m->nf[1], m->d_axis + 3 * m->maxf, m->maxf, rho);
+    else
+        hipLaunchKernelGGL(density_kernel<false>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, X, ld, N,
+                           f, m->n, (int)m->nf[0], (int)m->nf[1], m->d_axis + 3 * m->maxf, m->maxf, rho);
     FE_HIPD(hipGetLastError(), "density kernel");
     return FE_OK;
 }

@@ -23,7 +23,7 @@ def _meshes(L, ncell, p, bc):
 
 
 @pytest.mark.parametrize("case", CASES)
-@pytest.mark.parametrize("N,pad", [(1, 0), (37, 5), (64, 0)])
+@pytest.mark.parametrize("N,pad", [(1, 0), (37, 5), (64, 0), (40, 2), (38, 1)])
 def test_density_and_planar_match_oracle(case, N, pad):
     om, gm = _meshes(*case)
     print("case:", case, N, pad, flush=True)
