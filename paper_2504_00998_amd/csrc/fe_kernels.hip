@@ -2898,13 +2898,28 @@ hipError_t launch_potential_vjp(const fe_mesh *m, const double *g, double z0, do
 }
 
 // g_I += scale * sum_j U[I,j] V[I,j]; 16 lanes per row, fixed reduction order.
+// V2 (N even, U and V 16-byte aligned, even leading dimensions): lane l takes
+// the column pairs 2l + 32i, 2l + 1 + 32i with one 16-byte request per block,
+// even and odd columns summed apart and then added.
+template <bool V2>
 __global__ void rowdot_kernel(const double *U, int64_t ldu, const double *V, int64_t ldv, int64_t N, int64_t n,
                               double scale, double *g) {
     int64_t I = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4;
     int lane = threadIdx.x & 15;
     if (I >= n) return;
     double s = 0.0;
-    for (int64_t j = lane; j < N; j += 16) s += U[I * ldu + j] * V[I * ldv + j];
+    if constexpr (V2) {
+        double s1 = 0.0;
+        for (int64_t j = 2 * lane; j < N; j += 32) {
+            const double2 u = *reinterpret_cast<const double2 *>(U + I * ldu + j);
+            const double2 v = *reinterpret_cast<const double2 *>(V + I * ldv + j);
+            s += u.x * v.x;
+            s1 += u.y * v.y;
+        }
+        s += s1;
+    } else {
+        for (int64_t j = lane; j < N; j += 16) s += U[I * ldu + j] * V[I * ldv + j];
+    }
     for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
     if (lane == 0) g[I] += scale * s;
 }
@@ -2912,8 +2927,14 @@ __global__ void rowdot_kernel(const double *U, int64_t ldu, const double *V, int
 hipError_t launch_rowdot_accum(const fe_mesh *m, const double *U, int64_t ldu, const double *V, int64_t ldv,
                                int64_t N, double scale, double *g, hipStream_t s) {
     int64_t threads = m->n * 16;
-    hipLaunchKernelGGL(rowdot_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, U, ldu, V, ldv, N,
-                       m->n, scale, g);
+    const bool v2 = N % 2 == 0 && ldu % 2 == 0 && ldv % 2 == 0 && (reinterpret_cast<uintptr_t>(U) & 15) == 0 &&
+                    (reinterpret_cast<uintptr_t>(V) & 15) == 0;
+    if (v2)
+        hipLaunchKernelGGL(rowdot_kernel<true>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, U, ldu, V,
+                           ldv, N, m->n, scale, g);
+    else
+        hipLaunchKernelGGL(rowdot_kernel<false>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, U, ldu, V,
+                           ldv, N, m->n, scale, g);
     return hipGetLastError();
 }
 
