@@ -442,7 +442,7 @@ static hipError_t ensure_nl_work(fe_mesh *m, int64_t N) {
 
 hipError_t launch_nonlocal(fe_mesh *m, const double *X, int64_t ldx, double *Y, int64_t ldy, int64_t N,
                            double alpha, hipStream_t s, double *W) {
-    if (m->nl.n_site == 0) return hipSuccess;
+    if (m->nl.n_site == 0 || N <= 0) return hipSuccess;
     if (!W) {
         hipError_t e = ensure_nl_work(m, N);
         if (e != hipSuccess) return e;
@@ -480,7 +480,7 @@ hipError_t launch_nonlocal(fe_mesh *m, const double *X, int64_t ldx, double *Y, 
 // complex blocks: N complex columns, ldx / ldy in doubles
 hipError_t launch_nonlocal_k(fe_mesh *m, const double *X, int64_t ldx, double *Y, int64_t ldy, int64_t N,
                              double alpha, hipStream_t s) {
-    if (m->nl.n_site == 0) return hipSuccess;
+    if (m->nl.n_site == 0 || N <= 0) return hipSuccess;
     if (!m->nl.d_phase) return hipErrorInvalidValue;
     hipError_t e = ensure_nl_work(m, 2 * N);
     if (e != hipSuccess) return e;
